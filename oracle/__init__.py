@@ -1,0 +1,292 @@
+"""FP64 CPU oracle for the ExTraSS hot path: ctypes wrapper over liboracle.so.
+
+TEST INFRASTRUCTURE. Only tests/, __graft_entry__.smoke() and bench.py's
+cpu_baseline leg may import this package. The product path (the HIP library
+in paper_2511_07539_amd/) never imports it, and the two share no code.
+
+Functions whose parity is not pinned by an independent check say so in their
+docstring ("parity unpinned").
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+_lib = None
+
+PKT_FIELDS = 8
+N_STATS = 9
+STAT_NAMES = ["w_emit", "w_esc", "w_kill", "w_abs", "n_inter", "n_checks", "n_cross",
+              "n_escaped", "n_killed"]
+
+
+class _Transport(C.Structure):
+    _fields_ = [
+        ("n", C.c_int32), ("beta_max", C.c_double),
+        ("tau_scale", C.c_void_p), ("cell_photons", C.c_void_p), ("cell_packets", C.c_void_p),
+        ("n_lines", C.c_int32), ("line_lambda", C.c_void_p), ("line_tau0", C.c_void_p),
+        ("line_trans", C.c_void_p), ("n_trans", C.c_int32), ("tau_ct", C.c_void_p),
+        ("fcorr_ct", C.c_void_p), ("lambda_lo", C.c_double), ("lambda_hi", C.c_double),
+        ("seed", C.c_uint64), ("iteration", C.c_int32), ("explicit_packets", C.c_void_p),
+    ]
+
+
+class _Record(C.Structure):
+    _fields_ = [("packet", C.c_int64), ("cell", C.c_int32), ("line", C.c_int32),
+                ("value", C.c_double)]
+
+
+class _Atom(C.Structure):
+    _fields_ = [
+        ("n_species", C.c_int32), ("species_offset", C.c_void_p), ("n_levels", C.c_int32),
+        ("level_ion", C.c_void_p), ("level_energy", C.c_void_p), ("level_g", C.c_void_p),
+        ("n_trans", C.c_int32), ("trans_lower", C.c_void_p), ("trans_upper", C.c_void_p),
+        ("trans_A", C.c_void_p), ("trans_lambda", C.c_void_p), ("trans_upsilon", C.c_void_p),
+        ("ion_alpha0", C.c_void_p),
+    ]
+
+
+class _Cells(C.Structure):
+    _fields_ = [
+        ("t_exp", C.c_double), ("T_e", C.c_void_p), ("n_e", C.c_void_p),
+        ("n_species", C.c_void_p), ("gamma_ion", C.c_void_p), ("gamma_pe", C.c_void_p),
+    ]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            from . import build as _b
+            _b.build()
+        L = C.CDLL(LIB_PATH)
+        L.oracle_philox4x64.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+        L.oracle_transport.restype = C.c_int64
+        L.oracle_transport.argtypes = [C.POINTER(_Transport), C.c_int64, C.c_int64, C.c_int,
+                                       C.POINTER(C.POINTER(_Record)), C.c_void_p, C.c_void_p]
+        L.oracle_free.argtypes = [C.c_void_p]
+        L.oracle_line_tau.argtypes = [C.c_int64, C.c_int32, C.c_int32] + [C.c_void_p] * 6 + \
+            [C.c_double, C.c_void_p, C.c_void_p]
+        L.oracle_rates.argtypes = [C.c_int64, C.c_int32, C.c_int32, C.c_int32] + [C.c_void_p] * 4 + \
+            [C.c_double, C.c_void_p]
+        L.oracle_nlte.restype = C.c_int
+        L.oracle_nlte.argtypes = [C.POINTER(_Atom), C.POINTER(_Cells), C.c_int64, C.c_int64,
+                                  C.c_int, C.c_int, C.c_double, C.c_int, C.c_void_p, C.c_void_p,
+                                  C.c_void_p]
+        L.oracle_nlte_cold.argtypes = [C.POINTER(_Atom), C.POINTER(_Cells), C.c_int64, C.c_void_p]
+        L.oracle_rate_matrix.argtypes = [C.POINTER(_Atom), C.POINTER(_Cells), C.c_int64, C.c_int32,
+                                         C.c_void_p, C.c_void_p]
+        L.oracle_gth.argtypes = [C.c_int32, C.c_void_p, C.c_void_p]
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data
+
+
+def _keep(*arrays):
+    return [np.ascontiguousarray(a) if a is not None else None for a in arrays]
+
+
+def philox4x64(ctr, key):
+    c = np.array(ctr, dtype=np.uint64)
+    k = np.array(key, dtype=np.uint64)
+    out = np.zeros(4, dtype=np.uint64)
+    lib().oracle_philox4x64(_p(c), _p(k), _p(out))
+    return out
+
+
+class TransportInputs:
+    """Holds contiguous copies of every array the C structure points to."""
+
+    def __init__(self, n, beta_max, tau_scale, cell_photons, cell_packets, line_lambda, line_tau0,
+                 lambda_lo, lambda_hi, seed, iteration=0, line_trans=None, tau_ct=None,
+                 fcorr_ct=None, explicit_packets=None):
+        self.arrays = dict(
+            tau_scale=np.ascontiguousarray(tau_scale, dtype=np.float32),
+            cell_photons=np.ascontiguousarray(cell_photons, dtype=np.float64),
+            cell_packets=np.ascontiguousarray(cell_packets, dtype=np.int32),
+            line_lambda=np.ascontiguousarray(line_lambda, dtype=np.float64),
+            line_tau0=np.ascontiguousarray(line_tau0, dtype=np.float32),
+            line_trans=None if line_trans is None else np.ascontiguousarray(line_trans, np.int32),
+            tau_ct=None if tau_ct is None else np.ascontiguousarray(tau_ct, np.float64),
+            fcorr_ct=None if fcorr_ct is None else np.ascontiguousarray(fcorr_ct, np.float64),
+            explicit=None if explicit_packets is None else
+            np.ascontiguousarray(explicit_packets, np.float64).reshape(-1, 8),
+        )
+        a = self.arrays
+        n_trans = 0 if a["tau_ct"] is None else a["tau_ct"].size // (n ** 3)
+        self.n_cells = n ** 3
+        self.n_lines = len(a["line_lambda"])
+        self.s = _Transport(n, beta_max, _p(a["tau_scale"]), _p(a["cell_photons"]),
+                            _p(a["cell_packets"]), self.n_lines, _p(a["line_lambda"]),
+                            _p(a["line_tau0"]), _p(a["line_trans"]), n_trans, _p(a["tau_ct"]),
+                            _p(a["fcorr_ct"]), lambda_lo, lambda_hi, seed, iteration,
+                            _p(a["explicit"]))
+
+    @property
+    def n_packets(self):
+        if self.arrays["explicit"] is not None:
+            return len(self.arrays["explicit"])
+        return int(self.arrays["cell_packets"].astype(np.int64).sum())
+
+
+def transport_inputs_from_workload(w, iteration=0, tau_ct=None, fcorr_ct=None):
+    line_trans = None
+    if tau_ct is not None:
+        line_trans = np.full(w.n_lines, -1, dtype=np.int32)
+        line_trans[w.atom.trans_line] = np.arange(w.atom.n_trans, dtype=np.int32)
+    return TransportInputs(w.n, w.beta_max, w.tau_scale, w.cell_photons, w.cell_packets,
+                           w.line_lambda, w.line_tau0, w.lambda_lo, w.lambda_hi, w.seed,
+                           iteration, line_trans, tau_ct, fcorr_ct)
+
+
+def transport(inp: TransportInputs, first=0, count=None, nthreads=None, per_packet=False):
+    """Runs the oracle over packets [first, first+count).
+
+    Returns dict(records=(packet, cell, line, value) structured array in packet
+    order, stats=dict, packets=[count, 8] per-packet results if per_packet).
+    """
+    if count is None:
+        count = inp.n_packets - first
+    if nthreads is None:
+        nthreads = os.cpu_count() or 1
+    stats = np.zeros(N_STATS)
+    pk = np.zeros((count, PKT_FIELDS)) if per_packet else None
+    ptr = C.POINTER(_Record)()
+    nrec = lib().oracle_transport(C.byref(inp.s), first, count, nthreads, C.byref(ptr),
+                                  _p(stats), _p(pk))
+    if nrec < 0:
+        raise ValueError("oracle_transport: invalid input")
+    dt = np.dtype([("packet", np.int64), ("cell", np.int32), ("line", np.int32),
+                   ("value", np.float64)])
+    if nrec > 0:
+        buf = (C.c_char * (nrec * dt.itemsize)).from_address(C.addressof(ptr.contents))
+        recs = np.frombuffer(buf, dtype=dt).copy()
+    else:
+        recs = np.zeros(0, dtype=dt)
+    lib().oracle_free(ptr)
+    return dict(records=recs, stats=dict(zip(STAT_NAMES, stats)), packets=pk)
+
+
+def dense_estimator(records, n_cells, n_lines):
+    """[C, L] table accumulated in packet order (deterministic)."""
+    est = np.zeros(n_cells * n_lines)
+    idx = records["cell"].astype(np.int64) * n_lines + records["line"]
+    np.add.at(est, idx, records["value"])
+    return est.reshape(n_cells, n_lines)
+
+
+def line_tau(pops, atom, t_exp):
+    """Eq. A2 optical depth and stimulated-emission factor for every (cell, transition)."""
+    pops = np.ascontiguousarray(pops, dtype=np.float64)
+    C_ = pops.size // atom.n_levels
+    tau = np.zeros(C_ * atom.n_trans)
+    fc = np.zeros(C_ * atom.n_trans)
+    lo, up, A, lam, g = _keep(atom.trans_lower, atom.trans_upper, atom.trans_A, atom.trans_lambda,
+                              atom.level_g)
+    lib().oracle_line_tau(C_, atom.n_levels, atom.n_trans, _p(pops), _p(lo), _p(up), _p(A),
+                          _p(lam), _p(g), t_exp, _p(tau), _p(fc))
+    return tau, fc
+
+
+def rates(est, pops, atom, cell_volume):
+    est = np.ascontiguousarray(est, dtype=np.float64)
+    pops = np.ascontiguousarray(pops, dtype=np.float64)
+    C_ = pops.size // atom.n_levels
+    L = est.size // C_
+    out = np.zeros(C_ * atom.n_trans)
+    lo, tl = _keep(atom.trans_lower, atom.trans_line)
+    lib().oracle_rates(C_, L, atom.n_levels, atom.n_trans, _p(est), _p(pops), _p(lo), _p(tl),
+                       cell_volume, _p(out))
+    return out
+
+
+class NLTEInputs:
+    def __init__(self, atom, t_exp, T_e, n_e, n_species, gamma_ion, gamma_pe=None):
+        self.k = dict(
+            off=np.ascontiguousarray(atom.species_offset, np.int32),
+            ion=np.ascontiguousarray(atom.level_ion, np.int32),
+            E=np.ascontiguousarray(atom.level_energy, np.float64),
+            g=np.ascontiguousarray(atom.level_g, np.float64),
+            lo=np.ascontiguousarray(atom.trans_lower, np.int32),
+            up=np.ascontiguousarray(atom.trans_upper, np.int32),
+            A=np.ascontiguousarray(atom.trans_A, np.float64),
+            lam=np.ascontiguousarray(atom.trans_lambda, np.float64),
+            ups=np.ascontiguousarray(atom.trans_upsilon, np.float64),
+            alpha=np.ascontiguousarray(atom.ion_alpha0, np.float64),
+            T=np.ascontiguousarray(T_e, np.float64), ne=np.ascontiguousarray(n_e, np.float64),
+            ns=np.ascontiguousarray(n_species, np.float64),
+            gion=np.ascontiguousarray(gamma_ion, np.float64),
+            gpe=None if gamma_pe is None else np.ascontiguousarray(gamma_pe, np.float64),
+        )
+        k = self.k
+        self.n_levels = len(k["ion"])
+        self.n_cells = len(k["T"])
+        self.atom = _Atom(len(k["off"]) - 1, _p(k["off"]), self.n_levels, _p(k["ion"]), _p(k["E"]),
+                          _p(k["g"]), len(k["A"]), _p(k["lo"]), _p(k["up"]), _p(k["A"]),
+                          _p(k["lam"]), _p(k["ups"]), _p(k["alpha"]))
+        self.cells = _Cells(t_exp, _p(k["T"]), _p(k["ne"]), _p(k["ns"]), _p(k["gion"]),
+                            _p(k["gpe"]))
+
+
+def nlte_inputs_from_workload(w, gamma_pe=None, cells=None):
+    """NLTE inputs for all cells (or the given cell indices) of a workload."""
+    if cells is None:
+        sel = slice(None)
+        S = w.atom.n_species
+        return NLTEInputs(w.atom, w.t_exp, w.T_e, w.n_e, w.n_species, w.gamma_ion, gamma_pe)
+    cells = np.asarray(cells)
+    S = w.atom.n_species
+    T = w.atom.n_trans
+    gpe = None if gamma_pe is None else gamma_pe.reshape(-1, T)[cells].ravel()
+    return NLTEInputs(w.atom, w.t_exp, w.T_e[cells], w.n_e[cells],
+                      w.n_species.reshape(-1, S)[cells].ravel(),
+                      w.gamma_ion.reshape(-1, S, 3)[cells].ravel(), gpe)
+
+
+def nlte(inp: NLTEInputs, guess=None, max_iter=200, tol=1e-13, nthreads=None, first=0,
+         count=None):
+    """Solves statistical equilibrium for cells [first, first+count).
+
+    Returns (pops [C, N], status [C], iters [C]).
+    """
+    if count is None:
+        count = inp.n_cells - first
+    if nthreads is None:
+        nthreads = os.cpu_count() or 1
+    pops = np.zeros((inp.n_cells, inp.n_levels)) if guess is None else \
+        np.ascontiguousarray(guess, dtype=np.float64).reshape(inp.n_cells, inp.n_levels).copy()
+    status = np.full(inp.n_cells, -1, dtype=np.int32)
+    iters = np.zeros(inp.n_cells, dtype=np.int32)
+    lib().oracle_nlte(C.byref(inp.atom), C.byref(inp.cells), first, count,
+                      0 if guess is None else 1, max_iter, tol, nthreads, _p(pops), _p(status),
+                      _p(iters))
+    return pops, status, iters
+
+
+def nlte_cold(inp: NLTEInputs, c: int):
+    out = np.zeros(inp.n_levels)
+    lib().oracle_nlte_cold(C.byref(inp.atom), C.byref(inp.cells), c, _p(out))
+    return out
+
+
+def rate_matrix(inp: NLTEInputs, c: int, s: int, n_local):
+    off = inp.k["off"]
+    Ns = int(off[s + 1] - off[s])
+    n_local = np.ascontiguousarray(n_local, dtype=np.float64)
+    R = np.zeros((Ns, Ns))
+    lib().oracle_rate_matrix(C.byref(inp.atom), C.byref(inp.cells), c, s, _p(n_local), _p(R))
+    return R
+
+
+def gth(R):
+    R = np.ascontiguousarray(R, dtype=np.float64)
+    pi = np.zeros(len(R))
+    lib().oracle_gth(len(R), _p(R), _p(pi))
+    return pi

@@ -1,0 +1,114 @@
+/* Plain FP64 CPU oracle for the ExTraSS hot path (arXiv 2511.07539).
+ *
+ * TEST INFRASTRUCTURE ONLY. Only tests/, __graft_entry__.smoke() and the
+ * cpu_baseline leg of bench.py may load it. The product path (the HIP library)
+ * never links, calls or falls back to this code, and the two share no source.
+ *
+ * Everything here is FP64, serial per packet / per cell, written for
+ * readability rather than speed. Each function cites the passage of the paper
+ * it follows. Where the paper is silent, the reading taken is stated at the
+ * function.
+ */
+#ifndef EXTRASS_ORACLE_H
+#define EXTRASS_ORACLE_H
+#include <stdint.h>
+
+/* ---- Philox4x64-10 (Salmon, Moraes, Dror & Shaw, SC'11) ------------------ */
+void oracle_philox4x64(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);
+
+/* ---- Transport --------------------------------------------------------------
+ * Grid: cube [-beta_max, beta_max]^3 in x = v/c with n cells per axis,
+ * cell c = i + n*(j + n*k). Lines sorted by rest wavelength (cm).
+ * tau(c,k) = line_tau0[k]*tau_scale[c] for background lines (line_trans[k] < 0
+ * or line_trans == NULL); tau_ct[c*n_trans + t] for line k = transition t.
+ */
+typedef struct {
+  int32_t n;
+  double beta_max;
+  const float* tau_scale;       /* [C] */
+  const double* cell_photons;   /* [C] photons s^-1 */
+  const int32_t* cell_packets;  /* [C] packets per cell */
+  int32_t n_lines;
+  const double* line_lambda;    /* [L] cm ascending */
+  const float* line_tau0;       /* [L] */
+  const int32_t* line_trans;    /* [L] or NULL */
+  int32_t n_trans;
+  const double* tau_ct;         /* [C*T] or NULL */
+  const double* fcorr_ct;       /* [C*T] or NULL */
+  double lambda_lo, lambda_hi;  /* emission band, cm */
+  uint64_t seed;
+  int32_t iteration;
+  const double* explicit_packets; /* [P*8] x,y,z,nx,ny,nz,lambda_e,w0; NULL = sampled */
+} or_transport;
+
+/* Per-packet results (8 doubles per packet):
+ * 0 escaped weight, 1 lab wavelength lambda_L, 2 killed weight,
+ * 3 absorbed photons (sum of dN), 4 absorbed comoving energy / (hc),
+ * 5 adiabatic loss / (hc), 6 emitted comoving energy / (hc),
+ * 7 remaining comoving energy / (hc) at escape or kill. */
+enum { OR_PKT_FIELDS = 8 };
+/* Global stats (doubles): w_emit, w_esc, w_kill, w_abs, n_inter, n_checks,
+ * n_cross, n_escaped, n_killed. */
+enum { OR_STATS = 9 };
+
+typedef struct { int64_t packet; int32_t cell, line; double value; } or_record;
+
+/* Runs packets [first, first+count). Returns the number of records written to
+ * *records (malloc'ed; free with oracle_free), or -1 on invalid input. */
+int64_t oracle_transport(const or_transport* p, int64_t first, int64_t count, int nthreads,
+                         or_record** records, double* stats, double* pkt_out);
+void oracle_free(void* ptr);
+
+/* ---- Eq. A2 line optical depth from populations --------------------------- */
+void oracle_line_tau(int64_t n_cells, int32_t n_levels, int32_t n_trans, const double* pops,
+                     const int32_t* lower, const int32_t* upper, const double* A,
+                     const double* lambda, const double* g, double t_exp,
+                     double* tau_ct, double* fcorr_ct);
+
+/* ---- Photoexcitation rates -------------------------------------------------- */
+void oracle_rates(int64_t n_cells, int32_t n_lines, int32_t n_levels, int32_t n_trans,
+                  const double* est, const double* pops, const int32_t* lower,
+                  const int32_t* trans_line, double cell_volume, double* gamma_pe);
+
+/* ---- NLTE statistical equilibrium ------------------------------------------ */
+typedef struct {
+  int32_t n_species;
+  const int32_t* species_offset;  /* [S+1] */
+  int32_t n_levels;
+  const int32_t* level_ion;       /* [N] */
+  const double* level_energy;     /* [N] erg */
+  const double* level_g;          /* [N] */
+  int32_t n_trans;
+  const int32_t* trans_lower, *trans_upper;  /* [T] */
+  const double* trans_A, *trans_lambda, *trans_upsilon;  /* [T] */
+  const double* ion_alpha0;       /* [S*3] cm^3 s^-1 at 1e4 K */
+} or_atom;
+
+typedef struct {
+  double t_exp;
+  const double* T_e, *n_e;        /* [C] */
+  const double* n_species;        /* [C*S] */
+  const double* gamma_ion;        /* [C*S*3] */
+  const double* gamma_pe;         /* [C*T] or NULL */
+} or_cells;
+
+/* Solves cells [first, first+count). pops [C*N] in: initial guess (used when
+ * use_guess != 0), out: solution. status[c]: 0 converged, 2 failed, 3 empty.
+ * iters[c] (optional) receives the Newton iteration count. */
+int oracle_nlte(const or_atom* a, const or_cells* cells, int64_t first, int64_t count,
+                int use_guess, int max_iter, double tol, int nthreads,
+                double* pops, int32_t* status, int32_t* iters);
+
+/* Cold start (Boltzmann within each ion stage, stage ratios from a
+ * ground-state-only balance). */
+void oracle_nlte_cold(const or_atom* a, const or_cells* cells, int64_t c, double* pops_cell);
+
+/* Rate matrix R[i*Ns+j] (i -> j, per atom in i, s^-1) of one species in one
+ * cell at populations n (local numbering), exposed for the pins. */
+void oracle_rate_matrix(const or_atom* a, const or_cells* cells, int64_t c, int32_t s,
+                        const double* n_local, double* R);
+
+/* GTH stationary vector of a generator given by off-diagonal rates R (row i -> j). */
+void oracle_gth(int32_t N, const double* R, double* pi);
+
+#endif
