@@ -1,0 +1,226 @@
+/* extrass.h - C ABI of the MI355X (gfx950) hot path of ExTraSS
+ * (van Baal & Jerkstrand, arXiv 2511.07539): Monte Carlo photon-packet
+ * transport through homologous 3D ejecta with Sobolev line absorption,
+ * photoexcitation-rate estimators per (cell, line), and the per-cell NLTE
+ * statistical-equilibrium solve that consumes them.
+ *
+ * Conventions for every entry point:
+ *  - Array arguments are DEVICE pointers (HIP global memory on the handle's
+ *    device) unless a comment says "host". They are owned by the caller; the
+ *    library never frees them and keeps no pointer after the call's stream
+ *    work has finished.
+ *  - Scratch memory comes from the caller's workspace (`ws`, `ws_bytes`),
+ *    sized by the matching *_workspace query. The library performs no device
+ *    allocation during these calls.
+ *  - `stream` is a hipStream_t (NULL = the null stream). All work is
+ *    enqueued on it; outputs are valid once the stream has completed.
+ *  - Return codes: EXTRASS_OK, or a negative EXTRASS_E* code (below). Bad
+ *    arguments are detected on the host before any work is enqueued. Errors
+ *    found on the device (e.g. a full record buffer) are reported through the
+ *    `stats` output, documented per entry point. No C++ exception crosses
+ *    this interface.
+ *  - Units are CGS: wavelengths in cm, densities in cm^-3, rates in s^-1,
+ *    time in s. The velocity coordinate is x = v/c; the grid is the cube
+ *    [-beta_max, beta_max]^3 cut into n^3 equal cells, cell c = i + n*(j + n*k)
+ *    with lower corner -beta_max + (i, j, k) * 2*beta_max/n.
+ */
+#ifndef EXTRASS_H
+#define EXTRASS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EXTRASS_OK 0
+#define EXTRASS_EINVAL (-1)      /* invalid argument (null pointer, bad size, unsorted lines) */
+#define EXTRASS_ENOSPACE (-2)    /* workspace smaller than the query returned */
+#define EXTRASS_EHIP (-3)        /* a HIP runtime call failed; see extrass_last_error */
+#define EXTRASS_EUNSUPPORTED (-4) /* size outside what the kernels support */
+
+typedef struct extrass_ctx* extrass_handle;
+typedef struct extrass_atom_ctx* extrass_atom_handle;
+
+/* Creates a handle bound to HIP device `device` (reads its properties once).
+ * *out receives the handle; destroy it with extrass_destroy. */
+int extrass_create(extrass_handle* out, int device);
+int extrass_destroy(extrass_handle h);
+/* Static text for a return code. */
+const char* extrass_error_string(int code);
+/* Detail of the last error reported through `h` (host string owned by h). */
+const char* extrass_last_error(extrass_handle h);
+
+/* ------------------------------------------------------------------------
+ * Transport (Sec. 2.3 "Radiative transfer", Sec. 2.3.2 "Photoexcitation").
+ *
+ * Packets travel in straight lines (no scattering) through homologous flow.
+ * With first-order Doppler shifts, D = n.x grows by exactly the path length,
+ * and line k (rest wavelength lambda_k) comes into resonance at
+ * D_k = 1 - lambda_lab / lambda_k. Lines are visited in wavelength order,
+ * starting at the first line redward of the emission wavelength; in cell c a
+ * line is tested when D_k lies in (D, D_exit] of the packet's segment in that
+ * cell. A line with tau(c,k) > 1e-4 absorbs dN = w (1 - e^-tau) of the
+ * packet's w photons, leaving w e^-tau; est[c,k] receives dN / f_corr; the packet stops once
+ * w * lambda_e < 1e-6 * w0 * lambda_k (remaining comoving energy below 1e-6 of
+ * its start), and escapes when it leaves the cube.
+ *
+ * Opacity: tau(c,k) = line_tau0[k] * tau_scale[c] (f_corr = 1), except for
+ * lines with line_trans[k] = t >= 0 when tau_ct is given: then
+ * tau = tau_ct[c*n_trans + t], f_corr = fcorr_ct[c*n_trans + t] (Eq. A2 and
+ * its stimulated-emission factor; see extrass_line_tau).
+ */
+typedef struct {
+  int32_t n;                    /* cells per axis (1..1024) */
+  double beta_max;              /* cube half-width, in units of c */
+  const float* tau_scale;       /* [C] */
+  const double* cell_photons;   /* [C] photons s^-1 emitted by the cell */
+  const int32_t* cell_packets;  /* [C] packets emitted by the cell, >= 0 */
+  int32_t n_lines;              /* L >= 0 */
+  const double* line_lambda;    /* [L] rest wavelengths, cm, non-decreasing */
+  const float* line_tau0;       /* [L] */
+  const int32_t* line_trans;    /* [L] transition of each line or -1; may be NULL */
+  int32_t n_trans;              /* T (only with tau_ct) */
+  const double* tau_ct;         /* [C*T] or NULL */
+  const double* fcorr_ct;       /* [C*T] or NULL (then f_corr = 1) */
+} extrass_grid;
+
+/* Emission. Sampled mode (explicit_packets == NULL): packet ids are cell-major,
+ * cell c owning ids [sum_{c'<c} cell_packets[c'], ... + cell_packets[c]).
+ * Packet p (j-th of its cell's n_c) draws two Philox4x64-10 blocks with key
+ * (seed, 3) and counters (p, iteration, 0, 0), (p, iteration, 1, 0); with
+ * u_i = (r_i >> 11) * 2^-53: position corner + h*(u0, u1, u2), direction
+ * mu = 2*u3 - 1, phi = 2*pi*u4, wavelength
+ * lambda_lo + (lambda_hi - lambda_lo) * (j + u5) / n_c, weight
+ * cell_photons[c] / n_c. Explicit mode: packet p is the row
+ * explicit_packets[8p .. 8p+7] = (x, y, z, nx, ny, nz, lambda_e, w0).
+ * Runs packets [first_packet, first_packet + n_packets). */
+typedef struct {
+  uint64_t seed;
+  int32_t iteration;
+  int64_t first_packet;
+  int64_t n_packets;
+  double lambda_lo, lambda_hi;      /* emission band, cm */
+  const double* explicit_packets;   /* [P*8] or NULL */
+  int32_t geometry_fp32;            /* 0: FP64 positions and distances; 1: FP32 */
+} extrass_source;
+
+/* Transport statistics, written to `stats` (device, EXTRASS_STATS doubles). */
+enum {
+  EXTRASS_STAT_W_EMIT = 0,   /* photons s^-1 emitted */
+  EXTRASS_STAT_W_ESC = 1,    /* escaped */
+  EXTRASS_STAT_W_KILL = 2,   /* left in packets stopped by the 1e-6 rule */
+  EXTRASS_STAT_W_ABS = 3,    /* absorbed in lines (sum of dN) */
+  EXTRASS_STAT_N_INTER = 4,  /* line interactions (tau > 1e-4 resonances) */
+  EXTRASS_STAT_N_CHECKS = 5, /* line resonances tested */
+  EXTRASS_STAT_N_CROSS = 6,  /* cell-to-cell crossings */
+  EXTRASS_STAT_N_ESCAPED = 7,
+  EXTRASS_STAT_N_KILLED = 8,
+  EXTRASS_STAT_BAD_PACKETS = 14, /* 1.0 if some packet id lay beyond the sampling plan
+                                    or a packet had no wall ahead (NaN or zero direction);
+                                    such packets are dropped */
+  EXTRASS_STAT_BAD_LINES = 15,   /* 1.0 if line_lambda is not non-decreasing (est invalid) */
+  EXTRASS_STATS = 16
+};
+
+/* Bytes of workspace extrass_transport needs for this problem. */
+size_t extrass_transport_workspace(const extrass_grid* g, const extrass_source* s);
+
+/* Runs the packets and OVERWRITES est[C*L] (cell-major, FP64) with their
+ * photoexcitation counts (photons s^-1 absorbed per cell and line, divided by
+ * f_corr). stats[EXTRASS_STATS] is overwritten. packets_out, if not NULL,
+ * receives 4 doubles per packet: escaped weight, lab wavelength, weight at the
+ * stop, absorbed photons. Host structs `g` and `s` are read during the call
+ * only. */
+int extrass_transport(extrass_handle h, const extrass_grid* g, const extrass_source* s,
+                      double* est, double* stats, double* packets_out, void* ws,
+                      size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Eq. A2: tau_S = (A_ul / 8 pi) (g_u / g_l) lambda^3 n_l (1 - g_l n_u / (g_u n_l)) t
+ * for every (cell, transition), with f_corr = 1 - g_l n_u / (g_u n_l) (the
+ * stimulated-emission correction of the photoexcitation count). pops is
+ * [C*N] (number densities per level); a cell with n_l <= 0 gets tau = 0,
+ * f_corr = 1. Outputs tau_ct, fcorr_ct [C*T]. */
+int extrass_line_tau(extrass_handle h, extrass_atom_handle atom, int64_t n_cells,
+                     const double* pops, double t_exp, double* tau_ct, double* fcorr_ct,
+                     void* stream);
+
+/* ------------------------------------------------------------------------
+ * Rates (Sec. 2.3.1-2.3.2): photons absorbed per second in a cell's line,
+ * divided by the number of atoms in the line's lower level (population times
+ * cell volume), is the photoexcitation rate per lower atom:
+ *   gamma_pe[c*T + t] = est[c*L + line(t)] / (pops[c*N + lower(t)] * V),
+ * 0 where that population is 0. The photo-de-excitation rate per upper atom
+ * follows by detailed balance, (g_l/g_u) gamma_pe, inside the NLTE solve. */
+int extrass_rates(extrass_handle h, extrass_atom_handle atom, int64_t n_cells, int32_t n_lines,
+                  const double* est, const double* pops, double cell_volume, double* gamma_pe,
+                  void* stream);
+
+/* ------------------------------------------------------------------------
+ * Atom (Sec. 2.2: all ion stages of a species are solved together). HOST
+ * arrays; extrass_atom_create copies them to the device once. Levels of all
+ * species are numbered globally; species s owns [species_offset[s],
+ * species_offset[s+1]), at most 64 levels per species, ion stages 0..2 in
+ * order, each stage's first level its ground state. Each transition joins two
+ * levels of one stage (lower < upper), at most one transition per pair. */
+typedef struct {
+  int32_t n_species;
+  const int32_t* species_offset;   /* host [S+1] */
+  int32_t n_levels;
+  const int32_t* level_ion;        /* host [N] */
+  const double* level_energy;      /* host [N] erg above the stage's ground */
+  const double* level_g;           /* host [N] */
+  int32_t n_trans;
+  const int32_t* trans_lower;      /* host [T] */
+  const int32_t* trans_upper;      /* host [T] */
+  const double* trans_A;           /* host [T] s^-1 */
+  const double* trans_lambda;      /* host [T] cm */
+  const double* trans_upsilon;     /* host [T] effective collision strength */
+  const int32_t* trans_line;       /* host [T] line index, used by extrass_rates */
+  const double* ion_alpha0;        /* host [S*3] recombination into stage z at 1e4 K */
+} extrass_atom_desc;
+
+int extrass_atom_create(extrass_handle h, const extrass_atom_desc* desc, extrass_atom_handle* out);
+int extrass_atom_destroy(extrass_atom_handle a);
+
+/* Cell state for the NLTE solve (device arrays). */
+typedef struct {
+  int64_t n_cells;
+  double t_exp;                 /* s */
+  const double* T_e;            /* [C] K */
+  const double* n_e;            /* [C] cm^-3 */
+  const double* n_species;      /* [C*S] cm^-3 */
+  const double* gamma_ion;      /* [C*S*3] s^-1, stage z -> z+1 from any level */
+  const double* gamma_pe;       /* [C*T] s^-1 per lower atom, or NULL */
+} extrass_cells;
+
+typedef struct {
+  int32_t max_iter;    /* iteration cap per species (fixed-point + Newton) */
+  double tol;          /* convergence: max |d ln n| below tol */
+  int32_t use_guess;   /* 1: start from pops on entry; 0: cold start */
+  int32_t factor_fp32; /* 1: Newton systems factored in FP32, residuals in FP64 */
+} extrass_nlte_opts;
+
+/* Statistical equilibrium per cell and species (Sec. 2.2, Eqs. A1-A2):
+ * the positive root of inflow = outflow for every level with
+ * sum_i n_i = n_species, rates
+ *   R_ul += A_ul beta_S(tau_ul(n)) + n_e q_ul + (g_l/g_u) Gamma_PE,
+ *   R_lu += n_e q_lu + Gamma_PE,  q_ul = 8.629e-6 Upsilon / (g_u sqrt(T)),
+ *   q_lu = q_ul (g_u/g_l) exp(-(E_u - E_l)/kT),
+ *   ionisation stage z -> ground of z+1 at gamma_ion, recombination from the
+ *   ground of z+1 at n_e alpha0 (T/1e4)^-0.8, 1/3 to the ground state of z and
+ *   2/3 over its excited levels by statistical weight (Appendix A.2).
+ * pops [C*N]: in = guess (if use_guess), out = solution. status [C]: 0
+ * converged, 2 not converged within max_iter, 3 empty cell (all species 0).
+ * iters [C] (may be NULL): largest iteration count over the cell's species. */
+size_t extrass_nlte_workspace(extrass_atom_handle a, int64_t n_cells);
+int extrass_nlte_solve(extrass_handle h, extrass_atom_handle a, const extrass_cells* cells,
+                       const extrass_nlte_opts* opts, double* pops, int32_t* status,
+                       int32_t* iters, void* ws, size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -37,7 +37,7 @@ class _Transport(C.Structure):
 
 class _Record(C.Structure):
     _fields_ = [("packet", C.c_int64), ("cell", C.c_int32), ("line", C.c_int32),
-                ("value", C.c_double)]
+                ("value", C.c_double), ("margin", C.c_double)]
 
 
 class _Atom(C.Structure):
@@ -164,7 +164,7 @@ def transport(inp: TransportInputs, first=0, count=None, nthreads=None, per_pack
     if nrec < 0:
         raise ValueError("oracle_transport: invalid input")
     dt = np.dtype([("packet", np.int64), ("cell", np.int32), ("line", np.int32),
-                   ("value", np.float64)])
+                   ("value", np.float64), ("margin", np.float64)])
     if nrec > 0:
         buf = (C.c_char * (nrec * dt.itemsize)).from_address(C.addressof(ptr.contents))
         recs = np.frombuffer(buf, dtype=dt).copy()

@@ -193,35 +193,6 @@ void oracle_nlte_cold(const or_atom* a, const or_cells* cl, int64_t c, double* o
   }
 }
 
-/* Residual F_i = inflow_i - outflow_i of every level at populations n.
- * Returns sum_i (F_i / w_i)^2 with w_i = inflow_i + outflow_i at n when
- * `scale` is NULL, else w_i = scale[i]; stores the componentwise-scaled
- * maximum in *maxres and the scales in `scale_out` when given. */
-static double merit(const or_atom* a, const or_cells* cl, int64_t c, int32_t s, const double* n,
-                    double* R, const double* scale, double* maxres, double* scale_out) {
-  int32_t Ns = a->species_offset[s + 1] - a->species_offset[s];
-  oracle_rate_matrix(a, cl, c, s, n, R);
-  double acc = 0.0, mx = 0.0;
-  for (int32_t i = 0; i < Ns; ++i) {
-    double in = 0.0, outr = 0.0;
-    for (int32_t j = 0; j < Ns; ++j) {
-      if (j == i) continue;
-      in += n[j] * R[j * Ns + i];
-      outr += R[i * Ns + j];
-    }
-    outr *= n[i];
-    double sc = in + outr;
-    double r = sc > 0.0 ? fabs(in - outr) / sc : 0.0;
-    if (r > mx) mx = r;
-    if (scale_out) scale_out[i] = sc;
-    double wsc = scale ? scale[i] : sc;
-    double q = wsc > 0.0 ? (in - outr) / wsc : 0.0;
-    acc += q * q;
-  }
-  if (maxres) *maxres = mx;
-  return acc;
-}
-
 /* One species of one cell. n (local numbering, length Ns) holds the start on
  * entry and the solution on exit. Returns the iteration count, or -1.
  *
@@ -230,13 +201,16 @@ static double merit(const or_atom* a, const or_cells* cl, int64_t c, int32_t s, 
  * Step 2: Newton on the level equations in log(n): the correction
  *   delta = d ln n solves J diag(n) delta = -F with sum n_i delta_i fixed by
  *   conservation, and the update is n_i exp(delta_i) (positive by
- *   construction). Far from the root the step is limited to a trust radius
- *   (max |delta_i| <= Delta) and accepted only if it lowers the sum of squared
- *   residuals weighted by the current point's inflow + outflow per level (a
- *   fixed weighting, for which the Newton direction is a descent direction);
- *   a rejected step shrinks the radius.
- * Converged when max |delta| < tol with scaled residual < 1e-10, or when the
- * scaled residual is at rounding level (< 1e-13) and max |delta| < 1e-9.
+ *   construction). -F is formed as Q(n)^T (P(n) - n), P(n) being the
+ *   GTH stationary vector of the current rates scaled to n_species: the
+ *   same vector, free of the cancellation between gross inflow and outflow
+ *   that limits a directly summed F to ~1e-9 in weakly coupled stages. Far
+ *   from the root the step is limited to a trust radius (max |delta_i| <=
+ *   Delta) and accepted only if it lowers sum_i (P(n)_i/n_i - 1)^2; a
+ *   rejected step shrinks the radius.
+ * Converged when max |delta| < tol and max |P(n)_i/n_i - 1| < 1e-10, or when
+ * max |delta| < 1e-11 has not improved for 3 steps, or when no step lowers the
+ * fixed-point residual any more and it is at rounding level.
  */
 static int solve_species(const or_atom* a, const or_cells* cl, int64_t c, int32_t s, double* n,
                          int max_iter, double tol) {
@@ -253,9 +227,10 @@ static int solve_species(const or_atom* a, const or_cells* cl, int64_t c, int32_
   double* pi = (double*)malloc(sizeof(double) * Ns);
   double* trial = (double*)malloc(sizeof(double) * Ns);
   double* wscale = (double*)malloc(sizeof(double) * Ns);
+  double* hres = (double*)malloc(sizeof(double) * Ns);
   int32_t* perm = (int32_t*)malloc(sizeof(int32_t) * Ns);
-  int it, result = -1;
-  double Delta = 1.0;
+  int it, result = -1, best_it = 0;
+  double Delta = 1.0, best_step = INFINITY;
 
   /* fixed-point phase, under-relaxed in log(n): omega halves whenever the
    * change fails to shrink (this also breaks period-2 cycles) and never grows
@@ -283,24 +258,40 @@ static int solve_species(const or_atom* a, const or_cells* cl, int64_t c, int32_
     }
   }
 
+  int have_p = 0;
   for (; it < max_iter; ++it) {
-    /* residual F_i = inflow - outflow and its componentwise scale */
-    double res = 0.0;
-    double phi = merit(a, cl, c, s, n, R, NULL, &res, wscale);
-    for (int32_t i = 0; i < Ns; ++i) {
-      double in = 0.0, outr = 0.0;
-      for (int32_t j = 0; j < Ns; ++j) {
-        if (j == i) continue;
-        in += n[j] * R[j * Ns + i];
-        outr += R[i * Ns + j];
-      }
-      b[i] = -(in - outr * n[i]);
+    /* Fixed-point residual h_i = P(n)_i / n_i - 1, with P(n) = n_species *
+     * stationary(R(n)) from GTH: no cancellation, accurate componentwise. */
+    if (!have_p) {
+      oracle_rate_matrix(a, cl, c, s, n, R);
+      oracle_gth(Ns, R, pi);
+      if (!(pi[0] == pi[0])) goto out;
+      for (int32_t i = 0; i < Ns; ++i) hres[i] = ntot * pi[i] / n[i] - 1.0;
     }
-    /* scaled Jacobian as a generator: G_kj = n_k dF_j/dn_k (k != j) */
+    double res = 0.0, phi = 0.0;
+    for (int32_t i = 0; i < Ns; ++i) {
+      if (fabs(hres[i]) > res) res = fabs(hres[i]);
+      phi += hres[i] * hres[i];
+    }
+    /* Newton right-hand side -F(n) written as Q(n)^T (P(n) - n): with the flux
+     * matrix G_ij = n_i R_ij, (Q^T H)_i = sum_j h_j G_ji - h_i sum_j G_ij. It is
+     * the same vector as -F, formed from the small h instead of the cancelling
+     * gross inflows and outflows. */
+    oracle_rate_matrix(a, cl, c, s, n, R);
     for (size_t e = 0; e < NN; ++e) G[e] = 0.0;
     for (int32_t k = 0; k < Ns; ++k)
       for (int32_t j = 0; j < Ns; ++j)
         if (j != k) G[k * Ns + j] = n[k] * R[k * Ns + j];
+    for (int32_t i = 0; i < Ns; ++i) {
+      double in = 0.0, outr = 0.0;
+      for (int32_t j = 0; j < Ns; ++j) {
+        if (j == i) continue;
+        in += hres[j] * G[j * Ns + i];
+        outr += G[i * Ns + j];
+      }
+      b[i] = in - hres[i] * outr;
+    }
+    /* scaled Jacobian as a generator: G_kj = n_k dF_j/dn_k (k != j) */
     for (int32_t t = 0; t < a->n_trans; ++t) {
       int32_t lo = a->trans_lower[t], up = a->trans_upper[t];
       if (lo < base || lo >= base + Ns) continue;
@@ -353,8 +344,12 @@ static int solve_species(const or_atom* a, const or_cells* cl, int64_t c, int32_
       x[i] += cst * pi[i];
       if (fabs(x[i]) > step) step = fabs(x[i]);
     }
-    if ((step < tol && res < 1e-10) || (res < 1e-13 && step < 1e-9)) { result = it + 1; goto out; }
-    /* trust-region step in log(n) */
+    if (step < best_step) { best_step = step; best_it = it; }
+    if ((step < tol && res < 1e-10) || (step < 1e-11 && it - best_it >= 3)) {
+      result = it + 1;
+      goto out;
+    }
+    /* trust-region step in log(n), accepted when the fixed-point residual drops */
     int accepted = 0;
     double taken = 0.0;
     for (int bt = 0; bt < 40; ++bt) {
@@ -366,19 +361,28 @@ static int solve_species(const or_atom* a, const or_cells* cl, int64_t c, int32_
         tot += trial[i];
       }
       for (int32_t i = 0; i < Ns; ++i) trial[i] *= ntot / tot;
-      double phi2 = merit(a, cl, c, s, trial, R, wscale, NULL, NULL);
-      if (phi2 < phi || phi2 < 1e-28) { accepted = 1; break; }
+      oracle_rate_matrix(a, cl, c, s, trial, R);
+      oracle_gth(Ns, R, pi);
+      double phi2 = 0.0, res2 = 0.0;
+      for (int32_t i = 0; i < Ns; ++i) {
+        double hv = ntot * pi[i] / trial[i] - 1.0;
+        wscale[i] = hv;
+        phi2 += hv * hv;
+        if (fabs(hv) > res2) res2 = fabs(hv);
+      }
+      if (phi2 < phi || res2 < 1e-14) { accepted = 1; break; }
       Delta = (taken < Delta ? taken : Delta) / 4.0;
     }
     if (!accepted) {
-      if (step < 1e-9) result = it + 1; /* stalled at rounding level */
+      if (step < 1e-11 || res < 1e-14) result = it + 1; /* stalled at rounding level */
       goto out;
     }
-    for (int32_t i = 0; i < Ns; ++i) n[i] = trial[i];
+    for (int32_t i = 0; i < Ns; ++i) { n[i] = trial[i]; hres[i] = wscale[i]; }
+    have_p = 1;
     if (taken >= 0.99 * Delta) Delta = 2.0 * Delta < 30.0 ? 2.0 * Delta : 30.0;
   }
 out:
-  free(R); free(G); free(Gp); free(b); free(bp); free(x); free(pi); free(trial); free(perm); free(wscale);
+  free(R); free(G); free(Gp); free(b); free(bp); free(x); free(pi); free(trial); free(perm); free(wscale); free(hres);
   return result;
 }
 

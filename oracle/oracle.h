@@ -51,7 +51,11 @@ enum { OR_PKT_FIELDS = 8 };
  * n_cross, n_escaped, n_killed. */
 enum { OR_STATS = 9 };
 
-typedef struct { int64_t packet; int32_t cell, line; double value; } or_record;
+/* One line interaction: packet, cell, line, photons added to est (dN / f_corr),
+ * and the margin of the resonance inside its segment, min(D_k - D_entry,
+ * D_exit - D_k) / h (how far the decision "this line, this cell" was from a
+ * wall; used to classify reduced-precision differences as near ties). */
+typedef struct { int64_t packet; int32_t cell, line; double value, margin; } or_record;
 
 /* Runs packets [first, first+count). Returns the number of records written to
  * *records (malloc'ed; free with oracle_free), or -1 on invalid input. */

@@ -41,7 +41,7 @@ typedef struct {
   int64_t n, cap;
 } recbuf;
 
-static void rec_push(recbuf* b, int64_t p, int32_t c, int32_t k, double v) {
+static void rec_push(recbuf* b, int64_t p, int32_t c, int32_t k, double v, double margin) {
   if (b->n == b->cap) {
     b->cap = b->cap ? 2 * b->cap : 1024;
     b->r = (or_record*)realloc(b->r, (size_t)b->cap * sizeof(or_record));
@@ -50,6 +50,7 @@ static void rec_push(recbuf* b, int64_t p, int32_t c, int32_t k, double v) {
   b->r[b->n].cell = c;
   b->r[b->n].line = k;
   b->r[b->n].value = v;
+  b->r[b->n].margin = margin;
   b->n++;
 }
 
@@ -145,6 +146,7 @@ static void follow(const or_transport* P, int64_t p, const packet0* q, recbuf* r
   double D = dir[0] * x[0] + dir[1] * x[1] + dir[2] * x[2];
   double lamL = q->lam_e * (1.0 - D);         /* lab wavelength, fixed along the ray */
   int32_t k = first_line_above(P, q->lam_e);  /* no absorption at the emission wavelength */
+  double h = 2.0 * P->beta_max / n;
   double w = q->w0, Dcur = D;
   double e_abs = 0.0, e_adiab = 0.0, w_abs = 0.0;
   double res[OR_PKT_FIELDS] = {0};
@@ -174,10 +176,11 @@ static void follow(const or_transport* P, int64_t p, const packet0* q, recbuf* r
         e_adiab += w * (Dk - Dcur) / lamL;
         Dcur = Dk;
         double dN = w * (-expm1(-tau));
-        rec_push(rb, p, (int32_t)c, k, dN / fcorr);
+        double m1 = Dk - D, m2 = Dexit - Dk;
+        rec_push(rb, p, (int32_t)c, k, dN / fcorr, (m1 < m2 ? m1 : m2) / h);
         w_abs += dN;
         e_abs += dN / lamk;
-        w = w - dN;
+        w = w * exp(-tau);  /* N_phot - N_PE = N_phot e^-tau, in the accurate form */
         if (w * q->lam_e < (KILL_FRAC * q->w0) * lamk) {
           res[2] = w;
           res[7] = w / lamk;

@@ -1,0 +1,331 @@
+"""MI355X (gfx950) hot path of ExTraSS (arXiv 2511.07539): Python binding.
+
+The binding only marshals arguments: it passes device pointers of torch
+tensors and the current HIP stream to the C ABI of libextrass.so (declared in
+include/extrass.h), where every step of the path runs in hand-written HIP
+kernels. PyTorch provides device memory and streams. There is no CPU
+fallback: importing this package without the built library raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libextrass.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with "
+                      "`python -m paper_2511_07539_amd.build` (hipcc, gfx950)")
+
+_lib = C.CDLL(LIB_PATH)
+
+OK, EINVAL, ENOSPACE, EHIP, EUNSUPPORTED = 0, -1, -2, -3, -4
+STATS = 16
+STAT_NAMES = ["w_emit", "w_esc", "w_kill", "w_abs", "n_inter", "n_checks", "n_cross",
+              "n_escaped", "n_killed"]
+STAT_ERROR_FLAG = 15
+
+
+class _Grid(C.Structure):
+    _fields_ = [("n", C.c_int32), ("beta_max", C.c_double), ("tau_scale", C.c_void_p),
+                ("cell_photons", C.c_void_p), ("cell_packets", C.c_void_p),
+                ("n_lines", C.c_int32), ("line_lambda", C.c_void_p), ("line_tau0", C.c_void_p),
+                ("line_trans", C.c_void_p), ("n_trans", C.c_int32), ("tau_ct", C.c_void_p),
+                ("fcorr_ct", C.c_void_p)]
+
+
+class _Source(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("iteration", C.c_int32), ("first_packet", C.c_int64),
+                ("n_packets", C.c_int64), ("lambda_lo", C.c_double), ("lambda_hi", C.c_double),
+                ("explicit_packets", C.c_void_p), ("geometry_fp32", C.c_int32)]
+
+
+class _AtomDesc(C.Structure):
+    _fields_ = [("n_species", C.c_int32), ("species_offset", C.c_void_p),
+                ("n_levels", C.c_int32), ("level_ion", C.c_void_p), ("level_energy", C.c_void_p),
+                ("level_g", C.c_void_p), ("n_trans", C.c_int32), ("trans_lower", C.c_void_p),
+                ("trans_upper", C.c_void_p), ("trans_A", C.c_void_p),
+                ("trans_lambda", C.c_void_p), ("trans_upsilon", C.c_void_p),
+                ("trans_line", C.c_void_p), ("ion_alpha0", C.c_void_p)]
+
+
+class _Cells(C.Structure):
+    _fields_ = [("n_cells", C.c_int64), ("t_exp", C.c_double), ("T_e", C.c_void_p),
+                ("n_e", C.c_void_p), ("n_species", C.c_void_p), ("gamma_ion", C.c_void_p),
+                ("gamma_pe", C.c_void_p)]
+
+
+class _Opts(C.Structure):
+    _fields_ = [("max_iter", C.c_int32), ("tol", C.c_double), ("use_guess", C.c_int32),
+                ("factor_fp32", C.c_int32)]
+
+
+_vp = C.c_void_p
+_lib.extrass_create.argtypes = [C.POINTER(_vp), C.c_int]
+_lib.extrass_destroy.argtypes = [_vp]
+_lib.extrass_error_string.restype = C.c_char_p
+_lib.extrass_error_string.argtypes = [C.c_int]
+_lib.extrass_last_error.restype = C.c_char_p
+_lib.extrass_last_error.argtypes = [_vp]
+_lib.extrass_transport_workspace.restype = C.c_size_t
+_lib.extrass_transport_workspace.argtypes = [C.POINTER(_Grid), C.POINTER(_Source)]
+_lib.extrass_transport.argtypes = [_vp, C.POINTER(_Grid), C.POINTER(_Source), _vp, _vp, _vp, _vp,
+                                   C.c_size_t, _vp]
+_lib.extrass_line_tau.argtypes = [_vp, _vp, C.c_int64, _vp, C.c_double, _vp, _vp, _vp]
+_lib.extrass_rates.argtypes = [_vp, _vp, C.c_int64, C.c_int32, _vp, _vp, C.c_double, _vp, _vp]
+_lib.extrass_atom_create.argtypes = [_vp, C.POINTER(_AtomDesc), C.POINTER(_vp)]
+_lib.extrass_atom_destroy.argtypes = [_vp]
+_lib.extrass_nlte_workspace.restype = C.c_size_t
+_lib.extrass_nlte_workspace.argtypes = [_vp, C.c_int64]
+_lib.extrass_nlte_solve.argtypes = [_vp, _vp, C.POINTER(_Cells), C.POINTER(_Opts), _vp, _vp, _vp,
+                                    _vp, C.c_size_t, _vp]
+
+SYMBOLS = ["extrass_create", "extrass_destroy", "extrass_error_string", "extrass_last_error",
+           "extrass_transport_workspace", "extrass_transport", "extrass_line_tau",
+           "extrass_rates", "extrass_atom_create", "extrass_atom_destroy",
+           "extrass_nlte_workspace", "extrass_nlte_solve"]
+
+
+class ExtrassError(RuntimeError):
+    pass
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("extrass expects device tensors")
+    if not t.is_contiguous():
+        raise ValueError("extrass expects contiguous tensors")
+    return t.data_ptr()
+
+
+def _stream():
+    return torch.cuda.current_stream().cuda_stream
+
+
+class Context:
+    """A library handle bound to one HIP device."""
+
+    def __init__(self, device: int = 0):
+        self.device = device
+        h = _vp()
+        rc = _lib.extrass_create(C.byref(h), device)
+        if rc != OK:
+            raise ExtrassError(f"extrass_create: {_lib.extrass_error_string(rc).decode()}")
+        self.h = h
+        self._ws = None
+
+    def close(self):
+        if self.h:
+            _lib.extrass_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def check(self, rc, what):
+        if rc != OK:
+            detail = _lib.extrass_last_error(self.h).decode()
+            raise ExtrassError(f"{what}: {_lib.extrass_error_string(rc).decode()} ({detail})")
+
+    def workspace(self, nbytes):
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=f"cuda:{self.device}")
+        return self._ws
+
+
+def _dev(a, dtype, device):
+    if a is None:
+        return None
+    if isinstance(a, torch.Tensor):
+        return a.to(device=device, dtype=dtype).contiguous()
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device=device)
+
+
+class Grid:
+    """Device copies of the transport inputs of a workload."""
+
+    def __init__(self, n, beta_max, tau_scale, cell_photons, cell_packets, line_lambda,
+                 line_tau0, device="cuda:0", line_trans=None, tau_ct=None, fcorr_ct=None):
+        self.n = int(n)
+        self.beta_max = float(beta_max)
+        self.tau_scale = _dev(tau_scale, torch.float32, device)
+        self.cell_photons = _dev(cell_photons, torch.float64, device)
+        self.cell_packets = _dev(cell_packets, torch.int32, device)
+        self.line_lambda = _dev(line_lambda, torch.float64, device)
+        self.line_tau0 = _dev(line_tau0, torch.float32, device)
+        self.line_trans = _dev(line_trans, torch.int32, device)
+        self.tau_ct = _dev(tau_ct, torch.float64, device)
+        self.fcorr_ct = _dev(fcorr_ct, torch.float64, device)
+        self.n_cells = self.n ** 3
+        self.n_lines = int(self.line_lambda.numel())
+        self.n_trans = 0 if self.tau_ct is None else self.tau_ct.numel() // self.n_cells
+
+    def struct(self):
+        return _Grid(self.n, self.beta_max, _ptr(self.tau_scale), _ptr(self.cell_photons),
+                     _ptr(self.cell_packets), self.n_lines, _ptr(self.line_lambda),
+                     _ptr(self.line_tau0), _ptr(self.line_trans), self.n_trans,
+                     _ptr(self.tau_ct), _ptr(self.fcorr_ct))
+
+
+def grid_from_workload(w, device="cuda:0", tau_ct=None, fcorr_ct=None):
+    line_trans = None
+    if tau_ct is not None:
+        lt = np.full(w.n_lines, -1, dtype=np.int32)
+        lt[w.atom.trans_line] = np.arange(w.atom.n_trans, dtype=np.int32)
+        line_trans = lt
+    return Grid(w.n, w.beta_max, w.tau_scale, w.cell_photons, w.cell_packets, w.line_lambda,
+                w.line_tau0, device, line_trans, tau_ct, fcorr_ct)
+
+
+def transport(ctx: Context, grid: Grid, seed, lambda_lo, lambda_hi, n_packets, first_packet=0,
+              iteration=0, geometry_fp32=False, explicit_packets=None, est=None, stats=None,
+              packets_out=False):
+    """Runs extrass_transport; returns (est [C, L] f64, stats [16] f64, packets [P, 4] or None)."""
+    dev = grid.line_lambda.device
+    expl = _dev(explicit_packets, torch.float64, dev)
+    g = grid.struct()
+    s = _Source(int(seed), int(iteration), int(first_packet), int(n_packets), float(lambda_lo),
+                float(lambda_hi), _ptr(expl), 1 if geometry_fp32 else 0)
+    if est is None:
+        est = torch.empty((grid.n_cells, grid.n_lines), dtype=torch.float64, device=dev)
+    if stats is None:
+        stats = torch.empty(STATS, dtype=torch.float64, device=dev)
+    pk = torch.zeros((n_packets, 4), dtype=torch.float64, device=dev) if packets_out else None
+    need = _lib.extrass_transport_workspace(C.byref(g), C.byref(s))
+    ws = ctx.workspace(need)
+    rc = _lib.extrass_transport(ctx.h, C.byref(g), C.byref(s), _ptr(est), _ptr(stats), _ptr(pk),
+                                _ptr(ws), ws.numel(), _stream())
+    ctx.check(rc, "extrass_transport")
+    return est, stats, pk
+
+
+def stats_dict(stats):
+    v = stats.detach().cpu().numpy()
+    d = dict(zip(STAT_NAMES, v[: len(STAT_NAMES)]))
+    d["error_flag"] = v[STAT_ERROR_FLAG]
+    d["bad_packets"] = v[STAT_ERROR_FLAG - 1]
+    return d
+
+
+class Atom:
+    """An atom uploaded to the device once (extrass_atom_create)."""
+
+    def __init__(self, ctx: Context, atom):
+        self.ctx = ctx
+        self.src = atom
+        keep = dict(
+            off=np.ascontiguousarray(atom.species_offset, np.int32),
+            ion=np.ascontiguousarray(atom.level_ion, np.int32),
+            E=np.ascontiguousarray(atom.level_energy, np.float64),
+            g=np.ascontiguousarray(atom.level_g, np.float64),
+            lo=np.ascontiguousarray(atom.trans_lower, np.int32),
+            up=np.ascontiguousarray(atom.trans_upper, np.int32),
+            A=np.ascontiguousarray(atom.trans_A, np.float64),
+            lam=np.ascontiguousarray(atom.trans_lambda, np.float64),
+            ups=np.ascontiguousarray(atom.trans_upsilon, np.float64),
+            line=np.ascontiguousarray(atom.trans_line, np.int32),
+            alpha=np.ascontiguousarray(atom.ion_alpha0, np.float64),
+        )
+        p = {k: v.ctypes.data for k, v in keep.items()}
+        d = _AtomDesc(len(keep["off"]) - 1, p["off"], len(keep["ion"]), p["ion"], p["E"], p["g"],
+                      len(keep["A"]), p["lo"], p["up"], p["A"], p["lam"], p["ups"], p["line"],
+                      p["alpha"])
+        h = _vp()
+        ctx.check(_lib.extrass_atom_create(ctx.h, C.byref(d), C.byref(h)), "extrass_atom_create")
+        self.h = h
+        self.n_species = len(keep["off"]) - 1
+        self.n_levels = len(keep["ion"])
+        self.n_trans = len(keep["A"])
+
+    def close(self):
+        if self.h:
+            _lib.extrass_atom_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def line_tau(ctx: Context, atom: Atom, pops, t_exp):
+    """Eq. A2 opacity and stimulated-emission factor per (cell, transition)."""
+    C_ = pops.numel() // atom.n_levels
+    tau = torch.empty((C_, atom.n_trans), dtype=torch.float64, device=pops.device)
+    fc = torch.empty_like(tau)
+    ctx.check(_lib.extrass_line_tau(ctx.h, atom.h, C_, _ptr(pops), float(t_exp), _ptr(tau),
+                                    _ptr(fc), _stream()), "extrass_line_tau")
+    return tau, fc
+
+
+def rates(ctx: Context, atom: Atom, est, pops, cell_volume):
+    C_ = pops.numel() // atom.n_levels
+    L = est.numel() // C_
+    out = torch.empty((C_, atom.n_trans), dtype=torch.float64, device=pops.device)
+    ctx.check(_lib.extrass_rates(ctx.h, atom.h, C_, L, _ptr(est), _ptr(pops), float(cell_volume),
+                                 _ptr(out), _stream()), "extrass_rates")
+    return out
+
+
+class Cells:
+    def __init__(self, t_exp, T_e, n_e, n_species, gamma_ion, gamma_pe=None, device="cuda:0"):
+        self.t_exp = float(t_exp)
+        self.T_e = _dev(T_e, torch.float64, device)
+        self.n_e = _dev(n_e, torch.float64, device)
+        self.n_species = _dev(n_species, torch.float64, device)
+        self.gamma_ion = _dev(gamma_ion, torch.float64, device)
+        self.gamma_pe = _dev(gamma_pe, torch.float64, device)
+        self.n_cells = int(self.T_e.numel())
+
+    def struct(self):
+        return _Cells(self.n_cells, self.t_exp, _ptr(self.T_e), _ptr(self.n_e),
+                      _ptr(self.n_species), _ptr(self.gamma_ion), _ptr(self.gamma_pe))
+
+
+def cells_from_workload(w, gamma_pe=None, device="cuda:0", cells=None):
+    S = w.atom.n_species
+    if cells is None:
+        return Cells(w.t_exp, w.T_e, w.n_e, w.n_species, w.gamma_ion, gamma_pe, device)
+    cells = np.asarray(cells)
+    gpe = None
+    if gamma_pe is not None:
+        gpe = gamma_pe.reshape(-1, w.atom.n_trans)[torch.as_tensor(cells, device=gamma_pe.device)] \
+            if isinstance(gamma_pe, torch.Tensor) else gamma_pe.reshape(-1, w.atom.n_trans)[cells]
+    return Cells(w.t_exp, w.T_e[cells], w.n_e[cells], w.n_species.reshape(-1, S)[cells],
+                 w.gamma_ion.reshape(-1, S, 3)[cells], gpe, device)
+
+
+def nlte_solve(ctx: Context, atom: Atom, cells: Cells, max_iter=200, tol=1e-10, guess=None,
+               factor_fp32=False, pops=None, status=None, iters=None):
+    """Runs extrass_nlte_solve; returns (pops [C, N], status [C], iters [C])."""
+    dev = cells.T_e.device
+    if pops is None:
+        pops = torch.empty((cells.n_cells, atom.n_levels), dtype=torch.float64, device=dev)
+    if guess is not None:
+        pops.copy_(guess)
+    if status is None:
+        status = torch.empty(cells.n_cells, dtype=torch.int32, device=dev)
+    if iters is None:
+        iters = torch.empty(cells.n_cells, dtype=torch.int32, device=dev)
+    o = _Opts(int(max_iter), float(tol), 0 if guess is None else 1, 1 if factor_fp32 else 0)
+    cs = cells.struct()
+    need = _lib.extrass_nlte_workspace(atom.h, cells.n_cells)
+    ws = ctx.workspace(need)
+    rc = _lib.extrass_nlte_solve(ctx.h, atom.h, C.byref(cs), C.byref(o), _ptr(pops), _ptr(status),
+                                 _ptr(iters), _ptr(ws), ws.numel(), _stream())
+    ctx.check(rc, "extrass_nlte_solve")
+    return pops, status, iters
+
+
+def cell_volume(w):
+    return (2.0 * w.beta_max / w.n * 2.99792458e10 * w.t_exp) ** 3

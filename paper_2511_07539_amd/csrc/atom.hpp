@@ -1,0 +1,39 @@
+// Device-resident atom description shared by the NLTE, opacity and rate kernels.
+#pragma once
+#include <cstdint>
+#include <vector>
+
+#include "extrass.h"
+
+namespace extrass {
+constexpr int kMaxLevels = 64;  // one wavefront lane per level of a species
+}
+
+struct extrass_atom_ctx {
+  int device = 0;
+  int S = 0, N = 0, T = 0, maxNs = 0;
+  std::vector<int> off;   // host copy of species_offset
+  std::vector<int> toff;  // host: transitions of species s are [toff[s], toff[s+1])
+  struct {
+    int32_t* off = nullptr;       // [S+1]
+    int32_t* toff = nullptr;      // [S+1]
+    int32_t* nstage = nullptr;    // [S]
+    int32_t* lv_ion = nullptr;    // [N]
+    int32_t* lv_gnext = nullptr;  // [N] local index of the next stage's ground, -1 if none
+    double* lv_E = nullptr;       // [N]
+    double* lv_g = nullptr;       // [N]
+    double* lv_share = nullptr;   // [N] share of the recombination flux into the level
+    int32_t* t_l = nullptr;       // [T] grouped by species: local lower level
+    int32_t* t_u = nullptr;       // [T] local upper level
+    int32_t* t_glob = nullptr;    // [T] caller's transition index (gamma_pe column)
+    double* t_A = nullptr;
+    double* t_lam = nullptr;
+    double* t_ups = nullptr;
+    double* alpha0 = nullptr;     // [S*3]
+    int32_t* o_lo = nullptr;      // [T] caller's order: global lower level
+    int32_t* o_up = nullptr;
+    int32_t* o_line = nullptr;
+    double* o_A = nullptr;
+    double* o_lam = nullptr;
+  } d;
+};

@@ -1,0 +1,477 @@
+// NLTE statistical equilibrium per (cell, species) (Sec. 2.2; Eqs. A1-A2).
+//
+// One wavefront solves one (cell, species) system at a time: lane i owns
+// level i (up to 64 levels), the rate or flux matrix lives in LDS (row
+// stride padded to an odd number of doubles), and wavefronts take work items
+// from a global counter until all cells are done.
+//
+// Per system:
+//  1. cold start (Boltzmann within each ion stage, stage ratios from a
+//     ground-only ionisation balance) or the caller's guess;
+//  2. fixed-point steps n <- n_tot * stationary(R(n)), under-relaxed in
+//     log(n) when the change fails to shrink, until max |d ln n| < 0.1; the
+//     stationary vector comes from state reduction with pivots formed as sums
+//     of off-diagonal rates (Grassmann-Taksar-Heyman), which involves no
+//     subtraction and keeps every component accurate;
+//  3. Newton steps in log(n): the Jacobian scaled by diag(n) is a transposed
+//     generator (non-negative off-diagonals, zero column sums), so the Newton
+//     system is reduced the same way, the most populated level last, and
+//     conservation fixes the free multiple of the null vector. The right-hand
+//     side -F is formed as Q(n)^T (P(n) - n), P(n) the fixed-point map above:
+//     the same vector as the net inflow, without the cancellation of gross
+//     inflow against outflow that would limit accuracy to ~1e-9 in weakly
+//     coupled ion stages. A trust radius on max |d ln n| and a decrease test
+//     on sum (P(n)/n - 1)^2 globalise the iteration.
+// Convergence: max |d ln n| < tol with max |P(n)/n - 1| < 1e-10, or a step
+// below 1e-11 that has not improved for 3 Newton steps, or no step lowers a
+// fixed-point residual that is already at rounding level.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "atom.hpp"
+#include "common.hpp"
+
+namespace extrass {
+namespace {
+
+constexpr double kBoltzmann = 1.380649e-16;  // erg/K
+
+struct NArgs {
+  int S, N, T;
+  int64_t C;
+  double t_exp;
+  const int32_t* off;
+  const int32_t* toff;
+  const int32_t* nstage;
+  const int32_t* lv_ion;
+  const int32_t* lv_gnext;
+  const double* lv_E;
+  const double* lv_g;
+  const double* lv_share;
+  const int32_t* t_l;
+  const int32_t* t_u;
+  const int32_t* t_glob;
+  const double* t_A;
+  const double* t_lam;
+  const double* t_ups;
+  const double* alpha0;
+  const double* T_e;
+  const double* n_e;
+  const double* n_species;
+  const double* gamma_ion;
+  const double* gamma_pe;
+  int max_iter;
+  double tol;
+  int use_guess;
+  double* pops;
+  int32_t* status;
+  int32_t* iters;
+  unsigned long long* queue;
+  int NP;  // LDS row stride in doubles
+};
+
+// Everything one system needs, held per wave (uniform values) or per lane.
+struct Sys {
+  int64_t c;
+  int s, base, Ns, t0, t1, nst;
+  double T, ne, kT, sqT, ntot;
+  double gion[3], rec[3];
+  // lane-owned level data
+  int z, gnext;
+  double E, g, share;
+};
+
+__device__ __forceinline__ double beta_sobolev(double tau) {
+  return tau <= 0.0 ? 1.0 : -expm1(-tau) / tau;
+}
+
+__device__ __forceinline__ double dbeta_sobolev(double tau) {
+  if (tau <= 0.0) return 0.0;
+  if (tau < 1e-3) return -0.5 + tau * (1.0 / 3.0 - tau * (1.0 / 8.0 - tau / 30.0));
+  return (exp(-tau) * (1.0 + tau) - 1.0) / (tau * tau);
+}
+
+// Fills G[i][j] (i != j) with rs_i * R_ij at populations n (lane i holds n_i),
+// rs_i = n_i when rowscale (fluxes) else 1 (rates). With hb (the relative
+// fixed-point residual h_j = P(n)_j / n_j - 1 of every level, in LDS), lane i
+// gets the Newton right-hand side -F_i = (Q^T H)_i = sum_j h_j G_ji -
+// h_i sum_j G_ij (flux form): the same vector as inflow - outflow with its
+// sign flipped, but formed from the small h, so without the cancellation of
+// gross inflow against outflow. With jac, the derivative of the radiative
+// fluxes through beta_S(tau(n)) is then added, which turns G into the
+// diag(n)-scaled Newton matrix.
+__device__ void assemble(const NArgs& A, const Sys& y, double* G, double* nb, double n_mine,
+                         bool rowscale, const double* hb, double h_mine, bool jac, double& rhs) {
+  const int lane = threadIdx.x;
+  const int NP = A.NP;
+  const int Ns = y.Ns;
+  if (lane < Ns) nb[lane] = n_mine;
+  for (int r = 0; r < Ns; ++r)
+    if (lane < Ns) G[r * NP + lane] = 0.0;
+  __syncthreads();
+  const double* gpe = A.gamma_pe ? A.gamma_pe + y.c * A.T : nullptr;
+  for (int t = y.t0 + lane; t < y.t1; t += 64) {
+    const int l = A.t_l[t], u = A.t_u[t];
+    const double gl = A.lv_g[y.base + l], gu = A.lv_g[y.base + u];
+    const double Ad = A.t_A[t], lam = A.t_lam[t];
+    const double qul = 8.629e-6 * A.t_ups[t] / (gu * y.sqT);
+    const double qlu = qul * (gu / gl) * exp(-(A.lv_E[y.base + u] - A.lv_E[y.base + l]) / y.kT);
+    const double nl = nb[l], nu = nb[u];
+    const double K = Ad * lam * lam * lam * A.t_exp / (8.0 * M_PI);
+    const double tau = K * ((gu / gl) * nl - nu);
+    const double p = gpe ? gpe[A.t_glob[t]] : 0.0;
+    const double down = Ad * beta_sobolev(tau) + y.ne * qul + (gl / gu) * p;
+    const double up = y.ne * qlu + p;
+    G[u * NP + l] = (rowscale ? nu : 1.0) * down;
+    G[l * NP + u] = (rowscale ? nl : 1.0) * up;
+  }
+  if (lane < Ns && y.gnext >= 0) {
+    const double rs = rowscale ? n_mine : 1.0;
+    const double rsg = rowscale ? nb[y.gnext] : 1.0;
+    G[lane * NP + y.gnext] += rs * y.gion[y.z];
+    G[y.gnext * NP + lane] += rsg * y.rec[y.z] * y.share;
+  }
+  __syncthreads();
+  if (hb) {
+    // -F_i = (Q^T H)_i = sum_j h_j G_ji - h_i sum_j G_ij with H = P(n) - n
+    double in = 0.0, out = 0.0;
+    if (lane < Ns) {
+      for (int j = 0; j < Ns; ++j) {
+        out += G[lane * NP + j];
+        in += hb[j] * G[j * NP + lane];
+      }
+    }
+    rhs = in - h_mine * out;
+  }
+  if (jac) {
+    __syncthreads();
+    for (int t = y.t0 + lane; t < y.t1; t += 64) {
+      const int l = A.t_l[t], u = A.t_u[t];
+      const double gl = A.lv_g[y.base + l], gu = A.lv_g[y.base + u];
+      const double Ad = A.t_A[t], lam = A.t_lam[t];
+      const double nl = nb[l], nu = nb[u];
+      const double K = Ad * lam * lam * lam * A.t_exp / (8.0 * M_PI);
+      const double tau = K * ((gu / gl) * nl - nu);
+      const double db = dbeta_sobolev(tau);
+      if (db != 0.0) {
+        const double du = -nu * Ad * db * K;
+        const double dl = nu * Ad * db * K * (gu / gl);
+        G[u * NP + l] += du * nu;
+        G[l * NP + u] += -dl * nl;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ int perm(int a, int big, int last) {
+  return a == big ? last : (a == last ? big : a);
+}
+
+// State reduction of the generator in G (off-diagonal entries, row i -> j),
+// visiting states in the order perm(0..Ns-1) (the level `big` swapped to the
+// end). Solves x^T G = b^T with x_last = 0 when rhs, and the homogeneous
+// problem with pi_last = 1. Lane a holds b, x and pi of permuted position a.
+// Returns false when a pivot is not positive (reducible chain).
+__device__ bool reduce_solve(double* G, int NP, int Ns, int big, bool rhs, double b_perm,
+                             double& x_perm, double& pi_perm) {
+  const int lane = threadIdx.x;
+  const int last = Ns - 1;
+  const bool live = lane < Ns;
+  const int my_col = live ? perm(lane, big, last) : 0;
+  double S_mine = 0.0;
+  bool ok = true;
+  for (int k = 0; k < last; ++k) {
+    const int rk = perm(k, big, last);
+    const bool act = live && lane > k;
+    const double ub = act ? G[rk * NP + my_col] : 0.0;
+    const double S = wave_sum(ub);
+    if (!(S > 0.0)) ok = false;
+    if (lane == k) S_mine = S;
+    const double invS = 1.0 / S;
+    if (rhs) {
+      const double bk = __shfl(b_perm, k, 64);
+      if (act) b_perm += bk * ub * invS;
+    }
+    for (int a = k + 1; a < Ns; ++a) {
+      const int ra = perm(a, big, last);
+      const double f = G[ra * NP + rk] * invS;
+      if (f != 0.0 && act && lane != a) G[ra * NP + my_col] += f * ub;
+    }
+    __syncthreads();
+  }
+  double x = 0.0, pi = lane == last ? 1.0 : 0.0;
+  for (int k = last - 1; k >= 0; --k) {
+    const int ck = perm(k, big, last);
+    const double gk = (live && lane > k) ? G[my_col * NP + ck] : 0.0;
+    const double sx = rhs ? wave_sum(x * gk) : 0.0;
+    const double sp = wave_sum(pi * gk);
+    const double Sk = __shfl(S_mine, k, 64);
+    const double bk = rhs ? __shfl(b_perm, k, 64) : 0.0;
+    if (lane == k) {
+      x = (sx - bk) / Sk;
+      pi = sp / Sk;
+    }
+  }
+  x_perm = x;
+  pi_perm = pi;
+  return ok;
+}
+
+// Relative fixed-point residual h = P(n)/n - 1 with P(n) = n_tot * stationary
+// vector of R(n); returns false on a vanishing pivot.
+__device__ bool fixed_point_residual(const NArgs& A, const Sys& y, double* G, double* nb,
+                                     double n, double& h) {
+  const bool live = threadIdx.x < y.Ns;
+  double rhs = 0.0, xp = 0.0, pp = 0.0;
+  assemble(A, y, G, nb, n, false, nullptr, 0.0, false, rhs);
+  if (!reduce_solve(G, A.NP, y.Ns, y.Ns - 1, false, 0.0, xp, pp)) return false;
+  const double psum = wave_sum(live ? pp : 0.0);
+  h = live ? y.ntot * (pp / psum) / n - 1.0 : 0.0;
+  return true;
+}
+
+// Solves one (cell, species) system; returns the iteration count, or -1.
+__device__ int solve_system(const NArgs& A, const Sys& y, double* G, double* nb, double* hb,
+                            double& n) {
+  const int lane = threadIdx.x;
+  const bool live = lane < y.Ns;
+  const int last = y.Ns - 1;
+  double rhs = 0.0, xp = 0.0, pp = 0.0;
+  int it = 0;
+  // ---- fixed-point phase
+  double omega = 1.0, prev = INFINITY;
+  for (; it < A.max_iter && it < 60; ++it) {
+    assemble(A, y, G, nb, n, false, nullptr, 0.0, false, rhs);
+    if (!reduce_solve(G, A.NP, y.Ns, last, false, 0.0, xp, pp)) return -1;
+    const double psum = wave_sum(live ? pp : 0.0);
+    const double nw = live ? y.ntot * (pp / psum) : 0.0;
+    const double change = wave_max(live ? fabs(log(nw / n)) : 0.0);
+    if (change > 0.999 * prev) omega = omega * 0.5 > 1.0 / 1024 ? omega * 0.5 : 1.0 / 1024;
+    prev = change;
+    double v = live ? exp((1.0 - omega) * log(n) + omega * log(nw)) : 0.0;
+    const double tot = wave_sum(v);
+    n = live ? v * (y.ntot / tot) : 0.0;
+    if (change < 0.1) {
+      ++it;
+      break;
+    }
+  }
+  // ---- Newton phase
+  double Delta = 1.0, best_step = INFINITY;
+  int best_it = it;
+  double h = 0.0;
+  bool have_h = false;
+  for (; it < A.max_iter; ++it) {
+    if (!have_h && !fixed_point_residual(A, y, G, nb, n, h)) return -1;
+    const double res = wave_max(fabs(h));
+    const double phi = wave_sum(h * h);
+    if (live) hb[lane] = h;
+    assemble(A, y, G, nb, n, true, hb, h, true, rhs);
+    // most populated level (first one on ties) goes last
+    const double nmax = wave_max(live ? n : -1.0);
+    const uint64_t bm = __ballot(live && n == nmax);
+    const int big = __ffsll((unsigned long long)bm) - 1;
+    const double b_perm = __shfl(rhs, live ? perm(lane, big, last) : 0, 64);
+    if (!reduce_solve(G, A.NP, y.Ns, big, true, b_perm, xp, pp)) return -1;
+    const int src = live ? perm(lane, big, last) : 0;
+    double x = __shfl(xp, src, 64), pi = __shfl(pp, src, 64);
+    if (!live) x = pi = 0.0;
+    const double sum_n = wave_sum(n), sum_nx = wave_sum(n * x), sum_npi = wave_sum(n * pi);
+    const double cst = ((y.ntot - sum_n) - sum_nx) / sum_npi;
+    x += cst * pi;
+    if (!live) x = 0.0;
+    const double step = wave_max(fabs(x));
+    if (step < best_step) {
+      best_step = step;
+      best_it = it;
+    }
+    if ((step < A.tol && res < 1e-10) || (step < 1e-11 && it - best_it >= 3)) return it + 1;
+    // trust-region step in log(n), accepted when the fixed-point residual drops
+    bool accepted = false;
+    double taken = 0.0, trial = 0.0, h_trial = 0.0;
+    for (int bt = 0; bt < 40; ++bt) {
+      const double scale = step > Delta ? Delta / step : 1.0;
+      taken = step * scale;
+      const double v = live ? n * exp(scale * x) : 0.0;
+      const double tot = wave_sum(v);
+      trial = live ? v * (y.ntot / tot) : 0.0;
+      if (!fixed_point_residual(A, y, G, nb, trial, h_trial)) return -1;
+      const double phi2 = wave_sum(h_trial * h_trial);
+      const double res2 = wave_max(fabs(h_trial));
+      if (phi2 < phi || res2 < 1e-14) {
+        accepted = true;
+        break;
+      }
+      Delta = (taken < Delta ? taken : Delta) / 4.0;
+    }
+    if (!accepted) return (step < 1e-11 || res < 1e-14) ? it + 1 : -1;
+    n = trial;
+    h = h_trial;
+    have_h = true;
+    if (taken >= 0.99 * Delta) Delta = 2.0 * Delta < 30.0 ? 2.0 * Delta : 30.0;
+  }
+  return -1;
+}
+
+__global__ __launch_bounds__(64) void k_nlte(NArgs A) {
+  extern __shared__ double smem[];
+  double* nb = smem;        // 64 doubles: populations broadcast
+  double* hb = smem + 64;   // 64 doubles: fixed-point residuals broadcast
+  double* G = smem + 128;   // maxNs x NP doubles
+  const int lane = threadIdx.x;
+  const int64_t items = A.C * A.S;
+  for (;;) {
+    unsigned long long item = 0;
+    if (lane == 0) item = atomicAdd(A.queue, 1ull);
+    item = __shfl(item, 0, 64);
+    if (item >= (unsigned long long)items) break;
+    Sys y;
+    y.c = (int64_t)(item / A.S);
+    y.s = (int)(item % A.S);
+    y.base = A.off[y.s];
+    y.Ns = A.off[y.s + 1] - y.base;
+    y.t0 = A.toff[y.s];
+    y.t1 = A.toff[y.s + 1];
+    y.nst = A.nstage[y.s];
+    y.ntot = A.n_species[y.c * A.S + y.s];
+    double* out = A.pops + y.c * A.N + y.base;
+    if (!(y.ntot > 0.0)) {
+      if (lane < y.Ns) out[lane] = 0.0;
+      continue;
+    }
+    y.T = A.T_e[y.c];
+    y.ne = A.n_e[y.c];
+    y.kT = kBoltzmann * y.T;
+    y.sqT = sqrt(y.T);
+    const double tfac = pow(y.T / 1e4, -0.8);
+    for (int zz = 0; zz < 3; ++zz) {
+      y.gion[zz] = A.gamma_ion[(y.c * A.S + y.s) * 3 + zz];
+      y.rec[zz] = y.ne * A.alpha0[y.s * 3 + zz] * tfac;
+    }
+    const bool live = lane < y.Ns;
+    const int li = live ? y.base + lane : y.base;
+    y.z = A.lv_ion[li];
+    y.gnext = live ? A.lv_gnext[li] : -1;
+    y.E = A.lv_E[li];
+    y.g = A.lv_g[li];
+    y.share = A.lv_share[li];
+
+    double n = 0.0;
+    if (A.use_guess) {
+      n = live ? out[lane] : 0.0;
+    } else {
+      double w = live ? y.g * exp(-y.E / y.kT) : 0.0;
+      if (live && w < 1e-250) w = 1e-250;
+      double ss[3];
+      for (int zz = 0; zz < 3; ++zz) ss[zz] = wave_sum((live && y.z == zz) ? w : 0.0);
+      double ratio[3] = {1.0, 1.0, 1.0};
+      for (int zz = 1; zz < y.nst; ++zz) {
+        const double rc = y.rec[zz - 1];
+        double r = rc > 0.0 ? y.gion[zz - 1] / rc : 1e30;
+        r = r < 1e-30 ? 1e-30 : (r > 1e30 ? 1e30 : r);
+        ratio[zz] = ratio[zz - 1] * r;
+      }
+      double rsum = 0.0;
+      for (int zz = 0; zz < y.nst; ++zz) rsum += ratio[zz];
+      n = live ? y.ntot * (ratio[y.z] / rsum) * (w / ss[y.z]) : 0.0;
+    }
+    const int its = solve_system(A, y, G, nb, hb, n);
+    if (live) out[lane] = n;
+    if (lane == 0) {
+      atomicMax(A.status + y.c, its < 0 ? 2 : 0);
+      if (A.iters) atomicMax(A.iters + y.c, its < 0 ? A.max_iter : its);
+    }
+  }
+}
+
+__global__ void k_nlte_init(int64_t C, int S, const double* n_species, int32_t* status,
+                            int32_t* iters, unsigned long long* queue) {
+  for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < C;
+       c += (int64_t)gridDim.x * blockDim.x) {
+    bool empty = true;
+    for (int s = 0; s < S; ++s)
+      if (n_species[c * S + s] > 0.0) empty = false;
+    status[c] = empty ? 3 : 0;
+    if (iters) iters[c] = 0;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) *queue = 0ull;
+}
+
+}  // namespace
+}  // namespace extrass
+
+using namespace extrass;
+
+extern "C" size_t extrass_nlte_workspace(extrass_atom_handle a, int64_t n_cells) {
+  (void)a;
+  (void)n_cells;
+  return 512;
+}
+
+extern "C" int extrass_nlte_solve(extrass_handle h, extrass_atom_handle a, const extrass_cells* cl,
+                                  const extrass_nlte_opts* o, double* pops, int32_t* status,
+                                  int32_t* iters, void* ws, size_t ws_bytes, void* stream) {
+  if (!h || !a || !cl || !o || !pops || !status || !ws)
+    return fail(h, EXTRASS_EINVAL, "extrass_nlte_solve: null argument");
+  if (cl->n_cells < 0 || !cl->T_e || !cl->n_e || !cl->n_species || !cl->gamma_ion ||
+      o->max_iter < 0 || !(o->tol > 0.0))
+    return fail(h, EXTRASS_EINVAL, "extrass_nlte_solve: bad cells or options");
+  if (o->factor_fp32) return fail(h, EXTRASS_EUNSUPPORTED, "extrass_nlte_solve: FP32 factor not built");
+  if (ws_bytes < extrass_nlte_workspace(a, cl->n_cells))
+    return fail(h, EXTRASS_ENOSPACE, "extrass_nlte_solve: workspace too small");
+  if (cl->n_cells == 0) return EXTRASS_OK;
+  EXTRASS_HIP_TRY(h, hipSetDevice(h->device));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  auto* queue = static_cast<unsigned long long*>(ws);
+  {
+    int64_t blocks = std::min<int64_t>((cl->n_cells + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_nlte_init, dim3((unsigned)blocks), dim3(256), 0, st, cl->n_cells, a->S,
+                       cl->n_species, status, iters, queue);
+  }
+  NArgs A{};
+  A.S = a->S;
+  A.N = a->N;
+  A.T = a->T;
+  A.C = cl->n_cells;
+  A.t_exp = cl->t_exp;
+  A.off = a->d.off;
+  A.toff = a->d.toff;
+  A.nstage = a->d.nstage;
+  A.lv_ion = a->d.lv_ion;
+  A.lv_gnext = a->d.lv_gnext;
+  A.lv_E = a->d.lv_E;
+  A.lv_g = a->d.lv_g;
+  A.lv_share = a->d.lv_share;
+  A.t_l = a->d.t_l;
+  A.t_u = a->d.t_u;
+  A.t_glob = a->d.t_glob;
+  A.t_A = a->d.t_A;
+  A.t_lam = a->d.t_lam;
+  A.t_ups = a->d.t_ups;
+  A.alpha0 = a->d.alpha0;
+  A.T_e = cl->T_e;
+  A.n_e = cl->n_e;
+  A.n_species = cl->n_species;
+  A.gamma_ion = cl->gamma_ion;
+  A.gamma_pe = cl->gamma_pe;
+  A.max_iter = o->max_iter;
+  A.tol = o->tol;
+  A.use_guess = o->use_guess;
+  A.pops = pops;
+  A.status = status;
+  A.iters = iters;
+  A.queue = queue;
+  A.NP = a->maxNs | 1;
+  const size_t lds = sizeof(double) * (128 + (size_t)a->maxNs * A.NP);
+  const int64_t items = cl->n_cells * a->S;
+  int per_cu = (int)std::min<size_t>(16, (160 * 1024) / std::max<size_t>(lds, 1));
+  if (per_cu < 1) per_cu = 1;
+  int64_t blocks = std::min<int64_t>((int64_t)h->num_cus * per_cu, items);
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_nlte, dim3((unsigned)blocks), dim3(64), lds, st, A);
+  EXTRASS_HIP_TRY(h, hipGetLastError());
+  return EXTRASS_OK;
+}

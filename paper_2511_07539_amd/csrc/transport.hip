@@ -1,0 +1,466 @@
+// Monte Carlo packet transport with Sobolev line absorption (Sec. 2.3, 2.3.2).
+//
+// One persistent kernel: every lane follows one packet at a time, one event
+// per loop trip (either the next line resonance inside the current cell or
+// the crossing of the cell wall). When a lane's packet stops, the wave hands
+// it the next packet id from a wave-private pool of ids, refilled from a
+// global counter 256 ids at a time; a ballot over the wave finds the idle
+// lanes and a popcount gives each its slot, so lanes refill without one
+// atomic per packet and the wave stays full until the ids run out.
+//
+// Geometry (positions, directions, distances, Doppler coordinate D) runs in
+// the template type G: double for the reference path, float for the fast
+// path. Weights, estimators and the line wavelength arithmetic stay FP64.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "common.hpp"
+#include "philox.hpp"
+
+namespace extrass {
+namespace {
+
+constexpr double kTauMin = 1e-4;    // lines with tau > 1e-4 interact
+constexpr double kKillFrac = 1e-6;  // stop below 1e-6 of the starting energy
+constexpr int kPool = 256;          // ids taken from the global counter per refill
+constexpr int kBlock = 256;
+
+struct TArgs {
+  int n;
+  double beta, h;
+  const float* tau_scale;
+  const double* cell_photons;
+  const int32_t* cell_packets;
+  int L;
+  const double* lam;
+  const double* inv_lam;
+  const float* tau0;
+  const int32_t* line_trans;
+  int T;
+  const double* tau_ct;
+  const double* fcorr_ct;
+  uint64_t seed;
+  uint32_t iteration;
+  int64_t first, count;
+  double lam_lo, lam_hi;
+  const double* explicit_pk;
+  const int64_t* start;  // [C+1] exclusive prefix of cell_packets
+  int64_t C;
+  double* est;
+  double* stats;
+  double* pk_out;
+  unsigned long long* queue;
+};
+
+// ---- small helper kernels -------------------------------------------------
+
+__global__ void k_prep(const double* lam, double* inv_lam, int L, double* stats,
+                       unsigned long long* queue) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < EXTRASS_STATS) stats[t] = 0.0;
+  if (t == 0) *queue = 0ull;
+  for (int k = t; k < L; k += gridDim.x * blockDim.x) {
+    inv_lam[k] = 1.0 / lam[k];
+  }
+}
+
+__global__ void k_check_sorted(const double* lam, int L, double* stats) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  for (int k = t + 1; k < L; k += gridDim.x * blockDim.x)
+    if (!(lam[k] >= lam[k - 1])) stats[EXTRASS_STATS - 1] = 1.0;
+}
+
+// Exclusive prefix of cell_packets into start[0..C], one workgroup of 1024.
+__global__ __launch_bounds__(1024) void k_scan_counts(const int32_t* counts, int64_t C,
+                                                      int64_t* start) {
+  __shared__ int64_t part[1024];
+  const int t = threadIdx.x;
+  const int64_t chunk = (C + 1023) / 1024;
+  const int64_t a = t * chunk, b = a + chunk < C ? a + chunk : C;
+  int64_t s = 0;
+  for (int64_t i = a; i < b; ++i) s += counts[i];
+  part[t] = s;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    int64_t v = t >= off ? part[t - off] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int64_t run = part[t] - s;
+  for (int64_t i = a; i < b; ++i) {
+    start[i] = run;
+    run += counts[i];
+  }
+  if (t == 1023) start[C] = part[1023];
+}
+
+__global__ void k_zero(double* __restrict__ p, int64_t n) {
+  int64_t i = (int64_t)(blockIdx.x * blockDim.x + threadIdx.x);
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t n2 = n / 2;
+  double2* p2 = reinterpret_cast<double2*>(p);
+  for (int64_t j = i; j < n2; j += stride) p2[j] = make_double2(0.0, 0.0);
+  if (i == 0 && (n & 1)) p[n - 1] = 0.0;
+}
+
+// ---- the transport kernel -------------------------------------------------
+
+template <class G>
+struct Packet {
+  int ci[3];
+  G x[3], d[3];
+  G D, Dexit, s, smin, dist[3];
+  double lamL, lam_e, w, w0, wabs;
+  int k;
+  bool have_exit;
+  bool bad;
+};
+
+template <class G>
+__device__ __forceinline__ G wall(const TArgs& A, int i) {
+  return static_cast<G>(-A.beta + static_cast<double>(i) * A.h);
+}
+
+__device__ __forceinline__ int first_line_above(const TArgs& A, double lam) {
+  int lo = 0, hi = A.L;
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    if (A.lam[mid] > lam) hi = mid;
+    else lo = mid + 1;
+  }
+  return lo;
+}
+
+template <class G>
+__device__ void emit(const TArgs& A, int64_t p, Packet<G>& q) {
+  double x[3], d[3], lam_e, w0;
+  int ci[3];
+  q.bad = false;
+  if (A.explicit_pk) {
+    const double* e = A.explicit_pk + 8 * p;
+    for (int a = 0; a < 3; ++a) {
+      x[a] = e[a];
+      d[a] = e[3 + a];
+      int i = static_cast<int>(floor((e[a] + A.beta) / A.h));
+      ci[a] = i < 0 ? 0 : (i > A.n - 1 ? A.n - 1 : i);
+    }
+    lam_e = e[6];
+    w0 = e[7];
+  } else {
+    int64_t lo = 0, hi = A.C;
+    while (hi - lo > 1) {
+      int64_t mid = (lo + hi) >> 1;
+      if (A.start[mid] <= p) lo = mid;
+      else hi = mid;
+    }
+    const int64_t c = lo;
+    const int64_t j = p - A.start[c];
+    const int nc = A.cell_packets[c];
+    if (p >= A.start[A.C] || nc <= 0) {  // id beyond the sampling plan
+      q.bad = true;
+      return;
+    }
+    ci[0] = static_cast<int>(c % A.n);
+    ci[1] = static_cast<int>((c / A.n) % A.n);
+    ci[2] = static_cast<int>(c / ((int64_t)A.n * A.n));
+    const u64x4 r0 = philox4x64_10((uint64_t)p, A.iteration, 0, 0, A.seed, 3);
+    const u64x4 r1 = philox4x64_10((uint64_t)p, A.iteration, 1, 0, A.seed, 3);
+    for (int a = 0; a < 3; ++a) x[a] = (-A.beta + static_cast<double>(ci[a]) * A.h) + A.h * unit53(r0.v[a]);
+    const double mu = 2.0 * unit53(r0.v[3]) - 1.0;
+    const double phi = 2.0 * M_PI * unit53(r1.v[0]);
+    const double st = sqrt(fmax(0.0, 1.0 - mu * mu));
+    double sp, cp;
+    sincos(phi, &sp, &cp);
+    d[0] = st * cp;
+    d[1] = st * sp;
+    d[2] = mu;
+    lam_e = A.lam_lo + (A.lam_hi - A.lam_lo) * ((static_cast<double>(j) + unit53(r1.v[1])) / nc);
+    w0 = A.cell_photons[c] / nc;
+  }
+  for (int a = 0; a < 3; ++a) {
+    q.ci[a] = ci[a];
+    q.x[a] = static_cast<G>(x[a]);
+    q.d[a] = static_cast<G>(d[a]);
+  }
+  const double D0 = d[0] * x[0] + d[1] * x[1] + d[2] * x[2];
+  q.D = static_cast<G>(D0);
+  q.lamL = lam_e * (1.0 - D0);
+  q.lam_e = lam_e;
+  q.w = w0;
+  q.w0 = w0;
+  q.wabs = 0.0;
+  q.k = first_line_above(A, lam_e);
+  q.have_exit = false;
+}
+
+struct Tally {
+  double w_emit = 0, w_esc = 0, w_kill = 0, w_abs = 0;
+  uint64_t inter = 0, checks = 0, cross = 0, escaped = 0, killed = 0;
+  bool bad = false;
+};
+
+template <class G>
+__global__ __launch_bounds__(kBlock) void k_transport(TArgs A) {
+  const int lane = threadIdx.x & 63;
+  Packet<G> q;
+  int64_t pid = -1;
+  bool done = false;
+  uint64_t pool_base = 0, pool_left = 0;
+  bool exhausted = false;
+  Tally t;
+  const int64_t C = A.C;
+  (void)C;
+
+  for (;;) {
+    // ---- hand idle lanes new packet ids (ballot + popcount over the wave)
+    const bool need = (pid < 0) && !done;
+    uint64_t m = __ballot(need);
+    if (m) {
+      if (pool_left == 0 && !exhausted) {
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd(A.queue, (unsigned long long)kPool);
+        base = __shfl(base, 0);
+        pool_base = base;
+        pool_left = base >= (uint64_t)A.count ? 0 : ((uint64_t)A.count - base < (uint64_t)kPool
+                                                       ? (uint64_t)A.count - base : (uint64_t)kPool);
+        if (pool_left == 0) exhausted = true;
+      }
+      const int rank = __popcll(m & ((1ull << lane) - 1ull));
+      const uint64_t cnt = __popcll(m);
+      const uint64_t take = cnt < pool_left ? cnt : pool_left;
+      if (need) {
+        if ((uint64_t)rank < take) {
+          pid = A.first + (int64_t)(pool_base + rank);
+          emit<G>(A, pid, q);
+          if (q.bad) {
+            t.bad = true;
+            pid = -1;
+          } else {
+            t.w_emit += q.w0;
+          }
+        } else if (exhausted) {
+          done = true;
+        }
+      }
+      pool_base += take;
+      pool_left -= take;
+    }
+    if (__ballot(!done) == 0ull) break;
+    if (pid < 0) continue;
+
+    // ---- one event of this lane's packet
+    if (!q.have_exit) {
+      G smin = static_cast<G>(INFINITY);
+      for (int a = 0; a < 3; ++a) {
+        G dd = static_cast<G>(INFINITY);
+        if (q.d[a] > G(0)) dd = (wall<G>(A, q.ci[a] + 1) - q.x[a]) / q.d[a];
+        else if (q.d[a] < G(0)) dd = (wall<G>(A, q.ci[a]) - q.x[a]) / q.d[a];
+        q.dist[a] = dd;
+        smin = dd < smin ? dd : smin;
+      }
+      q.smin = smin;
+      q.s = smin > G(0) ? smin : G(0);
+      q.Dexit = q.D + q.s;
+      q.have_exit = true;
+      if (!(smin < static_cast<G>(INFINITY))) {  // NaN or zero direction: no wall ahead
+        t.bad = true;
+        pid = -1;
+        continue;
+      }
+    }
+    const int64_t c = q.ci[0] + (int64_t)A.n * (q.ci[1] + (int64_t)A.n * q.ci[2]);
+    bool line_event = false;
+    if (q.k < A.L) {
+      const G Dk = static_cast<G>(1.0 - q.lamL * A.inv_lam[q.k]);
+      line_event = Dk <= q.Dexit;
+    }
+    bool stop = false;
+    if (line_event) {
+      const int k = q.k;
+      t.checks++;
+      double tau, fc = 1.0;
+      const int tr = (A.line_trans && A.tau_ct) ? A.line_trans[k] : -1;
+      if (tr >= 0) {
+        tau = A.tau_ct[c * A.T + tr];
+        if (A.fcorr_ct) fc = A.fcorr_ct[c * A.T + tr];
+      } else {
+        tau = static_cast<double>(A.tau0[k]) * static_cast<double>(A.tau_scale[c]);
+      }
+      if (tau > kTauMin) {
+        t.inter++;
+        const double dN = q.w * (-expm1(-tau));
+        atomicAdd(A.est + c * A.L + k, dN / fc);
+        q.wabs += dN;
+        q.w = q.w * exp(-tau);
+        if (q.w * q.lam_e < (kKillFrac * q.w0) * A.lam[k]) {
+          t.w_kill += q.w;
+          t.killed++;
+          if (A.pk_out) {
+            double* o = A.pk_out + 4 * (pid - A.first);
+            o[0] = 0.0; o[1] = q.lamL; o[2] = q.w; o[3] = q.wabs;
+          }
+          stop = true;
+        }
+      }
+      q.k = k + 1;
+    } else {
+      bool out = false;
+      for (int a = 0; a < 3; ++a) {
+        if (q.dist[a] == q.smin) {
+          if (q.d[a] > G(0)) {
+            q.ci[a] += 1;
+            q.x[a] = wall<G>(A, q.ci[a]);
+          } else {
+            q.x[a] = wall<G>(A, q.ci[a]);
+            q.ci[a] -= 1;
+          }
+          if (q.ci[a] < 0 || q.ci[a] >= A.n) out = true;
+        } else {
+          q.x[a] = q.x[a] + q.s * q.d[a];
+        }
+      }
+      q.D = q.Dexit;
+      q.have_exit = false;
+      if (out) {
+        t.w_esc += q.w;
+        t.escaped++;
+        if (A.pk_out) {
+          double* o = A.pk_out + 4 * (pid - A.first);
+          o[0] = q.w; o[1] = q.lamL; o[2] = 0.0; o[3] = q.wabs;
+        }
+        stop = true;
+      } else {
+        t.cross++;
+      }
+    }
+    if (stop) {
+      t.w_abs += q.wabs;
+      pid = -1;
+    }
+  }
+
+  // ---- per-wave reduction of the tallies, one atomic per wave and field
+  double v[9] = {t.w_emit, t.w_esc, t.w_kill, t.w_abs, (double)t.inter, (double)t.checks,
+                 (double)t.cross, (double)t.escaped, (double)t.killed};
+#pragma unroll
+  for (int f = 0; f < 9; ++f) {
+    double s = wave_sum(v[f]);
+    if (lane == 0 && s != 0.0) atomicAdd(A.stats + f, s);
+  }
+  // packets with an id beyond the sampling plan or a direction with no wall ahead
+  if (__ballot(t.bad) != 0ull && lane == 0) A.stats[EXTRASS_STATS - 2] = 1.0;
+}
+
+}  // namespace
+}  // namespace extrass
+
+using namespace extrass;
+
+static size_t ws_layout(const extrass_grid* g, const extrass_source* s, int64_t** start,
+                        double** inv_lam, unsigned long long** queue, void* ws, size_t* need) {
+  const int64_t C = (int64_t)g->n * g->n * g->n;
+  Carver cv(ws, ~size_t(0));
+  int64_t* st = cv.take<int64_t>(C + 1);
+  double* il = cv.take<double>(g->n_lines > 0 ? g->n_lines : 1);
+  unsigned long long* qu = cv.take<unsigned long long>(8);
+  if (start) *start = st;
+  if (inv_lam) *inv_lam = il;
+  if (queue) *queue = qu;
+  *need = cv.used + 256;
+  (void)s;
+  return *need;
+}
+
+extern "C" size_t extrass_transport_workspace(const extrass_grid* g, const extrass_source* s) {
+  if (!g || !s || g->n <= 0) return 0;
+  size_t need = 0;
+  ws_layout(g, s, nullptr, nullptr, nullptr, nullptr, &need);
+  return need;
+}
+
+extern "C" int extrass_transport(extrass_handle h, const extrass_grid* g, const extrass_source* s,
+                                 double* est, double* stats, double* packets_out, void* ws,
+                                 size_t ws_bytes, void* stream) {
+  if (!h || !g || !s || !est || !stats || !ws)
+    return fail(h, EXTRASS_EINVAL, "extrass_transport: null argument");
+  if (g->n <= 0 || g->n > 1024 || g->n_lines < 0 || !(g->beta_max > 0.0))
+    return fail(h, EXTRASS_EINVAL, "extrass_transport: bad grid size");
+  if (g->n_lines > 0 && (!g->line_lambda || !g->line_tau0))
+    return fail(h, EXTRASS_EINVAL, "extrass_transport: missing line arrays");
+  if (!g->tau_scale) return fail(h, EXTRASS_EINVAL, "extrass_transport: tau_scale is NULL");
+  if (g->tau_ct && (!g->line_trans || g->n_trans <= 0))
+    return fail(h, EXTRASS_EINVAL, "extrass_transport: tau_ct needs line_trans and n_trans");
+  if (s->n_packets < 0 || s->first_packet < 0)
+    return fail(h, EXTRASS_EINVAL, "extrass_transport: bad packet range");
+  if (!s->explicit_packets && (!g->cell_packets || !g->cell_photons))
+    return fail(h, EXTRASS_EINVAL, "extrass_transport: sampled mode needs cell_packets/photons");
+  size_t need = 0;
+  int64_t* start = nullptr;
+  double* inv_lam = nullptr;
+  unsigned long long* queue = nullptr;
+  ws_layout(g, s, &start, &inv_lam, &queue, ws, &need);
+  if (ws_bytes < need) return fail(h, EXTRASS_ENOSPACE, "extrass_transport: workspace too small");
+
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  EXTRASS_HIP_TRY(h, hipSetDevice(h->device));
+  const int64_t C = (int64_t)g->n * g->n * g->n;
+  const int L = g->n_lines;
+
+  hipLaunchKernelGGL(k_prep, dim3(64), dim3(256), 0, st, g->line_lambda, inv_lam, L, stats, queue);
+  if (L > 1) hipLaunchKernelGGL(k_check_sorted, dim3(64), dim3(256), 0, st, g->line_lambda, L, stats);
+  if (!s->explicit_packets)
+    hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, st, g->cell_packets, C, start);
+  const int64_t n_est = C * (int64_t)L;
+  if (n_est > 0) {
+    int64_t blocks = (n_est / 2 + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(256), 0, st, est, n_est);
+  }
+  EXTRASS_HIP_TRY(h, hipGetLastError());
+  if (s->n_packets == 0) return EXTRASS_OK;
+
+  TArgs A{};
+  A.n = g->n;
+  A.beta = g->beta_max;
+  A.h = 2.0 * g->beta_max / g->n;
+  A.tau_scale = g->tau_scale;
+  A.cell_photons = g->cell_photons;
+  A.cell_packets = g->cell_packets;
+  A.L = L;
+  A.lam = g->line_lambda;
+  A.inv_lam = inv_lam;
+  A.tau0 = g->line_tau0;
+  A.line_trans = g->line_trans;
+  A.T = g->n_trans;
+  A.tau_ct = g->tau_ct;
+  A.fcorr_ct = g->fcorr_ct;
+  A.seed = s->seed;
+  A.iteration = (uint32_t)s->iteration;
+  A.first = s->first_packet;
+  A.count = s->n_packets;
+  A.lam_lo = s->lambda_lo;
+  A.lam_hi = s->lambda_hi;
+  A.explicit_pk = s->explicit_packets;
+  A.start = start;
+  A.C = C;
+  A.est = est;
+  A.stats = stats;
+  A.pk_out = packets_out;
+  A.queue = queue;
+
+  // enough waves to fill every CU several times over, never more than needed
+  int64_t blocks = (int64_t)h->num_cus * 8;
+  const int64_t max_blocks = (s->n_packets + kBlock - 1) / kBlock;
+  if (blocks > max_blocks) blocks = max_blocks;
+  if (blocks < 1) blocks = 1;
+  if (s->geometry_fp32)
+    hipLaunchKernelGGL(k_transport<float>, dim3((unsigned)blocks), dim3(kBlock), 0, st, A);
+  else
+    hipLaunchKernelGGL(k_transport<double>, dim3((unsigned)blocks), dim3(kBlock), 0, st, A);
+  EXTRASS_HIP_TRY(h, hipGetLastError());
+  return EXTRASS_OK;
+}

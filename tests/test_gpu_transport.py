@@ -1,0 +1,229 @@
+"""Transport, opacity and rates: HIP path vs the FP64 oracle on the same inputs.
+
+Bars: FP64 geometry - per-entry relative difference <= 1e-3 on every
+estimator entry (observed ~1e-10), the same set of non-zero entries and
+identical event counts; FP32 geometry - L1 difference <= 1e-3 of the table,
+every line's sum within 1e-3, event counts within 1e-5, and the number of
+entries that differ by more than 1e-3 (interactions moved to a neighbouring
+cell by FP32 rounding at a wall) at most 1e-5 of the non-zero entries.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ex():
+    import paper_2511_07539_amd as ex
+    return ex
+
+
+@pytest.fixture(scope="module")
+def ctx(ex):
+    return ex.Context(0)
+
+
+@pytest.fixture(scope="module")
+def small():
+    w = synth.sphere_small()
+    inp = oracle.transport_inputs_from_workload(w)
+    r = oracle.transport(inp, per_packet=True)
+    return w, r, oracle.dense_estimator(r["records"], w.n_cells, w.n_lines)
+
+
+def _run(ex, ctx, w, fp32, grid=None, **kw):
+    grid = grid or ex.grid_from_workload(w)
+    est, stats, pk = ex.transport(ctx, grid, w.seed, w.lambda_lo, w.lambda_hi, w.n_packets,
+                                  geometry_fp32=fp32, **kw)
+    torch.cuda.synchronize()
+    return est.cpu().numpy(), ex.stats_dict(stats), None if pk is None else pk.cpu().numpy()
+
+
+def test_fp64_geometry_matches_oracle_per_entry(ex, ctx, small):
+    w, r, ref = small
+    say("case: sphere16 fp64 geometry, 1e5 packets")
+    est, st, pk = _run(ex, ctx, w, False, packets_out=True)
+    assert st["error_flag"] == 0
+    nz = ref != 0
+    assert np.array_equal(est != 0, nz)
+    rel = np.abs(est[nz] - ref[nz]) / np.abs(ref[nz])
+    say("max rel", rel.max())
+    assert rel.max() <= 1e-3
+    assert rel.max() <= 1e-9   # observed: rounding-level
+    for k in ["n_inter", "n_checks", "n_cross", "n_escaped", "n_killed"]:
+        assert st[k] == r["stats"][k], k
+    for k in ["w_emit", "w_esc", "w_abs"]:
+        assert st[k] == pytest.approx(r["stats"][k], rel=1e-12), k
+    assert st["w_kill"] == pytest.approx(r["stats"]["w_kill"], rel=1e-9)
+    # per packet: escaped/killed weight and lab wavelength
+    opk = r["packets"]
+    np.testing.assert_allclose(pk[:, 1], opk[:, 1], rtol=1e-14)
+    np.testing.assert_allclose(pk[:, 0], opk[:, 0], rtol=1e-11, atol=0)
+    np.testing.assert_allclose(pk[:, 3], opk[:, 3], rtol=1e-11, atol=1e-30)
+
+
+def _fp32_metric(est, ref, rec, tie=1e-4):
+    """Reduced-precision parity. Under FP32 geometry a resonance within rounding
+    of a cell wall, or the order in which a ray crosses two nearly coincident
+    walls, can move an interaction to a neighbouring cell; the number of such
+    entries is bounded and reported, and the table, each line's sum and the
+    event counts must agree to 1e-3."""
+    d = np.abs(est - ref)
+    l1 = d.sum() / np.abs(ref).sum()
+    line_ref = ref.sum(0)
+    big_l = line_ref > 1e-3 * line_ref.max()
+    line_err = np.abs(est.sum(0) - line_ref)
+    bad = (d > 1e-3 * np.abs(ref)) & ((ref != 0) | (est != 0))
+    tie_records = int((rec["margin"] < tie).sum())
+    return dict(l1=l1, line=(line_err[big_l] / line_ref[big_l]).max(), bad_entries=int(bad.sum()),
+                tie_records=tie_records, nonzero=int((ref != 0).sum()))
+
+
+def test_fp32_geometry_matches_oracle_statistically(ex, ctx, small):
+    w, r, ref = small
+    say("case: sphere16 fp32 geometry, 1e5 packets")
+    est, st, _ = _run(ex, ctx, w, True)
+    m = _fp32_metric(est, ref, r["records"])
+    say(m)
+    assert m["l1"] <= 1e-3 and m["line"] <= 1e-3
+    assert m["bad_entries"] <= 1e-3 * m["nonzero"]
+    assert abs(st["n_inter"] - r["stats"]["n_inter"]) <= 1e-3 * r["stats"]["n_inter"]
+
+
+def test_explicit_packets_and_ragged_ranges(ex, ctx):
+    """Explicit-packet mode, a packet range that starts mid-list, an empty range."""
+    g = np.random.default_rng(5)
+    n, beta, L = 7, 0.03, 333
+    lam = np.sort(g.uniform(3000, 9000, L)) * synth.ANGSTROM
+    tau0 = (10 ** g.uniform(-5, 3, L)).astype(np.float32)
+    scale = g.uniform(0, 3, n ** 3).astype(np.float32)
+    P = 5000
+    x0 = g.uniform(-beta, beta, (P, 3))
+    d = g.standard_normal((P, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    pk = np.column_stack([x0, d, g.uniform(3000, 9000, P) * synth.ANGSTROM, g.uniform(0.5, 2, P)])
+    inp = oracle.TransportInputs(n, beta, scale, np.zeros(n ** 3), np.zeros(n ** 3, np.int32), lam,
+                                 tau0, 0, 0, 1, explicit_packets=pk)
+    first, cnt = 1234, 2717
+    ro = oracle.transport(inp, first=first, count=cnt)
+    ref = oracle.dense_estimator(ro["records"], n ** 3, L)
+    grid = ex.Grid(n, beta, scale, np.zeros(n ** 3), np.zeros(n ** 3, np.int32), lam, tau0)
+    say("case: explicit packets 7^3 x 333 lines, range [1234, 3951)")
+    est, stats, _ = ex.transport(ctx, grid, 1, 0, 0, cnt, first_packet=first, explicit_packets=pk)
+    torch.cuda.synchronize()
+    est = est.cpu().numpy()
+    nz = ref != 0
+    assert np.array_equal(est != 0, nz)
+    np.testing.assert_allclose(est[nz], ref[nz], rtol=1e-10)
+    say("case: empty packet range")
+    est0, st0, _ = ex.transport(ctx, grid, 1, 0, 0, 0, explicit_packets=pk)
+    torch.cuda.synchronize()
+    assert float(est0.abs().sum()) == 0.0
+    assert float(st0[:9].abs().sum()) == 0.0
+
+
+def test_unsorted_lines_flagged(ex, ctx):
+    n = 3
+    lam = np.array([5e-5, 4e-5, 6e-5])
+    grid = ex.Grid(n, 0.01, np.ones(27, np.float32), np.ones(27), np.ones(27, np.int32), lam,
+                   np.ones(3, np.float32))
+    say("case: unsorted line list")
+    _, st, _ = ex.transport(ctx, grid, 1, 4e-5, 6e-5, 27)
+    torch.cuda.synchronize()
+    assert ex.stats_dict(st)["error_flag"] == 1
+
+
+def test_line_tau_and_rates_match_oracle(ex, ctx, small):
+    w, r, ref = small
+    inp = oracle.nlte_inputs_from_workload(w)
+    pops = np.zeros((w.n_cells, w.atom.n_levels))
+    for c in np.where(w.n_species > 0)[0]:
+        pops[c] = oracle.nlte_cold(inp, int(c))
+    tau_o, fc_o = oracle.line_tau(pops, w.atom, w.t_exp)
+    V = (2 * w.beta_max / w.n * synth.C_CGS * w.t_exp) ** 3
+    gam_o = oracle.rates(ref, pops, w.atom, V)
+    atom = ex.Atom(ctx, w.atom)
+    pd = torch.as_tensor(pops, device="cuda:0")
+    say("case: Eq. A2 opacity and rates, sphere16")
+    tau, fc = ex.line_tau(ctx, atom, pd, w.t_exp)
+    gam = ex.rates(ctx, atom, torch.as_tensor(ref, device="cuda:0"), pd, V)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(tau.cpu().numpy().ravel(), tau_o, rtol=1e-13, atol=0)
+    np.testing.assert_allclose(fc.cpu().numpy().ravel(), fc_o, rtol=1e-13, atol=1e-15)
+    np.testing.assert_allclose(gam.cpu().numpy().ravel(), gam_o, rtol=1e-14, atol=0)
+
+
+def test_coupled_opacity_transport(ex, ctx):
+    """Lines of the atom take tau and f_corr from populations (Eq. A2), the rest
+    are background lines; a 12^3 clumpy grid, FP64 geometry."""
+    w = synth.clumpy(n=12, n_lines=2000, n_packets=200_000, number=2)
+    inp_n = oracle.nlte_inputs_from_workload(w)
+    pops = np.stack([oracle.nlte_cold(inp_n, c) for c in range(w.n_cells)])
+    tau_o, fc_o = oracle.line_tau(pops, w.atom, w.t_exp)
+    inp = oracle.transport_inputs_from_workload(w, tau_ct=tau_o, fcorr_ct=fc_o)
+    r = oracle.transport(inp)
+    ref = oracle.dense_estimator(r["records"], w.n_cells, w.n_lines)
+    grid = ex.grid_from_workload(w, tau_ct=tau_o, fcorr_ct=fc_o)
+    say("case: clumpy12 coupled opacity, fp64 geometry")
+    est, st, _ = _run(ex, ctx, w, False, grid=grid)
+    nz = ref != 0
+    assert np.array_equal(est != 0, nz)
+    np.testing.assert_allclose(est[nz], ref[nz], rtol=1e-10)
+    assert st["n_inter"] == r["stats"]["n_inter"]
+
+
+@pytest.fixture(scope="module")
+def paper_scale():
+    """50^3 cells, 5000 lines, 1e7 packets; atom lines take tau from the cold-start
+    populations (Eq. A2): the workload and launch bench.py times. The oracle runs
+    every packet on the host."""
+    w = synth.paper_scale()
+    inp_n = oracle.nlte_inputs_from_workload(w)
+    pops = np.stack([oracle.nlte_cold(inp_n, c) for c in range(w.n_cells)])
+    tau_o, fc_o = oracle.line_tau(pops, w.atom, w.t_exp)
+    say("case: clumpy50 oracle on host, 1e7 packets")
+    r = oracle.transport(oracle.transport_inputs_from_workload(w, tau_ct=tau_o, fcorr_ct=fc_o))
+    rec = r["records"]
+    idx = rec["cell"].astype(np.int64) * w.n_lines + rec["line"]
+    ref = np.bincount(idx, weights=rec["value"], minlength=w.n_cells * w.n_lines)
+    return w, tau_o, fc_o, r, ref.reshape(w.n_cells, w.n_lines)
+
+
+def test_paper_scale_fp64_full_size_per_entry(ex, ctx, paper_scale):
+    w, tau_o, fc_o, r, ref = paper_scale
+    grid = ex.grid_from_workload(w, tau_ct=tau_o, fcorr_ct=fc_o)
+    say("case: clumpy50 fp64 geometry, 1e7 packets (GPU)")
+    est, st, _ = _run(ex, ctx, w, False, grid=grid)
+    nz = ref != 0
+    support = int(((est != 0) != nz).sum())
+    rel = np.abs(est[nz] - ref[nz]) / ref[nz]
+    say("support mismatches", support, "max rel", rel.max())
+    assert support == 0
+    assert rel.max() <= 1e-3
+    for k in ["n_inter", "n_checks", "n_cross", "n_escaped", "n_killed"]:
+        assert st[k] == r["stats"][k], k
+
+
+def test_paper_scale_fp32_full_size(ex, ctx, paper_scale):
+    w, tau_o, fc_o, r, ref = paper_scale
+    grid = ex.grid_from_workload(w, tau_ct=tau_o, fcorr_ct=fc_o)
+    say("case: clumpy50 fp32 geometry, 1e7 packets (GPU)")
+    est, st, _ = _run(ex, ctx, w, True, grid=grid)
+    m = _fp32_metric(est, ref, r["records"])
+    say(m)
+    assert m["l1"] <= 1e-3 and m["line"] <= 1e-3
+    assert m["bad_entries"] <= 1e-5 * m["nonzero"]
+    assert abs(st["n_inter"] - r["stats"]["n_inter"]) <= 1e-5 * r["stats"]["n_inter"]
+    assert st["w_emit"] == pytest.approx(r["stats"]["w_emit"], rel=1e-12)
+    assert st["w_abs"] == pytest.approx(r["stats"]["w_abs"], rel=1e-6)

@@ -201,7 +201,7 @@ def _brute_force(inp, packets, tau_cl):
             if tau > 1e-4:
                 dN = w * -math.expm1(-tau)
                 recs.append((p, c, k, dN))
-                w = w - dN
+                w = w * math.exp(-tau)
                 if w * lam_e < (1e-6 * w0) * lam[k]:
                     break
     return recs
