@@ -1,0 +1,197 @@
+"""Benchmark of the hot path on one MI355X.
+
+One step = one global iteration of the method on the 50^3-cell workload
+(125 000 cells, 5 000 lines, 1e7 packets, 2 species x 50 levels):
+  Eq. A2 line opacities from the previous populations -> packet transport
+  (FP32 geometry, FP64 estimators) -> photoexcitation rates -> NLTE solve of
+  every cell, started from the previous populations.
+Every step starts from the same previous populations (the cold start), so the
+work per step is fixed. Inputs are resident in HBM before the timed region.
+
+Prints one JSON line. `value` is packet line-interactions per second of the
+whole step; NLTE cell-solves per second of the whole step are reported beside
+it. The roofline object covers the kernel that dominates the step, timed with
+HIP events on the stream the library launches on.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "packet line-interactions/s + NLTE cell-solves/s vs plain FP64 at 1e-8 accuracy"
+HBM_PEAK_GBS = 8000.0
+FP64_VALU_PEAK_TFLOPS = 78.6
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-fraction", type=float, default=0.1,
+                    help="fraction of packets and cells the oracle runs for cpu_baseline")
+    ap.add_argument("--geometry-fp64", action="store_true")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(sharding is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2511_07539_amd as ex
+    import synth
+
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    w = synth.paper_scale()
+    ctx = ex.Context(0)
+    atom = ex.Atom(ctx, w.atom)
+    V = ex.cell_volume(w)
+    cells0 = ex.cells_from_workload(w, device=dev)
+    # previous populations: the cold start (not timed)
+    prev, _, _ = ex.nlte_solve(ctx, atom, cells0, max_iter=0)
+    prev = prev.clone()
+    tau, fc = ex.line_tau(ctx, atom, prev, w.t_exp)
+    grid = ex.grid_from_workload(w, device=dev, tau_ct=tau, fcorr_ct=fc)
+    est = torch.empty((w.n_cells, w.n_lines), dtype=torch.float64, device=dev)
+    stats = torch.empty(ex.STATS, dtype=torch.float64, device=dev)
+    gamma = torch.empty((w.n_cells, w.atom.n_trans), dtype=torch.float64, device=dev)
+    pops = torch.empty_like(prev)
+    status = torch.empty(w.n_cells, dtype=torch.int32, device=dev)
+    iters = torch.empty(w.n_cells, dtype=torch.int32, device=dev)
+    cells = ex.Cells(w.t_exp, cells0.T_e, cells0.n_e, cells0.n_species, cells0.gamma_ion, gamma,
+                     device=dev)
+    fp32 = not args.geometry_fp64
+    s = torch.cuda.current_stream()
+    names = ["line_tau", "transport", "rates", "nlte"]
+
+    def step(ev=None):
+        def mark(i):
+            if ev is not None:
+                ev[i].record(s)
+        mark(0)
+        t, f = ex.line_tau(ctx, atom, prev, w.t_exp)
+        grid.tau_ct.copy_(t)
+        grid.fcorr_ct.copy_(f)
+        mark(1)
+        ex.transport(ctx, grid, w.seed, w.lambda_lo, w.lambda_hi, w.n_packets,
+                     geometry_fp32=fp32, est=est, stats=stats)
+        mark(2)
+        g = ex.rates(ctx, atom, est, prev, V)
+        gamma.copy_(g)
+        mark(3)
+        ex.nlte_solve(ctx, atom, cells, guess=prev, pops=pops, status=status, iters=iters)
+        mark(4)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    parts = {n: 0.0 for n in names}
+    for ev in evs:
+        for i, n in enumerate(names):
+            parts[n] += ev[i].elapsed_time(ev[i + 1])
+    parts = {n: v / args.steps for n, v in parts.items()}
+    ms = (t1 - t0) * 1e3 / args.steps
+    st = ex.stats_dict(stats)
+    n_inter = st["n_inter"]
+    st_np = status.cpu().numpy()
+    conv = int((st_np == 0).sum())
+    value = n_inter / (ms * 1e-3)
+    solves = w.n_cells / (ms * 1e-3)
+
+    # roofline of the dominant kernel
+    dom = max(parts, key=parts.get)
+    if dom == "transport":
+        bytes_alg = 8.0 * w.n_cells * w.n_lines + 16.0 * w.n_cells + 16.0 * w.n_lines
+        ach = bytes_alg / (parts["transport"] * 1e-3) / 1e9
+        roof = {"kernel": "extrass_transport (fill + transport kernels)", "bound": "hbm",
+                "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                "traffic": None, "algorithmic_bytes": bytes_alg}
+    else:
+        it_np = iters.cpu().numpy()
+        S = w.atom.n_species
+        Ns = np.diff(w.atom.species_offset)
+        # state reductions: about two per iteration (fixed-point or Newton + trial),
+        # (2/3) N^3 flops each
+        flops = float(sum(2.0 * it_np.sum() * (2.0 / 3.0) * n ** 3 for n in Ns))
+        ach = flops / (parts[dom] * 1e-3) / 1e12
+        roof = {"kernel": f"extrass_{dom}", "bound": "alu", "achieved": ach,
+                "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": ach / FP64_VALU_PEAK_TFLOPS, "traffic": None,
+                "algorithmic_flops": flops}
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "line-interactions/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "cells": w.n_cells, "lines": w.n_lines,
+                   "packets": w.n_packets, "levels": w.atom.n_levels,
+                   "species": w.atom.n_species, "geometry": "fp32" if fp32 else "fp64",
+                   "parallelism": "single GPU"},
+        "nlte_cell_solves_per_s": solves,
+        "interactions_per_step": n_inter,
+        "cells_converged": conv,
+        "ms_parts": parts,
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, prev.cpu().numpy(), args.cpu_fraction)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(w, prev, frac):
+    """The FP64 oracle on the host, as it stands, on a bounded sample: the first
+    `frac` of the packets and of the cells; the whole-step time is scaled up
+    from that sample."""
+    import numpy as np
+
+    import oracle
+    nthreads = oracle.default_threads()
+    tau, fc = oracle.line_tau(prev, w.atom, w.t_exp)
+    inp = oracle.transport_inputs_from_workload(w, tau_ct=tau, fcorr_ct=fc)
+    P = int(w.n_packets * frac)
+    t0 = time.perf_counter()
+    r = oracle.transport(inp, first=0, count=P, nthreads=nthreads)
+    t1 = time.perf_counter()
+    Cs = int(w.n_cells * frac)
+    cells = np.arange(Cs)
+    rec = r["records"]
+    sel = rec["cell"] < Cs
+    est = np.zeros(Cs * w.n_lines)
+    np.add.at(est, rec["cell"][sel].astype(np.int64) * w.n_lines + rec["line"][sel],
+              rec["value"][sel])
+    V = (2 * w.beta_max / w.n * 2.99792458e10 * w.t_exp) ** 3
+    gpe = oracle.rates(est, prev[:Cs], w.atom, V)
+    ninp = oracle.nlte_inputs_from_workload(w, gamma_pe=gpe, cells=cells)
+    t2 = time.perf_counter()
+    oracle.nlte(ninp, guess=prev[:Cs], nthreads=nthreads)
+    t3 = time.perf_counter()
+    t_step = (t1 - t0) / frac + (t3 - t2) / frac
+    inter_step = r["stats"]["n_inter"] / frac
+    return {"value": inter_step / t_step, "unit": "line-interactions/s", "cores": nthreads,
+            "kind": "oracle", "nlte_cell_solves_per_s": w.n_cells / t_step,
+            "sample": f"first {P} packets and first {Cs} cells ({frac:.0%}) of the workload; "
+                      f"transport {t1 - t0:.2f} s, NLTE {t3 - t2:.2f} s, scaled to the full step"}
+
+
+if __name__ == "__main__":
+    main()

@@ -85,6 +85,13 @@ def lib():
     return _lib
 
 
+def default_threads():
+    """Host threads for the oracle: OMP_NUM_THREADS if set, else at most 16."""
+    env = os.environ.get("OMP_NUM_THREADS")
+    n = int(env) if env and env.isdigit() else 16
+    return max(1, min(n, os.cpu_count() or 1))
+
+
 def _p(a):
     return None if a is None else a.ctypes.data
 
@@ -155,7 +162,7 @@ def transport(inp: TransportInputs, first=0, count=None, nthreads=None, per_pack
     if count is None:
         count = inp.n_packets - first
     if nthreads is None:
-        nthreads = os.cpu_count() or 1
+        nthreads = default_threads()
     stats = np.zeros(N_STATS)
     pk = np.zeros((count, PKT_FIELDS)) if per_packet else None
     ptr = C.POINTER(_Record)()
@@ -259,7 +266,7 @@ def nlte(inp: NLTEInputs, guess=None, max_iter=200, tol=1e-13, nthreads=None, fi
     if count is None:
         count = inp.n_cells - first
     if nthreads is None:
-        nthreads = os.cpu_count() or 1
+        nthreads = default_threads()
     pops = np.zeros((inp.n_cells, inp.n_levels)) if guess is None else \
         np.ascontiguousarray(guess, dtype=np.float64).reshape(inp.n_cells, inp.n_levels).copy()
     status = np.full(inp.n_cells, -1, dtype=np.int32)
