@@ -199,8 +199,11 @@ typedef struct {
 typedef struct {
   int32_t max_iter;    /* iteration cap per species (fixed-point + Newton) */
   double tol;          /* convergence: max |d ln n| below tol */
-  int32_t use_guess;   /* 1: start from pops on entry; 0: cold start */
+  int32_t use_guess;   /* 1: start from pops on entry (a non-positive entry means
+                          the cold start for that system); 0: cold start */
   int32_t factor_fp32; /* 1: Newton systems factored in FP32, residuals in FP64 */
+  int32_t warm_budget; /* with use_guess: iterations allowed from the guess before
+                          the system restarts from the cold start (0: never) */
 } extrass_nlte_opts;
 
 /* Statistical equilibrium per cell and species (Sec. 2.2, Eqs. A1-A2):
@@ -213,12 +216,46 @@ typedef struct {
  *   ground of z+1 at n_e alpha0 (T/1e4)^-0.8, 1/3 to the ground state of z and
  *   2/3 over its excited levels by statistical weight (Appendix A.2).
  * pops [C*N]: in = guess (if use_guess), out = solution. status [C]: 0
- * converged, 2 not converged within max_iter, 3 empty cell (all species 0).
+ * converged, 1 converged after falling back to the cold start, 2 not
+ * converged within max_iter, 3 empty cell (all species 0).
  * iters [C] (may be NULL): largest iteration count over the cell's species. */
 size_t extrass_nlte_workspace(extrass_atom_handle a, int64_t n_cells);
 int extrass_nlte_solve(extrass_handle h, extrass_atom_handle a, const extrass_cells* cells,
                        const extrass_nlte_opts* opts, double* pops, int32_t* status,
                        int32_t* iters, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Learned warm start (not part of the paper's method): an MLP
+ * 6 -> 256 -> 256 -> 256 -> 100 with SiLU hidden layers maps normalised cell
+ * features to normalised log10(n_i / n_species) of a 100-level, 2-species
+ * atom. Parameters: one FP32 vector of extrass_mlp_param_count() values,
+ * W1 [256*6], b1 [256], W2 [256*256], b2, W3 [256*256], b3, W4 [100*256],
+ * b4 [100], weights row-major [out][in]. GEMMs run on BF16 matrix cores with
+ * FP32 accumulation; master weights and optimiser state are FP32. */
+size_t extrass_mlp_param_count(void);
+size_t extrass_mlp_workspace(int64_t batch);
+/* y [batch*100] = MLP(x [batch*6]) (x already normalised). */
+int extrass_mlp_forward(extrass_handle h, const float* params, const float* x, float* y,
+                        int64_t batch, void* ws, size_t ws_bytes, void* stream);
+/* One training step on a batch with loss = mean((MLP(x) - t)^2) over all outputs:
+ * adds the batch loss to *loss (device float; may be NULL), writes the
+ * gradient to grad [P] when not NULL, and, when adam_m/adam_v [P] are given,
+ * applies Adam (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected with `step`
+ * >= 1) with learning rate lr to params. */
+int extrass_mlp_train_step(extrass_handle h, float* params, float* adam_m, float* adam_v,
+                           int32_t step, float lr, const float* x, const float* t, int64_t batch,
+                           float* loss, float* grad, void* ws, size_t ws_bytes, void* stream);
+/* Warm-start populations for extrass_nlte_solve (use_guess = 1): features of
+ * each cell (log10 of the total species density, T_e, n_e and the deposition
+ * [C] in erg s^-1 cm^-3, and the two species' number fractions), normalised by
+ * norm[0..5] (means) and norm[6..11] (standard deviations), pass through the
+ * MLP; outputs are de-normalised with norm[12..111] (means) and
+ * norm[112..211] (standard deviations), exponentiated and scaled so that each
+ * species sums to its density. The atom must have 2 species and 100 levels. */
+size_t extrass_nlte_warm_start_workspace(int64_t n_cells);
+int extrass_nlte_warm_start(extrass_handle h, extrass_atom_handle atom, const extrass_cells* cells,
+                            const double* deposition, const float* params, const float* norm,
+                            double* pops, void* ws, size_t ws_bytes, void* stream);
 
 #ifdef __cplusplus
 }

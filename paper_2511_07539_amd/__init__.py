@@ -61,7 +61,7 @@ class _Cells(C.Structure):
 
 class _Opts(C.Structure):
     _fields_ = [("max_iter", C.c_int32), ("tol", C.c_double), ("use_guess", C.c_int32),
-                ("factor_fp32", C.c_int32)]
+                ("factor_fp32", C.c_int32), ("warm_budget", C.c_int32)]
 
 
 _vp = C.c_void_p
@@ -84,10 +84,23 @@ _lib.extrass_nlte_workspace.argtypes = [_vp, C.c_int64]
 _lib.extrass_nlte_solve.argtypes = [_vp, _vp, C.POINTER(_Cells), C.POINTER(_Opts), _vp, _vp, _vp,
                                     _vp, C.c_size_t, _vp]
 
+_lib.extrass_mlp_param_count.restype = C.c_size_t
+_lib.extrass_mlp_workspace.restype = C.c_size_t
+_lib.extrass_mlp_workspace.argtypes = [C.c_int64]
+_lib.extrass_mlp_forward.argtypes = [_vp, _vp, _vp, _vp, C.c_int64, _vp, C.c_size_t, _vp]
+_lib.extrass_mlp_train_step.argtypes = [_vp, _vp, _vp, _vp, C.c_int32, C.c_float, _vp, _vp,
+                                        C.c_int64, _vp, _vp, _vp, C.c_size_t, _vp]
+_lib.extrass_nlte_warm_start_workspace.restype = C.c_size_t
+_lib.extrass_nlte_warm_start_workspace.argtypes = [C.c_int64]
+_lib.extrass_nlte_warm_start.argtypes = [_vp, _vp, C.POINTER(_Cells), _vp, _vp, _vp, _vp, _vp,
+                                         C.c_size_t, _vp]
+
 SYMBOLS = ["extrass_create", "extrass_destroy", "extrass_error_string", "extrass_last_error",
            "extrass_transport_workspace", "extrass_transport", "extrass_line_tau",
            "extrass_rates", "extrass_atom_create", "extrass_atom_destroy",
-           "extrass_nlte_workspace", "extrass_nlte_solve"]
+           "extrass_nlte_workspace", "extrass_nlte_solve", "extrass_mlp_param_count",
+           "extrass_mlp_workspace", "extrass_mlp_forward", "extrass_mlp_train_step",
+           "extrass_nlte_warm_start_workspace", "extrass_nlte_warm_start"]
 
 
 class ExtrassError(RuntimeError):
@@ -306,18 +319,22 @@ def cells_from_workload(w, gamma_pe=None, device="cuda:0", cells=None):
 
 
 def nlte_solve(ctx: Context, atom: Atom, cells: Cells, max_iter=200, tol=1e-10, guess=None,
-               factor_fp32=False, pops=None, status=None, iters=None):
+               factor_fp32=False, pops=None, status=None, iters=None, warm_budget=0,
+               use_guess=None):
     """Runs extrass_nlte_solve; returns (pops [C, N], status [C], iters [C])."""
     dev = cells.T_e.device
     if pops is None:
         pops = torch.empty((cells.n_cells, atom.n_levels), dtype=torch.float64, device=dev)
-    if guess is not None:
+    if guess is not None and guess.data_ptr() != pops.data_ptr():
         pops.copy_(guess)
+    if use_guess is None:
+        use_guess = guess is not None
     if status is None:
         status = torch.empty(cells.n_cells, dtype=torch.int32, device=dev)
     if iters is None:
         iters = torch.empty(cells.n_cells, dtype=torch.int32, device=dev)
-    o = _Opts(int(max_iter), float(tol), 0 if guess is None else 1, 1 if factor_fp32 else 0)
+    o = _Opts(int(max_iter), float(tol), 1 if use_guess else 0, 1 if factor_fp32 else 0,
+              int(warm_budget))
     cs = cells.struct()
     need = _lib.extrass_nlte_workspace(atom.h, cells.n_cells)
     ws = ctx.workspace(need)
@@ -329,3 +346,41 @@ def nlte_solve(ctx: Context, atom: Atom, cells: Cells, max_iter=200, tol=1e-10, 
 
 def cell_volume(w):
     return (2.0 * w.beta_max / w.n * 2.99792458e10 * w.t_exp) ** 3
+
+
+MLP_PARAMS = int(_lib.extrass_mlp_param_count())
+MLP_IN, MLP_OUT = 6, 100
+
+
+def mlp_forward(ctx: Context, params, x):
+    """y = MLP(x) for normalised features x [B, 6] (FP32 device tensors)."""
+    B = x.shape[0]
+    y = torch.empty((B, MLP_OUT), dtype=torch.float32, device=x.device)
+    ws = ctx.workspace(_lib.extrass_mlp_workspace(B))
+    ctx.check(_lib.extrass_mlp_forward(ctx.h, _ptr(params), _ptr(x), _ptr(y), B, _ptr(ws),
+                                       ws.numel(), _stream()), "extrass_mlp_forward")
+    return y
+
+
+def mlp_train_step(ctx: Context, params, x, t, adam_m=None, adam_v=None, step=1, lr=1e-3,
+                   loss=None, grad=None):
+    B = x.shape[0]
+    ws = ctx.workspace(_lib.extrass_mlp_workspace(B))
+    ctx.check(_lib.extrass_mlp_train_step(ctx.h, _ptr(params), _ptr(adam_m), _ptr(adam_v),
+                                          int(step), float(lr), _ptr(x), _ptr(t), B, _ptr(loss),
+                                          _ptr(grad), _ptr(ws), ws.numel(), _stream()),
+              "extrass_mlp_train_step")
+
+
+def nlte_warm_start(ctx: Context, atom: Atom, cells: Cells, deposition, params, norm, pops=None):
+    """Populations predicted by the MLP for every cell (extrass_nlte_warm_start)."""
+    dev = cells.T_e.device
+    if pops is None:
+        pops = torch.empty((cells.n_cells, atom.n_levels), dtype=torch.float64, device=dev)
+    dep = _dev(deposition, torch.float64, dev)
+    cs = cells.struct()
+    ws = ctx.workspace(_lib.extrass_nlte_warm_start_workspace(cells.n_cells))
+    ctx.check(_lib.extrass_nlte_warm_start(ctx.h, atom.h, C.byref(cs), _ptr(dep), _ptr(params),
+                                           _ptr(norm), _ptr(pops), _ptr(ws), ws.numel(),
+                                           _stream()), "extrass_nlte_warm_start")
+    return pops

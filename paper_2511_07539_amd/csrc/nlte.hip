@@ -65,6 +65,7 @@ struct NArgs {
   int max_iter;
   double tol;
   int use_guess;
+  int warm_budget;
   double* pops;
   int32_t* status;
   int32_t* iters;
@@ -235,7 +236,7 @@ __device__ bool fixed_point_residual(const NArgs& A, const Sys& y, double* G, do
 
 // Solves one (cell, species) system; returns the iteration count, or -1.
 __device__ int solve_system(const NArgs& A, const Sys& y, double* G, double* nb, double* hb,
-                            double& n) {
+                            double& n, int max_iter) {
   const int lane = threadIdx.x;
   const bool live = lane < y.Ns;
   const int last = y.Ns - 1;
@@ -243,7 +244,7 @@ __device__ int solve_system(const NArgs& A, const Sys& y, double* G, double* nb,
   int it = 0;
   // ---- fixed-point phase
   double omega = 1.0, prev = INFINITY;
-  for (; it < A.max_iter && it < 60; ++it) {
+  for (; it < max_iter && it < 60; ++it) {
     assemble(A, y, G, nb, n, false, nullptr, 0.0, false, rhs);
     if (!reduce_solve(G, A.NP, y.Ns, last, false, 0.0, xp, pp)) return -1;
     const double psum = wave_sum(live ? pp : 0.0);
@@ -264,7 +265,7 @@ __device__ int solve_system(const NArgs& A, const Sys& y, double* G, double* nb,
   int best_it = it;
   double h = 0.0;
   bool have_h = false;
-  for (; it < A.max_iter; ++it) {
+  for (; it < max_iter; ++it) {
     if (!have_h && !fixed_point_residual(A, y, G, nb, n, h)) return -1;
     const double res = wave_max(fabs(h));
     const double phi = wave_sum(h * h);
@@ -316,6 +317,25 @@ __device__ int solve_system(const NArgs& A, const Sys& y, double* G, double* nb,
   return -1;
 }
 
+// Cold start: Boltzmann populations within each ion stage at T_e, stage
+// ratios from a balance of ionisation against recombination of ground states.
+__device__ double cold_start(const Sys& y, bool live) {
+  double w = live ? y.g * exp(-y.E / y.kT) : 0.0;
+  if (live && w < 1e-250) w = 1e-250;
+  double ss[3];
+  for (int zz = 0; zz < 3; ++zz) ss[zz] = wave_sum((live && y.z == zz) ? w : 0.0);
+  double ratio[3] = {1.0, 1.0, 1.0};
+  for (int zz = 1; zz < y.nst; ++zz) {
+    const double rc = y.rec[zz - 1];
+    double r = rc > 0.0 ? y.gion[zz - 1] / rc : 1e30;
+    r = r < 1e-30 ? 1e-30 : (r > 1e30 ? 1e30 : r);
+    ratio[zz] = ratio[zz - 1] * r;
+  }
+  double rsum = 0.0;
+  for (int zz = 0; zz < y.nst; ++zz) rsum += ratio[zz];
+  return live ? y.ntot * (ratio[y.z] / rsum) * (w / ss[y.z]) : 0.0;
+}
+
 __global__ __launch_bounds__(64) void k_nlte(NArgs A) {
   extern __shared__ double smem[];
   double* nb = smem;        // 64 doubles: populations broadcast
@@ -359,29 +379,25 @@ __global__ __launch_bounds__(64) void k_nlte(NArgs A) {
     y.g = A.lv_g[li];
     y.share = A.lv_share[li];
 
-    double n = 0.0;
-    if (A.use_guess) {
-      n = live ? out[lane] : 0.0;
-    } else {
-      double w = live ? y.g * exp(-y.E / y.kT) : 0.0;
-      if (live && w < 1e-250) w = 1e-250;
-      double ss[3];
-      for (int zz = 0; zz < 3; ++zz) ss[zz] = wave_sum((live && y.z == zz) ? w : 0.0);
-      double ratio[3] = {1.0, 1.0, 1.0};
-      for (int zz = 1; zz < y.nst; ++zz) {
-        const double rc = y.rec[zz - 1];
-        double r = rc > 0.0 ? y.gion[zz - 1] / rc : 1e30;
-        r = r < 1e-30 ? 1e-30 : (r > 1e30 ? 1e30 : r);
-        ratio[zz] = ratio[zz - 1] * r;
+    double n = A.use_guess ? (live ? out[lane] : 0.0) : cold_start(y, live);
+    if (A.use_guess && __ballot(live && !(n > 0.0 && n < INFINITY)) != 0ull)
+      n = cold_start(y, live);  // unusable guess
+    int its, code = 0;
+    if (A.use_guess && A.warm_budget > 0) {
+      its = solve_system(A, y, G, nb, hb, n, std::min(A.warm_budget, A.max_iter));
+      if (its < 0) {  // fall back to the cold start with the remaining budget
+        n = cold_start(y, live);
+        const int rest = A.max_iter - std::min(A.warm_budget, A.max_iter);
+        its = solve_system(A, y, G, nb, hb, n, rest);
+        code = 1;
+        if (its >= 0) its += std::min(A.warm_budget, A.max_iter);
       }
-      double rsum = 0.0;
-      for (int zz = 0; zz < y.nst; ++zz) rsum += ratio[zz];
-      n = live ? y.ntot * (ratio[y.z] / rsum) * (w / ss[y.z]) : 0.0;
+    } else {
+      its = solve_system(A, y, G, nb, hb, n, A.max_iter);
     }
-    const int its = solve_system(A, y, G, nb, hb, n);
     if (live) out[lane] = n;
     if (lane == 0) {
-      atomicMax(A.status + y.c, its < 0 ? 2 : 0);
+      atomicMax(A.status + y.c, its < 0 ? 2 : code);
       if (A.iters) atomicMax(A.iters + y.c, its < 0 ? A.max_iter : its);
     }
   }
@@ -460,6 +476,7 @@ extern "C" int extrass_nlte_solve(extrass_handle h, extrass_atom_handle a, const
   A.max_iter = o->max_iter;
   A.tol = o->tol;
   A.use_guess = o->use_guess;
+  A.warm_budget = o->warm_budget;
   A.pops = pops;
   A.status = status;
   A.iters = iters;

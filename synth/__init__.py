@@ -103,6 +103,7 @@ class Workload:
     n_e: Optional[np.ndarray] = None        # f64 [C] cm^-3
     n_species: Optional[np.ndarray] = None  # f64 [C*S] cm^-3
     gamma_ion: Optional[np.ndarray] = None  # f64 [C*S*3] s^-1 (stage z -> z+1, any level)
+    deposition: Optional[np.ndarray] = None # f64 [C] erg s^-1 cm^-3 (gamma-ray deposition)
     couple_lines: bool = False              # atom lines take tau from populations
 
     @property
@@ -234,14 +235,31 @@ def _finish(name, number, n, beta_max, t_exp, rho, lines_lo_A, lines_hi_A, n_lin
         C = n ** 3
         lo, hi = T_range
         T_e = np.where(active, 10.0 ** gc.uniform(np.log10(lo), np.log10(hi), size=C), lo)
+        # mass fractions vary per cell around the given means (first species
+        # uniform within +-0.2 of its mean, the rest in proportion)
+        X = np.tile(np.asarray(mass_fractions, float), (C, 1))
+        if S > 1:
+            x0 = np.clip(X[:, 0] + gc.uniform(-0.2, 0.2, C), 0.05, 0.95)
+            rest = X[:, 1:] / X[:, 1:].sum(axis=1, keepdims=True)
+            X = np.column_stack([x0, (1.0 - x0)[:, None] * rest])
         n_sp = np.zeros((C, S))
         for s in range(S):
-            n_sp[:, s] = mass_fractions[s] * rho / (atom.species_mass[s] * M_U)
+            n_sp[:, s] = X[:, s] * rho / (atom.species_mass[s] * M_U)
         n_e = 0.5 * n_sp.sum(axis=1)
+        # gamma-ray deposition ~ rho times lognormal scatter (sigma_ln ~ 1); non-thermal
+        # ionisation per atom ~ deposition per atom, with one constant per
+        # (species, stage) drawn log-uniformly, scaled so that the rates span
+        # about 1e-7..1e-3 s^-1 over the cells
+        dep = np.where(active, rho * _lognormal_unit_mean(gc, 1.3, C), 0.0)
+        per_atom = np.where(active, dep / np.maximum(n_sp.sum(axis=1), 1e-300), 0.0)
+        ref = np.median(per_atom[active]) if active.any() else 1.0
         gam = np.zeros((C, S, 3))
         nz = int(atom.level_ion.max()) + 1
         if nz > 1:
-            gam[:, :, : nz - 1] = _log_uniform(gc, 1e-7, 1e-3, (C, S, nz - 1))
+            kz = _log_uniform(gc, 1e-6, 1e-4, (S, nz - 1))
+            gam[:, :, : nz - 1] = kz[None, :, :] * (per_atom / ref)[:, None, None]
+        dep_scale = 1e-7 / max(np.median(dep[active]) if active.any() else 1.0, 1e-300)
+        wl.deposition = dep * dep_scale
         wl.atom = atom
         wl.T_e = T_e
         wl.n_e = n_e
