@@ -3,15 +3,20 @@
 One step = one global iteration of the method on the 50^3-cell workload
 (125 000 cells, 5 000 lines, 1e7 packets, 2 species x 50 levels):
   Eq. A2 line opacities from the previous populations -> packet transport
-  (FP32 geometry, FP64 estimators) -> photoexcitation rates -> NLTE solve of
-  every cell, started from the previous populations.
+  (FP32 geometry, FP64 estimators) -> photoexcitation rates -> MLP warm
+  start -> NLTE solve of every cell from the MLP's populations (cold-start
+  fallback for systems that do not converge within the warm budget).
 Every step starts from the same previous populations (the cold start), so the
 work per step is fixed. Inputs are resident in HBM before the timed region.
+Setup (not timed) trains the warm-start network on solves of replicas of the
+workload's cells (temperature, deposition and abundances redrawn).
 
 Prints one JSON line. `value` is packet line-interactions per second of the
 whole step; NLTE cell-solves per second of the whole step are reported beside
-it. The roofline object covers the kernel that dominates the step, timed with
-HIP events on the stream the library launches on.
+it, and so is the plain FP64 cold-start NLTE pass on the same rates, timed
+after the step loop, with the largest population difference between the two.
+The roofline object covers the kernel that dominates the step, timed with HIP
+events on the stream the library launches on.
 """
 import argparse
 import json
@@ -36,6 +41,9 @@ def parse():
     ap.add_argument("--cpu-fraction", type=float, default=0.1,
                     help="fraction of packets and cells the oracle runs for cpu_baseline")
     ap.add_argument("--geometry-fp64", action="store_true")
+    ap.add_argument("--replicas", type=int, default=8)
+    ap.add_argument("--epochs", type=int, default=30)
+    ap.add_argument("--warm-budget", type=int, default=30)
     return ap.parse_args()
 
 
@@ -73,8 +81,19 @@ def main():
     cells = ex.Cells(w.t_exp, cells0.T_e, cells0.n_e, cells0.n_species, cells0.gamma_ion, gamma,
                      device=dev)
     fp32 = not args.geometry_fp64
+    # learned warm start: trained on the method's own solves (setup, not timed)
+    from paper_2511_07539_amd import warmstart
+    t_train = time.perf_counter()
+    gamma_train = warmstart.photoexcitation_rates(ctx, atom, w, dev)
+    X, Y = warmstart.make_dataset(ctx, atom, w, n_replicas=args.replicas, gamma=gamma_train)
+    del gamma_train
+    params, norm, hist = warmstart.train(ctx, X, Y, epochs=args.epochs, batch=8192)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t_train
+    dep = torch.as_tensor(w.deposition, device=dev)
+    guess = torch.empty_like(prev)
     s = torch.cuda.current_stream()
-    names = ["line_tau", "transport", "rates", "nlte"]
+    names = ["line_tau", "transport", "rates", "warm_start", "nlte"]
 
     def step(ev=None):
         def mark(i):
@@ -91,13 +110,16 @@ def main():
         g = ex.rates(ctx, atom, est, prev, V)
         gamma.copy_(g)
         mark(3)
-        ex.nlte_solve(ctx, atom, cells, guess=prev, pops=pops, status=status, iters=iters)
+        ex.nlte_warm_start(ctx, atom, cells, dep, params, norm, pops=pops)
         mark(4)
+        ex.nlte_solve(ctx, atom, cells, pops=pops, use_guess=True, warm_budget=args.warm_budget,
+                      status=status, iters=iters)
+        mark(5)
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(args.steps)]
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
@@ -113,7 +135,22 @@ def main():
     st = ex.stats_dict(stats)
     n_inter = st["n_inter"]
     st_np = status.cpu().numpy()
-    conv = int((st_np == 0).sum())
+    conv = int((st_np <= 1).sum())
+    fallbacks = int((st_np == 1).sum())
+    it_warm = iters.cpu().numpy()
+    # the plain FP64 pass from the cold start on the same rates, for comparison
+    pops_cold = torch.empty_like(pops)
+    st_cold = torch.empty_like(status)
+    it_cold = torch.empty_like(iters)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    ex.nlte_solve(ctx, atom, cells, pops=pops_cold, status=st_cold, iters=it_cold)
+    e1.record(s)
+    torch.cuda.synchronize()
+    cold_ms = e0.elapsed_time(e1)
+    both = (st_cold == 0) & (status <= 1)
+    pw, pc = pops[both], pops_cold[both]
+    warm_vs_cold = float(((pw - pc).abs() / pc).max().item()) if int(both.sum()) else None
     value = n_inter / (ms * 1e-3)
     solves = w.n_cells / (ms * 1e-3)
 
@@ -126,7 +163,7 @@ def main():
                 "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
                 "traffic": None, "algorithmic_bytes": bytes_alg}
     else:
-        it_np = iters.cpu().numpy()
+        it_np = it_warm
         S = w.atom.n_species
         Ns = np.diff(w.atom.species_offset)
         # state reductions: about two per iteration (fixed-point or Newton + trial),
@@ -150,6 +187,13 @@ def main():
         "nlte_cell_solves_per_s": solves,
         "interactions_per_step": n_inter,
         "cells_converged": conv,
+        "nlte_fallbacks": fallbacks,
+        "nlte_iters_mean": {"warm": float(it_warm.mean()), "cold": float(it_cold.float().mean())},
+        "nlte_plain_fp64_cold_ms": cold_ms,
+        "nlte_warm_vs_cold_max_rel": warm_vs_cold,
+        "warm_start_training": {"samples": int(X.shape[0]), "epochs": args.epochs,
+                                "loss_first": hist[0], "loss_last": hist[-1],
+                                "setup_s": t_train},
         "ms_parts": parts,
         "roofline": roof,
     }

@@ -12,7 +12,9 @@
 //     log(n) when the change fails to shrink, until max |d ln n| < 0.1; the
 //     stationary vector comes from state reduction with pivots formed as sums
 //     of off-diagonal rates (Grassmann-Taksar-Heyman), which involves no
-//     subtraction and keeps every component accurate;
+//     subtraction and keeps every component accurate. The matrix is assembled
+//     in LDS (one transition per lane at a time) and reduced in registers,
+//     one row per lane;
 //  3. Newton steps in log(n): the Jacobian scaled by diag(n) is a transposed
 //     generator (non-negative off-diagonals, zero column sums), so the Newton
 //     system is reduced the same way, the most populated level last, and
@@ -66,6 +68,7 @@ struct NArgs {
   double tol;
   int use_guess;
   int warm_budget;
+  int factor_fp32;
   double* pops;
   int32_t* status;
   int32_t* iters;
@@ -103,7 +106,7 @@ __device__ __forceinline__ double dbeta_sobolev(double tau) {
 // gross inflow against outflow. With jac, the derivative of the radiative
 // fluxes through beta_S(tau(n)) is then added, which turns G into the
 // diag(n)-scaled Newton matrix.
-__device__ void assemble(const NArgs& A, const Sys& y, double* G, double* nb, double n_mine,
+__device__ __forceinline__ void assemble(const NArgs& A, const Sys& y, double* G, double* nb, double n_mine,
                          bool rowscale, const double* hb, double h_mine, bool jac, double& rhs) {
   const int lane = threadIdx.x;
   const int NP = A.NP;
@@ -113,6 +116,7 @@ __device__ void assemble(const NArgs& A, const Sys& y, double* G, double* nb, do
     if (lane < Ns) G[r * NP + lane] = 0.0;
   __syncthreads();
   const double* gpe = A.gamma_pe ? A.gamma_pe + y.c * A.T : nullptr;
+#pragma unroll 1
   for (int t = y.t0 + lane; t < y.t1; t += 64) {
     const int l = A.t_l[t], u = A.t_u[t];
     const double gl = A.lv_g[y.base + l], gu = A.lv_g[y.base + u];
@@ -148,6 +152,7 @@ __device__ void assemble(const NArgs& A, const Sys& y, double* G, double* nb, do
   }
   if (jac) {
     __syncthreads();
+#pragma unroll 1
     for (int t = y.t0 + lane; t < y.t1; t += 64) {
       const int l = A.t_l[t], u = A.t_u[t];
       const double gl = A.lv_g[y.base + l], gu = A.lv_g[y.base + u];
@@ -171,150 +176,211 @@ __device__ __forceinline__ int perm(int a, int big, int last) {
   return a == big ? last : (a == last ? big : a);
 }
 
+__device__ __forceinline__ float read_lane(float v, int k) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
+}
+
+__device__ __forceinline__ double read_lane(double v, int k) {
+  const uint64_t u = __double_as_longlong(v);
+  const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)u, k);
+  const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), k);
+  return __longlong_as_double(((uint64_t)hi << 32) | lo);
+}
+
 // State reduction of the generator in G (off-diagonal entries, row i -> j),
 // visiting states in the order perm(0..Ns-1) (the level `big` swapped to the
 // end). Solves x^T G = b^T with x_last = 0 when rhs, and the homogeneous
 // problem with pi_last = 1. Lane a holds b, x and pi of permuted position a.
 // Returns false when a pivot is not positive (reducible chain).
-__device__ bool reduce_solve(double* G, int NP, int Ns, int big, bool rhs, double b_perm,
-                             double& x_perm, double& pi_perm) {
+//
+// Each lane copies its row into registers (NT >= Ns, a compile-time size);
+// the reduction then runs unrolled on registers: at step k every lane sums its
+// remaining row entries and lane k's sum is the pivot, lane k publishes its
+// row through a small LDS buffer, and the other lanes update their rows with
+// it. Entries beyond Ns stay zero. The diagonal is never read. Matrix and
+// right-hand side are multiplied by `scale` (a power of two) as they are
+// loaded, which leaves x and pi unchanged; T = float gives the
+// single-precision reduction.
+template <int NT, class T>
+__device__ __forceinline__ bool reduce_solve(const double* G, int NP, int Ns, int big, bool rhs,
+                                             double b_perm_in, double scale, T* rowbuf, double* out) {
   const int lane = threadIdx.x;
   const int last = Ns - 1;
   const bool live = lane < Ns;
-  const int my_col = live ? perm(lane, big, last) : 0;
-  double S_mine = 0.0;
+  const int my_row = live ? perm(lane, big, last) : 0;
+  T g[NT];
+#pragma unroll
+  for (int b = 0; b < NT; ++b)
+    g[b] = (live && b < Ns && b != lane) ? (T)(scale * G[my_row * NP + perm(b, big, last)]) : T(0);
+  T b_perm = (T)(scale * b_perm_in);
+  T S_mine = T(0);
   bool ok = true;
-  for (int k = 0; k < last; ++k) {
-    const int rk = perm(k, big, last);
-    const bool act = live && lane > k;
-    const double ub = act ? G[rk * NP + my_col] : 0.0;
-    const double S = wave_sum(ub);
-    if (!(S > 0.0)) ok = false;
-    if (lane == k) S_mine = S;
-    const double invS = 1.0 / S;
-    if (rhs) {
-      const double bk = __shfl(b_perm, k, 64);
-      if (act) b_perm += bk * ub * invS;
-    }
-    for (int a = k + 1; a < Ns; ++a) {
-      const int ra = perm(a, big, last);
-      const double f = G[ra * NP + rk] * invS;
-      if (f != 0.0 && act && lane != a) G[ra * NP + my_col] += f * ub;
-    }
-    __syncthreads();
-  }
-  double x = 0.0, pi = lane == last ? 1.0 : 0.0;
-  for (int k = last - 1; k >= 0; --k) {
-    const int ck = perm(k, big, last);
-    const double gk = (live && lane > k) ? G[my_col * NP + ck] : 0.0;
-    const double sx = rhs ? wave_sum(x * gk) : 0.0;
-    const double sp = wave_sum(pi * gk);
-    const double Sk = __shfl(S_mine, k, 64);
-    const double bk = rhs ? __shfl(b_perm, k, 64) : 0.0;
-    if (lane == k) {
-      x = (sx - bk) / Sk;
-      pi = sp / Sk;
+#pragma unroll
+  for (int k = 0; k < NT - 1; ++k) {
+    if (k < last) {
+      T part = T(0);
+#pragma unroll
+      for (int b = k + 1; b < NT; ++b) part += g[b];
+      const T S = read_lane(part, k);
+      if (!(S > T(0))) ok = false;
+      if (lane == k) {
+        S_mine = S;
+#pragma unroll
+        for (int b = k + 1; b < NT; ++b) rowbuf[b] = g[b];
+      }
+      __builtin_amdgcn_wave_barrier();
+      const T invS = T(1) / S;
+      const T f = g[k] * invS;
+      // eight columns at a time, so that only eight broadcast values are live
+#pragma unroll
+      for (int b0 = k + 1; b0 < NT; b0 += 8) {
+#pragma unroll
+        for (int b = b0; b < b0 + 8 && b < NT; ++b) g[b] += f * rowbuf[b];
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      if (rhs) {
+        const T bk = read_lane(b_perm, k);
+        if (live && lane > k) b_perm += bk * rowbuf[lane] * invS;
+      }
+      __builtin_amdgcn_wave_barrier();
     }
   }
-  x_perm = x;
-  pi_perm = pi;
+  T x = T(0), pi = lane == last ? T(1) : T(0);
+#pragma unroll
+  for (int k = NT - 2; k >= 0; --k) {
+    if (k < last) {
+      const T gk = (live && lane > k) ? g[k] : T(0);
+      const T sx = rhs ? wave_sum(x * gk) : T(0);
+      const T sp = wave_sum(pi * gk);
+      const T Sk = read_lane(S_mine, k);
+      const T bk = rhs ? read_lane(b_perm, k) : T(0);
+      if (lane == k) {
+        x = (sx - bk) / Sk;
+        pi = sp / Sk;
+      }
+    }
+  }
+  out[0] = (double)x;
+  out[1] = (double)pi;
   return ok;
 }
 
-// Relative fixed-point residual h = P(n)/n - 1 with P(n) = n_tot * stationary
-// vector of R(n); returns false on a vanishing pivot.
-__device__ bool fixed_point_residual(const NArgs& A, const Sys& y, double* G, double* nb,
-                                     double n, double& h) {
-  const bool live = threadIdx.x < y.Ns;
-  double rhs = 0.0, xp = 0.0, pp = 0.0;
-  assemble(A, y, G, nb, n, false, nullptr, 0.0, false, rhs);
-  if (!reduce_solve(G, A.NP, y.Ns, y.Ns - 1, false, 0.0, xp, pp)) return false;
-  const double psum = wave_sum(live ? pp : 0.0);
-  h = live ? y.ntot * (pp / psum) / n - 1.0 : 0.0;
-  return true;
-}
-
 // Solves one (cell, species) system; returns the iteration count, or -1.
+//
+// Written as a loop over phases so that the matrix assembly and the state
+// reduction each appear once (both are large once unrolled):
+//  FIXED  - one fixed-point step (stationary vector of R(n), relaxed in log n);
+//  RESID  - fixed-point residual h = P(n)/n - 1 at the current n;
+//  NEWTON - Newton step from the scaled Jacobian with right-hand side Q^T H;
+//  TRIAL  - fixed-point residual at a trial point inside the trust radius.
+template <int NT>
 __device__ int solve_system(const NArgs& A, const Sys& y, double* G, double* nb, double* hb,
-                            double& n, int max_iter) {
+                            double* rowbuf, double& n, int max_iter) {
+  enum { FIXED, RESID, NEWTON, TRIAL };
   const int lane = threadIdx.x;
   const bool live = lane < y.Ns;
   const int last = y.Ns - 1;
-  double rhs = 0.0, xp = 0.0, pp = 0.0;
-  int it = 0;
-  // ---- fixed-point phase
-  double omega = 1.0, prev = INFINITY;
-  for (; it < max_iter && it < 60; ++it) {
-    assemble(A, y, G, nb, n, false, nullptr, 0.0, false, rhs);
-    if (!reduce_solve(G, A.NP, y.Ns, last, false, 0.0, xp, pp)) return -1;
-    const double psum = wave_sum(live ? pp : 0.0);
-    const double nw = live ? y.ntot * (pp / psum) : 0.0;
-    const double change = wave_max(live ? fabs(log(nw / n)) : 0.0);
-    if (change > 0.999 * prev) omega = omega * 0.5 > 1.0 / 1024 ? omega * 0.5 : 1.0 / 1024;
-    prev = change;
-    double v = live ? exp((1.0 - omega) * log(n) + omega * log(nw)) : 0.0;
-    const double tot = wave_sum(v);
-    n = live ? v * (y.ntot / tot) : 0.0;
-    if (change < 0.1) {
+  if (max_iter <= 0) return -1;
+  int phase = FIXED, it = 0, bt = 0, best_it = 0;
+  double omega = 1.0, prev = INFINITY, Delta = 1.0, best_step = INFINITY;
+  double h = 0.0, x = 0.0, step = 0.0, taken = 0.0, trial = 0.0, phi = 0.0, res = 0.0;
+  for (;;) {
+    const bool newton = phase == NEWTON;
+    const double at = phase == TRIAL ? trial : n;
+    if (newton && live) hb[lane] = h;
+    double rhs = 0.0, xo[2];
+    assemble(A, y, G, nb, at, newton, newton ? hb : nullptr, h, newton, rhs);
+    int big = last;
+    double b_perm = 0.0;
+    if (newton) {
+      // most populated level (first one on ties) goes last
+      const double nmax = wave_max(live ? n : -1.0);
+      const uint64_t bm = __ballot(live && n == nmax);
+      big = __ffsll((unsigned long long)bm) - 1;
+      b_perm = __shfl(rhs, live ? perm(lane, big, last) : 0, 64);
+    }
+    bool ok = false, done = false;
+    if (newton && A.factor_fp32) {
+      // Single-precision Newton step: the matrix is brought to a largest
+      // entry of 2^100 so that fluxes spanning ~70 decades below it stay
+      // normal in FP32. The residual that judges the step stays FP64, so
+      // the outer iteration refines the inexact step; a step whose FP32
+      // pivots are not positive is redone in FP64.
+      double rmax = 0.0;
+      if (live)
+        for (int j = 0; j < y.Ns; ++j) rmax = fmax(rmax, fabs(G[lane * A.NP + j]));
+      rmax = fmax(wave_max(rmax), fabs(wave_max(fabs(b_perm))));
+      const double scale = rmax > 0.0 ? ldexp(1.0, 100 - ilogb(rmax)) : 1.0;
+      done = reduce_solve<NT, float>(G, A.NP, y.Ns, big, true, b_perm, scale,
+                                     reinterpret_cast<float*>(rowbuf), xo);
+      ok = done;
+    }
+    if (!done) ok = reduce_solve<NT, double>(G, A.NP, y.Ns, big, newton, b_perm, 1.0, rowbuf, xo);
+    if (!ok) return -1;
+    if (phase == FIXED) {
+      const double pp = xo[1];
+      const double psum = wave_sum(live ? pp : 0.0);
+      const double nw = live ? y.ntot * (pp / psum) : 0.0;
+      const double change = wave_max(live ? fabs(log(nw / n)) : 0.0);
+      if (change > 0.999 * prev) omega = omega * 0.5 > 1.0 / 1024 ? omega * 0.5 : 1.0 / 1024;
+      prev = change;
+      const double v = live ? exp((1.0 - omega) * log(n) + omega * log(nw)) : 0.0;
+      const double tot = wave_sum(v);
+      n = live ? v * (y.ntot / tot) : 0.0;
       ++it;
-      break;
-    }
-  }
-  // ---- Newton phase
-  double Delta = 1.0, best_step = INFINITY;
-  int best_it = it;
-  double h = 0.0;
-  bool have_h = false;
-  for (; it < max_iter; ++it) {
-    if (!have_h && !fixed_point_residual(A, y, G, nb, n, h)) return -1;
-    const double res = wave_max(fabs(h));
-    const double phi = wave_sum(h * h);
-    if (live) hb[lane] = h;
-    assemble(A, y, G, nb, n, true, hb, h, true, rhs);
-    // most populated level (first one on ties) goes last
-    const double nmax = wave_max(live ? n : -1.0);
-    const uint64_t bm = __ballot(live && n == nmax);
-    const int big = __ffsll((unsigned long long)bm) - 1;
-    const double b_perm = __shfl(rhs, live ? perm(lane, big, last) : 0, 64);
-    if (!reduce_solve(G, A.NP, y.Ns, big, true, b_perm, xp, pp)) return -1;
-    const int src = live ? perm(lane, big, last) : 0;
-    double x = __shfl(xp, src, 64), pi = __shfl(pp, src, 64);
-    if (!live) x = pi = 0.0;
-    const double sum_n = wave_sum(n), sum_nx = wave_sum(n * x), sum_npi = wave_sum(n * pi);
-    const double cst = ((y.ntot - sum_n) - sum_nx) / sum_npi;
-    x += cst * pi;
-    if (!live) x = 0.0;
-    const double step = wave_max(fabs(x));
-    if (step < best_step) {
-      best_step = step;
+      if (change < 0.1 || it >= 60) phase = RESID;
+      if (it >= max_iter) return -1;
       best_it = it;
+    } else if (phase == RESID || phase == TRIAL) {
+      const double pp = xo[1];
+      const double psum = wave_sum(live ? pp : 0.0);
+      const double hv = live ? y.ntot * (pp / psum) / at - 1.0 : 0.0;
+      if (phase == RESID) {
+        h = hv;
+        phase = NEWTON;
+      } else {
+        const double phi2 = wave_sum(hv * hv);
+        const double res2 = wave_max(fabs(hv));
+        if (phi2 < phi || res2 < 1e-14) {  // accept the trial point
+          n = trial;
+          h = hv;
+          if (taken >= 0.99 * Delta) Delta = 2.0 * Delta < 30.0 ? 2.0 * Delta : 30.0;
+          ++it;
+          if (it >= max_iter) return -1;
+          phase = NEWTON;
+        } else {
+          Delta = (taken < Delta ? taken : Delta) / 4.0;
+          if (++bt >= 40) return (step < 1e-11 || res < 1e-14) ? it + 1 : -1;
+        }
+      }
+    } else {  // NEWTON
+      res = wave_max(fabs(h));
+      phi = wave_sum(h * h);
+      const int src = live ? perm(lane, big, last) : 0;
+      x = __shfl(xo[0], src, 64);
+      double pi = __shfl(xo[1], src, 64);
+      if (!live) x = pi = 0.0;
+      const double sum_n = wave_sum(n), sum_nx = wave_sum(n * x), sum_npi = wave_sum(n * pi);
+      const double cst = ((y.ntot - sum_n) - sum_nx) / sum_npi;
+      x += cst * pi;
+      if (!live) x = 0.0;
+      step = wave_max(fabs(x));
+      if (step < best_step) {
+        best_step = step;
+        best_it = it;
+      }
+      if ((step < A.tol && res < 1e-10) || (step < 1e-11 && it - best_it >= 3)) return it + 1;
+      bt = 0;
+      phase = TRIAL;
     }
-    if ((step < A.tol && res < 1e-10) || (step < 1e-11 && it - best_it >= 3)) return it + 1;
-    // trust-region step in log(n), accepted when the fixed-point residual drops
-    bool accepted = false;
-    double taken = 0.0, trial = 0.0, h_trial = 0.0;
-    for (int bt = 0; bt < 40; ++bt) {
+    if (phase == TRIAL) {  // trial point in log(n) within the trust radius
       const double scale = step > Delta ? Delta / step : 1.0;
       taken = step * scale;
       const double v = live ? n * exp(scale * x) : 0.0;
       const double tot = wave_sum(v);
       trial = live ? v * (y.ntot / tot) : 0.0;
-      if (!fixed_point_residual(A, y, G, nb, trial, h_trial)) return -1;
-      const double phi2 = wave_sum(h_trial * h_trial);
-      const double res2 = wave_max(fabs(h_trial));
-      if (phi2 < phi || res2 < 1e-14) {
-        accepted = true;
-        break;
-      }
-      Delta = (taken < Delta ? taken : Delta) / 4.0;
     }
-    if (!accepted) return (step < 1e-11 || res < 1e-14) ? it + 1 : -1;
-    n = trial;
-    h = h_trial;
-    have_h = true;
-    if (taken >= 0.99 * Delta) Delta = 2.0 * Delta < 30.0 ? 2.0 * Delta : 30.0;
   }
-  return -1;
 }
 
 // Cold start: Boltzmann populations within each ion stage at T_e, stage
@@ -336,11 +402,13 @@ __device__ double cold_start(const Sys& y, bool live) {
   return live ? y.ntot * (ratio[y.z] / rsum) * (w / ss[y.z]) : 0.0;
 }
 
-__global__ __launch_bounds__(64) void k_nlte(NArgs A) {
+template <int NT>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_nlte(NArgs A) {
   extern __shared__ double smem[];
-  double* nb = smem;        // 64 doubles: populations broadcast
-  double* hb = smem + 64;   // 64 doubles: fixed-point residuals broadcast
-  double* G = smem + 128;   // maxNs x NP doubles
+  double* nb = smem;            // 64 doubles: populations broadcast
+  double* hb = smem + 64;       // 64 doubles: fixed-point residuals broadcast
+  double* rowbuf = smem + 128;  // 64 doubles: pivot row during the reduction
+  double* G = smem + 192;       // maxNs x NP doubles
   const int lane = threadIdx.x;
   const int64_t items = A.C * A.S;
   for (;;) {
@@ -384,16 +452,16 @@ __global__ __launch_bounds__(64) void k_nlte(NArgs A) {
       n = cold_start(y, live);  // unusable guess
     int its, code = 0;
     if (A.use_guess && A.warm_budget > 0) {
-      its = solve_system(A, y, G, nb, hb, n, std::min(A.warm_budget, A.max_iter));
+      its = solve_system<NT>(A, y, G, nb, hb, rowbuf, n, std::min(A.warm_budget, A.max_iter));
       if (its < 0) {  // fall back to the cold start with the remaining budget
         n = cold_start(y, live);
         const int rest = A.max_iter - std::min(A.warm_budget, A.max_iter);
-        its = solve_system(A, y, G, nb, hb, n, rest);
+        its = solve_system<NT>(A, y, G, nb, hb, rowbuf, n, rest);
         code = 1;
         if (its >= 0) its += std::min(A.warm_budget, A.max_iter);
       }
     } else {
-      its = solve_system(A, y, G, nb, hb, n, A.max_iter);
+      its = solve_system<NT>(A, y, G, nb, hb, rowbuf, n, A.max_iter);
     }
     if (live) out[lane] = n;
     if (lane == 0) {
@@ -435,7 +503,6 @@ extern "C" int extrass_nlte_solve(extrass_handle h, extrass_atom_handle a, const
   if (cl->n_cells < 0 || !cl->T_e || !cl->n_e || !cl->n_species || !cl->gamma_ion ||
       o->max_iter < 0 || !(o->tol > 0.0))
     return fail(h, EXTRASS_EINVAL, "extrass_nlte_solve: bad cells or options");
-  if (o->factor_fp32) return fail(h, EXTRASS_EUNSUPPORTED, "extrass_nlte_solve: FP32 factor not built");
   if (ws_bytes < extrass_nlte_workspace(a, cl->n_cells))
     return fail(h, EXTRASS_ENOSPACE, "extrass_nlte_solve: workspace too small");
   if (cl->n_cells == 0) return EXTRASS_OK;
@@ -477,18 +544,32 @@ extern "C" int extrass_nlte_solve(extrass_handle h, extrass_atom_handle a, const
   A.tol = o->tol;
   A.use_guess = o->use_guess;
   A.warm_budget = o->warm_budget;
+  A.factor_fp32 = o->factor_fp32;
   A.pops = pops;
   A.status = status;
   A.iters = iters;
   A.queue = queue;
   A.NP = a->maxNs | 1;
-  const size_t lds = sizeof(double) * (128 + (size_t)a->maxNs * A.NP);
+  const size_t lds = sizeof(double) * (192 + (size_t)a->maxNs * A.NP);
   const int64_t items = cl->n_cells * a->S;
   int per_cu = (int)std::min<size_t>(16, (160 * 1024) / std::max<size_t>(lds, 1));
   if (per_cu < 1) per_cu = 1;
   int64_t blocks = std::min<int64_t>((int64_t)h->num_cus * per_cu, items);
   if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(k_nlte, dim3((unsigned)blocks), dim3(64), lds, st, A);
+  // the register-resident reduction is compiled for a few system sizes; the
+  // smallest that holds the largest species is used
+  if (a->maxNs <= 16)
+    hipLaunchKernelGGL(k_nlte<16>, dim3((unsigned)blocks), dim3(64), lds, st, A);
+  else if (a->maxNs <= 24)
+    hipLaunchKernelGGL(k_nlte<24>, dim3((unsigned)blocks), dim3(64), lds, st, A);
+  else if (a->maxNs <= 32)
+    hipLaunchKernelGGL(k_nlte<32>, dim3((unsigned)blocks), dim3(64), lds, st, A);
+  else if (a->maxNs <= 40)
+    hipLaunchKernelGGL(k_nlte<40>, dim3((unsigned)blocks), dim3(64), lds, st, A);
+  else if (a->maxNs <= 50)
+    hipLaunchKernelGGL(k_nlte<50>, dim3((unsigned)blocks), dim3(64), lds, st, A);
+  else
+    hipLaunchKernelGGL(k_nlte<64>, dim3((unsigned)blocks), dim3(64), lds, st, A);
   EXTRASS_HIP_TRY(h, hipGetLastError());
   return EXTRASS_OK;
 }
