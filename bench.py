@@ -38,12 +38,15 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-fraction", type=float, default=0.1,
+    ap.add_argument("--cpu-fraction", type=float, default=1.0,
                     help="fraction of packets and cells the oracle runs for cpu_baseline")
     ap.add_argument("--geometry-fp64", action="store_true")
     ap.add_argument("--replicas", type=int, default=8)
     ap.add_argument("--epochs", type=int, default=30)
     ap.add_argument("--warm-budget", type=int, default=30)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one 1 GiB device-to-device copy before the step loop, whose "
+                         "FETCH_SIZE/WRITE_SIZE counters calibrate the HBM traffic figures")
     return ap.parse_args()
 
 
@@ -116,6 +119,13 @@ def main():
                       status=status, iters=iters)
         mark(5)
 
+    if args.copy_calibration:
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)  # reads 1 GiB, writes 1 GiB
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -161,7 +171,7 @@ def main():
         ach = bytes_alg / (parts["transport"] * 1e-3) / 1e9
         roof = {"kernel": "extrass_transport (fill + transport kernels)", "bound": "hbm",
                 "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
-                "traffic": None, "algorithmic_bytes": bytes_alg}
+                "traffic": recorded_traffic("extrass_transport"), "algorithmic_bytes": bytes_alg}
     else:
         it_np = it_warm
         S = w.atom.n_species
@@ -172,7 +182,7 @@ def main():
         ach = flops / (parts[dom] * 1e-3) / 1e12
         roof = {"kernel": f"extrass_{dom}", "bound": "alu", "achieved": ach,
                 "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": ach / FP64_VALU_PEAK_TFLOPS, "traffic": None,
+                "frac": ach / FP64_VALU_PEAK_TFLOPS, "traffic": recorded_traffic("extrass_nlte"),
                 "algorithmic_flops": flops}
 
     out = {
@@ -200,6 +210,24 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, prev.cpu().numpy(), args.cpu_fraction)
     print(json.dumps(out), flush=True)
+
+
+def recorded_traffic(key):
+    """HBM bytes per launch of a kernel from the committed FETCH_SIZE/WRITE_SIZE
+    counter record (scaled by the copy calibration), or None when the kernel's
+    sources have changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)["kernels"][key]
+        m = hashlib.sha256()
+        for src in rec["sources"]:
+            with open(os.path.join(ROOT, src), "rb") as f:
+                m.update(f.read())
+    except (OSError, KeyError, ValueError):
+        return None
+    return rec["bytes"] if m.hexdigest()[:16] == rec["source_hash"] else None
 
 
 def cpu_baseline(w, prev, frac):
