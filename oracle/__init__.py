@@ -57,6 +57,12 @@ class _Cells(C.Structure):
     ]
 
 
+class _Batched(C.Structure):
+    _fields_ = [("n_cells", C.c_int64), ("seed", C.c_uint64), ("level_count", C.c_void_p),
+                ("T_e", C.c_void_p), ("n_e", C.c_void_p), ("gamma_ion", C.c_void_p),
+                ("alpha0", C.c_double * 2)]
+
+
 def lib():
     global _lib
     if _lib is None:
@@ -81,6 +87,10 @@ def lib():
         L.oracle_rate_matrix.argtypes = [C.POINTER(_Atom), C.POINTER(_Cells), C.c_int64, C.c_int32,
                                          C.c_void_p, C.c_void_p]
         L.oracle_gth.argtypes = [C.c_int32, C.c_void_p, C.c_void_p]
+        L.oracle_batched_matrix.argtypes = [C.POINTER(_Batched), C.c_int64, C.c_void_p]
+        L.oracle_batched.restype = C.c_int64
+        L.oracle_batched.argtypes = [C.POINTER(_Batched), C.c_void_p, C.c_int64, C.c_int64,
+                                     C.c_int, C.c_void_p]
         _lib = L
     return _lib
 
@@ -297,3 +307,38 @@ def gth(R):
     pi = np.zeros(len(R))
     lib().oracle_gth(len(R), _p(R), _p(pi))
     return pi
+
+
+class BatchedInputs:
+    """ctypes view of a synth.Batched problem (keeps the arrays alive)."""
+
+    def __init__(self, b):
+        self.k = dict(level_count=np.ascontiguousarray(b.level_count, dtype=np.int32),
+                      T_e=np.ascontiguousarray(b.T_e, dtype=np.float64),
+                      n_e=np.ascontiguousarray(b.n_e, dtype=np.float64),
+                      gamma_ion=np.ascontiguousarray(b.gamma_ion, dtype=np.float64))
+        self.s = _Batched(int(b.n_cells), int(b.seed), _p(self.k["level_count"]),
+                          _p(self.k["T_e"]), _p(self.k["n_e"]), _p(self.k["gamma_ion"]),
+                          (C.c_double * 2)(*[float(a) for a in b.alpha0]))
+        self.pop_offset = np.ascontiguousarray(b.pop_offset, dtype=np.int64)
+        self.n_cells = int(b.n_cells)
+
+
+def batched_matrix(inp: BatchedInputs, c: int):
+    """Dense rate matrix (i -> j, s^-1) of cell c, levels stage-major, ground first."""
+    N = int(inp.pop_offset[c + 1] - inp.pop_offset[c])
+    R = np.zeros((N, N))
+    lib().oracle_batched_matrix(C.byref(inp.s), c, _p(R))
+    return R
+
+
+def batched(inp: BatchedInputs, first=0, count=None, nthreads=None, pops=None):
+    """Stationary populations (sum 1 per cell) of cells [first, first+count),
+    at pop_offset; returns (pops, number of cells with a failed reduction)."""
+    if count is None:
+        count = inp.n_cells - first
+    if pops is None:
+        pops = np.zeros(int(inp.pop_offset[-1]))
+    bad = lib().oracle_batched(C.byref(inp.s), _p(inp.pop_offset), int(first), int(count),
+                               int(nthreads or default_threads()), _p(pops))
+    return pops, int(bad)

@@ -115,4 +115,32 @@ void oracle_rate_matrix(const or_atom* a, const or_cells* cells, int64_t c, int3
 /* GTH stationary vector of a generator given by off-diagonal rates R (row i -> j). */
 void oracle_gth(int32_t N, const double* R, double* pi);
 
+/* ---- Batched NLTE problem (one element, three ion stages per cell) -------
+ * Sec. 2.2 rate model with frozen rates: every bound-bound pair of a stage has
+ * collisions (detailed balance upward), 20 % of pairs are radiative (A and a
+ * photoexcitation rate, photo-de-excitation by detailed balance, beta = 1);
+ * every level of stage z ionises to the ground of z+1; the ground of z+1
+ * recombines into stage z, 1/3 to the ground and 2/3 over the excited levels
+ * by statistical weight. Per-level and per-pair values are drawn from Philox
+ * (key seed, 6) by the definition in batched.c. Levels are numbered cell by
+ * cell, stage by stage, ground first. */
+typedef struct {
+  int64_t n_cells;
+  uint64_t seed;
+  const int32_t* level_count;     /* [C*3], stage 0 >= 1, absent stages last */
+  const double* T_e;              /* [C] */
+  const double* n_e;              /* [C] */
+  const double* gamma_ion;        /* [C*2] */
+  double alpha0[2];
+} or_batched;
+
+/* Dense rate matrix R[i*N+j] (i -> j, s^-1) of cell c, N = levels of the cell. */
+void oracle_batched_matrix(const or_batched* p, int64_t c, double* R);
+
+/* Stationary populations (sum 1) of cells [first, first+count) by GTH on the
+ * dense N x N matrix; pops indexed by the cell's first level pop_offset[c].
+ * Returns the number of cells whose reduction hit a non-positive pivot. */
+int64_t oracle_batched(const or_batched* p, const int64_t* pop_offset, int64_t first,
+                       int64_t count, int nthreads, double* pops);
+
 #endif

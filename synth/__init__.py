@@ -34,6 +34,8 @@ ANGSTROM = 1e-8
 # Seed base: Philox key word 0 = SEED_BASE + workload number; word 1 = stream.
 SEED_BASE = 2511075390
 STREAM_GRID, STREAM_LINES, STREAM_ATOM, STREAM_PACKETS, STREAM_CELLS, STREAM_MLP = range(6)
+# Key word 1 of the per-level and per-pair draws of the batched NLTE problem.
+STREAM_BATCHED = 6
 
 
 def rng(workload: int, stream: int) -> np.random.Generator:
@@ -332,6 +334,68 @@ def clumpy(n: int = 50, n_lines: int = 5000, n_packets: int = 10_000_000, number
 def paper_scale() -> Workload:
     """Transport at the paper's scale: 50^3 cells, 5000 lines, 1e7 packets."""
     return clumpy(50, 5000, 10_000_000, number=2)
+
+
+@dataclasses.dataclass
+class Batched:
+    """Batched NLTE problem: one element with three ion stages per cell.
+
+    Level counts differ from cell to cell; the per-level (g, E) and per-pair
+    (A, collision, photoexcitation) values are not stored. Both sides draw
+    them from Philox4x64-10 with key (seed, STREAM_BATCHED) by the definition
+    each side implements:
+      level i of stage z in cell c: counter (c, z, i, 2^63), uniforms u0..u3
+        g = 1 + floor(9 u0); E = 0 for i = 0, else 69 k T_e(c) u1
+      pair l < u of stage z in cell c: counter (c, z, l, u), uniforms u0..u3
+        radiative iff u0 < 0.2 with A = 10^(-3 + 11 u1) s^-1 and
+        Gamma_PE = 10^(-11 + 6 u3) s^-1; q_down = 10^(-10 + 3 u2) cm^3 s^-1
+    where uniforms are (x >> 11) * 2^-53 of the four 64-bit output words.
+    This module holds only the stored inputs below.
+    """
+    name: str
+    n_cells: int
+    seed: int
+    level_count: np.ndarray   # int32 [C*3] levels of stages 0..2 (stage 0 >= 1; 0 = absent)
+    T_e: np.ndarray           # f64 [C] K
+    n_e: np.ndarray           # f64 [C] cm^-3
+    gamma_ion: np.ndarray     # f64 [C*2] s^-1, any level of stage z -> ground of z+1
+    alpha0: np.ndarray        # f64 [2] cm^3 s^-1 at 1e4 K, recombination into stage z
+
+    @property
+    def pop_offset(self) -> np.ndarray:
+        n = self.level_count.reshape(-1, 3).sum(1).astype(np.int64)
+        return np.concatenate([[0], np.cumsum(n)])
+
+
+def batched(n: int = 50, lo: int = 20, hi: int = 300, number: int = 3,
+            cells: Optional[int] = None) -> Batched:
+    """The batched NLTE solve: cell states (T_e, n_e) of the n^3 clumpy
+    workload, level counts per stage uniform in lo..hi, ionisation rates
+    log-uniform in 1e-7..1e-3 s^-1. `cells` keeps only the first cells."""
+    w = clumpy(n, 1000, 1000, number=2)
+    C = w.n_cells if cells is None else int(cells)
+    g = rng(number, STREAM_CELLS)
+    counts = g.integers(lo, hi + 1, size=(w.n_cells, 3)).astype(np.int32)[:C]
+    gion = _log_uniform(g, 1e-7, 1e-3, (w.n_cells, 2))[:C]
+    return Batched(name=f"batched{n}_L{lo}-{hi}", n_cells=C, seed=SEED_BASE + number,
+                   level_count=counts.ravel().copy(), T_e=w.T_e[:C].copy(),
+                   n_e=w.n_e[:C].copy(), gamma_ion=gion.ravel().copy(),
+                   alpha0=np.array([2.0e-12, 4.0e-12]))
+
+
+def batched_custom(level_count, T_e, n_e, gamma_ion, alpha0=(2.0e-12, 4.0e-12),
+                   seed: int = SEED_BASE + 3) -> Batched:
+    """A batched problem with the given stored inputs (tests: small counts,
+    limits)."""
+    lc = np.asarray(level_count, dtype=np.int32).reshape(-1, 3)
+    C = len(lc)
+    return Batched(name="custom", n_cells=C, seed=int(seed), level_count=lc.ravel().copy(),
+                   T_e=np.broadcast_to(np.asarray(T_e, float), (C,)).copy(),
+                   n_e=np.broadcast_to(np.asarray(n_e, float), (C,)).copy(),
+                   gamma_ion=np.broadcast_to(np.asarray(gamma_ion, float).reshape(-1, 2)
+                                             if np.ndim(gamma_ion) else
+                                             np.full((1, 2), float(gamma_ion)), (C, 2)).ravel().copy(),
+                   alpha0=np.asarray(alpha0, float))
 
 
 def workload_by_name(name: str) -> Workload:
