@@ -257,6 +257,79 @@ int extrass_nlte_warm_start(extrass_handle h, extrass_atom_handle atom, const ex
                             const double* deposition, const float* params, const float* norm,
                             double* pops, void* ws, size_t ws_bytes, void* stream);
 
+/* ---- Batched NLTE solve: one element with three ion stages per cell -------
+ * The ion stages of an element are solved together (Sec. 2.2) under frozen
+ * rates: the linear problem that each fixed-point or Newton step of the
+ * statistical-equilibrium iteration solves. Cells have different level
+ * counts; all cells are solved by one persistent batched factorisation.
+ *
+ * Rate model (per atom, s^-1), with per-level and per-pair values drawn from
+ * Philox4x64-10 under key (seed, 6), uniforms u_k = (x_k >> 11) 2^-53:
+ *   level i of stage z in cell c, counter (c, z, i, 2^63):
+ *     g = 1 + floor(9 u0); E = 0 (ground, i = 0) or 69 k T_e u1
+ *   pair l < u of stage z, counter (c, z, l, u): radiative iff u0 < 0.2, with
+ *     A = 10^(-3 + 11 u1), Gamma_PE = 10^(-11 + 6 u3); q = 10^(-10 + 3 u2)
+ *   upper (higher E; higher index on a tie) -> lower: A + n_e q + (g_l/g_u) Gamma_PE
+ *   lower -> upper: n_e q (g_u/g_l) exp(-(E_u - E_l)/kT) + Gamma_PE
+ *   every level of stage z -> ground of z+1: gamma_ion[c*2 + z]
+ *   ground of z+1 -> level i of z: n_e alpha0[z] (T_e/1e4)^-0.8 x
+ *     (1/3 for the ground; (2/3) g_i / sum of g over the excited levels)
+ * Output: stationary populations, summing to 1 per cell, cell after cell,
+ * stage after stage, ground first: level i of stage z of cell c at
+ * sum_{c'<c} (L0+L1+L2)(c') + sum_{z'<z} L_z'(c) + i.
+ *
+ * Method: stages are coupled only through the next stage's ground state, so
+ * the excited levels of each stage are eliminated in a block of their own
+ * (state reduction with pivots formed as sums of off-diagonal rates,
+ * Grassmann-Taksar-Heyman; blocked, trailing updates on matrix cores), the
+ * ground states form a birth-death chain, and back-substitution recovers the
+ * rest. In exact arithmetic this is the reduction of the full N x N matrix in
+ * an order that skips its structural zeros. */
+typedef struct {
+  int64_t n_cells;
+  uint64_t seed;                 /* Philox key word 0 */
+  const int32_t* level_count;    /* HOST [C*3] levels of stages 0..2; stage 0 >= 1;
+                                    absent stages (0) only after present ones; <= 1023 */
+  const int32_t* level_count_d;  /* device copy of level_count */
+  const double* T_e;             /* device [C] K */
+  const double* n_e;             /* device [C] cm^-3 */
+  const double* gamma_ion;       /* device [C*2] s^-1 */
+  double alpha0[2];              /* cm^3 s^-1 at 1e4 K, recombination into stage z */
+} extrass_batched;
+
+typedef struct {
+  int32_t factor_fp32;  /* 0: FP64 factorisation; 1: FP32 factorisation (FP32 matrix
+                           cores) with FP64 residuals and iterative refinement */
+  int32_t refine;       /* refinement sweeps with factor_fp32 (each: residual, correction) */
+  double tol;           /* status 1 when the last correction exceeds tol relative, componentwise */
+  int32_t panel;        /* panel width 16, 32 or 64; 0 = tuned value (extrass_batched_tune) or 32 */
+  int32_t per_cu;       /* resident work-groups per compute unit; 0 = tuned value or 2 */
+} extrass_batched_opts;
+
+/* Workspace: *min_bytes solves one cell at a time; *all_bytes holds every
+ * cell at once. Any size in between works; cells are then solved in chunks. */
+int extrass_batched_workspace(extrass_handle h, const extrass_batched* p,
+                              const extrass_batched_opts* o, size_t* min_bytes, size_t* all_bytes);
+
+/* pops: device [sum of all level counts] out. status: device [C] out: 0 solved, 1 solved but
+ * the last refinement correction exceeded tol, 2 failed (non-positive pivot or
+ * non-finite result). EINVAL for bad counts or pointers, ENOSPACE for a
+ * workspace below *min_bytes. Stream-ordered; the host waits only for the
+ * upload of the chunk plan. */
+int extrass_batched_solve(extrass_handle h, const extrass_batched* p, const extrass_batched_opts* o,
+                          double* pops, int32_t* status, void* ws, size_t ws_bytes,
+                          hipStream_t stream);
+
+/* Autotuner: times the factorisation of the first cells of p (up to the
+ * workspace's capacity) for every panel width (16, 32, 64) and work-groups per
+ * compute unit (1, 2, 4) in the precision o->factor_fp32, keeps the fastest in
+ * the handle (used when panel/per_cu are 0) and reports it in choice[0..1];
+ * times[9] (optional, host) receives the milliseconds of each candidate, panel-major.
+ * Synchronises the stream. */
+int extrass_batched_tune(extrass_handle h, const extrass_batched* p, const extrass_batched_opts* o,
+                         void* ws, size_t ws_bytes, hipStream_t stream, int32_t* choice,
+                         float* times);
+
 #ifdef __cplusplus
 }
 #endif

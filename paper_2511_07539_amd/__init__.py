@@ -64,6 +64,17 @@ class _Opts(C.Structure):
                 ("factor_fp32", C.c_int32), ("warm_budget", C.c_int32)]
 
 
+class _Batched(C.Structure):
+    _fields_ = [("n_cells", C.c_int64), ("seed", C.c_uint64), ("level_count", C.c_void_p),
+                ("level_count_d", C.c_void_p), ("T_e", C.c_void_p), ("n_e", C.c_void_p),
+                ("gamma_ion", C.c_void_p), ("alpha0", C.c_double * 2)]
+
+
+class _BOpts(C.Structure):
+    _fields_ = [("factor_fp32", C.c_int32), ("refine", C.c_int32), ("tol", C.c_double),
+                ("panel", C.c_int32), ("per_cu", C.c_int32)]
+
+
 _vp = C.c_void_p
 _lib.extrass_create.argtypes = [C.POINTER(_vp), C.c_int]
 _lib.extrass_destroy.argtypes = [_vp]
@@ -92,6 +103,12 @@ _lib.extrass_mlp_train_step.argtypes = [_vp, _vp, _vp, _vp, C.c_int32, C.c_float
                                         C.c_int64, _vp, _vp, _vp, C.c_size_t, _vp]
 _lib.extrass_nlte_warm_start_workspace.restype = C.c_size_t
 _lib.extrass_nlte_warm_start_workspace.argtypes = [C.c_int64]
+_lib.extrass_batched_workspace.argtypes = [_vp, C.POINTER(_Batched), C.POINTER(_BOpts),
+                                           C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]
+_lib.extrass_batched_solve.argtypes = [_vp, C.POINTER(_Batched), C.POINTER(_BOpts), _vp, _vp, _vp,
+                                       C.c_size_t, _vp]
+_lib.extrass_batched_tune.argtypes = [_vp, C.POINTER(_Batched), C.POINTER(_BOpts), _vp, C.c_size_t,
+                                      _vp, _vp, _vp]
 _lib.extrass_nlte_warm_start.argtypes = [_vp, _vp, C.POINTER(_Cells), _vp, _vp, _vp, _vp, _vp,
                                          C.c_size_t, _vp]
 
@@ -100,7 +117,8 @@ SYMBOLS = ["extrass_create", "extrass_destroy", "extrass_error_string", "extrass
            "extrass_rates", "extrass_atom_create", "extrass_atom_destroy",
            "extrass_nlte_workspace", "extrass_nlte_solve", "extrass_mlp_param_count",
            "extrass_mlp_workspace", "extrass_mlp_forward", "extrass_mlp_train_step",
-           "extrass_nlte_warm_start_workspace", "extrass_nlte_warm_start"]
+           "extrass_nlte_warm_start_workspace", "extrass_nlte_warm_start",
+           "extrass_batched_workspace", "extrass_batched_solve", "extrass_batched_tune"]
 
 
 class ExtrassError(RuntimeError):
@@ -384,3 +402,73 @@ def nlte_warm_start(ctx: Context, atom: Atom, cells: Cells, deposition, params, 
                                            _ptr(norm), _ptr(pops), _ptr(ws), ws.numel(),
                                            _stream()), "extrass_nlte_warm_start")
     return pops
+
+
+class Batched:
+    """Device copies of a batched NLTE problem (one element, three ion stages
+    per cell); the level counts are kept on the host as well."""
+
+    def __init__(self, b, device="cuda:0"):
+        self.n_cells = int(b.n_cells)
+        self.seed = int(b.seed)
+        self.level_count = np.ascontiguousarray(b.level_count, dtype=np.int32)
+        self.level_count_d = torch.as_tensor(self.level_count, device=device)
+        self.T_e = _dev(b.T_e, torch.float64, device)
+        self.n_e = _dev(b.n_e, torch.float64, device)
+        self.gamma_ion = _dev(b.gamma_ion, torch.float64, device)
+        self.alpha0 = [float(a) for a in b.alpha0]
+        self.n_pops = int(self.level_count.astype(np.int64).sum())
+        self.device = device
+
+    def struct(self):
+        return _Batched(self.n_cells, self.seed, self.level_count.ctypes.data,
+                        _ptr(self.level_count_d), _ptr(self.T_e), _ptr(self.n_e),
+                        _ptr(self.gamma_ion), (C.c_double * 2)(*self.alpha0))
+
+
+def _bopts(factor_fp32, refine, tol, panel, per_cu):
+    return _BOpts(1 if factor_fp32 else 0, int(refine), float(tol), int(panel), int(per_cu))
+
+
+def batched_workspace(ctx: Context, prob: Batched, factor_fp32=False, panel=0, per_cu=0):
+    """(min_bytes, all_bytes) of extrass_batched_workspace."""
+    mn, al = C.c_size_t(0), C.c_size_t(0)
+    ps = prob.struct()
+    o = _bopts(factor_fp32, 0, 0.0, panel, per_cu)
+    ctx.check(_lib.extrass_batched_workspace(ctx.h, C.byref(ps), C.byref(o), C.byref(mn),
+                                             C.byref(al)), "extrass_batched_workspace")
+    return mn.value, al.value
+
+
+def batched_solve(ctx: Context, prob: Batched, factor_fp32=False, refine=2, tol=1e-12, panel=0,
+                  per_cu=0, ws_limit=16 << 30, pops=None, status=None):
+    """Stationary populations of every cell (extrass_batched_solve); the
+    workspace is the smaller of all cells at once and ws_limit (then chunked)."""
+    dev = prob.device
+    if pops is None:
+        pops = torch.empty(prob.n_pops, dtype=torch.float64, device=dev)
+    if status is None:
+        status = torch.empty(prob.n_cells, dtype=torch.int32, device=dev)
+    mn, al = batched_workspace(ctx, prob, factor_fp32, panel, per_cu)
+    ws = ctx.workspace(max(mn, min(al, ws_limit)))
+    ps = prob.struct()
+    o = _bopts(factor_fp32, refine, tol, panel, per_cu)
+    ctx.check(_lib.extrass_batched_solve(ctx.h, C.byref(ps), C.byref(o), _ptr(pops), _ptr(status),
+                                         _ptr(ws), ws.numel(), _stream()), "extrass_batched_solve")
+    return pops, status
+
+
+def batched_tune(ctx: Context, prob: Batched, factor_fp32=False, ws_limit=2 << 30):
+    """Runs extrass_batched_tune on the first cells of prob; returns
+    ((panel, per_cu), {(panel, per_cu): ms})."""
+    mn, al = batched_workspace(ctx, prob, factor_fp32, 64, 4)
+    ws = ctx.workspace(max(mn, min(al, ws_limit)))
+    ps = prob.struct()
+    o = _bopts(factor_fp32, 0, 0.0, 0, 0)
+    choice = (C.c_int32 * 2)()
+    times = (C.c_float * 9)()
+    ctx.check(_lib.extrass_batched_tune(ctx.h, C.byref(ps), C.byref(o), _ptr(ws), ws.numel(),
+                                        _stream(), choice, times), "extrass_batched_tune")
+    table = {(p, c): times[3 * i + j] for i, p in enumerate((16, 32, 64))
+             for j, c in enumerate((1, 2, 4))}
+    return (choice[0], choice[1]), table

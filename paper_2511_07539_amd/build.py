@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libextrass.so")
-SOURCES = ["atom.hip", "transport.hip", "nlte.hip", "mlp.hip"]
+SOURCES = ["atom.hip", "transport.hip", "nlte.hip", "mlp.hip", "batched.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

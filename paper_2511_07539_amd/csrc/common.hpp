@@ -12,6 +12,10 @@ struct extrass_ctx {
   int device = 0;
   int num_cus = 256;
   std::string last_error;
+  // batched NLTE launch shape per precision (0 FP64, 1 FP32): panel width and
+  // work-groups per compute unit; 0 until tuned
+  int batched_panel[2] = {0, 0};
+  int batched_per_cu[2] = {0, 0};
 };
 
 namespace extrass {
