@@ -117,6 +117,7 @@ enum {
   EXTRASS_STAT_N_CROSS = 6,  /* cell-to-cell crossings */
   EXTRASS_STAT_N_ESCAPED = 7,
   EXTRASS_STAT_N_KILLED = 8,
+  EXTRASS_STAT_QUEUE_FULL = 13,  /* streamed transport: 1.0 if an octant queue overflowed */
   EXTRASS_STAT_BAD_PACKETS = 14, /* 1.0 if some packet id lay beyond the sampling plan
                                     or a packet had no wall ahead (NaN or zero direction);
                                     such packets are dropped */
@@ -157,6 +158,40 @@ int extrass_line_tau(extrass_handle h, extrass_atom_handle atom, int64_t n_cells
 int extrass_rates(extrass_handle h, extrass_atom_handle atom, int64_t n_cells, int32_t n_lines,
                   const double* est, const double* pops, double cell_volume, double* gamma_pe,
                   void* stream);
+
+/* ------------------------------------------------------------------------
+ * Streamed transport over velocity octants (Sec. 2.4 decomposes the grid
+ * into subdomains; here the subdomains are the 8 octants of the cube, visited
+ * one after another on one GPU so that only one octant's estimator table
+ * is resident).
+ *
+ * Runs the packets of the whole sampling plan (first_packet 0, n_packets =
+ * sum of cell_packets; explicit packets are not supported) through the cube,
+ * one octant at a time: an octant's visit emits its own cells' packets (first
+ * visit), resumes the packets queued for it, accumulates into est_octant and
+ * queues every packet that crosses into another octant. Visits repeat in
+ * octant order until no packet is queued (at most 4 rounds: a straight ray
+ * crosses each coordinate plane once). Packets keep their ids, Philox streams
+ * and arithmetic, so the events equal those of extrass_transport.
+ *
+ * After each visit, if atom is not NULL, the visit's estimators are turned
+ * into photoexcitation rates and ADDED to gamma_pe[C*T] (zeroed at the start;
+ * rates are linear in the estimators): gamma_pe[c,t] += est/(n_l V). If
+ * est_global is not NULL ([C*L], tests and small grids), every visit's table
+ * is also added into it at the global cell rows (zeroed at the start).
+ *
+ * n: even. est_octant: device [(n/2)^3 * L] (local cell i + (n/2)(j + (n/2) k)
+ * within the octant, octant o = (i >= n/2) + 2 (j >= n/2) + 4 (k >= n/2)).
+ * queue_capacity: packets each octant's queue holds; the workspace holds 8
+ * queues of 120-byte records. A full queue loses packets: stats[QUEUE_FULL]
+ * is set and the call returns EXTRASS_ENOSPACE. The host waits for the stream
+ * between visits (queue lengths decide the next launch). */
+size_t extrass_transport_streamed_workspace(const extrass_grid* grid, int64_t queue_capacity);
+int extrass_transport_streamed(extrass_handle h, const extrass_grid* grid, const extrass_source* src,
+                               extrass_atom_handle atom, const double* pops, double cell_volume,
+                               double* est_octant, double* est_global, double* gamma_pe,
+                               double* stats, int64_t queue_capacity, void* ws, size_t ws_bytes,
+                               void* stream);
 
 /* ------------------------------------------------------------------------
  * Atom (Sec. 2.2: all ion stages of a species are solved together). HOST

@@ -103,6 +103,11 @@ _lib.extrass_mlp_train_step.argtypes = [_vp, _vp, _vp, _vp, C.c_int32, C.c_float
                                         C.c_int64, _vp, _vp, _vp, C.c_size_t, _vp]
 _lib.extrass_nlte_warm_start_workspace.restype = C.c_size_t
 _lib.extrass_nlte_warm_start_workspace.argtypes = [C.c_int64]
+_lib.extrass_transport_streamed_workspace.restype = C.c_size_t
+_lib.extrass_transport_streamed_workspace.argtypes = [C.POINTER(_Grid), C.c_int64]
+_lib.extrass_transport_streamed.argtypes = [_vp, C.POINTER(_Grid), C.POINTER(_Source), _vp, _vp,
+                                            C.c_double, _vp, _vp, _vp, _vp, C.c_int64, _vp,
+                                            C.c_size_t, _vp]
 _lib.extrass_batched_workspace.argtypes = [_vp, C.POINTER(_Batched), C.POINTER(_BOpts),
                                            C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]
 _lib.extrass_batched_solve.argtypes = [_vp, C.POINTER(_Batched), C.POINTER(_BOpts), _vp, _vp, _vp,
@@ -118,7 +123,8 @@ SYMBOLS = ["extrass_create", "extrass_destroy", "extrass_error_string", "extrass
            "extrass_nlte_workspace", "extrass_nlte_solve", "extrass_mlp_param_count",
            "extrass_mlp_workspace", "extrass_mlp_forward", "extrass_mlp_train_step",
            "extrass_nlte_warm_start_workspace", "extrass_nlte_warm_start",
-           "extrass_batched_workspace", "extrass_batched_solve", "extrass_batched_tune"]
+           "extrass_batched_workspace", "extrass_batched_solve", "extrass_batched_tune",
+           "extrass_transport_streamed_workspace", "extrass_transport_streamed"]
 
 
 class ExtrassError(RuntimeError):
@@ -237,6 +243,37 @@ def transport(ctx: Context, grid: Grid, seed, lambda_lo, lambda_hi, n_packets, f
                                 _ptr(ws), ws.numel(), _stream())
     ctx.check(rc, "extrass_transport")
     return est, stats, pk
+
+
+def transport_streamed(ctx: Context, grid: Grid, seed, lambda_lo, lambda_hi, n_packets,
+                       atom=None, pops=None, cell_volume=None, iteration=0, geometry_fp32=False,
+                       est_octant=None, est_global=False, gamma=None, stats=None,
+                       queue_capacity=None):
+    """Runs extrass_transport_streamed (8 velocity octants, one estimator table
+    of one octant resident). Returns (gamma [C, T] or None, stats [16],
+    est_global [C, L] or None). queue_capacity defaults to n_packets / 4 per
+    octant (at least 4096)."""
+    dev = grid.line_lambda.device
+    g = grid.struct()
+    s = _Source(int(seed), int(iteration), 0, int(n_packets), float(lambda_lo), float(lambda_hi),
+                None, 1 if geometry_fp32 else 0)
+    half = grid.n // 2
+    if est_octant is None:
+        est_octant = torch.empty((half ** 3, grid.n_lines), dtype=torch.float64, device=dev)
+    eg = (torch.empty((grid.n_cells, grid.n_lines), dtype=torch.float64, device=dev)
+          if est_global else None)
+    if stats is None:
+        stats = torch.empty(STATS, dtype=torch.float64, device=dev)
+    if atom is not None and gamma is None:
+        gamma = torch.empty((grid.n_cells, atom.n_trans), dtype=torch.float64, device=dev)
+    qcap = int(queue_capacity) if queue_capacity else max(4096, int(n_packets) // 4)
+    ws = ctx.workspace(_lib.extrass_transport_streamed_workspace(C.byref(g), qcap))
+    rc = _lib.extrass_transport_streamed(
+        ctx.h, C.byref(g), C.byref(s), atom.h if atom is not None else None, _ptr(pops),
+        float(cell_volume or 0.0), _ptr(est_octant), _ptr(eg), _ptr(gamma if atom is not None else None),
+        _ptr(stats), qcap, _ptr(ws), ws.numel(), _stream())
+    ctx.check(rc, "extrass_transport_streamed")
+    return (gamma if atom is not None else None), stats, eg
 
 
 def stats_dict(stats):

@@ -11,11 +11,23 @@
 // Geometry (positions, directions, distances, Doppler coordinate D) runs in
 // the template type G: double for the reference path, float for the fast
 // path. Weights, estimators and the line wavelength arithmetic stay FP64.
+//
+// Octant mode (velocity-space subdomains streamed through HBM): the kernel
+// follows only packets inside one octant of the cube and accumulates into
+// that octant's estimator table. A packet that crosses into another octant
+// is stored, whole, in that octant's queue and continues when the octant is
+// visited. A straight ray crosses each coordinate plane at most once, so it
+// never returns to an octant it has left and visits at most four. Emitted
+// packets keep their global ids and Philox streams, and a stored packet
+// resumes with the same arithmetic, so the split run takes the same events
+// as the unsplit one.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 
+#include "atom.hpp"
 #include "common.hpp"
 #include "philox.hpp"
 
@@ -52,7 +64,25 @@ struct TArgs {
   double* stats;
   double* pk_out;
   unsigned long long* queue;
+  // octant mode (oct >= 0)
+  int oct, half;
+  int lo[3];                 // first cell index of the octant per axis
+  int64_t n_emit;            // packets emitted in this visit (first visit only)
+  const int64_t* ostart;     // [Coct+1] prefix of cell_packets over the octant's cells
+  const struct QPk* inbox;   // packets entering this octant
+  int64_t n_in;
+  struct QPk* qbase;         // 8 queues of qcap records
+  unsigned long long* qtail; // [8]
+  int64_t qcap;
 };
+
+// A packet in flight between octants: the whole state after a wall crossing.
+struct QPk {
+  double x[3], d[3], D, lamL, lam_e, w, w0, wabs;
+  int32_t ci[3], k;
+  int64_t pid;
+};
+static_assert(sizeof(QPk) == 120, "queue record layout");
 
 // ---- small helper kernels -------------------------------------------------
 
@@ -95,6 +125,59 @@ __global__ __launch_bounds__(1024) void k_scan_counts(const int32_t* counts, int
     run += counts[i];
   }
   if (t == 1023) start[C] = part[1023];
+}
+
+// Octant mode: exclusive prefix of cell_packets over the octant's cells in
+// local order (i + half (j + half k)), one workgroup of 1024.
+__global__ __launch_bounds__(1024) void k_scan_octant(const int32_t* counts, int n, int oct,
+                                                      int64_t* ostart) {
+  __shared__ int64_t part[1024];
+  const int half = n / 2;
+  const int64_t Co = (int64_t)half * half * half;
+  const int o0 = (oct & 1) ? half : 0, o1 = (oct & 2) ? half : 0, o2 = (oct & 4) ? half : 0;
+  auto count = [&](int64_t r) {
+    const int i = (int)(r % half), j = (int)((r / half) % half), k = (int)(r / ((int64_t)half * half));
+    return (int64_t)counts[(i + o0) + (int64_t)n * ((j + o1) + (int64_t)n * (k + o2))];
+  };
+  const int t = threadIdx.x;
+  const int64_t chunk = (Co + 1023) / 1024;
+  const int64_t a = t * chunk, b = a + chunk < Co ? a + chunk : Co;
+  int64_t s = 0;
+  for (int64_t i = a; i < b; ++i) s += count(i);
+  part[t] = s;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    int64_t v = t >= off ? part[t - off] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int64_t run = part[t] - s;
+  for (int64_t i = a; i < b; ++i) {
+    ostart[i] = run;
+    run += count(i);
+  }
+  if (t == 1023) ostart[Co] = part[1023];
+}
+
+// est_global[c, :] += est_octant[r, :] for the rows r of one octant.
+__global__ void k_scatter_octant(const double* __restrict__ eo, int n, int oct, int L,
+                                 double* __restrict__ eg) {
+  const int half = n / 2;
+  const int64_t total = (int64_t)half * half * half * L;
+  const int o0 = (oct & 1) ? half : 0, o1 = (oct & 2) ? half : 0, o2 = (oct & 4) ? half : 0;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e / L;
+    const int64_t k = e - r * L;
+    const int i = (int)(r % half), j = (int)((r / half) % half), kk = (int)(r / ((int64_t)half * half));
+    const int64_t c = (i + o0) + (int64_t)n * ((j + o1) + (int64_t)n * (kk + o2));
+    eg[c * L + k] += eo[e];
+  }
+}
+
+__global__ void k_reset_u64(unsigned long long* p, int n) {
+  if ((int)threadIdx.x < n) p[threadIdx.x] = 0ull;
 }
 
 __global__ void k_zero(double* __restrict__ p, int64_t n) {
@@ -200,7 +283,63 @@ struct Tally {
   double w_emit = 0, w_esc = 0, w_kill = 0, w_abs = 0;
   uint64_t inter = 0, checks = 0, cross = 0, escaped = 0, killed = 0;
   bool bad = false;
+  bool overflow = false;
 };
+
+// Octant mode: the idx-th packet emitted in the octant (its cells in local
+// order, each cell's packets in id order) is global packet start[c] + j.
+template <class G>
+__device__ int64_t octant_emit(const TArgs& A, int64_t idx, Packet<G>& q) {
+  const int64_t Co = (int64_t)A.half * A.half * A.half;
+  int64_t lo = 0, hi = Co;
+  while (hi - lo > 1) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (A.ostart[mid] <= idx) lo = mid;
+    else hi = mid;
+  }
+  const int il = (int)(lo % A.half), jl = (int)((lo / A.half) % A.half), kl = (int)(lo / ((int64_t)A.half * A.half));
+  const int64_t c = (il + A.lo[0]) + (int64_t)A.n * ((jl + A.lo[1]) + (int64_t)A.n * (kl + A.lo[2]));
+  const int64_t p = A.start[c] + (idx - A.ostart[lo]);
+  emit<G>(A, p, q);
+  return q.bad ? -1 : p;
+}
+
+template <class G>
+__device__ void store(QPk* r, const Packet<G>& q, int64_t pid) {
+  for (int a = 0; a < 3; ++a) {
+    r->x[a] = (double)q.x[a];
+    r->d[a] = (double)q.d[a];
+    r->ci[a] = q.ci[a];
+  }
+  r->D = (double)q.D;
+  r->lamL = q.lamL;
+  r->lam_e = q.lam_e;
+  r->w = q.w;
+  r->w0 = q.w0;
+  r->wabs = q.wabs;
+  r->k = q.k;
+  r->pid = pid;
+}
+
+// Values stored from G convert back exactly.
+template <class G>
+__device__ int64_t resume(const QPk& r, Packet<G>& q) {
+  for (int a = 0; a < 3; ++a) {
+    q.x[a] = static_cast<G>(r.x[a]);
+    q.d[a] = static_cast<G>(r.d[a]);
+    q.ci[a] = r.ci[a];
+  }
+  q.D = static_cast<G>(r.D);
+  q.lamL = r.lamL;
+  q.lam_e = r.lam_e;
+  q.w = r.w;
+  q.w0 = r.w0;
+  q.wabs = r.wabs;
+  q.k = r.k;
+  q.have_exit = false;
+  q.bad = false;
+  return r.pid;
+}
 
 template <class G>
 __global__ __launch_bounds__(kBlock) void k_transport(TArgs A) {
@@ -233,13 +372,22 @@ __global__ __launch_bounds__(kBlock) void k_transport(TArgs A) {
       const uint64_t take = cnt < pool_left ? cnt : pool_left;
       if (need) {
         if ((uint64_t)rank < take) {
-          pid = A.first + (int64_t)(pool_base + rank);
-          emit<G>(A, pid, q);
-          if (q.bad) {
-            t.bad = true;
-            pid = -1;
+          const int64_t idx = (int64_t)(pool_base + rank);
+          if (A.oct < 0) {
+            pid = A.first + idx;
+            emit<G>(A, pid, q);
+            if (q.bad) {
+              t.bad = true;
+              pid = -1;
+            } else {
+              t.w_emit += q.w0;
+            }
+          } else if (idx < A.n_emit) {
+            pid = octant_emit<G>(A, idx, q);
+            if (pid < 0) t.bad = true;
+            else t.w_emit += q.w0;
           } else {
-            t.w_emit += q.w0;
+            pid = resume<G>(A.inbox[idx - A.n_emit], q);
           }
         } else if (exhausted) {
           done = true;
@@ -272,6 +420,8 @@ __global__ __launch_bounds__(kBlock) void k_transport(TArgs A) {
       }
     }
     const int64_t c = q.ci[0] + (int64_t)A.n * (q.ci[1] + (int64_t)A.n * q.ci[2]);
+    const int64_t row = A.oct < 0 ? c
+        : (q.ci[0] - A.lo[0]) + (int64_t)A.half * ((q.ci[1] - A.lo[1]) + (int64_t)A.half * (q.ci[2] - A.lo[2]));
     bool line_event = false;
     if (q.k < A.L) {
       const G Dk = static_cast<G>(1.0 - q.lamL * A.inv_lam[q.k]);
@@ -292,7 +442,7 @@ __global__ __launch_bounds__(kBlock) void k_transport(TArgs A) {
       if (tau > kTauMin) {
         t.inter++;
         const double dN = q.w * (-expm1(-tau));
-        atomicAdd(A.est + c * A.L + k, dN / fc);
+        atomicAdd(A.est + row * A.L + k, dN / fc);
         q.wabs += dN;
         q.w = q.w * exp(-tau);
         if (q.w * q.lam_e < (kKillFrac * q.w0) * A.lam[k]) {
@@ -334,6 +484,16 @@ __global__ __launch_bounds__(kBlock) void k_transport(TArgs A) {
         stop = true;
       } else {
         t.cross++;
+        if (A.oct >= 0) {
+          const int dst = (q.ci[0] >= A.half) | ((q.ci[1] >= A.half) << 1) | ((q.ci[2] >= A.half) << 2);
+          if (dst != A.oct) {  // hand the packet to its next octant
+            const unsigned long long slot = atomicAdd(A.qtail + dst, 1ull);
+            if ((int64_t)slot < A.qcap) store<G>(A.qbase + (int64_t)dst * A.qcap + (int64_t)slot, q, pid);
+            else t.overflow = true;
+            pid = -1;
+            continue;
+          }
+        }
       }
     }
     if (stop) {
@@ -352,6 +512,8 @@ __global__ __launch_bounds__(kBlock) void k_transport(TArgs A) {
   }
   // packets with an id beyond the sampling plan or a direction with no wall ahead
   if (__ballot(t.bad) != 0ull && lane == 0) A.stats[EXTRASS_STATS - 2] = 1.0;
+  // octant mode: a queue was full and packets were lost
+  if (__ballot(t.overflow) != 0ull && lane == 0) A.stats[EXTRASS_STAT_QUEUE_FULL] = 1.0;
 }
 
 }  // namespace
@@ -451,6 +613,7 @@ extern "C" int extrass_transport(extrass_handle h, const extrass_grid* g, const 
   A.stats = stats;
   A.pk_out = packets_out;
   A.queue = queue;
+  A.oct = -1;
 
   // enough waves to fill every CU several times over, never more than needed
   int64_t blocks = (int64_t)h->num_cus * 8;
@@ -462,5 +625,186 @@ extern "C" int extrass_transport(extrass_handle h, const extrass_grid* g, const 
   else
     hipLaunchKernelGGL(k_transport<double>, dim3((unsigned)blocks), dim3(kBlock), 0, st, A);
   EXTRASS_HIP_TRY(h, hipGetLastError());
+  return EXTRASS_OK;
+}
+
+// ---- streamed transport over velocity octants --------------------------------
+
+namespace {
+struct StreamWs {
+  int64_t* start;
+  double* inv_lam;
+  unsigned long long* counters;  // [0] packet pool, [1..8] queue tails
+  int64_t* ostart;               // 8 x (Co + 1)
+  QPk* queues;                   // 8 x qcap
+  size_t need;
+};
+
+StreamWs stream_layout(const extrass_grid* g, int64_t qcap, void* ws) {
+  const int64_t C = (int64_t)g->n * g->n * g->n;
+  const int64_t half = g->n / 2;
+  const int64_t Co = half * half * half;
+  Carver cv(ws, ~size_t(0));
+  StreamWs w;
+  w.start = cv.take<int64_t>(C + 1);
+  w.inv_lam = cv.take<double>(g->n_lines > 0 ? g->n_lines : 1);
+  w.counters = cv.take<unsigned long long>(16);
+  w.ostart = cv.take<int64_t>(8 * (Co + 1));
+  w.queues = cv.take<QPk>((size_t)(8 * (qcap > 0 ? qcap : 1)));
+  w.need = cv.used + 256;
+  return w;
+}
+
+void zero_doubles(double* p, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  int64_t blocks = (n / 2 + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(256), 0, st, p, n);
+}
+}  // namespace
+
+extern "C" size_t extrass_transport_streamed_workspace(const extrass_grid* g, int64_t queue_capacity) {
+  if (!g || g->n <= 0 || (g->n & 1) || queue_capacity < 0) return 0;
+  return stream_layout(g, queue_capacity, nullptr).need;
+}
+
+extern "C" int extrass_transport_streamed(extrass_handle h, const extrass_grid* g,
+                                          const extrass_source* s, extrass_atom_handle atom,
+                                          const double* pops, double cell_volume, double* est_octant,
+                                          double* est_global, double* gamma_pe, double* stats,
+                                          int64_t queue_capacity, void* ws, size_t ws_bytes,
+                                          void* stream) {
+  if (!h || !g || !s || !est_octant || !stats || !ws)
+    return fail(h, EXTRASS_EINVAL, "extrass_transport_streamed: null argument");
+  if (g->n <= 0 || g->n > 1024 || (g->n & 1) || g->n_lines <= 0 || !(g->beta_max > 0.0) ||
+      !g->line_lambda || !g->line_tau0 || !g->tau_scale || !g->cell_packets || !g->cell_photons)
+    return fail(h, EXTRASS_EINVAL, "extrass_transport_streamed: bad grid (n must be even)");
+  if (g->tau_ct && (!g->line_trans || g->n_trans <= 0))
+    return fail(h, EXTRASS_EINVAL, "extrass_transport_streamed: tau_ct needs line_trans and n_trans");
+  if (s->explicit_packets || s->first_packet != 0 || s->n_packets < 0)
+    return fail(h, EXTRASS_EINVAL, "extrass_transport_streamed: whole sampling plan only");
+  if (atom && (!pops || !gamma_pe || !(cell_volume > 0.0)))
+    return fail(h, EXTRASS_EINVAL, "extrass_transport_streamed: rates need pops, gamma_pe, volume");
+  if (queue_capacity <= 0) return fail(h, EXTRASS_EINVAL, "extrass_transport_streamed: queue capacity");
+  StreamWs w = stream_layout(g, queue_capacity, ws);
+  if (ws_bytes < w.need) return fail(h, EXTRASS_ENOSPACE, "extrass_transport_streamed: workspace too small");
+
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  EXTRASS_HIP_TRY(h, hipSetDevice(h->device));
+  const int n = g->n, half = n / 2, L = g->n_lines;
+  const int64_t C = (int64_t)n * n * n, Co = (int64_t)half * half * half;
+
+  hipLaunchKernelGGL(k_prep, dim3(64), dim3(256), 0, st, g->line_lambda, w.inv_lam, L, stats,
+                     w.counters);
+  if (L > 1) hipLaunchKernelGGL(k_check_sorted, dim3(64), dim3(256), 0, st, g->line_lambda, L, stats);
+  hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, st, g->cell_packets, C, w.start);
+  for (int o = 0; o < 8; ++o)
+    hipLaunchKernelGGL(k_scan_octant, dim3(1), dim3(1024), 0, st, g->cell_packets, n, o,
+                       w.ostart + o * (Co + 1));
+  hipLaunchKernelGGL(k_reset_u64, dim3(1), dim3(64), 0, st, w.counters, 16);
+  if (atom) zero_doubles(gamma_pe, C * (int64_t)atom->T, st);
+  if (est_global) zero_doubles(est_global, C * (int64_t)L, st);
+  EXTRASS_HIP_TRY(h, hipGetLastError());
+
+  // packets each octant emits, and the plan's total
+  int64_t n_emit[8];
+  for (int o = 0; o < 8; ++o)
+    EXTRASS_HIP_TRY(h, hipMemcpyAsync(&n_emit[o], w.ostart + o * (Co + 1) + Co, sizeof(int64_t),
+                                      hipMemcpyDeviceToHost, st));
+  EXTRASS_HIP_TRY(h, hipStreamSynchronize(st));
+  int64_t total = 0;
+  for (int o = 0; o < 8; ++o) total += n_emit[o];
+  if (total != s->n_packets)
+    return fail(h, EXTRASS_EINVAL, "extrass_transport_streamed: n_packets differs from the plan");
+
+  TArgs A{};
+  A.n = n;
+  A.beta = g->beta_max;
+  A.h = 2.0 * g->beta_max / n;
+  A.tau_scale = g->tau_scale;
+  A.cell_photons = g->cell_photons;
+  A.cell_packets = g->cell_packets;
+  A.L = L;
+  A.lam = g->line_lambda;
+  A.inv_lam = w.inv_lam;
+  A.tau0 = g->line_tau0;
+  A.line_trans = g->line_trans;
+  A.T = g->n_trans;
+  A.tau_ct = g->tau_ct;
+  A.fcorr_ct = g->fcorr_ct;
+  A.seed = s->seed;
+  A.iteration = (uint32_t)s->iteration;
+  A.first = 0;
+  A.lam_lo = s->lambda_lo;
+  A.lam_hi = s->lambda_hi;
+  A.explicit_pk = nullptr;
+  A.start = w.start;
+  A.C = C;
+  A.est = est_octant;
+  A.stats = stats;
+  A.pk_out = nullptr;
+  A.queue = w.counters;
+  A.half = half;
+  A.qbase = w.queues;
+  A.qtail = w.counters + 1;
+  A.qcap = queue_capacity;
+
+  int64_t head[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  unsigned long long tail[8];
+  // a ray crosses each coordinate plane at most once: <= 4 octants, <= 4 rounds
+  for (int round = 0; round < 5; ++round) {
+    bool any = false;
+    for (int o = 0; o < 8; ++o) {
+      EXTRASS_HIP_TRY(h, hipMemcpyAsync(tail, w.counters + 1, sizeof(tail), hipMemcpyDeviceToHost, st));
+      EXTRASS_HIP_TRY(h, hipStreamSynchronize(st));
+      const int64_t avail = std::min<int64_t>((int64_t)tail[o], queue_capacity);
+      const int64_t n_in = avail - head[o];
+      const int64_t ne = round == 0 ? n_emit[o] : 0;
+      if (n_in + ne == 0) continue;
+      any = true;
+      zero_doubles(est_octant, Co * (int64_t)L, st);
+      hipLaunchKernelGGL(k_reset_u64, dim3(1), dim3(64), 0, st, w.counters, 1);
+      A.oct = o;
+      A.lo[0] = (o & 1) ? half : 0;
+      A.lo[1] = (o & 2) ? half : 0;
+      A.lo[2] = (o & 4) ? half : 0;
+      A.ostart = w.ostart + o * (Co + 1);
+      A.n_emit = ne;
+      A.inbox = w.queues + (int64_t)o * queue_capacity + head[o];
+      A.n_in = n_in;
+      A.count = ne + n_in;
+      int64_t blocks = (int64_t)h->num_cus * 8;
+      const int64_t max_blocks = (A.count + kBlock - 1) / kBlock;
+      if (blocks > max_blocks) blocks = max_blocks;
+      if (s->geometry_fp32)
+        hipLaunchKernelGGL(k_transport<float>, dim3((unsigned)blocks), dim3(kBlock), 0, st, A);
+      else
+        hipLaunchKernelGGL(k_transport<double>, dim3((unsigned)blocks), dim3(kBlock), 0, st, A);
+      EXTRASS_HIP_TRY(h, hipGetLastError());
+      if (atom) {
+        const int r = rates_add_octant(h, atom, n, o, L, est_octant, pops, cell_volume, gamma_pe, st);
+        if (r) return r;
+      }
+      if (est_global) {
+        const int64_t tot = Co * (int64_t)L;
+        const int64_t blocks2 = std::min<int64_t>((tot + 255) / 256, 65536);
+        hipLaunchKernelGGL(k_scatter_octant, dim3((unsigned)blocks2), dim3(256), 0, st, est_octant,
+                           n, o, L, est_global);
+      }
+      head[o] = avail;
+    }
+    if (!any && round > 0) break;
+  }
+  double full = 0.0;
+  EXTRASS_HIP_TRY(h, hipMemcpyAsync(tail, w.counters + 1, sizeof(tail), hipMemcpyDeviceToHost, st));
+  EXTRASS_HIP_TRY(h, hipMemcpyAsync(&full, stats + EXTRASS_STAT_QUEUE_FULL, sizeof(double),
+                                    hipMemcpyDeviceToHost, st));
+  EXTRASS_HIP_TRY(h, hipStreamSynchronize(st));
+  if (full != 0.0)
+    return fail(h, EXTRASS_ENOSPACE, "extrass_transport_streamed: an octant queue overflowed");
+  for (int o = 0; o < 8; ++o)
+    if ((int64_t)tail[o] != head[o])
+      return fail(h, EXTRASS_EHIP, "extrass_transport_streamed: packets left in a queue");
   return EXTRASS_OK;
 }
