@@ -398,6 +398,11 @@ def batched_custom(level_count, T_e, n_e, gamma_ion, alpha0=(2.0e-12, 4.0e-12),
                    alpha0=np.asarray(alpha0, float))
 
 
+def large() -> Workload:
+    """The streamed case: 100^3 cells, 30000 lines, 1e8 packets, same recipe."""
+    return clumpy(100, 30000, 100_000_000, number=5)
+
+
 def workload_by_name(name: str) -> Workload:
-    table = {"sphere16": sphere_small, "clumpy50": paper_scale}
+    table = {"sphere16": sphere_small, "clumpy50": paper_scale, "clumpy100": large}
     return table[name]()
