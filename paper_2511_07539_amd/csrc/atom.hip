@@ -280,41 +280,6 @@ __global__ void k_rates(int64_t n_cells, int L, int N, int T, const double* __re
   }
 }
 
-__global__ void k_rates_add_octant(int n, int oct, int L, int N, int T, const double* __restrict__ est,
-                                   const double* __restrict__ pops, const int32_t* __restrict__ lo,
-                                   const int32_t* __restrict__ line, double V,
-                                   double* __restrict__ gamma) {
-  const int half = n / 2;
-  const int64_t Co = (int64_t)half * half * half;
-  const int64_t total = Co * T;
-  const int o0 = (oct & 1) ? half : 0, o1 = (oct & 2) ? half : 0, o2 = (oct & 4) ? half : 0;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t r = e / T;
-    const int t = static_cast<int>(e - r * T);
-    const int i = (int)(r % half), j = (int)((r / half) % half), k = (int)(r / ((int64_t)half * half));
-    const int64_t c = (i + o0) + (int64_t)n * ((j + o1) + (int64_t)n * (k + o2));
-    const double Nl = pops[c * N + lo[t]] * V;
-    const double x = est[r * L + line[t]];
-    if (Nl > 0.0) gamma[c * T + t] += x / Nl;
-  }
-}
-
-namespace extrass {
-int rates_add_octant(extrass_handle h, extrass_atom_handle a, int n, int oct, int L,
-                     const double* est, const double* pops, double V, double* gamma, void* stream) {
-  const int64_t half = n / 2;
-  const int64_t total = half * half * half * a->T;
-  if (total == 0) return EXTRASS_OK;
-  const int64_t blocks = std::min<int64_t>((total + 255) / 256, 65536);
-  hipLaunchKernelGGL(k_rates_add_octant, dim3((unsigned)blocks), dim3(256), 0,
-                     static_cast<hipStream_t>(stream), n, oct, L, a->N, a->T, est, pops, a->d.o_lo,
-                     a->d.o_line, V, gamma);
-  EXTRASS_HIP_TRY(h, hipGetLastError());
-  return EXTRASS_OK;
-}
-}  // namespace extrass
-
 extern "C" int extrass_rates(extrass_handle h, extrass_atom_handle a, int64_t n_cells,
                              int32_t n_lines, const double* est, const double* pops,
                              double cell_volume, double* gamma_pe, void* stream) {

@@ -38,9 +38,3 @@ struct extrass_atom_ctx {
   } d;
 };
 
-namespace extrass {
-// gamma[c*T + t] += est[r*L + line_t] / (pops[c*N + lower_t] V) for the rows r of
-// one octant of an n^3 grid (c its global cell). Stream-ordered.
-int rates_add_octant(extrass_handle h, extrass_atom_handle a, int n, int oct, int L,
-                     const double* est, const double* pops, double V, double* gamma, void* stream);
-}  // namespace extrass

@@ -74,6 +74,7 @@ struct TArgs {
   struct QPk* qbase;         // 8 queues of qcap records
   unsigned long long* qtail; // [8]
   int64_t qcap;
+  uint8_t* touched;          // [Coct] rows that received an estimator this visit
 };
 
 // A packet in flight between octants: the whole state after a wall crossing.
@@ -160,20 +161,34 @@ __global__ __launch_bounds__(1024) void k_scan_octant(const int32_t* counts, int
   if (t == 1023) ostart[Co] = part[1023];
 }
 
-// est_global[c, :] += est_octant[r, :] for the rows r of one octant.
-__global__ void k_scatter_octant(const double* __restrict__ eo, int n, int oct, int L,
-                                 double* __restrict__ eg) {
+// After an octant visit, for every row the visit touched: add its rates into
+// gamma (atom lines) and, if asked, the row into the global table; then zero
+// the row, so that the octant table is all zero again for the next visit.
+// One work-group per row; untouched rows return at once.
+__global__ __launch_bounds__(256) void k_octant_flush(double* __restrict__ eo, uint8_t* touched,
+                                                      int n, int oct, int L, int N, int T,
+                                                      const int32_t* __restrict__ lo,
+                                                      const int32_t* __restrict__ line,
+                                                      const double* __restrict__ pops, double V,
+                                                      double* __restrict__ gamma,
+                                                      double* __restrict__ eg) {
+  const int64_t r = blockIdx.x;
+  if (!touched[r]) return;
   const int half = n / 2;
-  const int64_t total = (int64_t)half * half * half * L;
   const int o0 = (oct & 1) ? half : 0, o1 = (oct & 2) ? half : 0, o2 = (oct & 4) ? half : 0;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t r = e / L;
-    const int64_t k = e - r * L;
-    const int i = (int)(r % half), j = (int)((r / half) % half), kk = (int)(r / ((int64_t)half * half));
-    const int64_t c = (i + o0) + (int64_t)n * ((j + o1) + (int64_t)n * (kk + o2));
-    eg[c * L + k] += eo[e];
-  }
+  const int i = (int)(r % half), j = (int)((r / half) % half), k = (int)(r / ((int64_t)half * half));
+  const int64_t c = (i + o0) + (int64_t)n * ((j + o1) + (int64_t)n * (k + o2));
+  double* row = eo + r * L;
+  if (gamma)
+    for (int t = threadIdx.x; t < T; t += blockDim.x) {
+      const double Nl = pops[c * N + lo[t]] * V;
+      if (Nl > 0.0) gamma[c * T + t] += row[line[t]] / Nl;
+    }
+  if (eg)
+    for (int q = threadIdx.x; q < L; q += blockDim.x) eg[c * L + q] += row[q];
+  __syncthreads();
+  for (int q = threadIdx.x; q < L; q += blockDim.x) row[q] = 0.0;
+  if (threadIdx.x == 0) touched[r] = 0;
 }
 
 __global__ void k_reset_u64(unsigned long long* p, int n) {
@@ -443,6 +458,7 @@ __global__ __launch_bounds__(kBlock) void k_transport(TArgs A) {
         t.inter++;
         const double dN = q.w * (-expm1(-tau));
         atomicAdd(A.est + row * A.L + k, dN / fc);
+        if (A.touched) A.touched[row] = 1;
         q.wabs += dN;
         q.w = q.w * exp(-tau);
         if (q.w * q.lam_e < (kKillFrac * q.w0) * A.lam[k]) {
@@ -637,6 +653,7 @@ struct StreamWs {
   unsigned long long* counters;  // [0] packet pool, [1..8] queue tails
   int64_t* ostart;               // 8 x (Co + 1)
   QPk* queues;                   // 8 x qcap
+  uint8_t* touched;              // [Co]
   size_t need;
 };
 
@@ -651,6 +668,7 @@ StreamWs stream_layout(const extrass_grid* g, int64_t qcap, void* ws) {
   w.counters = cv.take<unsigned long long>(16);
   w.ostart = cv.take<int64_t>(8 * (Co + 1));
   w.queues = cv.take<QPk>((size_t)(8 * (qcap > 0 ? qcap : 1)));
+  w.touched = cv.take<uint8_t>(Co);
   w.need = cv.used + 256;
   return w;
 }
@@ -705,6 +723,9 @@ extern "C" int extrass_transport_streamed(extrass_handle h, const extrass_grid* 
   hipLaunchKernelGGL(k_reset_u64, dim3(1), dim3(64), 0, st, w.counters, 16);
   if (atom) zero_doubles(gamma_pe, C * (int64_t)atom->T, st);
   if (est_global) zero_doubles(est_global, C * (int64_t)L, st);
+  // the octant table stays zero between visits (each visit's flush clears its rows)
+  zero_doubles(est_octant, Co * (int64_t)L, st);
+  EXTRASS_HIP_TRY(h, hipMemsetAsync(w.touched, 0, (size_t)Co, st));
   EXTRASS_HIP_TRY(h, hipGetLastError());
 
   // packets each octant emits, and the plan's total
@@ -749,6 +770,7 @@ extern "C" int extrass_transport_streamed(extrass_handle h, const extrass_grid* 
   A.qbase = w.queues;
   A.qtail = w.counters + 1;
   A.qcap = queue_capacity;
+  A.touched = w.touched;
 
   int64_t head[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   unsigned long long tail[8];
@@ -763,7 +785,6 @@ extern "C" int extrass_transport_streamed(extrass_handle h, const extrass_grid* 
       const int64_t ne = round == 0 ? n_emit[o] : 0;
       if (n_in + ne == 0) continue;
       any = true;
-      zero_doubles(est_octant, Co * (int64_t)L, st);
       hipLaunchKernelGGL(k_reset_u64, dim3(1), dim3(64), 0, st, w.counters, 1);
       A.oct = o;
       A.lo[0] = (o & 1) ? half : 0;
@@ -782,16 +803,11 @@ extern "C" int extrass_transport_streamed(extrass_handle h, const extrass_grid* 
       else
         hipLaunchKernelGGL(k_transport<double>, dim3((unsigned)blocks), dim3(kBlock), 0, st, A);
       EXTRASS_HIP_TRY(h, hipGetLastError());
-      if (atom) {
-        const int r = rates_add_octant(h, atom, n, o, L, est_octant, pops, cell_volume, gamma_pe, st);
-        if (r) return r;
-      }
-      if (est_global) {
-        const int64_t tot = Co * (int64_t)L;
-        const int64_t blocks2 = std::min<int64_t>((tot + 255) / 256, 65536);
-        hipLaunchKernelGGL(k_scatter_octant, dim3((unsigned)blocks2), dim3(256), 0, st, est_octant,
-                           n, o, L, est_global);
-      }
+      hipLaunchKernelGGL(k_octant_flush, dim3((unsigned)Co), dim3(256), 0, st, est_octant, w.touched,
+                         n, o, L, atom ? atom->N : 0, atom ? atom->T : 0,
+                         atom ? atom->d.o_lo : nullptr, atom ? atom->d.o_line : nullptr, pops,
+                         cell_volume, atom ? gamma_pe : nullptr, est_global);
+      EXTRASS_HIP_TRY(h, hipGetLastError());
       head[o] = avail;
     }
     if (!any && round > 0) break;
