@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--replicas", type=int, default=8)
     ap.add_argument("--epochs", type=int, default=30)
     ap.add_argument("--warm-budget", type=int, default=30)
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched three-stage NLTE measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device-to-device copy before the step loop, whose "
                          "FETCH_SIZE/WRITE_SIZE counters calibrate the HBM traffic figures")
@@ -207,9 +209,47 @@ def main():
         "ms_parts": parts,
         "roofline": roof,
     }
+    if not args.no_batched:
+        del est, grid, gamma
+        torch.cuda.empty_cache()
+        out["batched_nlte"] = bench_batched(ex, ctx)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, prev.cpu().numpy(), args.cpu_fraction)
     print(json.dumps(out), flush=True)
+
+
+def bench_batched(ex, ctx):
+    """The batched three-stage NLTE problem (125 000 cells, 20-300 levels per
+    stage): tuned launch shape, then one FP64 solve and one FP32-factor solve
+    with two FP64 refinement sweeps, each timed with HIP events on the stream
+    the library launches on. Not part of the step."""
+    import numpy as np
+    import torch
+
+    import synth
+    b = synth.batched()
+    prob = ex.Batched(b)
+    L = b.level_count.reshape(-1, 3).astype(np.float64)
+    flops = float(((2.0 / 3.0) * np.maximum(L - 1, 0) ** 3).sum())  # excited levels eliminated
+    s = torch.cuda.current_stream()
+    res = {"workload": b.name, "cells": b.n_cells, "levels_total": int(b.level_count.sum()),
+           "flops_per_factorisation_pass": flops}
+    for name, f32, refine in (("fp64", False, 0), ("fp32_refine2", True, 2)):
+        shape, table = ex.batched_tune(ctx, prob, factor_fp32=f32)
+        pops, status = ex.batched_solve(ctx, prob, factor_fp32=f32, refine=refine, tol=1e-10)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        pops, status = ex.batched_solve(ctx, prob, factor_fp32=f32, refine=refine, tol=1e-10,
+                                        pops=pops, status=status)
+        e1.record(s)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        st = status.cpu().numpy()
+        res[name] = {"ms": ms, "cell_solves_per_s": b.n_cells / (ms * 1e-3),
+                     "tuned_panel_per_cu": list(shape), "status_counts": np.bincount(st, minlength=3).tolist(),
+                     "achieved_tflops_factor_equivalent": flops / (ms * 1e-3) / 1e12}
+        del pops, status
+    return res
 
 
 def recorded_traffic(key):

@@ -37,4 +37,3 @@ struct extrass_atom_ctx {
     double* o_lam = nullptr;
   } d;
 };
-
