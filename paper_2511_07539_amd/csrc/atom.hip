@@ -104,6 +104,17 @@ extern "C" int extrass_atom_create(extrass_handle h, const extrass_atom_desc* d,
       nst = z + 1;
     }
     lv_stage_count[s] = nst;
+    {
+      int count[3] = {0, 0, 0};
+      for (int i = b; i < e; ++i) ++count[d->level_ion[i]];
+      int lanes = 0;
+      for (int z = 0; z < nst; ++z) {
+        const int B = count[z] + (z + 1 < nst ? 1 : 0);
+        a->maxBlock = std::max(a->maxBlock, B);
+        lanes += B;
+      }
+      a->blockLanes = std::max(a->blockLanes, lanes);
+    }
     int ground[3] = {-1, -1, -1};
     double sumg[3] = {0, 0, 0};
     for (int i = b; i < e; ++i) {

@@ -12,6 +12,10 @@ constexpr int kMaxLevels = 64;  // one wavefront lane per level of a species
 struct extrass_atom_ctx {
   int device = 0;
   int S = 0, N = 0, T = 0, maxNs = 0;
+  // stage blocks of the NLTE reduction (stage z's excited levels, its ground,
+  // the next stage's ground): the largest block, and the most lanes a species'
+  // blocks take side by side
+  int maxBlock = 0, blockLanes = 0;
   std::vector<int> off;   // host copy of species_offset
   std::vector<int> toff;  // host: transitions of species s are [toff[s], toff[s+1])
   struct {

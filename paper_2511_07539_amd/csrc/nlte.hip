@@ -265,6 +265,226 @@ __device__ __forceinline__ bool reduce_solve(const double* G, int NP, int Ns, in
   return ok;
 }
 
+
+// ---- stage-block reduction ---------------------------------------------------
+// A level exchanges population only with the levels of its own ion stage and
+// with the next stage's ground state (ionisation into it, recombination out of
+// it). Block z holds [the excited levels of stage z][the ground of z][the
+// ground of z+1, below the top stage]; the ground rows appear in two blocks,
+// each copy holding the columns of its block. Reducing the excited levels of
+// every block is the state reduction of the whole system in an order that
+// skips only exact zeros. The ground states left form a birth-death chain,
+// solved in closed form with the most populated ground as reference, and
+// back-substitution gives the excited levels. The blocks sit side by side in
+// one wavefront (one block row per lane) and are reduced in lockstep.
+struct Blocks {
+  int nst;
+  int st[4];    // first level (the ground) of each stage; st[z] = Ns for z >= nst
+  int nex[3];   // excited levels of each stage
+  int B[3];     // states of each block
+  int base[4];  // first lane of each block
+};
+
+__device__ __forceinline__ Blocks make_blocks(const Sys& y) {
+  Blocks k;
+  k.nst = y.nst;
+  const bool live = (int)threadIdx.x < y.Ns;
+#pragma unroll
+  for (int z = 0; z < 3; ++z) {
+    const uint64_t m = __ballot(live && y.z == z);
+    k.st[z] = (z < y.nst && m) ? (int)__ffsll((unsigned long long)m) - 1 : y.Ns;
+  }
+  k.st[3] = y.Ns;
+  k.base[0] = 0;
+#pragma unroll
+  for (int z = 0; z < 3; ++z) {
+    const bool has = z < k.nst;
+    k.nex[z] = has ? k.st[z + 1] - k.st[z] - 1 : 0;
+    k.B[z] = has ? k.nex[z] + 1 + (z + 1 < k.nst ? 1 : 0) : 0;
+    k.base[z + 1] = k.base[z] + k.B[z];
+  }
+  return k;
+}
+
+// Level of position p of block z.
+__device__ __forceinline__ int block_level(const Blocks& k, int z, int p) {
+  const int st = z == 0 ? k.st[0] : (z == 1 ? k.st[1] : k.st[2]);
+  const int nx = z == 0 ? k.nex[0] : (z == 1 ? k.nex[1] : k.nex[2]);
+  const int sn = z == 0 ? k.st[1] : (z == 1 ? k.st[2] : k.st[3]);
+  return p < nx ? st + 1 + p : (p == nx ? st : sn);
+}
+
+// Solves x^T Q = b^T (rhs, with x of the ground `pin` fixed at 0) and the
+// stationary problem (pi of the ground `pin` = 1) for the generator whose
+// off-diagonal entries are in G. b_nat: lane = level. Lane l < Ns receives
+// (x_l, pi_l) in out. LDS: scratch >= 304 doubles, xo/po >= 64 doubles each.
+// Returns false when a pivot is not positive.
+template <int NTB>
+__device__ __forceinline__ bool reduce_blocks(const double* G, int NP, int Ns, const Blocks& k,
+                                              bool rhs, double b_nat, int pin, double* scratch,
+                                              double* xo, double* po, double* out) {
+  const int lane = threadIdx.x;
+  double* rows = scratch;          // [3][32]: pivot rows (forward), x-weighted rows (backward)
+  double* piv = scratch + 96;     // [3][32]: pivots
+  double* prow = scratch + 192;   // [3][32]: pi-weighted rows (backward)
+  double* small = scratch + 288;  // reduced rates and right-hand sides of the ground pairs
+  const int z = lane < k.base[1] ? 0 : (lane < k.base[2] ? 1 : 2);
+  const bool live = z < k.nst && lane < k.base[3];
+  const int base = z == 0 ? k.base[0] : (z == 1 ? k.base[1] : k.base[2]);
+  const int r = lane - base;
+  const int nex = live ? (z == 0 ? k.nex[0] : (z == 1 ? k.nex[1] : k.nex[2])) : 0;
+  const int B = live ? (z == 0 ? k.B[0] : (z == 1 ? k.B[1] : k.B[2])) : 0;
+  const int my_lev = live ? block_level(k, z, r) : 0;
+  double g[NTB];
+#pragma unroll
+  for (int b = 0; b < NTB; ++b)
+    g[b] = (live && b < B && b != r) ? G[my_lev * NP + block_level(k, z, b)] : 0.0;
+  // right-hand side: a ground's entry is counted in its own block only
+  double bb = __shfl(b_nat, my_lev, 64);
+  bb = (rhs && live && r <= nex) ? bb : 0.0;
+  double* myrow = rows + 32 * z;
+  bool ok = true;
+  // a block has at most NTB - 1 excited levels (the top stage has no next ground)
+#pragma unroll
+  for (int kk = 0; kk < NTB - 1; ++kk) {
+    double acc[8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) acc[a] = 0.0;
+#pragma unroll
+    for (int b = kk + 1; b < NTB; ++b) acc[(b - kk - 1) & 7] += g[b];
+    const double part = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+    const double S = __shfl(part, base + kk, 64);   // pivot of this lane's block
+    const double bk = __shfl(bb, base + kk, 64);
+    const bool act = live && kk < nex;
+    if (act && r == kk) {
+      piv[32 * z + kk] = S;
+#pragma unroll
+      for (int b = kk + 1; b < NTB; ++b) myrow[b] = g[b];
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (act) {
+      if (!(S > 0.0)) ok = false;
+      const double inv = 1.0 / S;
+      const double f = g[kk] * inv;
+#pragma unroll
+      for (int b0 = kk + 1; b0 < NTB; b0 += 8) {
+#pragma unroll
+        for (int b = b0; b < b0 + 8 && b < NTB; ++b) g[b] += f * myrow[b];
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      if (rhs && r > kk) bb += bk * myrow[r] * inv;
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  // reduced rates between the ground pair of each block: u_z (g_z -> g_z+1)
+  // in the own-ground row, d_z (g_z+1 -> g_z) in the next-ground row
+  double cu = 0.0, cd = 0.0;
+#pragma unroll
+  for (int b = 0; b < NTB; ++b) {
+    cu = (b == nex + 1) ? g[b] : cu;
+    cd = (b == nex) ? g[b] : cd;
+  }
+  if (live && r == nex && B == nex + 2) { small[2 * z] = cu; small[6 + 2 * z] = bb; }
+  if (live && r == nex && B == nex + 1) small[6 + 2 * z] = bb;
+  if (live && r == nex + 1) { small[2 * z + 1] = cd; small[6 + 2 * z + 1] = bb; }
+  __builtin_amdgcn_wave_barrier();
+  // ground-state chain
+  const int K = k.nst;
+  double u[2], d[2], bg[3], pg[3], xg[3];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    u[q] = q + 1 < K ? small[2 * q] : 1.0;
+    d[q] = q + 1 < K ? small[2 * q + 1] : 1.0;
+  }
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    bg[q] = (rhs && q < K) ? small[6 + 2 * q] + (q > 0 ? small[6 + 2 * (q - 1) + 1] : 0.0) : 0.0;
+    pg[q] = 0.0;
+    xg[q] = 0.0;
+  }
+  pg[pin] = 1.0;
+#pragma unroll
+  for (int q = 1; q < 3; ++q)
+    if (q > pin && q < K) pg[q] = pg[q - 1] * u[q - 1] / d[q - 1];
+#pragma unroll
+  for (int q = 1; q >= 0; --q)
+    if (q < pin) pg[q] = pg[q + 1] * d[q] / u[q];
+  if (rhs) {
+    // reduce the chain towards `pin` from both ends; each pivot is the one
+    // remaining rate of its state and carries the right-hand side along
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+      if (q < pin) bg[q + 1] += bg[q];
+#pragma unroll
+    for (int q = 2; q >= 1; --q)
+      if (q > pin && q < K) bg[q - 1] += bg[q];
+#pragma unroll
+    for (int q = 1; q < 3; ++q)
+      if (q > pin && q < K) xg[q] = (xg[q - 1] * u[q - 1] - bg[q]) / d[q - 1];
+#pragma unroll
+    for (int q = 1; q >= 0; --q)
+      if (q < pin) xg[q] = (xg[q + 1] * d[q] - bg[q]) / u[q];
+  }
+  // back-substitution, right-looking: once x_j is known, row j sends
+  // x_j * a[j][c] to the rows c < j of its block; the ground rows first
+  const double gz_x = z == 0 ? xg[0] : (z == 1 ? xg[1] : xg[2]);
+  const double gz_p = z == 0 ? pg[0] : (z == 1 ? pg[1] : pg[2]);
+  const double gn_x = z == 0 ? xg[1] : (z == 1 ? xg[2] : 0.0);
+  const double gn_p = z == 0 ? pg[1] : (z == 1 ? pg[2] : 0.0);
+  double xm = 0.0, pm = 0.0;
+  if (live && r == nex) { xm = gz_x; pm = gz_p; }
+  if (live && r == nex + 1) { xm = gn_x; pm = gn_p; }
+  double tx = 0.0, tp = 0.0;
+  double* xr = rows + 32 * z;
+  double* pr = prow + 32 * z;
+#pragma unroll
+  for (int which = 0; which < 2; ++which) {  // own ground, then next ground
+    const bool send = live && r == nex + which && r < B;
+    if (send) {
+#pragma unroll
+      for (int b = 0; b < NTB; ++b) {
+        xr[b] = xm * g[b];
+        pr[b] = pm * g[b];
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    const bool any = __ballot(send) != 0ull;  // uniform: some block sends
+    if (any && live && r < nex && B > nex + which) {
+      tx += xr[r];
+      tp += pr[r];
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+#pragma unroll
+  for (int kk = NTB - 2; kk >= 0; --kk) {
+    const bool mine = live && r == kk && kk < nex;
+    if (mine) {
+      xm = rhs ? (tx - bb) / piv[32 * z + kk] : 0.0;
+      pm = tp / piv[32 * z + kk];
+#pragma unroll
+      for (int b = 0; b < kk; ++b) {
+        xr[b] = xm * g[b];
+        pr[b] = pm * g[b];
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (live && r < kk && kk < nex) {
+      tx += xr[r];
+      tp += pr[r];
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  // back to level order
+  if (live && r <= nex) {
+    xo[my_lev] = xm;
+    po[my_lev] = pm;
+  }
+  __builtin_amdgcn_wave_barrier();
+  out[0] = lane < Ns ? xo[lane] : 0.0;
+  out[1] = lane < Ns ? po[lane] : 0.0;
+  return __ballot(!ok) == 0ull;
+}
+
 // Solves one (cell, species) system; returns the iteration count, or -1.
 //
 // Written as a loop over phases so that the matrix assembly and the state
@@ -273,7 +493,7 @@ __device__ __forceinline__ bool reduce_solve(const double* G, int NP, int Ns, in
 //  RESID  - fixed-point residual h = P(n)/n - 1 at the current n;
 //  NEWTON - Newton step from the scaled Jacobian with right-hand side Q^T H;
 //  TRIAL  - fixed-point residual at a trial point inside the trust radius.
-template <int NT>
+template <int NT, int NTB>
 __device__ int solve_system(const NArgs& A, const Sys& y, double* G, double* nb, double* hb,
                             double* rowbuf, double& n, int max_iter) {
   enum { FIXED, RESID, NEWTON, TRIAL };
@@ -283,6 +503,8 @@ __device__ int solve_system(const NArgs& A, const Sys& y, double* G, double* nb,
   if (max_iter <= 0) return -1;
   int phase = FIXED, it = 0, bt = 0, best_it = 0;
   double omega = 1.0, prev = INFINITY, Delta = 1.0, best_step = INFINITY;
+  Blocks bl{};
+  if constexpr (NTB > 0) bl = make_blocks(y);
   double h = 0.0, x = 0.0, step = 0.0, taken = 0.0, trial = 0.0, phi = 0.0, res = 0.0;
   for (;;) {
     const bool newton = phase == NEWTON;
@@ -292,15 +514,29 @@ __device__ int solve_system(const NArgs& A, const Sys& y, double* G, double* nb,
     assemble(A, y, G, nb, at, newton, newton ? hb : nullptr, h, newton, rhs);
     int big = last;
     double b_perm = 0.0;
-    if (newton) {
+    bool ok = false, done = false;
+    if constexpr (NTB > 0) {
+      // the most populated ground state is the chain's reference
+      int pin = 0;
+      double best = -1.0;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const double v = __shfl(n, q < y.nst ? bl.st[q] : 0, 64);
+        if (q < y.nst && v > best) {
+          best = v;
+          pin = q;
+        }
+      }
+      ok = reduce_blocks<NTB>(G, A.NP, y.Ns, bl, newton, rhs, pin, rowbuf, nb, hb, xo);
+      done = true;
+    } else if (newton) {
       // most populated level (first one on ties) goes last
       const double nmax = wave_max(live ? n : -1.0);
       const uint64_t bm = __ballot(live && n == nmax);
       big = __ffsll((unsigned long long)bm) - 1;
       b_perm = __shfl(rhs, live ? perm(lane, big, last) : 0, 64);
     }
-    bool ok = false, done = false;
-    if (newton && A.factor_fp32) {
+    if constexpr (NTB == 0) if (newton && A.factor_fp32) {
       // Single-precision Newton step: the matrix is brought to a largest
       // entry of 2^100 so that fluxes spanning ~70 decades below it stay
       // normal in FP32. The residual that judges the step stays FP64, so
@@ -315,7 +551,8 @@ __device__ int solve_system(const NArgs& A, const Sys& y, double* G, double* nb,
                                      reinterpret_cast<float*>(rowbuf), xo);
       ok = done;
     }
-    if (!done) ok = reduce_solve<NT, double>(G, A.NP, y.Ns, big, newton, b_perm, 1.0, rowbuf, xo);
+    if constexpr (NTB == 0)
+      if (!done) ok = reduce_solve<NT, double>(G, A.NP, y.Ns, big, newton, b_perm, 1.0, rowbuf, xo);
     if (!ok) return -1;
     if (phase == FIXED) {
       const double pp = xo[1];
@@ -402,13 +639,15 @@ __device__ double cold_start(const Sys& y, bool live) {
   return live ? y.ntot * (ratio[y.z] / rsum) * (w / ss[y.z]) : 0.0;
 }
 
-template <int NT>
+// NTB > 0: stage-block reduction with blocks of at most NTB states (every
+// species fits); NTB = 0: whole-system reduction with NT >= the largest species.
+template <int NT, int NTB>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_nlte(NArgs A) {
   extern __shared__ double smem[];
   double* nb = smem;            // 64 doubles: populations broadcast
   double* hb = smem + 64;       // 64 doubles: fixed-point residuals broadcast
-  double* rowbuf = smem + 128;  // 64 doubles: pivot row during the reduction
-  double* G = smem + 192;       // maxNs x NP doubles
+  double* rowbuf = smem + 128;  // 320 doubles: reduction scratch (pivot rows, pivots)
+  double* G = smem + 448;       // maxNs x NP doubles
   const int lane = threadIdx.x;
   const int64_t items = A.C * A.S;
   for (;;) {
@@ -452,16 +691,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
       n = cold_start(y, live);  // unusable guess
     int its, code = 0;
     if (A.use_guess && A.warm_budget > 0) {
-      its = solve_system<NT>(A, y, G, nb, hb, rowbuf, n, std::min(A.warm_budget, A.max_iter));
+      its = solve_system<NT, NTB>(A, y, G, nb, hb, rowbuf, n, std::min(A.warm_budget, A.max_iter));
       if (its < 0) {  // fall back to the cold start with the remaining budget
         n = cold_start(y, live);
         const int rest = A.max_iter - std::min(A.warm_budget, A.max_iter);
-        its = solve_system<NT>(A, y, G, nb, hb, rowbuf, n, rest);
+        its = solve_system<NT, NTB>(A, y, G, nb, hb, rowbuf, n, rest);
         code = 1;
         if (its >= 0) its += std::min(A.warm_budget, A.max_iter);
       }
     } else {
-      its = solve_system<NT>(A, y, G, nb, hb, rowbuf, n, A.max_iter);
+      its = solve_system<NT, NTB>(A, y, G, nb, hb, rowbuf, n, A.max_iter);
     }
     if (live) out[lane] = n;
     if (lane == 0) {
@@ -550,26 +789,35 @@ extern "C" int extrass_nlte_solve(extrass_handle h, extrass_atom_handle a, const
   A.iters = iters;
   A.queue = queue;
   A.NP = a->maxNs | 1;
-  const size_t lds = sizeof(double) * (192 + (size_t)a->maxNs * A.NP);
+  const size_t lds = sizeof(double) * (448 + (size_t)a->maxNs * A.NP);
   const int64_t items = cl->n_cells * a->S;
   int per_cu = (int)std::min<size_t>(16, (160 * 1024) / std::max<size_t>(lds, 1));
   if (per_cu < 1) per_cu = 1;
   int64_t blocks = std::min<int64_t>((int64_t)h->num_cus * per_cu, items);
   if (blocks < 1) blocks = 1;
-  // the register-resident reduction is compiled for a few system sizes; the
-  // smallest that holds the largest species is used
-  if (a->maxNs <= 16)
-    hipLaunchKernelGGL(k_nlte<16>, dim3((unsigned)blocks), dim3(64), lds, st, A);
+  // The stage-block reduction serves atoms whose blocks fit (at most 32
+  // states each, side by side in 64 lanes) in FP64; otherwise the
+  // whole-system register reduction, compiled for a few system sizes, the
+  // smallest that holds the largest species.
+  const bool blocks_fit = !o->factor_fp32 && a->maxBlock <= 32 && a->blockLanes <= 64;
+  if (blocks_fit && a->maxBlock <= 16)
+    hipLaunchKernelGGL((k_nlte<0, 16>), dim3((unsigned)blocks), dim3(64), lds, st, A);
+  else if (blocks_fit && a->maxBlock <= 24)
+    hipLaunchKernelGGL((k_nlte<0, 24>), dim3((unsigned)blocks), dim3(64), lds, st, A);
+  else if (blocks_fit)
+    hipLaunchKernelGGL((k_nlte<0, 32>), dim3((unsigned)blocks), dim3(64), lds, st, A);
+  else if (a->maxNs <= 16)
+    hipLaunchKernelGGL((k_nlte<16, 0>), dim3((unsigned)blocks), dim3(64), lds, st, A);
   else if (a->maxNs <= 24)
-    hipLaunchKernelGGL(k_nlte<24>, dim3((unsigned)blocks), dim3(64), lds, st, A);
+    hipLaunchKernelGGL((k_nlte<24, 0>), dim3((unsigned)blocks), dim3(64), lds, st, A);
   else if (a->maxNs <= 32)
-    hipLaunchKernelGGL(k_nlte<32>, dim3((unsigned)blocks), dim3(64), lds, st, A);
+    hipLaunchKernelGGL((k_nlte<32, 0>), dim3((unsigned)blocks), dim3(64), lds, st, A);
   else if (a->maxNs <= 40)
-    hipLaunchKernelGGL(k_nlte<40>, dim3((unsigned)blocks), dim3(64), lds, st, A);
+    hipLaunchKernelGGL((k_nlte<40, 0>), dim3((unsigned)blocks), dim3(64), lds, st, A);
   else if (a->maxNs <= 50)
-    hipLaunchKernelGGL(k_nlte<50>, dim3((unsigned)blocks), dim3(64), lds, st, A);
+    hipLaunchKernelGGL((k_nlte<50, 0>), dim3((unsigned)blocks), dim3(64), lds, st, A);
   else
-    hipLaunchKernelGGL(k_nlte<64>, dim3((unsigned)blocks), dim3(64), lds, st, A);
+    hipLaunchKernelGGL((k_nlte<64, 0>), dim3((unsigned)blocks), dim3(64), lds, st, A);
   EXTRASS_HIP_TRY(h, hipGetLastError());
   return EXTRASS_OK;
 }

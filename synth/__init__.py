@@ -298,7 +298,7 @@ def sphere_small() -> Workload:
 
 
 def clumpy(n: int = 50, n_lines: int = 5000, n_packets: int = 10_000_000, number: int = 2,
-           couple_lines: bool = True) -> Workload:
+           couple_lines: bool = True, ion_levels=(20, 15, 15)) -> Workload:
     """Clumped homologous ejecta on an n^3 cube, v_max 5000 km/s, t = 200 d.
 
     rho ~ |v|^-2 out to the cube corners; clumps with filling factor 0.2
@@ -326,7 +326,7 @@ def clumpy(n: int = 50, n_lines: int = 5000, n_packets: int = 10_000_000, number
     rho = dens * (M_SUN / (dens.sum() * V))
     return _finish(f"clumpy{n}_l{n_lines}_p{n_packets:.0e}".replace("+0", ""), number, n, beta_max,
                    t_exp, rho, 2000.0, 25000.0, n_lines, 1e-4, 1e4, n_packets, 2.5e52,
-                   dict(ion_levels=[20, 15, 15], masses=[16.0, 56.0],
+                   dict(ion_levels=list(ion_levels), masses=[16.0, 56.0],
                         e_max_ev=10.0),
                    (2000.0, 10000.0), couple_lines, [0.7, 0.3])
 
