@@ -73,7 +73,8 @@ struct NArgs {
   int32_t* status;
   int32_t* iters;
   unsigned long long* queue;
-  int NP;  // LDS row stride in doubles
+  int NP;   // LDS row stride in doubles
+  int gsz;  // doubles of LDS holding G
 };
 
 // Everything one system needs, held per wave (uniform values) or per lane.
@@ -212,6 +213,8 @@ __device__ __forceinline__ bool reduce_solve(const double* G, int NP, int Ns, in
 #pragma unroll
   for (int b = 0; b < NT; ++b)
     g[b] = (live && b < Ns && b != lane) ? (T)(scale * G[my_row * NP + perm(b, big, last)]) : T(0);
+  // the pivot-row buffer overlays G: keep every row load ahead of its stores
+  __asm__ volatile("" ::: "memory");
   T b_perm = (T)(scale * b_perm_in);
   T S_mine = T(0);
   bool ok = true;
@@ -339,6 +342,8 @@ __device__ __forceinline__ bool reduce_blocks(const double* G, int NP, int Ns, c
 #pragma unroll
   for (int b = 0; b < NTB; ++b)
     g[b] = (live && b < B && b != r) ? G[my_lev * NP + block_level(k, z, b)] : 0.0;
+  // the scratch below overlays G: keep every row load ahead of its stores
+  __asm__ volatile("" ::: "memory");
   // right-hand side: a ground's entry is counted in its own block only
   double bb = __shfl(b_nat, my_lev, 64);
   bb = (rhs && live && r <= nex) ? bb : 0.0;
@@ -646,8 +651,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
   extern __shared__ double smem[];
   double* nb = smem;            // 64 doubles: populations broadcast
   double* hb = smem + 64;       // 64 doubles: fixed-point residuals broadcast
-  double* rowbuf = smem + 128;  // 320 doubles: reduction scratch (pivot rows, pivots)
-  double* G = smem + 448;       // maxNs x NP doubles
+  double* G = smem + 128;       // maxNs x NP doubles (at least 320)
+  // The stage-block reduction copies its rows out of G into registers before
+  // it writes its scratch (pivot rows, pivots), and G is assembled afresh
+  // before it is read again, so its scratch shares G's space. The
+  // whole-system reduction may redo an FP32 step in FP64 from the same G, so
+  // its 64-double pivot-row buffer follows G.
+  double* rowbuf = NTB > 0 ? G : G + A.gsz;
   const int lane = threadIdx.x;
   const int64_t items = A.C * A.S;
   for (;;) {
@@ -789,7 +799,10 @@ extern "C" int extrass_nlte_solve(extrass_handle h, extrass_atom_handle a, const
   A.iters = iters;
   A.queue = queue;
   A.NP = a->maxNs | 1;
-  const size_t lds = sizeof(double) * (448 + (size_t)a->maxNs * A.NP);
+  A.gsz = a->maxNs * A.NP;
+  const bool blocks_fit = !o->factor_fp32 && a->maxBlock <= 32 && a->blockLanes <= 64;
+  const size_t lds = sizeof(double) * (128 + (blocks_fit ? std::max<size_t>(320, (size_t)A.gsz)
+                                                         : (size_t)A.gsz + 64));
   const int64_t items = cl->n_cells * a->S;
   int per_cu = (int)std::min<size_t>(16, (160 * 1024) / std::max<size_t>(lds, 1));
   if (per_cu < 1) per_cu = 1;
@@ -799,7 +812,6 @@ extern "C" int extrass_nlte_solve(extrass_handle h, extrass_atom_handle a, const
   // states each, side by side in 64 lanes) in FP64; otherwise the
   // whole-system register reduction, compiled for a few system sizes, the
   // smallest that holds the largest species.
-  const bool blocks_fit = !o->factor_fp32 && a->maxBlock <= 32 && a->blockLanes <= 64;
   if (blocks_fit && a->maxBlock <= 16)
     hipLaunchKernelGGL((k_nlte<0, 16>), dim3((unsigned)blocks), dim3(64), lds, st, A);
   else if (blocks_fit && a->maxBlock <= 24)
