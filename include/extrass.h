@@ -237,8 +237,11 @@ typedef struct {
   int32_t use_guess;   /* 1: start from pops on entry (a non-positive entry means
                           the cold start for that system); 0: cold start */
   int32_t factor_fp32; /* 1: Newton systems factored in FP32, residuals in FP64 */
-  int32_t warm_budget; /* with use_guess: iterations allowed from the guess before
-                          the system restarts from the cold start (0: never) */
+  int32_t warm_budget; /* with use_guess: after this many iterations from the guess,
+                          a system still in its fixed-point phase or with a
+                          fixed-point residual above 1e-6 restarts from the cold
+                          start with the iterations left (status 1); so does one
+                          whose line search stalls before. 0: never */
 } extrass_nlte_opts;
 
 /* Statistical equilibrium per cell and species (Sec. 2.2, Eqs. A1-A2):

@@ -299,24 +299,26 @@ __global__ __launch_bounds__(kThreads) void k_factor(Args A) {
         D[r][q] = (double)M[(int64_t)(p0 + r) * B + p0 + q];
       }
       __syncthreads();
-      // (b) reduce the diagonal block
-      for (int i = 0; i < np; ++i) {
-        if (wave == 0) {
+      // (b) reduce the diagonal block in one wavefront: its LDS accesses are
+      // performed in program order, so the steps need no work-group barrier
+      if (wave == 0) {
+        for (int i = 0; i < np; ++i) {
           double s = 0.0;
           for (int q = i + 1 + lane; q < np; q += 64) s += D[i][q];
           s = wave_sum(s) + ts[i];
-          if (lane == 0) Sp[i] = s > 0.0 ? s : NAN;
+          const double Si = s > 0.0 ? s : NAN;
+          if (lane == 0) Sp[i] = Si;
+          const double inv = 1.0 / Si;
+          const int m = np - 1 - i;
+          for (int e = lane; e < m * m; e += 64) {
+            const int k = i + 1 + e / m, q = i + 1 + e % m;
+            if (k != q) D[k][q] += D[k][i] * D[i][q] * inv;
+          }
+          for (int k = i + 1 + lane; k < np; k += 64) ts[k] += D[k][i] * ts[i] * inv;
+          __asm__ volatile("" ::: "memory");  // step i's stores before step i+1's loads
         }
-        __syncthreads();
-        const double inv = 1.0 / Sp[i];
-        const int m = np - 1 - i;
-        for (int e = tid; e < m * m; e += kThreads) {
-          const int k = i + 1 + e / m, q = i + 1 + e % m;
-          if (k != q) D[k][q] += D[k][i] * D[i][q] * inv;
-        }
-        for (int k = i + 1 + tid; k < np; k += kThreads) ts[k] += D[k][i] * ts[i] * inv;
-        __syncthreads();
       }
+      __syncthreads();
       for (int e = tid; e < np * np; e += kThreads) {
         const int r = e / np, q = e - r * np;
         U[r][q] = q > r ? D[r][q] / Sp[r] : (q < r ? D[r][q] / Sp[q] : 0.0);
@@ -522,12 +524,15 @@ __global__ __launch_bounds__(kThreads) void k_forward(Args A) {
   __syncthreads();
   for (int p0 = 0; p0 < ne; p0 += NB) {
     const int np = min(NB, ne - p0), t0 = p0 + np;
-    for (int k = 0; k < np; ++k) {
-      const double f = bs[p0 + k] / S[p0 + k];
-      const int q = p0 + k + 1 + tid;
-      if (q < t0) bs[q] += f * (double)M[(int64_t)(p0 + k) * B + q];
-      __syncthreads();
+    if (tid < 64) {  // in-panel steps in one wavefront (LDS in program order)
+      for (int k = 0; k < np; ++k) {
+        const double f = bs[p0 + k] / S[p0 + k];
+        const int q = p0 + k + 1 + tid;
+        if (q < t0) bs[q] += f * (double)M[(int64_t)(p0 + k) * B + q];
+        __asm__ volatile("" ::: "memory");
+      }
     }
+    __syncthreads();
     for (int j = t0 + tid; j < B; j += kThreads) {
       double acc = bs[j];
       for (int k = 0; k < np; ++k)

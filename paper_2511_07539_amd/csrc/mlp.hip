@@ -143,8 +143,12 @@ __global__ void k_mse(const float* __restrict__ y, const float* __restrict__ t, 
     dy[e] = 2.f * r * inv;
     acc += r * r * inv;
   }
+  // one atomic per block: wavefront sums, then the block's sum in LDS
+  __shared__ float part[4];
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-  if ((threadIdx.x & 63) == 0 && loss) atomicAdd(loss, acc);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0 && loss) atomicAdd(loss, (part[0] + part[1]) + (part[2] + part[3]));
 }
 
 __global__ void k_dsilu(const float* __restrict__ da, const float* __restrict__ z, int64_t n,
@@ -259,9 +263,11 @@ void forward(hipStream_t st, const float* P, const float* x, int64_t B, const Ac
 void backward(hipStream_t st, const float* P, const float* x, const float* t, int64_t B,
               const Acts& a, float* g, float* loss) {
   hipLaunchKernelGGL(k_fill, dim3(blocks_for(kParams)), dim3(256), 0, st, g, kParams, 0.f);
-  hipLaunchKernelGGL(k_mse, dim3(blocks_for(B * kOut)), dim3(256), 0, st, a.y, t, B * kOut,
-                     1.0f / (float)(B * kOut), a.dy, loss);
-  const unsigned ysplit = (unsigned)std::max<int64_t>(1, std::min<int64_t>(B / 256, 64));
+  hipLaunchKernelGGL(k_mse, dim3((unsigned)std::min<int64_t>(blocks_for(B * kOut), 512)), dim3(256),
+                     0, st, a.y, t, B * kOut, 1.0f / (float)(B * kOut), a.dy, loss);
+  // row splits of the column sums and of dW1: enough work-groups to fill the
+  // GPU, 16 rows each (atomics then land on N addresses from B/16 groups)
+  const unsigned ysplit = (unsigned)std::max<int64_t>(1, std::min<int64_t>(B / 16, 1024));
   // output layer: dW4 = dy^T a3, db4 = colsum(dy), da3 = dy W4
   gemm(st, Gemm{kOut, kHid, (int)B, a.dy, 1, kOut, a.a3, kHid, 1, g + kOffW4, kHid, nullptr,
                 nullptr, EPI_ATOMIC, 0});

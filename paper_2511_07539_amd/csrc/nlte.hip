@@ -499,12 +499,14 @@ __device__ __forceinline__ bool reduce_blocks(const double* G, int NP, int Ns, c
 //  NEWTON - Newton step from the scaled Jacobian with right-hand side Q^T H;
 //  TRIAL  - fixed-point residual at a trial point inside the trust radius.
 template <int NT, int NTB>
-__device__ int solve_system(const NArgs& A, const Sys& y, double* G, double* nb, double* hb,
-                            double* rowbuf, double& n, int max_iter) {
+__device__ __forceinline__ int solve_system(const NArgs& A, const Sys& y, double* G, double* nb,
+                                         double* hb,
+                            double* rowbuf, double& n, int max_iter, int check_at, int& used) {
   enum { FIXED, RESID, NEWTON, TRIAL };
   const int lane = threadIdx.x;
   const bool live = lane < y.Ns;
   const int last = y.Ns - 1;
+  used = 0;
   if (max_iter <= 0) return -1;
   int phase = FIXED, it = 0, bt = 0, best_it = 0;
   double omega = 1.0, prev = INFINITY, Delta = 1.0, best_step = INFINITY;
@@ -571,7 +573,8 @@ __device__ int solve_system(const NArgs& A, const Sys& y, double* G, double* nb,
       n = live ? v * (y.ntot / tot) : 0.0;
       ++it;
       if (change < 0.1 || it >= 60) phase = RESID;
-      if (it >= max_iter) return -1;
+      used = it;
+      if (it >= max_iter || (check_at > 0 && it == check_at)) return -1;
       best_it = it;
     } else if (phase == RESID || phase == TRIAL) {
       const double pp = xo[1];
@@ -588,7 +591,10 @@ __device__ int solve_system(const NArgs& A, const Sys& y, double* G, double* nb,
           h = hv;
           if (taken >= 0.99 * Delta) Delta = 2.0 * Delta < 30.0 ? 2.0 * Delta : 30.0;
           ++it;
+          used = it;
           if (it >= max_iter) return -1;
+          // warm-start check: still far from the root after the budget
+          if (check_at > 0 && it == check_at && !(res < 1e-6)) return -1;
           phase = NEWTON;
         } else {
           Delta = (taken < Delta ? taken : Delta) / 4.0;
@@ -699,18 +705,25 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
     double n = A.use_guess ? (live ? out[lane] : 0.0) : cold_start(y, live);
     if (A.use_guess && __ballot(live && !(n > 0.0 && n < INFINITY)) != 0ull)
       n = cold_start(y, live);  // unusable guess
-    int its, code = 0;
-    if (A.use_guess && A.warm_budget > 0) {
-      its = solve_system<NT, NTB>(A, y, G, nb, hb, rowbuf, n, std::min(A.warm_budget, A.max_iter));
-      if (its < 0) {  // fall back to the cold start with the remaining budget
+    // From the guess (or the cold start) with the whole budget. With a warm
+    // budget, a system still in its fixed-point phase or with a fixed-point
+    // residual above 1e-6 after warm_budget iterations, or one whose line
+    // search stalls, restarts once from the cold start with the iterations
+    // left. One call site, so that the solver is compiled once.
+    const bool checked = A.use_guess && A.warm_budget > 0 && A.warm_budget < A.max_iter;
+    int its = -1, code = 0, spent = 0;
+#pragma unroll 1
+    for (int attempt = 0; attempt < 2; ++attempt) {
+      if (attempt == 1) {
+        if (its >= 0 || !checked || spent >= A.max_iter) break;
         n = cold_start(y, live);
-        const int rest = A.max_iter - std::min(A.warm_budget, A.max_iter);
-        its = solve_system<NT, NTB>(A, y, G, nb, hb, rowbuf, n, rest);
         code = 1;
-        if (its >= 0) its += std::min(A.warm_budget, A.max_iter);
       }
-    } else {
-      its = solve_system<NT, NTB>(A, y, G, nb, hb, rowbuf, n, A.max_iter);
+      int used = 0;
+      its = solve_system<NT, NTB>(A, y, G, nb, hb, rowbuf, n, A.max_iter - spent,
+                                  attempt == 0 && checked ? A.warm_budget : 0, used);
+      if (its >= 0) its += spent;
+      spent += used;
     }
     if (live) out[lane] = n;
     if (lane == 0) {

@@ -37,6 +37,13 @@ namespace {
 constexpr double kTauMin = 1e-4;    // lines with tau > 1e-4 interact
 constexpr double kKillFrac = 1e-6;  // stop below 1e-6 of the starting energy
 constexpr int kPool = 256;          // ids taken from the global counter per refill
+// Wavelength lookup bins for the first line above lambda_e: a power of two at
+// least 4 per line, between 1024 and 2^18 (at most 1 MB of table).
+static inline int lam_bins(int L) {
+  int n = 1024;
+  while (n < 4 * L && n < (1 << 18)) n <<= 1;
+  return n;
+}
 constexpr int kBlock = 256;
 
 struct TArgs {
@@ -59,6 +66,11 @@ struct TArgs {
   double lam_lo, lam_hi;
   const double* explicit_pk;
   const int64_t* start;  // [C+1] exclusive prefix of cell_packets
+  const int32_t* lam_bin;   // [nbin] first line above each log-lambda bin edge (lowered)
+  const double* lam_par;    // lambda_0, bins per unit lambda
+  int nbin;
+  const int32_t* chunk_cell;  // [nchunk] cell of packet first + 256 j (sampled mode)
+  int64_t nchunk;
   int64_t C;
   double* est;
   double* stats;
@@ -101,6 +113,48 @@ __global__ void k_check_sorted(const double* lam, int L, double* stats) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   for (int k = t + 1; k < L; k += gridDim.x * blockDim.x)
     if (!(lam[k] >= lam[k - 1])) stats[EXTRASS_STATS - 1] = 1.0;
+}
+
+// Lookup for the first line above a wavelength: bin b of [lambda_0,
+// lambda_{L-1}] (uniform bins) stores the first line above its lower edge,
+// lowered by 1e-9 relative. The search starts one bin below the wavelength's
+// own, so rounding in the bin index or the edge can only start the forward
+// scan early, never late.
+__global__ void k_lambin(const double* lam, int L, int nbin, int32_t* bin, double* par) {
+  const double l0 = L > 0 ? lam[0] : 0.0;
+  const double span = L > 1 ? lam[L - 1] - l0 : 0.0;
+  const double inv = span > 0.0 ? nbin / span : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    par[0] = l0;
+    par[1] = inv;
+  }
+  for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < nbin; b += gridDim.x * blockDim.x) {
+    const double edge = inv > 0.0 ? (l0 + b / inv) * (1.0 - 1e-9) : 0.0;
+    int lo = 0, hi = L;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (lam[mid] > edge) hi = mid;
+      else lo = mid + 1;
+    }
+    bin[b] = lo;
+  }
+}
+
+// Sampled mode: cell of packet first + 256 j, so that a packet's cell search
+// starts from the cells of its 256-id chunk.
+__global__ void k_chunk_cells(const int64_t* start, int64_t C, int64_t first, int64_t nchunk,
+                              int32_t* chunk_cell) {
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < nchunk;
+       j += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t p = first + (j << 8);
+    int64_t lo = 0, hi = C;
+    while (hi - lo > 1) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (start[mid] <= p) lo = mid;
+      else hi = mid;
+    }
+    chunk_cell[j] = (int32_t)lo;
+  }
 }
 
 // Exclusive prefix of cell_packets into start[0..C], one workgroup of 1024.
@@ -222,14 +276,15 @@ __device__ __forceinline__ G wall(const TArgs& A, int i) {
   return static_cast<G>(-A.beta + static_cast<double>(i) * A.h);
 }
 
+// First line with lambda_k > lam: a table lookup one bin below lam's bin,
+// then a forward scan (about one line per bin).
 __device__ __forceinline__ int first_line_above(const TArgs& A, double lam) {
-  int lo = 0, hi = A.L;
-  while (lo < hi) {
-    int mid = (lo + hi) >> 1;
-    if (A.lam[mid] > lam) hi = mid;
-    else lo = mid + 1;
-  }
-  return lo;
+  const double x = (lam - A.lam_par[0]) * A.lam_par[1];
+  int b = x > 0.0 ? (x < (double)A.nbin ? (int)x : A.nbin - 1) : 0;
+  b = b > 0 ? b - 1 : 0;
+  int k = A.lam_bin[b];
+  while (k < A.L && A.lam[k] <= lam) ++k;
+  return k;
 }
 
 template <class G>
@@ -248,7 +303,18 @@ __device__ void emit(const TArgs& A, int64_t p, Packet<G>& q) {
     lam_e = e[6];
     w0 = e[7];
   } else {
+    if (p >= A.start[A.C]) {  // id beyond the sampling plan
+      q.bad = true;
+      return;
+    }
     int64_t lo = 0, hi = A.C;
+    if (A.chunk_cell) {  // the cells of the packet's 256-id chunk bound the search
+      const int64_t jc = (p - A.first) >> 8;
+      if (jc >= 0 && jc < A.nchunk) {
+        lo = A.chunk_cell[jc];
+        hi = jc + 1 < A.nchunk ? (int64_t)A.chunk_cell[jc + 1] + 1 : A.C;
+      }
+    }
     while (hi - lo > 1) {
       int64_t mid = (lo + hi) >> 1;
       if (A.start[mid] <= p) lo = mid;
@@ -257,7 +323,7 @@ __device__ void emit(const TArgs& A, int64_t p, Packet<G>& q) {
     const int64_t c = lo;
     const int64_t j = p - A.start[c];
     const int nc = A.cell_packets[c];
-    if (p >= A.start[A.C] || nc <= 0) {  // id beyond the sampling plan
+    if (nc <= 0) {  // id beyond the sampling plan
       q.bad = true;
       return;
     }
@@ -296,15 +362,14 @@ __device__ void emit(const TArgs& A, int64_t p, Packet<G>& q) {
 
 struct Tally {
   double w_emit = 0, w_esc = 0, w_kill = 0, w_abs = 0;
-  uint64_t inter = 0, checks = 0, cross = 0, escaped = 0, killed = 0;
+  uint32_t inter = 0, checks = 0, cross = 0, escaped = 0, killed = 0;  // per lane
   bool bad = false;
   bool overflow = false;
 };
 
 // Octant mode: the idx-th packet emitted in the octant (its cells in local
 // order, each cell's packets in id order) is global packet start[c] + j.
-template <class G>
-__device__ int64_t octant_emit(const TArgs& A, int64_t idx, Packet<G>& q) {
+__device__ __forceinline__ int64_t octant_packet(const TArgs& A, int64_t idx) {
   const int64_t Co = (int64_t)A.half * A.half * A.half;
   int64_t lo = 0, hi = Co;
   while (hi - lo > 1) {
@@ -314,9 +379,7 @@ __device__ int64_t octant_emit(const TArgs& A, int64_t idx, Packet<G>& q) {
   }
   const int il = (int)(lo % A.half), jl = (int)((lo / A.half) % A.half), kl = (int)(lo / ((int64_t)A.half * A.half));
   const int64_t c = (il + A.lo[0]) + (int64_t)A.n * ((jl + A.lo[1]) + (int64_t)A.n * (kl + A.lo[2]));
-  const int64_t p = A.start[c] + (idx - A.ostart[lo]);
-  emit<G>(A, p, q);
-  return q.bad ? -1 : p;
+  return A.start[c] + (idx - A.ostart[lo]);
 }
 
 template <class G>
@@ -388,21 +451,18 @@ __global__ __launch_bounds__(kBlock) void k_transport(TArgs A) {
       if (need) {
         if ((uint64_t)rank < take) {
           const int64_t idx = (int64_t)(pool_base + rank);
-          if (A.oct < 0) {
-            pid = A.first + idx;
-            emit<G>(A, pid, q);
+          if (A.oct >= 0 && idx >= A.n_emit) {
+            pid = resume<G>(A.inbox[idx - A.n_emit], q);
+          } else {  // one emission site for both modes keeps the register peak down
+            const int64_t p = A.oct < 0 ? A.first + idx : octant_packet(A, idx);
+            emit<G>(A, p, q);
             if (q.bad) {
               t.bad = true;
               pid = -1;
             } else {
+              pid = p;
               t.w_emit += q.w0;
             }
-          } else if (idx < A.n_emit) {
-            pid = octant_emit<G>(A, idx, q);
-            if (pid < 0) t.bad = true;
-            else t.w_emit += q.w0;
-          } else {
-            pid = resume<G>(A.inbox[idx - A.n_emit], q);
           }
         } else if (exhausted) {
           done = true;
@@ -537,26 +597,34 @@ __global__ __launch_bounds__(kBlock) void k_transport(TArgs A) {
 
 using namespace extrass;
 
-static size_t ws_layout(const extrass_grid* g, const extrass_source* s, int64_t** start,
-                        double** inv_lam, unsigned long long** queue, void* ws, size_t* need) {
+struct TransportWs {
+  int64_t* start = nullptr;
+  double* inv_lam = nullptr;
+  unsigned long long* queue = nullptr;
+  int32_t* lam_bin = nullptr;
+  double* lam_par = nullptr;
+  int32_t* chunk_cell = nullptr;
+  int64_t nchunk = 0;
+};
+
+static size_t ws_layout(const extrass_grid* g, const extrass_source* s, TransportWs* w, void* ws) {
   const int64_t C = (int64_t)g->n * g->n * g->n;
   Carver cv(ws, ~size_t(0));
-  int64_t* st = cv.take<int64_t>(C + 1);
-  double* il = cv.take<double>(g->n_lines > 0 ? g->n_lines : 1);
-  unsigned long long* qu = cv.take<unsigned long long>(8);
-  if (start) *start = st;
-  if (inv_lam) *inv_lam = il;
-  if (queue) *queue = qu;
-  *need = cv.used + 256;
-  (void)s;
-  return *need;
+  TransportWs t;
+  t.start = cv.take<int64_t>(C + 1);
+  t.inv_lam = cv.take<double>(g->n_lines > 0 ? g->n_lines : 1);
+  t.queue = cv.take<unsigned long long>(8);
+  t.lam_bin = cv.take<int32_t>(lam_bins(g->n_lines));
+  t.lam_par = cv.take<double>(2);
+  t.nchunk = s->n_packets > 0 ? (s->n_packets + 255) / 256 + 1 : 1;
+  t.chunk_cell = cv.take<int32_t>(t.nchunk);
+  if (w) *w = t;
+  return cv.used + 256;
 }
 
 extern "C" size_t extrass_transport_workspace(const extrass_grid* g, const extrass_source* s) {
-  if (!g || !s || g->n <= 0) return 0;
-  size_t need = 0;
-  ws_layout(g, s, nullptr, nullptr, nullptr, nullptr, &need);
-  return need;
+  if (!g || !s || g->n <= 0 || s->n_packets < 0) return 0;
+  return ws_layout(g, s, nullptr, nullptr);
 }
 
 extern "C" int extrass_transport(extrass_handle h, const extrass_grid* g, const extrass_source* s,
@@ -575,12 +643,12 @@ extern "C" int extrass_transport(extrass_handle h, const extrass_grid* g, const 
     return fail(h, EXTRASS_EINVAL, "extrass_transport: bad packet range");
   if (!s->explicit_packets && (!g->cell_packets || !g->cell_photons))
     return fail(h, EXTRASS_EINVAL, "extrass_transport: sampled mode needs cell_packets/photons");
-  size_t need = 0;
-  int64_t* start = nullptr;
-  double* inv_lam = nullptr;
-  unsigned long long* queue = nullptr;
-  ws_layout(g, s, &start, &inv_lam, &queue, ws, &need);
+  TransportWs tw;
+  const size_t need = ws_layout(g, s, &tw, ws);
   if (ws_bytes < need) return fail(h, EXTRASS_ENOSPACE, "extrass_transport: workspace too small");
+  int64_t* start = tw.start;
+  double* inv_lam = tw.inv_lam;
+  unsigned long long* queue = tw.queue;
 
   hipStream_t st = static_cast<hipStream_t>(stream);
   EXTRASS_HIP_TRY(h, hipSetDevice(h->device));
@@ -589,8 +657,14 @@ extern "C" int extrass_transport(extrass_handle h, const extrass_grid* g, const 
 
   hipLaunchKernelGGL(k_prep, dim3(64), dim3(256), 0, st, g->line_lambda, inv_lam, L, stats, queue);
   if (L > 1) hipLaunchKernelGGL(k_check_sorted, dim3(64), dim3(256), 0, st, g->line_lambda, L, stats);
-  if (!s->explicit_packets)
+  hipLaunchKernelGGL(k_lambin, dim3(64), dim3(256), 0, st, g->line_lambda, L, lam_bins(L),
+                     tw.lam_bin, tw.lam_par);
+  if (!s->explicit_packets) {
     hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, st, g->cell_packets, C, start);
+    const int64_t b2 = std::min<int64_t>((tw.nchunk + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_chunk_cells, dim3((unsigned)std::max<int64_t>(b2, 1)), dim3(256), 0, st,
+                       start, C, s->first_packet, tw.nchunk, tw.chunk_cell);
+  }
   const int64_t n_est = C * (int64_t)L;
   if (n_est > 0) {
     int64_t blocks = (n_est / 2 + 255) / 256;
@@ -624,6 +698,11 @@ extern "C" int extrass_transport(extrass_handle h, const extrass_grid* g, const 
   A.lam_hi = s->lambda_hi;
   A.explicit_pk = s->explicit_packets;
   A.start = start;
+  A.lam_bin = tw.lam_bin;
+  A.lam_par = tw.lam_par;
+  A.nbin = lam_bins(L);
+  A.chunk_cell = s->explicit_packets ? nullptr : tw.chunk_cell;
+  A.nchunk = tw.nchunk;
   A.C = C;
   A.est = est;
   A.stats = stats;
@@ -654,6 +733,8 @@ struct StreamWs {
   int64_t* ostart;               // 8 x (Co + 1)
   QPk* queues;                   // 8 x qcap
   uint8_t* touched;              // [Co]
+  int32_t* lam_bin;              // [lam_bins(L)]
+  double* lam_par;               // [2]
   size_t need;
 };
 
@@ -669,6 +750,8 @@ StreamWs stream_layout(const extrass_grid* g, int64_t qcap, void* ws) {
   w.ostart = cv.take<int64_t>(8 * (Co + 1));
   w.queues = cv.take<QPk>((size_t)(8 * (qcap > 0 ? qcap : 1)));
   w.touched = cv.take<uint8_t>(Co);
+  w.lam_bin = cv.take<int32_t>(lam_bins(g->n_lines));
+  w.lam_par = cv.take<double>(2);
   w.need = cv.used + 256;
   return w;
 }
@@ -717,6 +800,8 @@ extern "C" int extrass_transport_streamed(extrass_handle h, const extrass_grid* 
                      w.counters);
   if (L > 1) hipLaunchKernelGGL(k_check_sorted, dim3(64), dim3(256), 0, st, g->line_lambda, L, stats);
   hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, st, g->cell_packets, C, w.start);
+  hipLaunchKernelGGL(k_lambin, dim3(64), dim3(256), 0, st, g->line_lambda, L, lam_bins(L),
+                     w.lam_bin, w.lam_par);
   for (int o = 0; o < 8; ++o)
     hipLaunchKernelGGL(k_scan_octant, dim3(1), dim3(1024), 0, st, g->cell_packets, n, o,
                        w.ostart + o * (Co + 1));
@@ -761,6 +846,10 @@ extern "C" int extrass_transport_streamed(extrass_handle h, const extrass_grid* 
   A.lam_hi = s->lambda_hi;
   A.explicit_pk = nullptr;
   A.start = w.start;
+  A.lam_bin = w.lam_bin;
+  A.lam_par = w.lam_par;
+  A.nbin = lam_bins(L);
+  A.chunk_cell = nullptr;
   A.C = C;
   A.est = est_octant;
   A.stats = stats;
