@@ -88,6 +88,7 @@ struct Args {
   double* gval;          // [ncell*3] ground-state values (populations or corrections)
   unsigned long long* maxrel;  // [ncell] bits of max |correction / population|
   void* ct;              // panel-column scratch per resident work-group
+  int maxB;              // largest block of the problem (LDS of the assembly)
   int ldct;
   unsigned int* queue;
   double* pops;
@@ -109,11 +110,50 @@ __device__ __forceinline__ int64_t pos_index(const Args& A, int64_t c, int z, in
 }
 
 // ---- assembly -------------------------------------------------------------
+// Rates of the pair of block positions p != q, both directions: v = p -> q,
+// vt = q -> p. Two levels share one Philox draw (keyed by the lower and the
+// higher level index); the next stage's ground pairs with every level through
+// ionisation (level -> next ground) and recombination (next ground -> level).
+__device__ __forceinline__ void pair_rates(const Args& A, int64_t c, int z, int L, int p, int q,
+                                           const double* gs, const double* Es, double kT,
+                                           double ne, double gi, double rec, double gex,
+                                           double& v, double& vt) {
+  const int lp = pos_level(p, L), lq = pos_level(q, L);
+  if (lp >= 0 && lq >= 0) {
+    const int l = min(lp, lq), u = max(lp, lq);
+    const u64x4 r = philox4x64_10((uint64_t)c, (uint64_t)z, (uint64_t)l, (uint64_t)u, A.seed,
+                                  kPhiloxStream);
+    const int up = Es[u] >= Es[l] ? u : l, lo = up == u ? l : u;
+    const bool rad = unit53(r.v[0]) < 0.2;
+    const double Ad = rad ? exp10(-3.0 + 11.0 * unit53(r.v[1])) : 0.0;
+    const double gam = rad ? exp10(-11.0 + 6.0 * unit53(r.v[3])) : 0.0;
+    const double q10 = exp10(-10.0 + 3.0 * unit53(r.v[2]));
+    const double down = Ad + ne * q10 + (gs[lo] / gs[up]) * gam;
+    const double upw = ne * q10 * (gs[up] / gs[lo]) * exp(-(Es[up] - Es[lo]) / kT) + gam;
+    v = lp == up ? down : upw;
+    vt = lp == up ? upw : down;
+  } else {
+    const int lv = lp >= 0 ? lp : lq;  // the level paired with the next ground
+    const double rc = lv == 0 ? rec / 3.0 : rec * (2.0 / 3.0) * gs[lv] / gex;
+    v = lp >= 0 ? gi : rc;
+    vt = lp >= 0 ? rc : gi;
+  }
+}
+
+// One work-group per block. The B x B matrix is walked in 64 x 64 tile pairs
+// (I <= J): each pair of positions is drawn once, the rates p -> q go straight
+// to tile (I, J) and the rates q -> p through LDS, transposed, to tile (J, I),
+// so that both stores are coalesced. Row sums (FP32 mode) are accumulated in
+// LDS in a fixed tile order.
 __global__ __launch_bounds__(kThreads) void k_assemble(Args A, int fp32) {
-  __shared__ double gs[kMaxLevels + 1];
-  __shared__ double Es[kMaxLevels + 1];
-  __shared__ double gex_s;
+  extern __shared__ double sm[];
   const Blk bk = A.blk[blockIdx.x];
+  const int maxB = A.maxB;
+  double* gs = sm;                  // [maxB] statistical weights
+  double* Es = sm + maxB;           // [maxB] level energies
+  double* racc = sm + 2 * maxB;     // [maxB] row sums
+  double* tile = sm + 3 * maxB;     // [64][65] transposed rates of a tile pair
+  double* gex_s = tile + 64 * 65;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t c = A.c0 + bk.cell;
   const int z = bk.z, L = bk.L, B = bk.B;
@@ -124,15 +164,16 @@ __global__ __launch_bounds__(kThreads) void k_assemble(Args A, int fp32) {
     gs[i] = 1.0 + floor(9.0 * unit53(r.v[0]));
     Es[i] = i == 0 ? 0.0 : 69.0 * kT * unit53(r.v[1]);
   }
+  for (int i = tid; i < B; i += kThreads) racc[i] = 0.0;
   __syncthreads();
   if (wave == 0) {
     double s = 0.0;
     for (int i = 1 + lane; i < L; i += 64) s += gs[i];
     s = wave_sum(s);
-    if (lane == 0) gex_s = s;
+    if (lane == 0) *gex_s = s;
   }
   __syncthreads();
-  const double gex = gex_s;
+  const double gex = *gex_s;
   const double rec = ne * (z == 0 ? A.alpha0_0 : A.alpha0_1) * pow(T / 1e4, -0.8);
   const double gi = z < 2 ? A.gion[2 * c + z] : 0.0;
   double* M64 = A.A64 + bk.a;
@@ -150,40 +191,54 @@ __global__ __launch_bounds__(kThreads) void k_assemble(Args A, int fp32) {
     sc = ldexp(1.0, 100 - ilogb(bound));
     if (tid == 0) A.scale[blockIdx.x] = sc;
   }
-  for (int p = wave; p < B; p += 4) {
-    const int lp = pos_level(p, L);
-    double rs = 0.0;
-    for (int q = lane; q < B; q += 64) {
-      const int lq = pos_level(q, L);
-      double v = 0.0;
-      if (p != q) {
-        if (lp >= 0 && lq >= 0) {
-          const int l = min(lp, lq), u = max(lp, lq);
-          const u64x4 r = philox4x64_10((uint64_t)c, (uint64_t)z, (uint64_t)l, (uint64_t)u,
-                                        A.seed, kPhiloxStream);
-          const int up = Es[u] >= Es[l] ? u : l, lo = up == u ? l : u;
-          const bool rad = unit53(r.v[0]) < 0.2;
-          const double Ad = rad ? exp10(-3.0 + 11.0 * unit53(r.v[1])) : 0.0;
-          const double gam = rad ? exp10(-11.0 + 6.0 * unit53(r.v[3])) : 0.0;
-          const double q10 = exp10(-10.0 + 3.0 * unit53(r.v[2]));
-          if (lp == up)
-            v = Ad + ne * q10 + (gs[lo] / gs[up]) * gam;
-          else
-            v = ne * q10 * (gs[up] / gs[lo]) * exp(-(Es[up] - Es[lo]) / kT) + gam;
-        } else if (lq < 0) {
-          v = gi;                                   // ionisation into the next ground
-        } else {
-          v = lq == 0 ? rec / 3.0 : rec * (2.0 / 3.0) * gs[lq] / gex;  // recombination
+  const int nt = (B + 63) >> 6;
+  for (int I = 0; I < nt; ++I)
+    for (int J = I; J < nt; ++J) {
+      const int p0 = 64 * I, q0 = 64 * J;
+      const int q = q0 + lane;
+      // rows p of tile I against columns q of tile J (p < q on the diagonal tile)
+#pragma unroll 1
+      for (int pl = wave; pl < 64; pl += 4) {
+        const int p = p0 + pl;
+        if (p >= B) break;
+        double v = 0.0, vt = 0.0;
+        if (q < B && (I < J || pl < lane))
+          pair_rates(A, c, z, L, p, q, gs, Es, kT, ne, gi, rec, gex, v, vt);
+        if (q < B && (I < J || pl <= lane)) {
+          M64[(int64_t)p * B + q] = v;
+          if (M32) M32[(int64_t)p * B + q] = (float)(v * sc);
+        }
+        tile[lane * 65 + pl] = vt;
+        if (fp32) {
+          const double rs = wave_sum(v);
+          if (lane == 0) racc[p] += rs;
         }
       }
-      M64[(int64_t)p * B + q] = v;
-      if (M32) M32[(int64_t)p * B + q] = (float)(v * sc);
-      rs += v;
+      __syncthreads();
+      // the transposed rates: rows r of tile J, columns of tile I
+#pragma unroll 1
+      for (int rl = wave; rl < 64; rl += 4) {
+        const int rr = q0 + rl, col = p0 + lane;
+        if (rr >= B) break;
+        // on the diagonal tile only the part below the diagonal comes from here
+        const bool mine = col < B && (I < J || lane < rl);
+        const double vt = mine ? tile[rl * 65 + lane] : 0.0;
+        if (mine) {
+          M64[(int64_t)rr * B + col] = vt;
+          if (M32) M32[(int64_t)rr * B + col] = (float)(vt * sc);
+        }
+        if (fp32) {
+          const double rs = wave_sum(vt);
+          if (lane == 0) racc[rr] += rs;
+        }
+      }
+      __syncthreads();
     }
-    rs = wave_sum(rs);
-    if (fp32 && lane == 0) A.rowsum[bk.v + p] = rs;
-  }
+  if (fp32)
+    for (int i = tid; i < B; i += kThreads) A.rowsum[bk.v + i] = racc[i];
 }
+
+size_t assemble_lds(const Args& a) { return sizeof(double) * (3 * (size_t)a.maxB + 64 * 65 + 1); }
 
 // ---- matrix-core trailing update -----------------------------------------
 typedef double d4 __attribute__((ext_vector_type(4)));
@@ -693,6 +748,7 @@ void make_plan(const extrass_batched* p, const Layout& y, size_t ws_bytes, Plan&
       for (int z = 0; z < 3; ++z) {
         if (Lc[z] == 0) continue;
         const int B = block_states(Lc, z);
+        P.maxB = std::max(P.maxB, B);
         Blk b;
         b.a = ch.a_elems;
         b.v = ch.v_elems;
@@ -823,18 +879,18 @@ Args chunk_args(const extrass_batched* p, const Layout& y, const Plan& P, const 
   a.gval = cw.take<double>(3 * (ch.c1 - ch.c0));
   a.maxrel = cw.take<unsigned long long>(ch.c1 - ch.c0);
   a.ct = cv.ct;
+  a.maxB = P.maxB;
   a.ldct = y.ldct;
   a.queue = cv.queue;
   a.pops = pops;
   a.status = status;
-  (void)P;
   return a;
 }
 
 int run_chunk(extrass_handle h, const Layout& y, const Args& a, int refine, double tol,
               hipStream_t s, hipEvent_t f0 = nullptr, hipEvent_t f1 = nullptr) {
   const int nblk = a.nblk, ncell = a.ncell;
-  k_assemble<<<nblk, kThreads, 0, s>>>(a, y.fp32);
+  k_assemble<<<nblk, kThreads, assemble_lds(a), s>>>(a, y.fp32);
   k_zero_queue<<<1, 1, 0, s>>>(a.queue);
   const dim3 grid((unsigned)std::min<int64_t>(y.G, nblk));
   if (f0) EXTRASS_HIP_TRY(h, hipEventRecord(f0, s));
@@ -956,7 +1012,7 @@ extern "C" int extrass_batched_tune(extrass_handle h, const extrass_batched* p,
       const int nblk = a.nblk;
       float ms = 0.0f;
       for (int rep = 0; rep < 2; ++rep) {  // first run warms up
-        k_assemble<<<nblk, kThreads, 0, stream>>>(a, fp32);
+        k_assemble<<<nblk, kThreads, assemble_lds(a), stream>>>(a, fp32);
         k_zero_queue<<<1, 1, 0, stream>>>(a.queue);
         const dim3 grid((unsigned)std::min<int64_t>(y.G, nblk));
         EXTRASS_HIP_TRY(h, hipEventRecord(e0, stream));

@@ -419,8 +419,11 @@ __device__ int64_t resume(const QPk& r, Packet<G>& q) {
   return r.pid;
 }
 
+// Three waves per SIMD: the kernel is bound by the latency of its gathers and
+// scattered atomics, and the third wave (a few dwords of rarely used state
+// spilled) is worth more than the spill.
 template <class G>
-__global__ __launch_bounds__(kBlock) void k_transport(TArgs A) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_transport(TArgs A) {
   const int lane = threadIdx.x & 63;
   Packet<G> q;
   int64_t pid = -1;
