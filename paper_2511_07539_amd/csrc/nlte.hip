@@ -321,17 +321,19 @@ __device__ __forceinline__ int block_level(const Blocks& k, int z, int p) {
 // Solves x^T Q = b^T (rhs, with x of the ground `pin` fixed at 0) and the
 // stationary problem (pi of the ground `pin` = 1) for the generator whose
 // off-diagonal entries are in G. b_nat: lane = level. Lane l < Ns receives
-// (x_l, pi_l) in out. LDS: scratch >= 304 doubles, xo/po >= 64 doubles each.
+// (x_l, pi_l) in out. LDS: scratch >= 216 doubles, xo/po >= 64 doubles each.
 // Returns false when a pivot is not positive.
 template <int NTB>
 __device__ __forceinline__ bool reduce_blocks(const double* G, int NP, int Ns, const Blocks& k,
                                               bool rhs, double b_nat, int pin, double* scratch,
                                               double* xo, double* po, double* out) {
+  static_assert(NTB <= 32, "row slots 32 and 33 carry the pivot and right-hand side");
   const int lane = threadIdx.x;
-  double* rows = scratch;          // [3][32]: pivot rows (forward), x-weighted rows (backward)
-  double* piv = scratch + 96;     // [3][32]: pivots
-  double* prow = scratch + 192;   // [3][32]: pi-weighted rows (backward)
-  double* small = scratch + 288;  // reduced rates and right-hand sides of the ground pairs
+  // [3][34]: pivot rows with the pivot and right-hand side in slots 32, 33
+  // (forward), x-weighted rows (backward)
+  double* rows = scratch;
+  double* prow = scratch + 102;   // [3][34]: pi-weighted rows (backward)
+  double* small = scratch + 204;  // reduced rates and right-hand sides of the ground pairs
   const int z = lane < k.base[1] ? 0 : (lane < k.base[2] ? 1 : 2);
   const bool live = z < k.nst && lane < k.base[3];
   const int base = z == 0 ? k.base[0] : (z == 1 ? k.base[1] : k.base[2]);
@@ -348,29 +350,40 @@ __device__ __forceinline__ bool reduce_blocks(const double* G, int NP, int Ns, c
   // right-hand side: a ground's entry is counted in its own block only
   double bb = __shfl(b_nat, my_lev, 64);
   bb = (rhs && live && r <= nex) ? bb : 0.0;
-  double* myrow = rows + 32 * z;
+  double* myrow = rows + 34 * z;
   bool ok = true;
+  double my_inv = 0.0;  // 1 / pivot of this lane's state, kept for the back-substitution
   // a block has at most NTB - 1 excited levels (the top stage has no next ground)
 #pragma unroll
   for (int kk = 0; kk < NTB - 1; ++kk) {
+    // row sum over the remaining states in 8 partial sums (the first term of
+    // each seeds it: no additions of zero)
     double acc[8];
 #pragma unroll
-    for (int a = 0; a < 8; ++a) acc[a] = 0.0;
+    for (int b = kk + 1; b < NTB; ++b) {
+      const int a = (b - kk - 1) & 7;
+      acc[a] = b - kk - 1 < 8 ? g[b] : acc[a] + g[b];
+    }
+    const int nrem = NTB - kk - 1;
 #pragma unroll
-    for (int b = kk + 1; b < NTB; ++b) acc[(b - kk - 1) & 7] += g[b];
+    for (int a = 0; a < 8; ++a)
+      if (a >= nrem) acc[a] = 0.0;
     const double part = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
-    const double S = __shfl(part, base + kk, 64);   // pivot of this lane's block
-    const double bk = __shfl(bb, base + kk, 64);
     const bool act = live && kk < nex;
+    // the pivot lane of each block publishes its row, its row sum (the pivot)
+    // and its right-hand side
     if (act && r == kk) {
-      piv[32 * z + kk] = S;
 #pragma unroll
       for (int b = kk + 1; b < NTB; ++b) myrow[b] = g[b];
+      myrow[32] = part;
+      myrow[33] = bb;
     }
     __builtin_amdgcn_wave_barrier();
     if (act) {
+      const double S = myrow[32], bk = myrow[33];
       if (!(S > 0.0)) ok = false;
       const double inv = 1.0 / S;
+      if (r == kk) my_inv = inv;
       const double f = g[kk] * inv;
 #pragma unroll
       for (int b0 = kk + 1; b0 < NTB; b0 += 8) {
@@ -378,7 +391,9 @@ __device__ __forceinline__ bool reduce_blocks(const double* G, int NP, int Ns, c
         for (int b = b0; b < b0 + 8 && b < NTB; ++b) g[b] += f * myrow[b];
         __builtin_amdgcn_sched_barrier(0);
       }
-      if (rhs && r > kk) bb += bk * myrow[r] * inv;
+      // every lane reads (no branch around the load); only r > kk keeps it
+      const double mr = myrow[r < NTB ? r : NTB - 1];
+      bb += (rhs && r > kk) ? bk * mr * inv : 0.0;
     }
     __builtin_amdgcn_wave_barrier();
   }
@@ -441,8 +456,8 @@ __device__ __forceinline__ bool reduce_blocks(const double* G, int NP, int Ns, c
   if (live && r == nex) { xm = gz_x; pm = gz_p; }
   if (live && r == nex + 1) { xm = gn_x; pm = gn_p; }
   double tx = 0.0, tp = 0.0;
-  double* xr = rows + 32 * z;
-  double* pr = prow + 32 * z;
+  double* xr = rows + 34 * z;
+  double* pr = prow + 34 * z;
 #pragma unroll
   for (int which = 0; which < 2; ++which) {  // own ground, then next ground
     const bool send = live && r == nex + which && r < B;
@@ -465,8 +480,8 @@ __device__ __forceinline__ bool reduce_blocks(const double* G, int NP, int Ns, c
   for (int kk = NTB - 2; kk >= 0; --kk) {
     const bool mine = live && r == kk && kk < nex;
     if (mine) {
-      xm = rhs ? (tx - bb) / piv[32 * z + kk] : 0.0;
-      pm = tp / piv[32 * z + kk];
+      xm = rhs ? (tx - bb) * my_inv : 0.0;
+      pm = tp * my_inv;
 #pragma unroll
       for (int b = 0; b < kk; ++b) {
         xr[b] = xm * g[b];
