@@ -155,7 +155,6 @@ extern "C" int extrass_atom_create(extrass_handle h, const extrass_atom_desc* d,
   });
   a->toff.assign(S + 1, 0);
   std::vector<int32_t> tl(T), tu(T), tg(T), tline(T), tlo_glob(T);
-  std::vector<double> tA(T), tlam(T), tups(T);
   for (int i = 0; i < T; ++i) {
     int t = order[i];
     int s = species_of(d->trans_lower[t]);
@@ -163,11 +162,24 @@ extern "C" int extrass_atom_create(extrass_handle h, const extrass_atom_desc* d,
     tl[i] = d->trans_lower[t] - a->off[s];
     tu[i] = d->trans_upper[t] - a->off[s];
     tg[i] = t;
-    tA[i] = d->trans_A[t];
-    tlam[i] = d->trans_lambda[t];
-    tups[i] = d->trans_upsilon[t];
   }
   for (int s = 0; s < S; ++s) a->toff[s + 1] += a->toff[s];
+  std::vector<double> tpack(6 * (size_t)T);
+  std::vector<int32_t> tidx(4 * (size_t)T, 0);
+  for (int i = 0; i < T; ++i) {
+    const int t = order[i];
+    const int lo = d->trans_lower[t], up = d->trans_upper[t];
+    const double gl = d->level_g[lo], gu = d->level_g[up], lam = d->trans_lambda[t];
+    tpack[6 * i + 0] = d->trans_A[t] * lam * lam * lam / (8.0 * M_PI);
+    tpack[6 * i + 1] = d->trans_A[t];
+    tpack[6 * i + 2] = gu / gl;
+    tpack[6 * i + 3] = gl / gu;
+    tpack[6 * i + 4] = 8.629e-6 * d->trans_upsilon[t] / gu;
+    tpack[6 * i + 5] = d->level_energy[up] - d->level_energy[lo];
+    tidx[4 * i + 0] = tl[i];
+    tidx[4 * i + 1] = tu[i];
+    tidx[4 * i + 2] = tg[i];
+  }
   for (int s = 0; s < S; ++s) {  // at most one transition per level pair
     const int Ns = a->off[s + 1] - a->off[s];
     seen_pair.assign((size_t)Ns * Ns, 0);
@@ -203,12 +215,8 @@ extern "C" int extrass_atom_create(extrass_handle h, const extrass_atom_desc* d,
   if (e == hipSuccess) e = upload(&a->d.lv_E, lv_E);
   if (e == hipSuccess) e = upload(&a->d.lv_g, lv_g);
   if (e == hipSuccess) e = upload(&a->d.lv_share, lv_share);
-  if (e == hipSuccess) e = upload(&a->d.t_l, tl);
-  if (e == hipSuccess) e = upload(&a->d.t_u, tu);
-  if (e == hipSuccess) e = upload(&a->d.t_glob, tg);
-  if (e == hipSuccess) e = upload(&a->d.t_A, tA);
-  if (e == hipSuccess) e = upload(&a->d.t_lam, tlam);
-  if (e == hipSuccess) e = upload(&a->d.t_ups, tups);
+  if (e == hipSuccess) e = upload(&a->d.t_pack, tpack);
+  if (e == hipSuccess) e = upload(&a->d.t_idx, tidx);
   if (e == hipSuccess) e = upload(&a->d.alpha0, alpha);
   if (e == hipSuccess) e = upload(&a->d.o_lo, olo);
   if (e == hipSuccess) e = upload(&a->d.o_up, oup);
@@ -227,9 +235,8 @@ extern "C" int extrass_atom_create(extrass_handle h, const extrass_atom_desc* d,
 extern "C" int extrass_atom_destroy(extrass_atom_handle a) {
   if (!a) return EXTRASS_OK;
   void* ptrs[] = {a->d.off, a->d.toff, a->d.nstage, a->d.lv_ion, a->d.lv_gnext, a->d.lv_E,
-                  a->d.lv_g, a->d.lv_share, a->d.t_l, a->d.t_u, a->d.t_glob, a->d.t_A,
-                  a->d.t_lam, a->d.t_ups, a->d.alpha0, a->d.o_lo, a->d.o_up, a->d.o_line,
-                  a->d.o_A, a->d.o_lam};
+                  a->d.lv_g, a->d.lv_share, a->d.t_pack, a->d.t_idx, a->d.alpha0, a->d.o_lo,
+                  a->d.o_up, a->d.o_line, a->d.o_A, a->d.o_lam};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete a;

@@ -27,12 +27,11 @@ struct extrass_atom_ctx {
     double* lv_E = nullptr;       // [N]
     double* lv_g = nullptr;       // [N]
     double* lv_share = nullptr;   // [N] share of the recombination flux into the level
-    int32_t* t_l = nullptr;       // [T] grouped by species: local lower level
-    int32_t* t_u = nullptr;       // [T] local upper level
-    int32_t* t_glob = nullptr;    // [T] caller's transition index (gamma_pe column)
-    double* t_A = nullptr;
-    double* t_lam = nullptr;
-    double* t_ups = nullptr;
+    // transitions grouped by species, for the NLTE assembly:
+    // A lambda^3 / (8 pi), A, g_u/g_l, g_l/g_u, 8.629e-6 Upsilon / g_u, E_u - E_l
+    double* t_pack = nullptr;     // [T*6]
+    // local lower level, local upper level, caller's index (gamma_pe column), 0
+    int32_t* t_idx = nullptr;     // [T*4]
     double* alpha0 = nullptr;     // [S*3]
     int32_t* o_lo = nullptr;      // [T] caller's order: global lower level
     int32_t* o_up = nullptr;

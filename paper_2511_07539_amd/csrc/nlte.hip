@@ -53,12 +53,8 @@ struct NArgs {
   const double* lv_E;
   const double* lv_g;
   const double* lv_share;
-  const int32_t* t_l;
-  const int32_t* t_u;
-  const int32_t* t_glob;
-  const double* t_A;
-  const double* t_lam;
-  const double* t_ups;
+  const double* t_pack;   // [T*6] A lambda^3/(8 pi), A, g_u/g_l, g_l/g_u, 8.629e-6 Upsilon/g_u, dE
+  const int32_t* t_idx;   // [T*4] lower, upper (species-local), global index, 0
   const double* alpha0;
   const double* T_e;
   const double* n_e;
@@ -82,7 +78,7 @@ struct NArgs {
 struct Sys {
   int64_t c;
   int s, base, Ns, t0, t1, nst;
-  double T, ne, kT, sqT, ntot;
+  double T, ne, kT, ikT, isqT, ntot;
   double gion[3], rec[3];
   // lane-owned level data
   int z, gnext;
@@ -120,16 +116,18 @@ __device__ __forceinline__ void assemble(const NArgs& A, const Sys& y, double* G
   const double* gpe = A.gamma_pe ? A.gamma_pe + y.c * A.T : nullptr;
 #pragma unroll 1
   for (int t = y.t0 + lane; t < y.t1; t += 64) {
-    const int l = A.t_l[t], u = A.t_u[t];
-    const double gl = A.lv_g[y.base + l], gu = A.lv_g[y.base + u];
-    const double Ad = A.t_A[t], lam = A.t_lam[t];
-    const double qul = 8.629e-6 * A.t_ups[t] / (gu * y.sqT);
-    const double qlu = qul * (gu / gl) * exp(-(A.lv_E[y.base + u] - A.lv_E[y.base + l]) / y.kT);
+    const int4 ix = reinterpret_cast<const int4*>(A.t_idx)[t];
+    const int l = ix.x, u = ix.y;
+    const double2 p01 = reinterpret_cast<const double2*>(A.t_pack)[3 * t];
+    const double2 p23 = reinterpret_cast<const double2*>(A.t_pack)[3 * t + 1];
+    const double2 p45 = reinterpret_cast<const double2*>(A.t_pack)[3 * t + 2];
+    const double Ad = p01.y, gul = p23.x, glu = p23.y;
+    const double qul = p45.x * y.isqT;
+    const double qlu = qul * gul * exp(-p45.y * y.ikT);
     const double nl = nb[l], nu = nb[u];
-    const double K = Ad * lam * lam * lam * A.t_exp / (8.0 * M_PI);
-    const double tau = K * ((gu / gl) * nl - nu);
-    const double p = gpe ? gpe[A.t_glob[t]] : 0.0;
-    const double down = Ad * beta_sobolev(tau) + y.ne * qul + (gl / gu) * p;
+    const double tau = (p01.x * A.t_exp) * (gul * nl - nu);
+    const double p = gpe ? gpe[ix.z] : 0.0;
+    const double down = Ad * beta_sobolev(tau) + y.ne * qul + glu * p;
     const double up = y.ne * qlu + p;
     G[u * NP + l] = (rowscale ? nu : 1.0) * down;
     G[l * NP + u] = (rowscale ? nl : 1.0) * up;
@@ -156,16 +154,18 @@ __device__ __forceinline__ void assemble(const NArgs& A, const Sys& y, double* G
     __syncthreads();
 #pragma unroll 1
     for (int t = y.t0 + lane; t < y.t1; t += 64) {
-      const int l = A.t_l[t], u = A.t_u[t];
-      const double gl = A.lv_g[y.base + l], gu = A.lv_g[y.base + u];
-      const double Ad = A.t_A[t], lam = A.t_lam[t];
+      const int4 ix = reinterpret_cast<const int4*>(A.t_idx)[t];
+      const int l = ix.x, u = ix.y;
+      const double2 p01 = reinterpret_cast<const double2*>(A.t_pack)[3 * t];
+      const double gul = A.t_pack[6 * t + 2];
+      const double Ad = p01.y;
       const double nl = nb[l], nu = nb[u];
-      const double K = Ad * lam * lam * lam * A.t_exp / (8.0 * M_PI);
-      const double tau = K * ((gu / gl) * nl - nu);
+      const double K = p01.x * A.t_exp;
+      const double tau = K * (gul * nl - nu);
       const double db = dbeta_sobolev(tau);
       if (db != 0.0) {
         const double du = -nu * Ad * db * K;
-        const double dl = nu * Ad * db * K * (gu / gl);
+        const double dl = nu * Ad * db * K * gul;
         G[u * NP + l] += du * nu;
         G[l * NP + u] += -dl * nl;
       }
@@ -281,6 +281,12 @@ __device__ __forceinline__ bool reduce_solve(const double* G, int NP, int Ns, in
 // solved in closed form with the most populated ground as reference, and
 // back-substitution gives the excited levels. The blocks sit side by side in
 // one wavefront (one block row per lane) and are reduced in lockstep.
+// LDS of the stage-block reduction (doubles, in the space of the assembled
+// matrix): pivot rows and the ground-pair values, then the eliminated rows
+// [64][NTB + 1] and the published (x, pi) [64][2].
+constexpr int kBlockScratch = 114;
+constexpr int block_scratch(int ntb) { return kBlockScratch + 64 * (ntb + 1) + 128; }
+
 struct Blocks {
   int nst;
   int st[4];    // first level (the ground) of each stage; st[z] = Ns for z >= nst
@@ -321,7 +327,8 @@ __device__ __forceinline__ int block_level(const Blocks& k, int z, int p) {
 // Solves x^T Q = b^T (rhs, with x of the ground `pin` fixed at 0) and the
 // stationary problem (pi of the ground `pin` = 1) for the generator whose
 // off-diagonal entries are in G. b_nat: lane = level. Lane l < Ns receives
-// (x_l, pi_l) in out. LDS: scratch >= 216 doubles, xo/po >= 64 doubles each.
+// (x_l, pi_l) in out. LDS: scratch >= block_scratch(NTB) doubles (16-byte
+// aligned), xo/po >= 64 doubles each.
 // Returns false when a pivot is not positive.
 template <int NTB>
 __device__ __forceinline__ bool reduce_blocks(const double* G, int NP, int Ns, const Blocks& k,
@@ -330,10 +337,8 @@ __device__ __forceinline__ bool reduce_blocks(const double* G, int NP, int Ns, c
   static_assert(NTB <= 32, "row slots 32 and 33 carry the pivot and right-hand side");
   const int lane = threadIdx.x;
   // [3][34]: pivot rows with the pivot and right-hand side in slots 32, 33
-  // (forward), x-weighted rows (backward)
   double* rows = scratch;
-  double* prow = scratch + 102;   // [3][34]: pi-weighted rows (backward)
-  double* small = scratch + 204;  // reduced rates and right-hand sides of the ground pairs
+  double* small = scratch + 102;  // reduced rates and right-hand sides of the ground pairs
   const int z = lane < k.base[1] ? 0 : (lane < k.base[2] ? 1 : 2);
   const bool live = z < k.nst && lane < k.base[3];
   const int base = z == 0 ? k.base[0] : (z == 1 ? k.base[1] : k.base[2]);
@@ -446,8 +451,10 @@ __device__ __forceinline__ bool reduce_blocks(const double* G, int NP, int Ns, c
     for (int q = 1; q >= 0; --q)
       if (q < pin) xg[q] = (xg[q + 1] * d[q] - bg[q]) / u[q];
   }
-  // back-substitution, right-looking: once x_j is known, row j sends
-  // x_j * a[j][c] to the rows c < j of its block; the ground rows first
+  // back-substitution: every eliminated row goes to LDS once (G is no longer
+  // needed); then, state by state in reverse elimination order, the state's
+  // (x, pi) is published and the rows c < j of its block add x_j * a[j][c];
+  // the ground rows first
   const double gz_x = z == 0 ? xg[0] : (z == 1 ? xg[1] : xg[2]);
   const double gz_p = z == 0 ? pg[0] : (z == 1 ? pg[1] : pg[2]);
   const double gn_x = z == 0 ? xg[1] : (z == 1 ? xg[2] : 0.0);
@@ -455,43 +462,44 @@ __device__ __forceinline__ bool reduce_blocks(const double* G, int NP, int Ns, c
   double xm = 0.0, pm = 0.0;
   if (live && r == nex) { xm = gz_x; pm = gz_p; }
   if (live && r == nex + 1) { xm = gn_x; pm = gn_p; }
-  double tx = 0.0, tp = 0.0;
-  double* xr = rows + 34 * z;
-  double* pr = prow + 34 * z;
+  constexpr int LDW = NTB + 1;
+  double* Ld = scratch + kBlockScratch;   // [64][LDW] eliminated rows, by lane
+  double2* pv = reinterpret_cast<double2*>(Ld + 64 * LDW);  // [64] (x, pi) by lane
+  if (live) {
 #pragma unroll
-  for (int which = 0; which < 2; ++which) {  // own ground, then next ground
-    const bool send = live && r == nex + which && r < B;
-    if (send) {
-#pragma unroll
-      for (int b = 0; b < NTB; ++b) {
-        xr[b] = xm * g[b];
-        pr[b] = pm * g[b];
-      }
-    }
-    __builtin_amdgcn_wave_barrier();
-    const bool any = __ballot(send) != 0ull;  // uniform: some block sends
-    if (any && live && r < nex && B > nex + which) {
-      tx += xr[r];
-      tp += pr[r];
-    }
-    __builtin_amdgcn_wave_barrier();
+    for (int b = 0; b < NTB; ++b) Ld[lane * LDW + b] = g[b];
+    if (r == nex || r == nex + 1) pv[lane] = make_double2(xm, pm);
   }
+  __builtin_amdgcn_wave_barrier();
+  double tx = 0.0, tp = 0.0;
+  if (live && r < nex) {
+    const int jg = base + nex;  // own ground, then the next ground
+    const double ag = Ld[jg * LDW + r];
+    const double2 vg = pv[jg];
+    tx += vg.x * ag;
+    tp += vg.y * ag;
+    if (B > nex + 1) {
+      const double an = Ld[(jg + 1) * LDW + r];
+      const double2 vn = pv[jg + 1];
+      tx += vn.x * an;
+      tp += vn.y * an;
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
 #pragma unroll
   for (int kk = NTB - 2; kk >= 0; --kk) {
-    const bool mine = live && r == kk && kk < nex;
-    if (mine) {
+    if (live && r == kk && kk < nex) {
       xm = rhs ? (tx - bb) * my_inv : 0.0;
       pm = tp * my_inv;
-#pragma unroll
-      for (int b = 0; b < kk; ++b) {
-        xr[b] = xm * g[b];
-        pr[b] = pm * g[b];
-      }
+      pv[lane] = make_double2(xm, pm);
     }
     __builtin_amdgcn_wave_barrier();
     if (live && r < kk && kk < nex) {
-      tx += xr[r];
-      tp += pr[r];
+      const int j = base + kk;
+      const double a = Ld[j * LDW + r];
+      const double2 v = pv[j];
+      tx += v.x * a;
+      tp += v.y * a;
     }
     __builtin_amdgcn_wave_barrier();
   }
@@ -674,7 +682,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
   extern __shared__ double smem[];
   double* nb = smem;            // 64 doubles: populations broadcast
   double* hb = smem + 64;       // 64 doubles: fixed-point residuals broadcast
-  double* G = smem + 128;       // maxNs x NP doubles (at least 320)
+  double* G = smem + 128;       // maxNs x NP doubles (at least block_scratch(NTB))
   // The stage-block reduction copies its rows out of G into registers before
   // it writes its scratch (pivot rows, pivots), and G is assembled afresh
   // before it is read again, so its scratch shares G's space. The
@@ -705,7 +713,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
     y.T = A.T_e[y.c];
     y.ne = A.n_e[y.c];
     y.kT = kBoltzmann * y.T;
-    y.sqT = sqrt(y.T);
+    y.ikT = 1.0 / y.kT;
+    y.isqT = 1.0 / sqrt(y.T);
     const double tfac = pow(y.T / 1e4, -0.8);
     for (int zz = 0; zz < 3; ++zz) {
       y.gion[zz] = A.gamma_ion[(y.c * A.S + y.s) * 3 + zz];
@@ -808,12 +817,8 @@ extern "C" int extrass_nlte_solve(extrass_handle h, extrass_atom_handle a, const
   A.lv_E = a->d.lv_E;
   A.lv_g = a->d.lv_g;
   A.lv_share = a->d.lv_share;
-  A.t_l = a->d.t_l;
-  A.t_u = a->d.t_u;
-  A.t_glob = a->d.t_glob;
-  A.t_A = a->d.t_A;
-  A.t_lam = a->d.t_lam;
-  A.t_ups = a->d.t_ups;
+  A.t_pack = a->d.t_pack;
+  A.t_idx = a->d.t_idx;
   A.alpha0 = a->d.alpha0;
   A.T_e = cl->T_e;
   A.n_e = cl->n_e;
@@ -832,8 +837,10 @@ extern "C" int extrass_nlte_solve(extrass_handle h, extrass_atom_handle a, const
   A.NP = a->maxNs | 1;
   A.gsz = a->maxNs * A.NP;
   const bool blocks_fit = !o->factor_fp32 && a->maxBlock <= 32 && a->blockLanes <= 64;
-  const size_t lds = sizeof(double) * (128 + (blocks_fit ? std::max<size_t>(320, (size_t)A.gsz)
-                                                         : (size_t)A.gsz + 64));
+  const int ntb = a->maxBlock <= 16 ? 16 : (a->maxBlock <= 24 ? 24 : 32);
+  const size_t lds = sizeof(double) *
+                     (128 + (blocks_fit ? std::max<size_t>(block_scratch(ntb), (size_t)A.gsz)
+                                        : (size_t)A.gsz + 64));
   const int64_t items = cl->n_cells * a->S;
   int per_cu = (int)std::min<size_t>(16, (160 * 1024) / std::max<size_t>(lds, 1));
   if (per_cu < 1) per_cu = 1;
@@ -843,9 +850,9 @@ extern "C" int extrass_nlte_solve(extrass_handle h, extrass_atom_handle a, const
   // states each, side by side in 64 lanes) in FP64; otherwise the
   // whole-system register reduction, compiled for a few system sizes, the
   // smallest that holds the largest species.
-  if (blocks_fit && a->maxBlock <= 16)
+  if (blocks_fit && ntb == 16)
     hipLaunchKernelGGL((k_nlte<0, 16>), dim3((unsigned)blocks), dim3(64), lds, st, A);
-  else if (blocks_fit && a->maxBlock <= 24)
+  else if (blocks_fit && ntb == 24)
     hipLaunchKernelGGL((k_nlte<0, 24>), dim3((unsigned)blocks), dim3(64), lds, st, A);
   else if (blocks_fit)
     hipLaunchKernelGGL((k_nlte<0, 32>), dim3((unsigned)blocks), dim3(64), lds, st, A);
