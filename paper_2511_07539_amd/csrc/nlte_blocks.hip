@@ -1,0 +1,17 @@
+// Stage-block NLTE kernels (k_nlte<0, NTB>), one per block-size bound.
+#include "nlte_kernel.hpp"
+
+namespace extrass {
+
+bool launch_nlte_blocks(int ntb, unsigned blocks, size_t lds, hipStream_t st, const NArgs& A) {
+  switch (ntb) {
+    case 12: hipLaunchKernelGGL((k_nlte<0, 12>), dim3(blocks), dim3(64), lds, st, A); return true;
+    case 16: hipLaunchKernelGGL((k_nlte<0, 16>), dim3(blocks), dim3(64), lds, st, A); return true;
+    case 22: hipLaunchKernelGGL((k_nlte<0, 22>), dim3(blocks), dim3(64), lds, st, A); return true;
+    case 24: hipLaunchKernelGGL((k_nlte<0, 24>), dim3(blocks), dim3(64), lds, st, A); return true;
+    case 32: hipLaunchKernelGGL((k_nlte<0, 32>), dim3(blocks), dim3(64), lds, st, A); return true;
+    default: return false;
+  }
+}
+
+}  // namespace extrass
