@@ -113,14 +113,21 @@ __device__ __forceinline__ double dbeta_sobolev(double tau) {
 // gross inflow against outflow. With jac, the derivative of the radiative
 // fluxes through beta_S(tau(n)) is then added, which turns G into the
 // diag(n)-scaled Newton matrix.
+//
+// Row i and column i of the matrix can be nonzero only for levels in
+// [rlo, rhi] (lane i's own range: its ion stage and the next stage's ground,
+// and for a ground state also the stage below it); only that range is
+// cleared and summed.
 __device__ __forceinline__ void assemble(const NArgs& A, const Sys& y, double* G, double* nb, double n_mine,
-                         bool rowscale, const double* hb, double h_mine, bool jac, double& rhs) {
+                         bool rowscale, const double* hb, double h_mine, bool jac, double& rhs,
+                         int rlo, int rhi) {
   const int lane = threadIdx.x;
   const int NP = A.NP;
   const int Ns = y.Ns;
-  if (lane < Ns) nb[lane] = n_mine;
-  for (int r = 0; r < Ns; ++r)
-    if (lane < Ns) G[r * NP + lane] = 0.0;
+  if (lane < Ns) {
+    nb[lane] = n_mine;
+    for (int j = rlo; j <= rhi; ++j) G[lane * NP + j] = 0.0;
+  }
   __syncthreads();
   const double* gpe = A.gamma_pe ? A.gamma_pe + y.c * A.T : nullptr;
 #pragma unroll 1
@@ -152,7 +159,7 @@ __device__ __forceinline__ void assemble(const NArgs& A, const Sys& y, double* G
     // -F_i = (Q^T H)_i = sum_j h_j G_ji - h_i sum_j G_ij with H = P(n) - n
     double in = 0.0, out = 0.0;
     if (lane < Ns) {
-      for (int j = 0; j < Ns; ++j) {
+      for (int j = rlo; j <= rhi; ++j) {
         out += G[lane * NP + j];
         in += hb[j] * G[j * NP + lane];
       }
@@ -545,14 +552,23 @@ __device__ __forceinline__ int solve_system(const NArgs& A, const Sys& y, double
   int phase = FIXED, it = 0, bt = 0, best_it = 0;
   double omega = 1.0, prev = INFINITY, Delta = 1.0, best_step = INFINITY;
   Blocks bl{};
-  if constexpr (NTB > 0) bl = make_blocks(y);
+  int rlo = 0, rhi = y.Ns - 1;  // the levels row and column `lane` can couple to
+  if constexpr (NTB > 0) {
+    bl = make_blocks(y);
+    if (live) {
+      const int st = y.z == 0 ? bl.st[0] : (y.z == 1 ? bl.st[1] : bl.st[2]);
+      const int below = y.z == 1 ? bl.st[0] : (y.z == 2 ? bl.st[1] : 0);
+      rlo = (lane == st && y.z > 0) ? below : st;
+      rhi = y.z + 1 < bl.nst ? (y.z == 0 ? bl.st[1] : bl.st[2]) : y.Ns - 1;
+    }
+  }
   double h = 0.0, x = 0.0, step = 0.0, taken = 0.0, trial = 0.0, phi = 0.0, res = 0.0;
   for (;;) {
     const bool newton = phase == NEWTON;
     const double at = phase == TRIAL ? trial : n;
     if (newton && live) hb[lane] = h;
     double rhs = 0.0, xo[2];
-    assemble(A, y, G, nb, at, newton, newton ? hb : nullptr, h, newton, rhs);
+    assemble(A, y, G, nb, at, newton, newton ? hb : nullptr, h, newton, rhs, rlo, rhi);
     int big = last;
     double b_perm = 0.0;
     bool ok = false, done = false;
