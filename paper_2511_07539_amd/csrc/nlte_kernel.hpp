@@ -82,7 +82,6 @@ namespace {
 
 constexpr double kBoltzmann = 1.380649e-16;  // erg/K
 
-
 // Everything one system needs, held per wave (uniform values) or per lane.
 struct Sys {
   int64_t c;
@@ -332,6 +331,17 @@ __device__ __forceinline__ Blocks make_blocks(const Sys& y) {
   return k;
 }
 
+// 1/S for a positive normal S: the hardware reciprocal refined by two Newton
+// steps (error within a few ulps), without the scaling a full division does
+// for operands near the ends of the exponent range.
+__device__ __forceinline__ double rcp_pos(double S) {
+  double r = __builtin_amdgcn_rcp(S);
+  double e = fma(-S, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-S, r, 1.0);
+  return fma(r, e, r);
+}
+
 // Level of position p of block z.
 __device__ __forceinline__ int block_level(const Blocks& k, int z, int p) {
   const int st = z == 0 ? k.st[0] : (z == 1 ? k.st[1] : k.st[2]);
@@ -403,7 +413,7 @@ __device__ __forceinline__ bool reduce_blocks(const double* G, int NP, int Ns, c
     if (act) {
       const double S = myrow[32], bk = myrow[33];
       if (!(S > 0.0)) ok = false;
-      const double inv = 1.0 / S;
+      const double inv = rcp_pos(S);
       if (r == kk) my_inv = inv;
       const double f = g[kk] * inv;
 #pragma unroll
