@@ -15,6 +15,8 @@ Prints one JSON line. `value` is packet line-interactions per second of the
 whole step; NLTE cell-solves per second of the whole step are reported beside
 it, and so is the plain FP64 cold-start NLTE pass on the same rates, timed
 after the step loop, with the largest population difference between the two.
+Both NLTE passes run to the metric's population accuracy (--nlte-tol, 1e-8);
+an untimed solve to 1e-12 then gives the accuracy each pass reached.
 The roofline object covers the kernel that dominates the step, timed with HIP
 events on the stream the library launches on.
 """
@@ -44,6 +46,8 @@ def parse():
     ap.add_argument("--replicas", type=int, default=8)
     ap.add_argument("--epochs", type=int, default=30)
     ap.add_argument("--warm-budget", type=int, default=30)
+    ap.add_argument("--nlte-tol", type=float, default=1e-8,
+                    help="population accuracy of both NLTE passes (the metric's 1e-8)")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched three-stage NLTE measurement")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -118,6 +122,7 @@ def main():
         ex.nlte_warm_start(ctx, atom, cells, dep, params, norm, pops=pops)
         mark(4)
         ex.nlte_solve(ctx, atom, cells, pops=pops, use_guess=True, warm_budget=args.warm_budget,
+                      tol=args.nlte_tol,
                       status=status, iters=iters)
         mark(5)
 
@@ -156,13 +161,25 @@ def main():
     it_cold = torch.empty_like(iters)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(s)
-    ex.nlte_solve(ctx, atom, cells, pops=pops_cold, status=st_cold, iters=it_cold)
+    ex.nlte_solve(ctx, atom, cells, pops=pops_cold, status=st_cold, iters=it_cold,
+                  tol=args.nlte_tol)
     e1.record(s)
     torch.cuda.synchronize()
     cold_ms = e0.elapsed_time(e1)
     both = (st_cold == 0) & (status <= 1)
     pw, pc = pops[both], pops_cold[both]
     warm_vs_cold = float(((pw - pc).abs() / pc).max().item()) if int(both.sum()) else None
+    # accuracy of both passes against a tight FP64 solve (tol 1e-12, untimed)
+    ref, st_ref, _ = ex.nlte_solve(ctx, atom, cells, tol=1e-12, max_iter=400)
+    ok_ref = st_ref == 0
+
+    def max_rel(p, st):
+        m = ok_ref & (st <= 1)
+        return float((((p - ref).abs() / ref)[m]).max().item()) if int(m.sum()) else None
+    accuracy = {"tol": args.nlte_tol, "reference_tol": 1e-12,
+                "reference_converged": int(ok_ref.sum().item()),
+                "warm_max_rel": max_rel(pops, status), "cold_max_rel": max_rel(pops_cold, st_cold)}
+    del ref
     value = n_inter / (ms * 1e-3)
     solves = w.n_cells / (ms * 1e-3)
 
@@ -203,6 +220,7 @@ def main():
         "nlte_iters_mean": {"warm": float(it_warm.mean()), "cold": float(it_cold.float().mean())},
         "nlte_plain_fp64_cold_ms": cold_ms,
         "nlte_warm_vs_cold_max_rel": warm_vs_cold,
+        "nlte_accuracy": accuracy,
         "warm_start_training": {"samples": int(X.shape[0]), "epochs": args.epochs,
                                 "loss_first": hist[0], "loss_last": hist[-1],
                                 "setup_s": t_train},

@@ -233,7 +233,9 @@ typedef struct {
 
 typedef struct {
   int32_t max_iter;    /* iteration cap per species (fixed-point + Newton) */
-  double tol;          /* convergence: max |d ln n| below tol */
+  double tol;          /* convergence: the last Newton correction max |d ln n| and the
+                          fixed-point residual max |P(n)/n - 1| both below tol; the
+                          populations are then within about tol relative of the root */
   int32_t use_guess;   /* 1: start from pops on entry (a non-positive entry means
                           the cold start for that system); 0: cold start */
   int32_t factor_fp32; /* 1: Newton systems factored in FP32, residuals in FP64 */

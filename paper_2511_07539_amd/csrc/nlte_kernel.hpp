@@ -25,7 +25,7 @@
 //     inflow against outflow that would limit accuracy to ~1e-9 in weakly
 //     coupled ion stages. A trust radius on max |d ln n| and a decrease test
 //     on sum (P(n)/n - 1)^2 globalise the iteration.
-// Convergence: max |d ln n| < tol with max |P(n)/n - 1| < 1e-10, or a step
+// Convergence: max |d ln n| < tol with max |P(n)/n - 1| < tol, or a step
 // below 1e-11 that has not improved for 3 Newton steps, or no step lowers a
 // fixed-point residual that is already at rounding level.
 #pragma once
@@ -677,7 +677,7 @@ __device__ __forceinline__ int solve_system(const NArgs& A, const Sys& y, double
         best_step = step;
         best_it = it;
       }
-      if ((step < A.tol && res < 1e-10) || (step < 1e-11 && it - best_it >= 3)) return it + 1;
+      if ((step < A.tol && res < A.tol) || (step < 1e-11 && it - best_it >= 3)) return it + 1;
       bt = 0;
       phase = TRIAL;
     }
