@@ -109,15 +109,12 @@ def main():
             if ev is not None:
                 ev[i].record(s)
         mark(0)
-        t, f = ex.line_tau(ctx, atom, prev, w.t_exp)
-        grid.tau_ct.copy_(t)
-        grid.fcorr_ct.copy_(f)
+        ex.line_tau(ctx, atom, prev, w.t_exp, tau=grid.tau_ct, fcorr=grid.fcorr_ct)
         mark(1)
         ex.transport(ctx, grid, w.seed, w.lambda_lo, w.lambda_hi, w.n_packets,
                      geometry_fp32=fp32, est=est, stats=stats)
         mark(2)
-        g = ex.rates(ctx, atom, est, prev, V)
-        gamma.copy_(g)
+        ex.rates(ctx, atom, est, prev, V, out=gamma)
         mark(3)
         ex.nlte_warm_start(ctx, atom, cells, dep, params, norm, pops=pops)
         mark(4)

@@ -326,20 +326,30 @@ class Atom:
             pass
 
 
-def line_tau(ctx: Context, atom: Atom, pops, t_exp):
-    """Eq. A2 opacity and stimulated-emission factor per (cell, transition)."""
+def line_tau(ctx: Context, atom: Atom, pops, t_exp, tau=None, fcorr=None):
+    """Eq. A2 opacity and stimulated-emission factor per (cell, transition),
+    written into tau / fcorr when given (contiguous f64 [C, T])."""
     C_ = pops.numel() // atom.n_levels
-    tau = torch.empty((C_, atom.n_trans), dtype=torch.float64, device=pops.device)
-    fc = torch.empty_like(tau)
+    if tau is None:
+        tau = torch.empty((C_, atom.n_trans), dtype=torch.float64, device=pops.device)
+    fc = torch.empty_like(tau) if fcorr is None else fcorr
+    for t in (tau, fc):
+        if t.dtype != torch.float64 or not t.is_contiguous() or t.numel() != C_ * atom.n_trans:
+            raise ValueError("line_tau: outputs must be contiguous float64 [C, T]")
     ctx.check(_lib.extrass_line_tau(ctx.h, atom.h, C_, _ptr(pops), float(t_exp), _ptr(tau),
                                     _ptr(fc), _stream()), "extrass_line_tau")
     return tau, fc
 
 
-def rates(ctx: Context, atom: Atom, est, pops, cell_volume):
+def rates(ctx: Context, atom: Atom, est, pops, cell_volume, out=None):
+    """Photoexcitation rates per (cell, transition) (extrass_rates), written into
+    out when given (contiguous f64 [C, T])."""
     C_ = pops.numel() // atom.n_levels
     L = est.numel() // C_
-    out = torch.empty((C_, atom.n_trans), dtype=torch.float64, device=pops.device)
+    if out is None:
+        out = torch.empty((C_, atom.n_trans), dtype=torch.float64, device=pops.device)
+    elif out.dtype != torch.float64 or not out.is_contiguous() or out.numel() != C_ * atom.n_trans:
+        raise ValueError("rates: out must be contiguous float64 [C, T]")
     ctx.check(_lib.extrass_rates(ctx.h, atom.h, C_, L, _ptr(est), _ptr(pops), float(cell_volume),
                                  _ptr(out), _stream()), "extrass_rates")
     return out

@@ -6,7 +6,7 @@
 // (FP32 values rounded when staged into LDS) and FP32 accumulation. Master
 // weights, activations, gradients and the Adam moments stay FP32. A 64x64
 // output tile per 256-thread workgroup, each wavefront owning a 32x32 quarter
-// as 2x2 MFMA tiles; K advances 16 at a time through LDS. Weight gradients
+// as 2x2 MFMA tiles; K advances 64 at a time through LDS. Weight gradients
 // reduce over the batch, so their K range is split across workgroups that add
 // into a zeroed FP32 result. The first layer (K = 6) is too thin for a
 // matrix instruction and runs as plain FP32 FMAs.
@@ -30,7 +30,7 @@ constexpr int64_t kOffW1 = 0, kOffB1 = kOffW1 + kHid * kIn, kOffW2 = kOffB1 + kH
                   kOffB3 = kOffW3 + kHid * kHid, kOffW4 = kOffB3 + kHid,
                   kOffB4 = kOffW4 + kOut * kHid, kParams = kOffB4 + kOut;
 
-constexpr int BM = 64, BN = 64, BK = 16, KPAD = 4;
+constexpr int BM = 64, BN = 64, BK = 64, KPAD = 4;
 
 enum { EPI_STORE = 0, EPI_BIAS_SILU = 1, EPI_BIAS = 2, EPI_ATOMIC = 3 };
 
@@ -77,20 +77,23 @@ __global__ __launch_bounds__(256) void k_gemm(Gemm g) {
       Bs[r][kk] = static_cast<__bf16>(v);
     }
     __syncthreads();
-    const int kq = 4 * (lane >> 4);
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      bf16x4 a;
-      const int ar = wm + i * 16 + (lane & 15);
+    for (int ks = 0; ks < BK; ks += 16) {
+      const int kq = ks + 4 * (lane >> 4);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) a[q] = As[ar][kq + q];
+      for (int i = 0; i < 2; ++i) {
+        bf16x4 a;
+        const int ar = wm + i * 16 + (lane & 15);
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        bf16x4 b;
-        const int br = wn + j * 16 + (lane & 15);
+        for (int q = 0; q < 4; ++q) a[q] = As[ar][kq + q];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) b[q] = Bs[br][kq + q];
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[i][j], 0, 0, 0);
+        for (int j = 0; j < 2; ++j) {
+          bf16x4 b;
+          const int br = wn + j * 16 + (lane & 15);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) b[q] = Bs[br][kq + q];
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[i][j], 0, 0, 0);
+        }
       }
     }
     __syncthreads();
@@ -321,26 +324,31 @@ __global__ void k_features(int64_t c0, int64_t n, int S, const double* __restric
 }
 
 // y (normalised log10 n_i / n_species) -> populations, renormalised per species
-__global__ void k_warm_out(int64_t c0, int64_t n, int S, const int32_t* __restrict__ off,
-                           const double* __restrict__ ns, const float* __restrict__ norm,
-                           const float* __restrict__ y, double* __restrict__ pops) {
+// One wavefront per (cell, species), lane i holding the species' level i (a
+// species has at most 64 levels): log10 populations from the network's
+// normalised outputs, scaled to the species' total.
+__global__ __launch_bounds__(256) void k_warm_out(int64_t c0, int64_t n, int S,
+                                                 const int32_t* __restrict__ off,
+                                                 const double* __restrict__ ns,
+                                                 const float* __restrict__ norm,
+                                                 const float* __restrict__ y,
+                                                 double* __restrict__ pops) {
   const float* ym = norm + 2 * kIn;
   const float* ys = ym + kOut;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n * S;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t cl = e / S;
-    const int s = (int)(e - cl * S);
-    const int64_t c = c0 + cl;
-    const int b = off[s], t = off[s + 1];
-    double mx = -1e300;
-    for (int i = b; i < t; ++i) mx = fmax(mx, (double)(y[cl * kOut + i] * ys[i] + ym[i]));
-    double sum = 0.0;
-    for (int i = b; i < t; ++i) sum += exp10((double)(y[cl * kOut + i] * ys[i] + ym[i]) - mx);
-    const double ntot = ns[c * S + s];
-    for (int i = b; i < t; ++i)
-      pops[c * kOut + i] = ntot > 0.0
-          ? ntot * exp10((double)(y[cl * kOut + i] * ys[i] + ym[i]) - mx) / sum : 0.0;
-  }
+  const int lane = threadIdx.x & 63;
+  const int64_t item = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (item >= n * S) return;  // whole wavefronts
+  const int64_t cl = item / S;
+  const int s = (int)(item - cl * S);
+  const int64_t c = c0 + cl;
+  const int i = off[s] + lane;
+  const bool live = i < off[s + 1];
+  const double v = live ? (double)(y[cl * kOut + i] * ys[i] + ym[i]) : -1e300;
+  const double mx = wave_max(v);
+  const double e = live ? exp10(v - mx) : 0.0;
+  const double sum = wave_sum(e);
+  const double ntot = ns[c * S + s];
+  if (live) pops[c * kOut + i] = ntot > 0.0 ? ntot * e / sum : 0.0;
 }
 
 }  // namespace
@@ -424,8 +432,8 @@ extern "C" int extrass_nlte_warm_start(extrass_handle h, extrass_atom_handle ato
     hipLaunchKernelGGL(k_features, dim3(blocks_for(n)), dim3(256), 0, st, c0, n, atom->S,
                        cells->T_e, cells->n_e, cells->n_species, deposition, norm, x);
     forward(st, params, x, n, a);
-    hipLaunchKernelGGL(k_warm_out, dim3(blocks_for(n * atom->S)), dim3(256), 0, st, c0, n,
-                       atom->S, atom->d.off, cells->n_species, norm, a.y, pops);
+    hipLaunchKernelGGL(k_warm_out, dim3((unsigned)((n * atom->S + 3) / 4)), dim3(256), 0, st, c0,
+                       n, atom->S, atom->d.off, cells->n_species, norm, a.y, pops);
   }
   EXTRASS_HIP_TRY(h, hipGetLastError());
   return EXTRASS_OK;

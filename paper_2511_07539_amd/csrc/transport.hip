@@ -157,63 +157,101 @@ __global__ void k_chunk_cells(const int64_t* start, int64_t C, int64_t first, in
   }
 }
 
-// Exclusive prefix of cell_packets into start[0..C], one workgroup of 1024.
-__global__ __launch_bounds__(1024) void k_scan_counts(const int32_t* counts, int64_t C,
-                                                      int64_t* start) {
-  __shared__ int64_t part[1024];
-  const int t = threadIdx.x;
-  const int64_t chunk = (C + 1023) / 1024;
-  const int64_t a = t * chunk, b = a + chunk < C ? a + chunk : C;
-  int64_t s = 0;
-  for (int64_t i = a; i < b; ++i) s += counts[i];
-  part[t] = s;
-  __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    int64_t v = t >= off ? part[t - off] : 0;
-    __syncthreads();
-    part[t] += v;
-    __syncthreads();
-  }
-  int64_t run = part[t] - s;
-  for (int64_t i = a; i < b; ++i) {
-    start[i] = run;
-    run += counts[i];
-  }
-  if (t == 1023) start[C] = part[1023];
+// Exclusive prefix of cell_packets in three launches: sums of tiles of
+// kScanTile cells, an exclusive scan of the tile sums (one workgroup), then
+// each tile's scan plus its offset. Cells are taken in the grid's order, or
+// with oct >= 0 over octant oct's cells in local order (i + half (j + half k)).
+constexpr int kScanTile = 1024;  // 256 threads x 4 cells
+
+__device__ __forceinline__ int64_t scan_count(const int32_t* counts, int64_t r, int n, int oct) {
+  if (oct < 0) return counts[r];
+  const int half = n / 2;
+  const int i = (int)(r % half), j = (int)((r / half) % half), k = (int)(r / ((int64_t)half * half));
+  const int o0 = (oct & 1) ? half : 0, o1 = (oct & 2) ? half : 0, o2 = (oct & 4) ? half : 0;
+  return counts[(i + o0) + (int64_t)n * ((j + o1) + (int64_t)n * (k + o2))];
 }
 
-// Octant mode: exclusive prefix of cell_packets over the octant's cells in
-// local order (i + half (j + half k)), one workgroup of 1024.
-__global__ __launch_bounds__(1024) void k_scan_octant(const int32_t* counts, int n, int oct,
-                                                      int64_t* ostart) {
-  __shared__ int64_t part[1024];
-  const int half = n / 2;
-  const int64_t Co = (int64_t)half * half * half;
-  const int o0 = (oct & 1) ? half : 0, o1 = (oct & 2) ? half : 0, o2 = (oct & 4) ? half : 0;
-  auto count = [&](int64_t r) {
-    const int i = (int)(r % half), j = (int)((r / half) % half), k = (int)(r / ((int64_t)half * half));
-    return (int64_t)counts[(i + o0) + (int64_t)n * ((j + o1) + (int64_t)n * (k + o2))];
-  };
-  const int t = threadIdx.x;
-  const int64_t chunk = (Co + 1023) / 1024;
-  const int64_t a = t * chunk, b = a + chunk < Co ? a + chunk : Co;
-  int64_t s = 0;
-  for (int64_t i = a; i < b; ++i) s += count(i);
-  part[t] = s;
-  __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    int64_t v = t >= off ? part[t - off] : 0;
-    __syncthreads();
-    part[t] += v;
-    __syncthreads();
+__device__ __forceinline__ int64_t wave_incl_scan(int64_t v, int lane) {
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int64_t u = __shfl_up(v, off, 64);
+    if (lane >= off) v += u;
   }
-  int64_t run = part[t] - s;
-  for (int64_t i = a; i < b; ++i) {
-    ostart[i] = run;
-    run += count(i);
-  }
-  if (t == 1023) ostart[Co] = part[1023];
+  return v;
 }
+
+// Exclusive scan of the 256 values of a workgroup of 256 threads; the total
+// goes to *total.
+__device__ __forceinline__ int64_t block_excl_scan(int64_t v, int64_t* wsum, int64_t* total) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t inc = wave_incl_scan(v, lane);
+  if (lane == 63) wsum[wave] = inc;
+  __syncthreads();
+  int64_t off = 0;
+  for (int w = 0; w < wave; ++w) off += wsum[w];
+  if (total) *total = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+  __syncthreads();
+  return off + inc - v;
+}
+
+__global__ __launch_bounds__(256) void k_scan_tiles(const int32_t* counts, int64_t C, int n,
+                                                   int oct, int64_t* tsum) {
+  __shared__ int64_t wsum[4];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + 4 * threadIdx.x;
+  int64_t v = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+    if (base + j < C) v += scan_count(counts, base + j, n, oct);
+  int64_t tot = 0;
+  block_excl_scan(v, wsum, &tot);
+  if (threadIdx.x == 0) tsum[blockIdx.x] = tot;
+}
+
+// One workgroup of 256: exclusive scan of nt tile sums in place, total to *end.
+__global__ __launch_bounds__(256) void k_scan_sums(int64_t* tsum, int64_t nt, int64_t* end) {
+  __shared__ int64_t wsum[4];
+  int64_t carry = 0;
+  for (int64_t b0 = 0; b0 < nt; b0 += 256) {
+    const int64_t i = b0 + threadIdx.x;
+    const int64_t v = i < nt ? tsum[i] : 0;
+    int64_t tot = 0;
+    const int64_t ex = block_excl_scan(v, wsum, &tot);
+    if (i < nt) tsum[i] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) *end = carry;
+}
+
+__global__ __launch_bounds__(256) void k_scan_apply(const int32_t* counts, int64_t C, int n,
+                                                   int oct, const int64_t* tsum, int64_t* start) {
+  __shared__ int64_t wsum[4];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + 4 * threadIdx.x;
+  int64_t c[4], v = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    c[j] = base + j < C ? scan_count(counts, base + j, n, oct) : 0;
+    v += c[j];
+  }
+  int64_t run = tsum[blockIdx.x] + block_excl_scan(v, wsum, nullptr);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    if (base + j < C) start[base + j] = run;
+    run += c[j];
+  }
+}
+
+// start[0..m) = exclusive prefix of the m counts, start[m] = their total.
+void scan_counts(hipStream_t st, const int32_t* counts, int64_t m, int n, int oct, int64_t* tsum,
+                 int64_t* start) {
+  const int64_t nt = (m + kScanTile - 1) / kScanTile;
+  if (nt > 0)
+    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)nt), dim3(256), 0, st, counts, m, n, oct, tsum);
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(256), 0, st, tsum, nt, start + m);
+  if (nt > 0)
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nt), dim3(256), 0, st, counts, m, n, oct, tsum,
+                       start);
+}
+
 
 // After an octant visit, for every row the visit touched: add its rates into
 // gamma (atom lines) and, if asked, the row into the global table; then zero
@@ -608,6 +646,7 @@ struct TransportWs {
   double* lam_par = nullptr;
   int32_t* chunk_cell = nullptr;
   int64_t nchunk = 0;
+  int64_t* tsum = nullptr;  // tile sums of the packet-count scan
 };
 
 static size_t ws_layout(const extrass_grid* g, const extrass_source* s, TransportWs* w, void* ws) {
@@ -621,6 +660,7 @@ static size_t ws_layout(const extrass_grid* g, const extrass_source* s, Transpor
   t.lam_par = cv.take<double>(2);
   t.nchunk = s->n_packets > 0 ? (s->n_packets + 255) / 256 + 1 : 1;
   t.chunk_cell = cv.take<int32_t>(t.nchunk);
+  t.tsum = cv.take<int64_t>((C + kScanTile - 1) / kScanTile + 1);
   if (w) *w = t;
   return cv.used + 256;
 }
@@ -663,7 +703,7 @@ extern "C" int extrass_transport(extrass_handle h, const extrass_grid* g, const 
   hipLaunchKernelGGL(k_lambin, dim3(64), dim3(256), 0, st, g->line_lambda, L, lam_bins(L),
                      tw.lam_bin, tw.lam_par);
   if (!s->explicit_packets) {
-    hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, st, g->cell_packets, C, start);
+    scan_counts(st, g->cell_packets, C, g->n, -1, tw.tsum, start);
     const int64_t b2 = std::min<int64_t>((tw.nchunk + 255) / 256, 4096);
     hipLaunchKernelGGL(k_chunk_cells, dim3((unsigned)std::max<int64_t>(b2, 1)), dim3(256), 0, st,
                        start, C, s->first_packet, tw.nchunk, tw.chunk_cell);
@@ -736,6 +776,7 @@ struct StreamWs {
   int64_t* ostart;               // 8 x (Co + 1)
   QPk* queues;                   // 8 x qcap
   uint8_t* touched;              // [Co]
+  int64_t* tsum;                 // tile sums of the packet-count scans
   int32_t* lam_bin;              // [lam_bins(L)]
   double* lam_par;               // [2]
   size_t need;
@@ -753,6 +794,7 @@ StreamWs stream_layout(const extrass_grid* g, int64_t qcap, void* ws) {
   w.ostart = cv.take<int64_t>(8 * (Co + 1));
   w.queues = cv.take<QPk>((size_t)(8 * (qcap > 0 ? qcap : 1)));
   w.touched = cv.take<uint8_t>(Co);
+  w.tsum = cv.take<int64_t>((C + kScanTile - 1) / kScanTile + 1);
   w.lam_bin = cv.take<int32_t>(lam_bins(g->n_lines));
   w.lam_par = cv.take<double>(2);
   w.need = cv.used + 256;
@@ -802,12 +844,11 @@ extern "C" int extrass_transport_streamed(extrass_handle h, const extrass_grid* 
   hipLaunchKernelGGL(k_prep, dim3(64), dim3(256), 0, st, g->line_lambda, w.inv_lam, L, stats,
                      w.counters);
   if (L > 1) hipLaunchKernelGGL(k_check_sorted, dim3(64), dim3(256), 0, st, g->line_lambda, L, stats);
-  hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, st, g->cell_packets, C, w.start);
+  scan_counts(st, g->cell_packets, C, n, -1, w.tsum, w.start);
   hipLaunchKernelGGL(k_lambin, dim3(64), dim3(256), 0, st, g->line_lambda, L, lam_bins(L),
                      w.lam_bin, w.lam_par);
   for (int o = 0; o < 8; ++o)
-    hipLaunchKernelGGL(k_scan_octant, dim3(1), dim3(1024), 0, st, g->cell_packets, n, o,
-                       w.ostart + o * (Co + 1));
+    scan_counts(st, g->cell_packets, Co, n, o, w.tsum, w.ostart + o * (Co + 1));
   hipLaunchKernelGGL(k_reset_u64, dim3(1), dim3(64), 0, st, w.counters, 16);
   if (atom) zero_doubles(gamma_pe, C * (int64_t)atom->T, st);
   if (est_global) zero_doubles(est_global, C * (int64_t)L, st);
