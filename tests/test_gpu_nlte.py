@@ -146,3 +146,34 @@ def test_warm_start_and_iteration_cap(ex, ctx):
     torch.cuda.synchronize()
     s1 = s1.cpu().numpy()
     assert np.all(s1[act] == 2) and np.all(s1[so == 3] == 3)
+
+
+def test_tolerance_bounds_the_error(ex, ctx):
+    """tol is the population accuracy: solved at tol (both the last Newton
+    correction and the fixed-point residual below tol), every converged cell
+    is within a small multiple of tol of the oracle's root (tol 1e-13), cold
+    and warm-started alike. The bench runs both NLTE passes at 1e-8."""
+    w = synth.paper_scale()
+    g = np.random.default_rng(1)
+    cells = np.sort(g.choice(w.n_cells, 2000, replace=False))
+    T = w.atom.n_trans
+    gpe = np.abs(g.standard_normal((w.n_cells, T))) * 10 ** g.uniform(-8, 0, (w.n_cells, T))
+    inp = oracle.nlte_inputs_from_workload(w, gamma_pe=gpe.ravel(), cells=cells)
+    po, so, _ = oracle.nlte(inp, tol=1e-13)
+    atom = ex.Atom(ctx, w.atom)
+    cl = ex.cells_from_workload(w, gamma_pe=gpe, cells=cells)
+    for tol in (1e-6, 1e-8):
+        say(f"case: clumpy50 NLTE, 2000 sampled cells, tol {tol:g}, cold and from a perturbed guess")
+        pg, sg, ig = ex.nlte_solve(ctx, atom, cl, max_iter=200, tol=tol)
+        # a guess off by up to a factor 1.5 per level, as a learned start would be
+        guess = torch.as_tensor(po * np.exp(g.uniform(-0.4, 0.4, po.shape)), device="cuda:0")
+        pw, sw, iw = ex.nlte_solve(ctx, atom, cl, max_iter=200, tol=tol, guess=guess,
+                                   warm_budget=30)
+        torch.cuda.synchronize()
+        for name, p, s in (("cold", pg, sg), ("warm", pw, sw)):
+            p, s = p.cpu().numpy(), s.cpu().numpy()
+            ok = (so == 0) & (s <= 1)
+            assert ok.sum() >= 0.999 * len(cells)
+            rel = np.max(np.abs(p[ok] - po[ok]) / po[ok])
+            say(f"  {name}: max rel {rel:.2e}")
+            assert rel <= 3 * tol
