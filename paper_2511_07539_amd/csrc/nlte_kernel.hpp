@@ -9,8 +9,9 @@
 //  1. cold start (Boltzmann within each ion stage, stage ratios from a
 //     ground-only ionisation balance) or the caller's guess;
 //  2. fixed-point steps n <- n_tot * stationary(R(n)), under-relaxed in
-//     log(n) when the change fails to shrink, until max |d ln n| < 0.3 (0.5
-//     from a caller's guess, which Newton then takes over sooner); the
+//     log(n) when the change fails to shrink, until max |d ln n| < 0.7 (1.0
+//     from a caller's guess); the trust-region Newton below takes over from
+//     there; the
 //     stationary vector comes from state reduction with pivots formed as sums
 //     of off-diagonal rates (Grassmann-Taksar-Heyman), which involves no
 //     subtraction and keeps every component accurate. The matrix is assembled
@@ -632,7 +633,7 @@ __device__ __forceinline__ int solve_system(const NArgs& A, const Sys& y, double
       const double tot = wave_sum(v);
       n = live ? v * (y.ntot / tot) : 0.0;
       ++it;
-      if (change < (warm ? 0.5 : 0.3) || it >= 60) phase = RESID;
+      if (change < (warm ? 1.0 : 0.7) || it >= 60) phase = RESID;
       used = it;
       if (it >= max_iter || (check_at > 0 && it == check_at)) return -1;
       best_it = it;
