@@ -114,6 +114,15 @@ extern "C" int extrass_atom_create(extrass_handle h, const extrass_atom_desc* d,
         lanes += B;
       }
       a->blockLanes = std::max(a->blockLanes, lanes);
+      int st[4] = {0, count[0], count[0] + count[1], count[0] + count[1] + count[2]};
+      int packed = 0;
+      for (int z = 0; z < nst; ++z)
+        for (int i = st[z]; i < st[z + 1]; ++i) {
+          const int lo = (i == st[z] && z > 0) ? st[z - 1] : st[z];
+          const int hi = z + 1 < nst ? st[z + 1] : (e - b) - 1;
+          packed += hi - lo + 1;
+        }
+      a->maxPacked = std::max(a->maxPacked, packed);
     }
     int ground[3] = {-1, -1, -1};
     double sumg[3] = {0, 0, 0};

@@ -16,6 +16,10 @@ struct extrass_atom_ctx {
   // the next stage's ground): the largest block, and the most lanes a species'
   // blocks take side by side
   int maxBlock = 0, blockLanes = 0;
+  // the NLTE matrix with rows packed to the levels each level couples to (its
+  // stage, the next stage's ground, and for a ground the stage below): the
+  // largest species' size in doubles
+  int maxPacked = 0;
   std::vector<int> off;   // host copy of species_offset
   std::vector<int> toff;  // host: transitions of species s are [toff[s], toff[s+1])
   struct {

@@ -95,7 +95,7 @@ extern "C" int extrass_nlte_solve(extrass_handle h, extrass_atom_handle a, const
                : a->maxNs <= 40 ? 40
                : a->maxNs <= 50 ? 50 : 64;
   const size_t lds = sizeof(double) *
-                     (128 + (blocks_fit ? std::max<size_t>(block_scratch(ntb), (size_t)A.gsz)
+                     (192 + (blocks_fit ? std::max<size_t>(block_scratch(ntb), (size_t)a->maxPacked)
                                         : (size_t)A.gsz + 64));
   const int64_t items = cl->n_cells * a->S;
   int per_cu = (int)std::min<size_t>(16, (160 * 1024) / std::max<size_t>(lds, 1));

@@ -69,7 +69,7 @@ struct NArgs {
   int32_t* status;
   int32_t* iters;
   unsigned long long* queue;
-  int NP;   // LDS row stride in doubles
+  int NP;   // LDS row stride in doubles (whole-system layout)
   int gsz;  // doubles of LDS holding G
 };
 
@@ -92,6 +92,9 @@ struct Sys {
   // lane-owned level data
   int z, gnext;
   double E, g, share;
+  // row table in LDS: row i of G starts at rt[i].x and holds columns
+  // rt[i].y, rt[i].y + 1, ... (element (i, j) at rt[i].x + j - rt[i].y)
+  const int2* rt;
 };
 
 __device__ __forceinline__ double beta_sobolev(double tau) {
@@ -118,15 +121,21 @@ __device__ __forceinline__ double dbeta_sobolev(double tau) {
 // [rlo, rhi] (lane i's own range: its ion stage and the next stage's ground,
 // and for a ground state also the stage below it); only that range is
 // cleared and summed.
+__device__ __forceinline__ int gat(const int2* rt, int i, int j) {
+  const int2 r = rt[i];
+  return r.x + j - r.y;
+}
+
 __device__ __forceinline__ void assemble(const NArgs& A, const Sys& y, double* G, double* nb, double n_mine,
                          bool rowscale, const double* hb, double h_mine, bool jac, double& rhs,
                          int rlo, int rhi) {
   const int lane = threadIdx.x;
-  const int NP = A.NP;
   const int Ns = y.Ns;
+  const int2* rt = y.rt;
+  double* myrow = G + (lane < Ns ? rt[lane].x - rlo : 0);  // element (lane, j) at myrow[j]
   if (lane < Ns) {
     nb[lane] = n_mine;
-    for (int j = rlo; j <= rhi; ++j) G[lane * NP + j] = 0.0;
+    for (int j = rlo; j <= rhi; ++j) myrow[j] = 0.0;
   }
   __syncthreads();
   const double* gpe = A.gamma_pe ? A.gamma_pe + y.c * A.T : nullptr;
@@ -145,14 +154,14 @@ __device__ __forceinline__ void assemble(const NArgs& A, const Sys& y, double* G
     const double p = gpe ? gpe[ix.z] : 0.0;
     const double down = Ad * beta_sobolev(tau) + y.ne * qul + glu * p;
     const double up = y.ne * qlu + p;
-    G[u * NP + l] = (rowscale ? nu : 1.0) * down;
-    G[l * NP + u] = (rowscale ? nl : 1.0) * up;
+    G[gat(rt, u, l)] = (rowscale ? nu : 1.0) * down;
+    G[gat(rt, l, u)] = (rowscale ? nl : 1.0) * up;
   }
   if (lane < Ns && y.gnext >= 0) {
     const double rs = rowscale ? n_mine : 1.0;
     const double rsg = rowscale ? nb[y.gnext] : 1.0;
-    G[lane * NP + y.gnext] += rs * y.gion[y.z];
-    G[y.gnext * NP + lane] += rsg * y.rec[y.z] * y.share;
+    myrow[y.gnext] += rs * y.gion[y.z];
+    G[gat(rt, y.gnext, lane)] += rsg * y.rec[y.z] * y.share;
   }
   __syncthreads();
   if (hb) {
@@ -160,8 +169,8 @@ __device__ __forceinline__ void assemble(const NArgs& A, const Sys& y, double* G
     double in = 0.0, out = 0.0;
     if (lane < Ns) {
       for (int j = rlo; j <= rhi; ++j) {
-        out += G[lane * NP + j];
-        in += hb[j] * G[j * NP + lane];
+        out += myrow[j];
+        in += hb[j] * G[gat(rt, j, lane)];
       }
     }
     rhs = in - h_mine * out;
@@ -182,8 +191,8 @@ __device__ __forceinline__ void assemble(const NArgs& A, const Sys& y, double* G
       if (db != 0.0) {
         const double du = -nu * Ad * db * K;
         const double dl = nu * Ad * db * K * gul;
-        G[u * NP + l] += du * nu;
-        G[l * NP + u] += -dl * nl;
+        G[gat(rt, u, l)] += du * nu;
+        G[gat(rt, l, u)] += -dl * nl;
       }
     }
     __syncthreads();
@@ -358,7 +367,7 @@ __device__ __forceinline__ int block_level(const Blocks& k, int z, int p) {
 // aligned), xo/po >= 64 doubles each.
 // Returns false when a pivot is not positive.
 template <int NTB>
-__device__ __forceinline__ bool reduce_blocks(const double* G, int NP, int Ns, const Blocks& k,
+__device__ __forceinline__ bool reduce_blocks(const double* G, const int2* rt, int Ns, const Blocks& k,
                                               bool rhs, double b_nat, int pin, double* scratch,
                                               double* xo, double* po, double* out) {
   static_assert(NTB <= 32, "row slots 32 and 33 carry the pivot and right-hand side");
@@ -376,7 +385,7 @@ __device__ __forceinline__ bool reduce_blocks(const double* G, int NP, int Ns, c
   double g[NTB];
 #pragma unroll
   for (int b = 0; b < NTB; ++b)
-    g[b] = (live && b < B && b != r) ? G[my_lev * NP + block_level(k, z, b)] : 0.0;
+    g[b] = (live && b < B && b != r) ? G[gat(rt, my_lev, block_level(k, z, b))] : 0.0;
   // the scratch below overlays G: keep every row load ahead of its stores
   __asm__ volatile("" ::: "memory");
   // right-hand side: a ground's entry is counted in its own block only
@@ -573,6 +582,22 @@ __device__ __forceinline__ int solve_system(const NArgs& A, const Sys& y, double
       rhi = y.z + 1 < bl.nst ? (y.z == 0 ? bl.st[1] : bl.st[2]) : y.Ns - 1;
     }
   }
+  {
+    // row table of G: rows packed back to back, each holding its own range
+    // (stage blocks), or the dense layout with stride NP (whole system)
+    int off = lane * A.NP;
+    if constexpr (NTB > 0) {
+      const int w = live ? rhi - rlo + 1 : 0;
+      int inc = w;
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const int u = __shfl_up(inc, d, 64);
+        if (lane >= d) inc += u;
+      }
+      off = inc - w;
+    }
+    if (live) const_cast<int2*>(y.rt)[lane] = make_int2(off, rlo);
+  }
   double h = 0.0, x = 0.0, step = 0.0, taken = 0.0, trial = 0.0, phi = 0.0, res = 0.0;
   for (;;) {
     const bool newton = phase == NEWTON;
@@ -595,7 +620,7 @@ __device__ __forceinline__ int solve_system(const NArgs& A, const Sys& y, double
           pin = q;
         }
       }
-      ok = reduce_blocks<NTB>(G, A.NP, y.Ns, bl, newton, rhs, pin, rowbuf, nb, hb, xo);
+      ok = reduce_blocks<NTB>(G, y.rt, y.Ns, bl, newton, rhs, pin, rowbuf, nb, hb, xo);
       done = true;
     } else if (newton) {
       // most populated level (first one on ties) goes last
@@ -718,7 +743,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
   extern __shared__ double smem[];
   double* nb = smem;            // 64 doubles: populations broadcast
   double* hb = smem + 64;       // 64 doubles: fixed-point residuals broadcast
-  double* G = smem + 128;       // maxNs x NP doubles (at least block_scratch(NTB))
+  int2* rt = reinterpret_cast<int2*>(smem + 128);  // 64 entries: the row table of G
+  double* G = smem + 192;       // the matrix (row table layout), at least block_scratch(NTB)
   // The stage-block reduction copies its rows out of G into registers before
   // it writes its scratch (pivot rows, pivots), and G is assembled afresh
   // before it is read again, so its scratch shares G's space. The
@@ -763,6 +789,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
     y.E = A.lv_E[li];
     y.g = A.lv_g[li];
     y.share = A.lv_share[li];
+    y.rt = rt;
 
     double n = A.use_guess ? (live ? out[lane] : 0.0) : cold_start(y, live);
     if (A.use_guess && __ballot(live && !(n > 0.0 && n < INFINITY)) != 0ull)
