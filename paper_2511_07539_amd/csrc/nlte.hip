@@ -82,6 +82,7 @@ extern "C" int extrass_nlte_solve(extrass_handle h, extrass_atom_handle a, const
   A.queue = queue;
   A.NP = a->maxNs | 1;
   A.gsz = a->maxNs * A.NP;
+  A.block_rows = (a->blockLanes + 1) & ~1;
   const bool blocks_fit = !o->factor_fp32 && a->maxBlock <= 32 && a->blockLanes <= 64;
   // stage blocks: kernels for blocks of at most 12, 16, 22, 24 or 32 states
   const int ntb = a->maxBlock <= 12 ? 12
@@ -95,7 +96,8 @@ extern "C" int extrass_nlte_solve(extrass_handle h, extrass_atom_handle a, const
                : a->maxNs <= 40 ? 40
                : a->maxNs <= 50 ? 50 : 64;
   const size_t lds = sizeof(double) *
-                     (192 + (blocks_fit ? std::max<size_t>(block_scratch(ntb), (size_t)a->maxPacked)
+                     (192 + (blocks_fit ? std::max<size_t>(block_scratch(ntb, A.block_rows),
+                                                           (size_t)a->maxPacked)
                                         : (size_t)A.gsz + 64));
   const int64_t items = cl->n_cells * a->S;
   int per_cu = (int)std::min<size_t>(16, (160 * 1024) / std::max<size_t>(lds, 1));

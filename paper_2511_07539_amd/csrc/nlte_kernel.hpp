@@ -70,7 +70,8 @@ struct NArgs {
   int32_t* iters;
   unsigned long long* queue;
   int NP;   // LDS row stride in doubles (whole-system layout)
-  int gsz;  // doubles of LDS holding G
+  int gsz;  // doubles of LDS holding G (whole-system layout)
+  int block_rows;  // lanes of the stage blocks of the largest species, rounded up to even
 };
 
 // Kernel launchers, one translation unit each (compiled in parallel):
@@ -310,7 +311,9 @@ __device__ __forceinline__ bool reduce_solve(const double* G, int NP, int Ns, in
 // matrix): pivot rows and the ground-pair values, then the eliminated rows
 // [64][NTB + 1] and the published (x, pi) [64][2].
 constexpr int kBlockScratch = 114;
-constexpr int block_scratch(int ntb) { return kBlockScratch + 64 * (ntb + 1) + 128; }
+// rows: the lanes the stage blocks take, rounded up to even (keeps pv 16-byte
+// aligned): eliminated rows [rows][ntb + 1], then (x, pi) [rows][2]
+constexpr int block_scratch(int ntb, int rows) { return kBlockScratch + rows * (ntb + 3); }
 
 struct Blocks {
   int nst;
@@ -363,11 +366,12 @@ __device__ __forceinline__ int block_level(const Blocks& k, int z, int p) {
 // Solves x^T Q = b^T (rhs, with x of the ground `pin` fixed at 0) and the
 // stationary problem (pi of the ground `pin` = 1) for the generator whose
 // off-diagonal entries are in G. b_nat: lane = level. Lane l < Ns receives
-// (x_l, pi_l) in out. LDS: scratch >= block_scratch(NTB) doubles (16-byte
-// aligned), xo/po >= 64 doubles each.
+// (x_l, pi_l) in out. LDS: scratch >= block_scratch(NTB, nrow) doubles
+// (16-byte aligned), xo/po >= 64 doubles each; nrow >= the lanes of the blocks.
 // Returns false when a pivot is not positive.
 template <int NTB>
-__device__ __forceinline__ bool reduce_blocks(const double* G, const int2* rt, int Ns, const Blocks& k,
+__device__ __forceinline__ bool reduce_blocks(const double* G, const int2* rt, int Ns, int nrow,
+                                              const Blocks& k,
                                               bool rhs, double b_nat, int pin, double* scratch,
                                               double* xo, double* po, double* out) {
   static_assert(NTB <= 32, "row slots 32 and 33 carry the pivot and right-hand side");
@@ -499,8 +503,8 @@ __device__ __forceinline__ bool reduce_blocks(const double* G, const int2* rt, i
   if (live && r == nex) { xm = gz_x; pm = gz_p; }
   if (live && r == nex + 1) { xm = gn_x; pm = gn_p; }
   constexpr int LDW = NTB + 1;
-  double* Ld = scratch + kBlockScratch;   // [64][LDW] eliminated rows, by lane
-  double2* pv = reinterpret_cast<double2*>(Ld + 64 * LDW);  // [64] (x, pi) by lane
+  double* Ld = scratch + kBlockScratch;   // [nrow][LDW] eliminated rows, by lane
+  double2* pv = reinterpret_cast<double2*>(Ld + nrow * LDW);  // [nrow] (x, pi) by lane
   if (live) {
 #pragma unroll
     for (int b = 0; b < NTB; ++b) Ld[lane * LDW + b] = g[b];
@@ -620,7 +624,7 @@ __device__ __forceinline__ int solve_system(const NArgs& A, const Sys& y, double
           pin = q;
         }
       }
-      ok = reduce_blocks<NTB>(G, y.rt, y.Ns, bl, newton, rhs, pin, rowbuf, nb, hb, xo);
+      ok = reduce_blocks<NTB>(G, y.rt, y.Ns, A.block_rows, bl, newton, rhs, pin, rowbuf, nb, hb, xo);
       done = true;
     } else if (newton) {
       // most populated level (first one on ties) goes last
@@ -739,12 +743,15 @@ __device__ double cold_start(const Sys& y, bool live) {
 // NTB > 0: stage-block reduction with blocks of at most NTB states (every
 // species fits); NTB = 0: whole-system reduction with NT >= the largest species.
 template <int NT, int NTB>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_nlte(NArgs A) {
+// Three wavefronts per SIMD (168 VGPRs): the solver is bound by the latency
+// of its wave-serial steps, and the third wavefront hides more of it than the
+// extra register spills cost.
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_nlte(NArgs A) {
   extern __shared__ double smem[];
   double* nb = smem;            // 64 doubles: populations broadcast
   double* hb = smem + 64;       // 64 doubles: fixed-point residuals broadcast
   int2* rt = reinterpret_cast<int2*>(smem + 128);  // 64 entries: the row table of G
-  double* G = smem + 192;       // the matrix (row table layout), at least block_scratch(NTB)
+  double* G = smem + 192;       // the matrix (row table layout), at least block_scratch(NTB, rows)
   // The stage-block reduction copies its rows out of G into registers before
   // it writes its scratch (pivot rows, pivots), and G is assembled afresh
   // before it is read again, so its scratch shares G's space. The
