@@ -143,7 +143,8 @@ int extrass_transport(extrass_handle h, const extrass_grid* g, const extrass_sou
  * for every (cell, transition), with f_corr = 1 - g_l n_u / (g_u n_l) (the
  * stimulated-emission correction of the photoexcitation count). pops is
  * [C*N] (number densities per level); a cell with n_l <= 0 gets tau = 0,
- * f_corr = 1. Outputs tau_ct, fcorr_ct [C*T]. */
+ * f_corr = 1. Outputs tau_ct, fcorr_ct [C*T]. Atoms of more than 8192 levels
+ * return EXTRASS_EUNSUPPORTED (a cell's populations are staged in LDS). */
 int extrass_line_tau(extrass_handle h, extrass_atom_handle atom, int64_t n_cells,
                      const double* pops, double t_exp, double* tau_ct, double* fcorr_ct,
                      void* stream);

@@ -232,6 +232,16 @@ extern "C" int extrass_atom_create(extrass_handle h, const extrass_atom_desc* d,
   if (e == hipSuccess) e = upload(&a->d.o_line, oline);
   if (e == hipSuccess) e = upload(&a->d.o_A, oA);
   if (e == hipSuccess) e = upload(&a->d.o_lam, olam);
+  {
+    std::vector<double> oK(T), orr(T);
+    for (int t = 0; t < T; ++t) {
+      const double gl = d->level_g[olo[t]], gu = d->level_g[oup[t]], l = olam[t];
+      oK[t] = oA[t] / (8.0 * M_PI) * (gu / gl) * l * l * l;
+      orr[t] = gl / gu;
+    }
+    if (e == hipSuccess) e = upload(&a->d.o_K, oK);
+    if (e == hipSuccess) e = upload(&a->d.o_r, orr);
+  }
   if (e != hipSuccess) {
     extrass_atom_destroy(a);
     return fail(h, EXTRASS_EHIP, std::string("extrass_atom_create: ") + hipGetErrorString(e));
@@ -245,7 +255,7 @@ extern "C" int extrass_atom_destroy(extrass_atom_handle a) {
   if (!a) return EXTRASS_OK;
   void* ptrs[] = {a->d.off, a->d.toff, a->d.nstage, a->d.lv_ion, a->d.lv_gnext, a->d.lv_E,
                   a->d.lv_g, a->d.lv_share, a->d.t_pack, a->d.t_idx, a->d.alpha0, a->d.o_lo,
-                  a->d.o_up, a->d.o_line, a->d.o_A, a->d.o_lam};
+                  a->d.o_up, a->d.o_line, a->d.o_A, a->d.o_lam, a->d.o_K, a->d.o_r};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete a;
@@ -253,26 +263,32 @@ extern "C" int extrass_atom_destroy(extrass_atom_handle a) {
 }
 
 // ---------------------------------------------------------------- Eq. A2
-__global__ void k_line_tau(int64_t n_cells, int N, int T, const double* __restrict__ pops,
-                           const int32_t* __restrict__ lo, const int32_t* __restrict__ up,
-                           const double* __restrict__ A, const double* __restrict__ lam,
-                           const double* __restrict__ g, double t_exp, double* __restrict__ tau,
-                           double* __restrict__ fcorr) {
-  const int64_t total = n_cells * T;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t c = e / T;
-    const int t = static_cast<int>(e - c * T);
-    const double nl = pops[c * N + lo[t]], nu = pops[c * N + up[t]];
-    const double gl = g[lo[t]], gu = g[up[t]];
-    double tv = 0.0, fc = 1.0;
-    if (nl > 0.0) {
-      fc = 1.0 - (gl * nu) / (gu * nl);
-      const double l = lam[t];
-      tv = A[t] / (8.0 * M_PI) * (gu / gl) * l * l * l * nl * fc * t_exp;
+// One workgroup per cell at a time: the cell's populations are staged in LDS,
+// then every transition's tau and stimulated-emission factor is written, in
+// the caller's transition order (coalesced stores).
+__global__ __launch_bounds__(256) void k_line_tau(int64_t n_cells, int N, int T,
+                                                 const double* __restrict__ pops,
+                                                 const int32_t* __restrict__ lo,
+                                                 const int32_t* __restrict__ up,
+                                                 const double* __restrict__ K,
+                                                 const double* __restrict__ r, double t_exp,
+                                                 double* __restrict__ tau,
+                                                 double* __restrict__ fcorr) {
+  extern __shared__ double pc[];  // [N]
+  for (int64_t c = blockIdx.x; c < n_cells; c += gridDim.x) {
+    for (int i = threadIdx.x; i < N; i += blockDim.x) pc[i] = pops[c * N + i];
+    __syncthreads();
+    for (int t = threadIdx.x; t < T; t += blockDim.x) {
+      const double nl = pc[lo[t]], nu = pc[up[t]];
+      double tv = 0.0, fc = 1.0;
+      if (nl > 0.0) {
+        fc = 1.0 - r[t] * nu / nl;
+        tv = K[t] * nl * fc * t_exp;
+      }
+      tau[c * T + t] = tv;
+      fcorr[c * T + t] = fc;
     }
-    tau[e] = tv;
-    fcorr[e] = fc;
+    __syncthreads();
   }
 }
 
@@ -283,11 +299,12 @@ extern "C" int extrass_line_tau(extrass_handle h, extrass_atom_handle a, int64_t
     return fail(h, EXTRASS_EINVAL, "extrass_line_tau: bad argument");
   if (n_cells == 0 || a->T == 0) return EXTRASS_OK;
   EXTRASS_HIP_TRY(h, hipSetDevice(h->device));
-  const int64_t total = n_cells * a->T;
-  int64_t blocks = std::min<int64_t>((total + 255) / 256, 65536);
-  hipLaunchKernelGGL(k_line_tau, dim3((unsigned)blocks), dim3(256), 0,
+  if (a->N > 8192)  // a cell's populations are staged in 64 KB of LDS
+    return fail(h, EXTRASS_EUNSUPPORTED, "extrass_line_tau: more than 8192 levels");
+  const int64_t blocks = std::min<int64_t>(n_cells, (int64_t)h->num_cus * 32);
+  hipLaunchKernelGGL(k_line_tau, dim3((unsigned)blocks), dim3(256), sizeof(double) * a->N,
                      static_cast<hipStream_t>(stream), n_cells, a->N, a->T, pops, a->d.o_lo,
-                     a->d.o_up, a->d.o_A, a->d.o_lam, a->d.lv_g, t_exp, tau_ct, fcorr_ct);
+                     a->d.o_up, a->d.o_K, a->d.o_r, t_exp, tau_ct, fcorr_ct);
   EXTRASS_HIP_TRY(h, hipGetLastError());
   return EXTRASS_OK;
 }

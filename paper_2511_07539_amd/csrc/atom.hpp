@@ -42,5 +42,7 @@ struct extrass_atom_ctx {
     int32_t* o_line = nullptr;
     double* o_A = nullptr;
     double* o_lam = nullptr;
+    double* o_K = nullptr;         // [T] A lambda^3 / (8 pi) * g_u / g_l (Eq. A2 without n_l, t)
+    double* o_r = nullptr;         // [T] g_l / g_u
   } d;
 };
