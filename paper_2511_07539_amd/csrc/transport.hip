@@ -46,6 +46,12 @@ static inline int lam_bins(int L) {
 }
 constexpr int kBlock = 256;
 
+struct alignas(16) LineRec {
+  double inv_lam;
+  int32_t trans;
+  float tau0;
+};
+
 struct TArgs {
   int n;
   double beta, h;
@@ -54,9 +60,7 @@ struct TArgs {
   const int32_t* cell_packets;
   int L;
   const double* lam;
-  const double* inv_lam;
-  const float* tau0;
-  const int32_t* line_trans;
+  const LineRec* lines;  // [L] per line: 1/lambda, transition (-1: tau0 x tau_scale), tau0
   int T;
   const double* tau_ct;
   const double* fcorr_ct;
@@ -99,13 +103,20 @@ static_assert(sizeof(QPk) == 120, "queue record layout");
 
 // ---- small helper kernels -------------------------------------------------
 
-__global__ void k_prep(const double* lam, double* inv_lam, int L, double* stats,
+// The line list packed into one 16-byte record per line, so that the event
+// loop's line test and opacity choice take one load.
+__global__ void k_prep(const double* lam, const float* tau0, const int32_t* line_trans,
+                       int has_ct, LineRec* lines, int L, double* stats,
                        unsigned long long* queue) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t < EXTRASS_STATS) stats[t] = 0.0;
   if (t == 0) *queue = 0ull;
   for (int k = t; k < L; k += gridDim.x * blockDim.x) {
-    inv_lam[k] = 1.0 / lam[k];
+    LineRec r;
+    r.inv_lam = 1.0 / lam[k];
+    r.trans = has_ct ? line_trans[k] : -1;
+    r.tau0 = tau0[k];
+    lines[k] = r;
   }
 }
 
@@ -539,8 +550,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     const int64_t row = A.oct < 0 ? c
         : (q.ci[0] - A.lo[0]) + (int64_t)A.half * ((q.ci[1] - A.lo[1]) + (int64_t)A.half * (q.ci[2] - A.lo[2]));
     bool line_event = false;
+    LineRec lr;
+    lr.trans = -1;
+    lr.tau0 = 0.0f;
     if (q.k < A.L) {
-      const G Dk = static_cast<G>(1.0 - q.lamL * A.inv_lam[q.k]);
+      lr = A.lines[q.k];
+      const G Dk = static_cast<G>(1.0 - q.lamL * lr.inv_lam);
       line_event = Dk <= q.Dexit;
     }
     bool stop = false;
@@ -548,12 +563,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
       const int k = q.k;
       t.checks++;
       double tau, fc = 1.0;
-      const int tr = (A.line_trans && A.tau_ct) ? A.line_trans[k] : -1;
+      const int tr = lr.trans;
       if (tr >= 0) {
         tau = A.tau_ct[c * A.T + tr];
         if (A.fcorr_ct) fc = A.fcorr_ct[c * A.T + tr];
       } else {
-        tau = static_cast<double>(A.tau0[k]) * static_cast<double>(A.tau_scale[c]);
+        tau = static_cast<double>(lr.tau0) * static_cast<double>(A.tau_scale[c]);
       }
       if (tau > kTauMin) {
         t.inter++;
@@ -640,7 +655,7 @@ using namespace extrass;
 
 struct TransportWs {
   int64_t* start = nullptr;
-  double* inv_lam = nullptr;
+  LineRec* lines = nullptr;
   unsigned long long* queue = nullptr;
   int32_t* lam_bin = nullptr;
   double* lam_par = nullptr;
@@ -654,7 +669,7 @@ static size_t ws_layout(const extrass_grid* g, const extrass_source* s, Transpor
   Carver cv(ws, ~size_t(0));
   TransportWs t;
   t.start = cv.take<int64_t>(C + 1);
-  t.inv_lam = cv.take<double>(g->n_lines > 0 ? g->n_lines : 1);
+  t.lines = cv.take<LineRec>(g->n_lines > 0 ? g->n_lines : 1);
   t.queue = cv.take<unsigned long long>(8);
   t.lam_bin = cv.take<int32_t>(lam_bins(g->n_lines));
   t.lam_par = cv.take<double>(2);
@@ -690,7 +705,6 @@ extern "C" int extrass_transport(extrass_handle h, const extrass_grid* g, const 
   const size_t need = ws_layout(g, s, &tw, ws);
   if (ws_bytes < need) return fail(h, EXTRASS_ENOSPACE, "extrass_transport: workspace too small");
   int64_t* start = tw.start;
-  double* inv_lam = tw.inv_lam;
   unsigned long long* queue = tw.queue;
 
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -698,7 +712,9 @@ extern "C" int extrass_transport(extrass_handle h, const extrass_grid* g, const 
   const int64_t C = (int64_t)g->n * g->n * g->n;
   const int L = g->n_lines;
 
-  hipLaunchKernelGGL(k_prep, dim3(64), dim3(256), 0, st, g->line_lambda, inv_lam, L, stats, queue);
+  const int has_ct = (g->tau_ct && g->line_trans) ? 1 : 0;
+  hipLaunchKernelGGL(k_prep, dim3(64), dim3(256), 0, st, g->line_lambda, g->line_tau0,
+                     g->line_trans, has_ct, tw.lines, L, stats, queue);
   if (L > 1) hipLaunchKernelGGL(k_check_sorted, dim3(64), dim3(256), 0, st, g->line_lambda, L, stats);
   hipLaunchKernelGGL(k_lambin, dim3(64), dim3(256), 0, st, g->line_lambda, L, lam_bins(L),
                      tw.lam_bin, tw.lam_par);
@@ -727,9 +743,7 @@ extern "C" int extrass_transport(extrass_handle h, const extrass_grid* g, const 
   A.cell_packets = g->cell_packets;
   A.L = L;
   A.lam = g->line_lambda;
-  A.inv_lam = inv_lam;
-  A.tau0 = g->line_tau0;
-  A.line_trans = g->line_trans;
+  A.lines = tw.lines;
   A.T = g->n_trans;
   A.tau_ct = g->tau_ct;
   A.fcorr_ct = g->fcorr_ct;
@@ -771,7 +785,7 @@ extern "C" int extrass_transport(extrass_handle h, const extrass_grid* g, const 
 namespace {
 struct StreamWs {
   int64_t* start;
-  double* inv_lam;
+  LineRec* lines;
   unsigned long long* counters;  // [0] packet pool, [1..8] queue tails
   int64_t* ostart;               // 8 x (Co + 1)
   QPk* queues;                   // 8 x qcap
@@ -789,7 +803,7 @@ StreamWs stream_layout(const extrass_grid* g, int64_t qcap, void* ws) {
   Carver cv(ws, ~size_t(0));
   StreamWs w;
   w.start = cv.take<int64_t>(C + 1);
-  w.inv_lam = cv.take<double>(g->n_lines > 0 ? g->n_lines : 1);
+  w.lines = cv.take<LineRec>(g->n_lines > 0 ? g->n_lines : 1);
   w.counters = cv.take<unsigned long long>(16);
   w.ostart = cv.take<int64_t>(8 * (Co + 1));
   w.queues = cv.take<QPk>((size_t)(8 * (qcap > 0 ? qcap : 1)));
@@ -841,8 +855,9 @@ extern "C" int extrass_transport_streamed(extrass_handle h, const extrass_grid* 
   const int n = g->n, half = n / 2, L = g->n_lines;
   const int64_t C = (int64_t)n * n * n, Co = (int64_t)half * half * half;
 
-  hipLaunchKernelGGL(k_prep, dim3(64), dim3(256), 0, st, g->line_lambda, w.inv_lam, L, stats,
-                     w.counters);
+  const int has_ct = (g->tau_ct && g->line_trans) ? 1 : 0;
+  hipLaunchKernelGGL(k_prep, dim3(64), dim3(256), 0, st, g->line_lambda, g->line_tau0,
+                     g->line_trans, has_ct, w.lines, L, stats, w.counters);
   if (L > 1) hipLaunchKernelGGL(k_check_sorted, dim3(64), dim3(256), 0, st, g->line_lambda, L, stats);
   scan_counts(st, g->cell_packets, C, n, -1, w.tsum, w.start);
   hipLaunchKernelGGL(k_lambin, dim3(64), dim3(256), 0, st, g->line_lambda, L, lam_bins(L),
@@ -877,9 +892,7 @@ extern "C" int extrass_transport_streamed(extrass_handle h, const extrass_grid* 
   A.cell_packets = g->cell_packets;
   A.L = L;
   A.lam = g->line_lambda;
-  A.inv_lam = w.inv_lam;
-  A.tau0 = g->line_tau0;
-  A.line_trans = g->line_trans;
+  A.lines = w.lines;
   A.T = g->n_trans;
   A.tau_ct = g->tau_ct;
   A.fcorr_ct = g->fcorr_ct;
