@@ -26,7 +26,9 @@
 //     inflow against outflow that would limit accuracy to ~1e-9 in weakly
 //     coupled ion stages. A trust radius on max |d ln n| and a decrease test
 //     on sum (P(n)/n - 1)^2 globalise the iteration.
-// Convergence: max |d ln n| < tol with max |P(n)/n - 1| < tol, or a step
+// Convergence: max |d ln n| < tol with max |P(n)/n - 1| < tol; or, after a
+// full Newton step s following a full step s', a predicted next step
+// (s / s'^2) s^2 below tol / 100 with the residual below tol; or a step
 // below 1e-11 that has not improved for 3 Newton steps, or no step lowers a
 // fixed-point residual that is already at rounding level.
 #pragma once
@@ -574,7 +576,7 @@ __device__ __forceinline__ int solve_system(const NArgs& A, const Sys& y, double
   used = 0;
   if (max_iter <= 0) return -1;
   int phase = FIXED, it = 0, bt = 0, best_it = 0;
-  double omega = 1.0, prev = INFINITY, Delta = 1.0, best_step = INFINITY;
+  double omega = 1.0, prev = INFINITY, Delta = 1.0, best_step = INFINITY, last_full = 0.0;
   Blocks bl{};
   int rlo = 0, rhi = y.Ns - 1;  // the levels row and column `lane` can couple to
   if constexpr (NTB > 0) {
@@ -685,6 +687,15 @@ __device__ __forceinline__ int solve_system(const NArgs& A, const Sys& y, double
           if (it >= max_iter) return -1;
           // warm-start check: still far from the root after the budget
           if (check_at > 0 && it == check_at && !(res < 1e-6)) return -1;
+          // In the quadratic end game the next full Newton step is about
+          // (s / s_prev^2) s^2 for this full step s and the one before it;
+          // when that is far below tol and the residual is already below
+          // tol, the verifying Newton step is skipped.
+          if (taken == step && last_full > 0.0) {
+            const double pred = (step / (last_full * last_full)) * step * step;
+            if (pred < 0.01 * A.tol && res2 < A.tol) return it;
+          }
+          last_full = taken == step ? step : 0.0;
           phase = NEWTON;
         } else {
           Delta = (taken < Delta ? taken : Delta) / 4.0;
