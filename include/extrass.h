@@ -183,6 +183,13 @@ int extrass_rates(extrass_handle h, extrass_atom_handle atom, int64_t n_cells, i
  *
  * n: even. est_octant: device [(n/2)^3 * L] (local cell i + (n/2)(j + (n/2) k)
  * within the octant, octant o = (i >= n/2) + 2 (j >= n/2) + 4 (k >= n/2)).
+ * est_octant may be NULL when only the rates are wanted (atom given,
+ * est_global NULL, the grid's tau_ct/line_trans set and line_trans the
+ * inverse of the atom's transition -> line map, else EXTRASS_EINVAL): each
+ * interaction on an atom line then adds dN / f_corr straight into
+ * gamma_pe[c,t], which is divided by n_l V at the end. No octant table is
+ * kept and no flush runs; lines of no atom transition are not recorded. The
+ * rates equal the table path's up to the order of the additions.
  * queue_capacity: packets each octant's queue holds; the workspace holds 8
  * queues of 120-byte records. A full queue loses packets: stats[QUEUE_FULL]
  * is set and the call returns EXTRASS_ENOSPACE. The host waits for the stream

@@ -248,17 +248,18 @@ def transport(ctx: Context, grid: Grid, seed, lambda_lo, lambda_hi, n_packets, f
 def transport_streamed(ctx: Context, grid: Grid, seed, lambda_lo, lambda_hi, n_packets,
                        atom=None, pops=None, cell_volume=None, iteration=0, geometry_fp32=False,
                        est_octant=None, est_global=False, gamma=None, stats=None,
-                       queue_capacity=None):
+                       queue_capacity=None, octant_table=True):
     """Runs extrass_transport_streamed (8 velocity octants, one estimator table
     of one octant resident). Returns (gamma [C, T] or None, stats [16],
     est_global [C, L] or None). queue_capacity defaults to n_packets / 4 per
-    octant (at least 4096)."""
+    octant (at least 4096). With octant_table=False (rates only, atom given)
+    no table is allocated and the rates are summed per interaction."""
     dev = grid.line_lambda.device
     g = grid.struct()
     s = _Source(int(seed), int(iteration), 0, int(n_packets), float(lambda_lo), float(lambda_hi),
                 None, 1 if geometry_fp32 else 0)
     half = grid.n // 2
-    if est_octant is None:
+    if est_octant is None and octant_table:
         est_octant = torch.empty((half ** 3, grid.n_lines), dtype=torch.float64, device=dev)
     eg = (torch.empty((grid.n_cells, grid.n_lines), dtype=torch.float64, device=dev)
           if est_global else None)

@@ -91,6 +91,8 @@ struct TArgs {
   unsigned long long* qtail; // [8]
   int64_t qcap;
   uint8_t* touched;          // [Coct] rows that received an estimator this visit
+  double* gdirect;           // octant mode without a table: [C*T] sums of dN / f_corr per
+                             // (cell, atom transition); other lines are not recorded
 };
 
 // A packet in flight between octants: the whole state after a wall crossing.
@@ -292,6 +294,30 @@ __global__ __launch_bounds__(256) void k_octant_flush(double* __restrict__ eo, u
   __syncthreads();
   for (int q = threadIdx.x; q < L; q += blockDim.x) row[q] = 0.0;
   if (threadIdx.x == 0) touched[r] = 0;
+}
+
+// Rates from the direct sums: gamma_pe[c,t] = sum(dN / f_corr) / (n_l V).
+__global__ void k_rates_direct(int64_t C, int N, int T, const int32_t* __restrict__ lo,
+                               const double* __restrict__ pops, double V,
+                               double* __restrict__ gamma) {
+  const int64_t total = C * T;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = e / T;
+    const int t = (int)(e - c * T);
+    const double Nl = pops[c * N + lo[t]] * V;
+    gamma[e] = Nl > 0.0 ? gamma[e] / Nl : 0.0;
+  }
+}
+
+// The direct sums need the grid's line -> transition map to be the inverse of
+// the atom's transition -> line map; flag[0] is set when it is not.
+__global__ void k_check_map(const int32_t* __restrict__ line_trans, int L,
+                            const int32_t* __restrict__ o_line, int T, unsigned long long* flag) {
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < T; t += gridDim.x * blockDim.x) {
+    const int k = o_line[t];
+    if (k < 0 || k >= L || line_trans[k] != t) flag[0] = 1ull;
+  }
 }
 
 __global__ void k_reset_u64(unsigned long long* p, int n) {
@@ -573,8 +599,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
       if (tau > kTauMin) {
         t.inter++;
         const double dN = q.w * (-expm1(-tau));
-        atomicAdd(A.est + row * A.L + k, dN / fc);
-        if (A.touched) A.touched[row] = 1;
+        if (A.gdirect) {
+          if (tr >= 0) atomicAdd(A.gdirect + c * A.T + tr, dN / fc);
+        } else {
+          atomicAdd(A.est + row * A.L + k, dN / fc);
+          if (A.touched) A.touched[row] = 1;
+        }
         q.wabs += dN;
         q.w = q.w * exp(-tau);
         if (q.w * q.lam_e < (kKillFrac * q.w0) * A.lam[k]) {
@@ -835,8 +865,15 @@ extern "C" int extrass_transport_streamed(extrass_handle h, const extrass_grid* 
                                           double* est_global, double* gamma_pe, double* stats,
                                           int64_t queue_capacity, void* ws, size_t ws_bytes,
                                           void* stream) {
-  if (!h || !g || !s || !est_octant || !stats || !ws)
+  if (!h || !g || !s || !stats || !ws)
     return fail(h, EXTRASS_EINVAL, "extrass_transport_streamed: null argument");
+  // without an octant table the rates are summed directly per interaction
+  const bool direct = est_octant == nullptr;
+  if (direct && (!atom || est_global || !g->tau_ct || !g->line_trans ||
+                 g->n_trans != (atom ? atom->T : -1)))
+    return fail(h, EXTRASS_EINVAL,
+                "extrass_transport_streamed: without est_octant, rates need the atom, the grid's "
+                "transition opacities and no est_global");
   if (g->n <= 0 || g->n > 1024 || (g->n & 1) || g->n_lines <= 0 || !(g->beta_max > 0.0) ||
       !g->line_lambda || !g->line_tau0 || !g->tau_scale || !g->cell_packets || !g->cell_photons)
     return fail(h, EXTRASS_EINVAL, "extrass_transport_streamed: bad grid (n must be even)");
@@ -867,9 +904,21 @@ extern "C" int extrass_transport_streamed(extrass_handle h, const extrass_grid* 
   hipLaunchKernelGGL(k_reset_u64, dim3(1), dim3(64), 0, st, w.counters, 16);
   if (atom) zero_doubles(gamma_pe, C * (int64_t)atom->T, st);
   if (est_global) zero_doubles(est_global, C * (int64_t)L, st);
-  // the octant table stays zero between visits (each visit's flush clears its rows)
-  zero_doubles(est_octant, Co * (int64_t)L, st);
-  EXTRASS_HIP_TRY(h, hipMemsetAsync(w.touched, 0, (size_t)Co, st));
+  if (direct) {
+    unsigned long long* flag = w.counters + 15;  // zeroed with the counters above
+    hipLaunchKernelGGL(k_check_map, dim3(16), dim3(256), 0, st, g->line_trans, L, atom->d.o_line,
+                       atom->T, flag);
+    unsigned long long bad = 0;
+    EXTRASS_HIP_TRY(h, hipMemcpyAsync(&bad, flag, sizeof(bad), hipMemcpyDeviceToHost, st));
+    EXTRASS_HIP_TRY(h, hipStreamSynchronize(st));
+    if (bad != 0)
+      return fail(h, EXTRASS_EINVAL,
+                  "extrass_transport_streamed: grid line_trans is not the inverse of the atom's lines");
+  } else {
+    // the octant table stays zero between visits (each visit's flush clears its rows)
+    zero_doubles(est_octant, Co * (int64_t)L, st);
+    EXTRASS_HIP_TRY(h, hipMemsetAsync(w.touched, 0, (size_t)Co, st));
+  }
   EXTRASS_HIP_TRY(h, hipGetLastError());
 
   // packets each octant emits, and the plan's total
@@ -916,7 +965,8 @@ extern "C" int extrass_transport_streamed(extrass_handle h, const extrass_grid* 
   A.qbase = w.queues;
   A.qtail = w.counters + 1;
   A.qcap = queue_capacity;
-  A.touched = w.touched;
+  A.touched = direct ? nullptr : w.touched;
+  A.gdirect = direct ? gamma_pe : nullptr;
 
   int64_t head[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   unsigned long long tail[8];
@@ -949,10 +999,11 @@ extern "C" int extrass_transport_streamed(extrass_handle h, const extrass_grid* 
       else
         hipLaunchKernelGGL(k_transport<double>, dim3((unsigned)blocks), dim3(kBlock), 0, st, A);
       EXTRASS_HIP_TRY(h, hipGetLastError());
-      hipLaunchKernelGGL(k_octant_flush, dim3((unsigned)Co), dim3(256), 0, st, est_octant, w.touched,
-                         n, o, L, atom ? atom->N : 0, atom ? atom->T : 0,
-                         atom ? atom->d.o_lo : nullptr, atom ? atom->d.o_line : nullptr, pops,
-                         cell_volume, atom ? gamma_pe : nullptr, est_global);
+      if (!direct)
+        hipLaunchKernelGGL(k_octant_flush, dim3((unsigned)Co), dim3(256), 0, st, est_octant,
+                           w.touched, n, o, L, atom ? atom->N : 0, atom ? atom->T : 0,
+                           atom ? atom->d.o_lo : nullptr, atom ? atom->d.o_line : nullptr, pops,
+                           cell_volume, atom ? gamma_pe : nullptr, est_global);
       EXTRASS_HIP_TRY(h, hipGetLastError());
       head[o] = avail;
     }
@@ -968,5 +1019,11 @@ extern "C" int extrass_transport_streamed(extrass_handle h, const extrass_grid* 
   for (int o = 0; o < 8; ++o)
     if ((int64_t)tail[o] != head[o])
       return fail(h, EXTRASS_EHIP, "extrass_transport_streamed: packets left in a queue");
+  if (direct) {
+    const int64_t blocks = std::min<int64_t>((C * atom->T + 255) / 256, 16384);
+    hipLaunchKernelGGL(k_rates_direct, dim3((unsigned)blocks), dim3(256), 0, st, C, atom->N, atom->T,
+                       atom->d.o_lo, pops, cell_volume, gamma_pe);
+    EXTRASS_HIP_TRY(h, hipGetLastError());
+  }
   return EXTRASS_OK;
 }

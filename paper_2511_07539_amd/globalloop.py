@@ -25,9 +25,12 @@ from . import (Atom, Cells, Context, cell_volume, cells_from_workload, grid_from
 
 
 def run(ctx: Context, w, iterations=5, params=None, norm=None, warm_budget=30, geometry_fp32=True,
-        queue_capacity=None, max_iter=200, tol=1e-10, device="cuda:0", log=None):
+        queue_capacity=None, max_iter=200, tol=1e-10, device="cuda:0", log=None,
+        octant_table=False):
     """Returns (pops [C, N], status [C], history). With params/norm the first
-    iteration's populations come from the MLP, else from the cold start."""
+    iteration's populations come from the MLP, else from the cold start. The
+    streamed transport sums the rates per interaction (no octant estimator
+    table) unless octant_table is set."""
     atom = Atom(ctx, w.atom)
     cells0 = cells_from_workload(w, device=device)
     V = cell_volume(w)
@@ -49,22 +52,21 @@ def run(ctx: Context, w, iterations=5, params=None, norm=None, warm_budget=30, g
         np.repeat(np.arange(w.atom.n_species), np.diff(w.atom.species_offset)), device=device)
     ns_lv = cells0.n_species.view(w.n_cells, -1)[:, lv_species]
     half = w.n // 2
-    est_oct = torch.empty((half ** 3, w.n_lines), dtype=torch.float64, device=device)
+    est_oct = (torch.empty((half ** 3, w.n_lines), dtype=torch.float64, device=device)
+               if octant_table else None)
     new = torch.empty_like(pops)
     st = torch.empty(w.n_cells, dtype=torch.int32, device=device)
     it_ = torch.empty(w.n_cells, dtype=torch.int32, device=device)
     for k in range(iterations):
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
         ev[0].record(s)
-        t, f = line_tau(ctx, atom, pops, w.t_exp)
-        grid.tau_ct.copy_(t)
-        grid.fcorr_ct.copy_(f)
-        del t, f
+        line_tau(ctx, atom, pops, w.t_exp, tau=grid.tau_ct, fcorr=grid.fcorr_ct)
         ev[1].record(s)
         _, stats, _ = transport_streamed(ctx, grid, w.seed, w.lambda_lo, w.lambda_hi, w.n_packets,
                                          atom=atom, pops=pops, cell_volume=V, iteration=k,
                                          geometry_fp32=geometry_fp32, est_octant=est_oct,
-                                         gamma=gamma, queue_capacity=queue_capacity)
+                                         gamma=gamma, queue_capacity=queue_capacity,
+                                         octant_table=octant_table)
         ev[2].record(s)
         nlte_solve(ctx, atom, cells, max_iter=max_iter, tol=tol, guess=pops,
                    warm_budget=warm_budget if k == 0 and params is not None else 0,

@@ -80,6 +80,47 @@ def test_streamed_equals_unsplit_coupled_clumpy(ex, ctx, fp32):
     _close(gam_s, gam_u, 1e-12, "rates")
 
 
+@pytest.mark.parametrize("fp32", [False, True])
+def test_direct_rates_equal_table_rates(ex, ctx, fp32):
+    """Without an octant table the rates are summed per interaction: the same
+    sums in another order, so equal to the table path's rates to 1e-12."""
+    w = synth.clumpy(n=16, n_lines=1500, n_packets=300_000, number=2)
+    say(f"case: streamed rates without the octant table, clumpy 16^3, fp32={fp32}")
+    atom, cold, grid = _coupled(ex, ctx, w)
+    V = ex.cell_volume(w)
+    gam_t, st_t, _ = ex.transport_streamed(ctx, grid, w.seed, w.lambda_lo, w.lambda_hi,
+                                           w.n_packets, atom=atom, pops=cold, cell_volume=V,
+                                           geometry_fp32=fp32)
+    gam_d, st_d, _ = ex.transport_streamed(ctx, grid, w.seed, w.lambda_lo, w.lambda_hi,
+                                           w.n_packets, atom=atom, pops=cold, cell_volume=V,
+                                           geometry_fp32=fp32, octant_table=False)
+    torch.cuda.synchronize()
+    a, b = ex.stats_dict(st_d), ex.stats_dict(st_t)
+    for k in ("n_inter", "n_checks", "n_cross", "n_escaped", "n_killed"):
+        assert a[k] == b[k], k
+    assert a["error_flag"] == 0 and a["bad_packets"] == 0
+    _close(gam_d, gam_t, 1e-12, "rates")
+
+
+def test_direct_rates_need_a_consistent_line_map(ex, ctx):
+    w = synth.clumpy(n=16, n_lines=1500, n_packets=10_000, number=2)
+    atom, cold, grid = _coupled(ex, ctx, w)
+    say("case: direct streamed rates with the grid's line map broken")
+    lt = grid.line_trans.clone()
+    k = int(torch.nonzero(lt >= 0)[0])
+    grid.line_trans[k] = -1  # one atom line no longer maps back to its transition
+    with pytest.raises(ex.ExtrassError, match="inverse"):
+        ex.transport_streamed(ctx, grid, w.seed, w.lambda_lo, w.lambda_hi, w.n_packets,
+                              atom=atom, pops=cold, cell_volume=ex.cell_volume(w),
+                              octant_table=False)
+    torch.cuda.synchronize()
+    grid.line_trans.copy_(lt)
+    with pytest.raises(ex.ExtrassError, match="invalid argument"):
+        ex.transport_streamed(ctx, grid, w.seed, w.lambda_lo, w.lambda_hi, w.n_packets,
+                              atom=atom, pops=cold, cell_volume=ex.cell_volume(w),
+                              octant_table=False, est_global=True)
+
+
 def test_streamed_fp64_matches_oracle(ex, ctx):
     w = synth.sphere_small()
     say("case: streamed FP64 vs oracle, sphere 16^3, 200 lines, 1e5 packets")
