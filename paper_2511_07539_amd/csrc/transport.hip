@@ -347,6 +347,16 @@ struct Packet {
   bool bad;
 };
 
+// The record of line k, or an empty one past the red end of the list.
+__device__ __forceinline__ LineRec line_rec(const TArgs& A, int k) {
+  LineRec r;
+  r.inv_lam = 0.0;
+  r.trans = -1;
+  r.tau0 = 0.0f;
+  if (k < A.L) r = A.lines[k];
+  return r;
+}
+
 template <class G>
 __device__ __forceinline__ G wall(const TArgs& A, int i) {
   return static_cast<G>(-A.beta + static_cast<double>(i) * A.h);
@@ -502,6 +512,8 @@ template <class G>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_transport(TArgs A) {
   const int lane = threadIdx.x & 63;
   Packet<G> q;
+  LineRec nxt;  // record of line q.k, loaded ahead so that the event does not wait for it
+  nxt.trans = -1;
   int64_t pid = -1;
   bool done = false;
   uint64_t pool_base = 0, pool_left = 0;
@@ -538,6 +550,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
           const int64_t idx = (int64_t)(pool_base + rank);
           if (A.oct >= 0 && idx >= A.n_emit) {
             pid = resume<G>(A.inbox[idx - A.n_emit], q);
+            nxt = line_rec(A, q.k);
           } else {  // one emission site for both modes keeps the register peak down
             const int64_t p = A.oct < 0 ? A.first + idx : octant_packet(A, idx);
             emit<G>(A, p, q);
@@ -547,6 +560,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
             } else {
               pid = p;
               t.w_emit += q.w0;
+              nxt = line_rec(A, q.k);
             }
           }
         } else if (exhausted) {
@@ -583,11 +597,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     const int64_t row = A.oct < 0 ? c
         : (q.ci[0] - A.lo[0]) + (int64_t)A.half * ((q.ci[1] - A.lo[1]) + (int64_t)A.half * (q.ci[2] - A.lo[2]));
     bool line_event = false;
-    LineRec lr;
-    lr.trans = -1;
-    lr.tau0 = 0.0f;
+    const LineRec lr = nxt;
     if (q.k < A.L) {
-      lr = A.lines[q.k];
       const G Dk = static_cast<G>(1.0 - q.lamL * lr.inv_lam);
       line_event = Dk <= q.Dexit;
     }
@@ -603,18 +614,24 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
       } else {
         tau = static_cast<double>(lr.tau0) * static_cast<double>(A.tau_scale[c]);
       }
+      // the next line's record, and this line's wavelength, are loaded
+      // before the estimator atomic: a later wait for them then need not
+      // wait for the atomic as well
+      q.k = k + 1;
+      nxt = line_rec(A, k + 1);
       if (tau > kTauMin) {
         t.inter++;
+        const double lam_k = A.lam[k];
         const double dN = q.w * (-expm1(-tau));
+        q.wabs += dN;
+        q.w = q.w * exp(-tau);
         if (A.gdirect) {
           if (tr >= 0) atomicAdd(A.gdirect + c * A.T + tr, dN / fc);
         } else {
           atomicAdd(A.est + row * A.L + k, dN / fc);
           if (A.touched) A.touched[row] = 1;
         }
-        q.wabs += dN;
-        q.w = q.w * exp(-tau);
-        if (q.w * q.lam_e < (kKillFrac * q.w0) * A.lam[k]) {
+        if (q.w * q.lam_e < (kKillFrac * q.w0) * lam_k) {
           t.w_kill += q.w;
           t.killed++;
           if (A.pk_out) {
@@ -624,7 +641,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
           stop = true;
         }
       }
-      q.k = k + 1;
     } else {
       bool out = false;
       for (int a = 0; a < 3; ++a) {
