@@ -606,14 +606,16 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     if (line_event) {
       const int k = q.k;
       t.checks++;
-      double tau, fc = 1.0;
+      // the cell's scale is loaded for every lane, so that the opacity
+      // loads of both kinds of line are in flight before the first use
+      const float ts = A.tau_scale[c];
+      double tct = 0.0, fc = 1.0;
       const int tr = lr.trans;
       if (tr >= 0) {
-        tau = A.tau_ct[c * A.T + tr];
+        tct = A.tau_ct[c * A.T + tr];
         if (A.fcorr_ct) fc = A.fcorr_ct[c * A.T + tr];
-      } else {
-        tau = static_cast<double>(lr.tau0) * static_cast<double>(A.tau_scale[c]);
       }
+      const double tau = tr >= 0 ? tct : static_cast<double>(lr.tau0) * static_cast<double>(ts);
       // the next line's record, and this line's wavelength, are loaded
       // before the estimator atomic: a later wait for them then need not
       // wait for the atomic as well
