@@ -573,8 +573,54 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     if (__ballot(!done) == 0ull) break;
     if (pid < 0) continue;
 
-    // ---- one event of this lane's packet
-    if (!q.have_exit) {
+    // ---- events of this lane's packet. A lane whose segment has no line
+    // left before the wall crosses it, and the line test of the new segment
+    // follows in the same pass, so that a pass of the wave does a crossing
+    // and a line event where the packet's next two events are those. The
+    // order of events of each packet is unchanged.
+    bool stop = false;
+    bool line_event = q.have_exit && q.k < A.L && static_cast<G>(1.0 - q.lamL * nxt.inv_lam) <= q.Dexit;
+    if (q.have_exit && !line_event) {
+      bool out = false;
+      for (int a = 0; a < 3; ++a) {
+        if (q.dist[a] == q.smin) {
+          if (q.d[a] > G(0)) {
+            q.ci[a] += 1;
+            q.x[a] = wall<G>(A, q.ci[a]);
+          } else {
+            q.x[a] = wall<G>(A, q.ci[a]);
+            q.ci[a] -= 1;
+          }
+          if (q.ci[a] < 0 || q.ci[a] >= A.n) out = true;
+        } else {
+          q.x[a] = q.x[a] + q.s * q.d[a];
+        }
+      }
+      q.D = q.Dexit;
+      q.have_exit = false;
+      if (out) {
+        t.w_esc += q.w;
+        t.escaped++;
+        if (A.pk_out) {
+          double* o = A.pk_out + 4 * (pid - A.first);
+          o[0] = q.w; o[1] = q.lamL; o[2] = 0.0; o[3] = q.wabs;
+        }
+        stop = true;
+      } else {
+        t.cross++;
+        if (A.oct >= 0) {
+          const int dst = (q.ci[0] >= A.half) | ((q.ci[1] >= A.half) << 1) | ((q.ci[2] >= A.half) << 2);
+          if (dst != A.oct) {  // hand the packet to its next octant
+            const unsigned long long slot = atomicAdd(A.qtail + dst, 1ull);
+            if ((int64_t)slot < A.qcap) store<G>(A.qbase + (int64_t)dst * A.qcap + (int64_t)slot, q, pid);
+            else t.overflow = true;
+            pid = -1;
+            continue;
+          }
+        }
+      }
+    }
+    if (!stop && !q.have_exit) {  // a new packet, or a new segment after a crossing
       G smin = static_cast<G>(INFINITY);
       for (int a = 0; a < 3; ++a) {
         G dd = static_cast<G>(INFINITY);
@@ -592,18 +638,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
         pid = -1;
         continue;
       }
+      line_event = q.k < A.L && static_cast<G>(1.0 - q.lamL * nxt.inv_lam) <= q.Dexit;
     }
-    const int64_t c = q.ci[0] + (int64_t)A.n * (q.ci[1] + (int64_t)A.n * q.ci[2]);
-    const int64_t row = A.oct < 0 ? c
-        : (q.ci[0] - A.lo[0]) + (int64_t)A.half * ((q.ci[1] - A.lo[1]) + (int64_t)A.half * (q.ci[2] - A.lo[2]));
-    bool line_event = false;
-    const LineRec lr = nxt;
-    if (q.k < A.L) {
-      const G Dk = static_cast<G>(1.0 - q.lamL * lr.inv_lam);
-      line_event = Dk <= q.Dexit;
-    }
-    bool stop = false;
     if (line_event) {
+      const LineRec lr = nxt;
+      const int64_t c = q.ci[0] + (int64_t)A.n * (q.ci[1] + (int64_t)A.n * q.ci[2]);
+      const int64_t row = A.oct < 0 ? c
+          : (q.ci[0] - A.lo[0]) + (int64_t)A.half * ((q.ci[1] - A.lo[1]) + (int64_t)A.half * (q.ci[2] - A.lo[2]));
       const int k = q.k;
       t.checks++;
       // the cell's scale is loaded for every lane, so that the opacity
@@ -641,45 +682,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
             o[0] = 0.0; o[1] = q.lamL; o[2] = q.w; o[3] = q.wabs;
           }
           stop = true;
-        }
-      }
-    } else {
-      bool out = false;
-      for (int a = 0; a < 3; ++a) {
-        if (q.dist[a] == q.smin) {
-          if (q.d[a] > G(0)) {
-            q.ci[a] += 1;
-            q.x[a] = wall<G>(A, q.ci[a]);
-          } else {
-            q.x[a] = wall<G>(A, q.ci[a]);
-            q.ci[a] -= 1;
-          }
-          if (q.ci[a] < 0 || q.ci[a] >= A.n) out = true;
-        } else {
-          q.x[a] = q.x[a] + q.s * q.d[a];
-        }
-      }
-      q.D = q.Dexit;
-      q.have_exit = false;
-      if (out) {
-        t.w_esc += q.w;
-        t.escaped++;
-        if (A.pk_out) {
-          double* o = A.pk_out + 4 * (pid - A.first);
-          o[0] = q.w; o[1] = q.lamL; o[2] = 0.0; o[3] = q.wabs;
-        }
-        stop = true;
-      } else {
-        t.cross++;
-        if (A.oct >= 0) {
-          const int dst = (q.ci[0] >= A.half) | ((q.ci[1] >= A.half) << 1) | ((q.ci[2] >= A.half) << 2);
-          if (dst != A.oct) {  // hand the packet to its next octant
-            const unsigned long long slot = atomicAdd(A.qtail + dst, 1ull);
-            if ((int64_t)slot < A.qcap) store<G>(A.qbase + (int64_t)dst * A.qcap + (int64_t)slot, q, pid);
-            else t.overflow = true;
-            pid = -1;
-            continue;
-          }
         }
       }
     }
