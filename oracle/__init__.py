@@ -18,7 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 _lib = None
 
-PKT_FIELDS = 8
+PKT_FIELDS = 11
 N_STATS = 9
 STAT_NAMES = ["w_emit", "w_esc", "w_kill", "w_abs", "n_inter", "n_checks", "n_cross",
               "n_escaped", "n_killed"]
@@ -167,7 +167,7 @@ def transport(inp: TransportInputs, first=0, count=None, nthreads=None, per_pack
     """Runs the oracle over packets [first, first+count).
 
     Returns dict(records=(packet, cell, line, value) structured array in packet
-    order, stats=dict, packets=[count, 8] per-packet results if per_packet).
+    order, stats=dict, packets=[count, 11] per-packet results if per_packet).
     """
     if count is None:
         count = inp.n_packets - first
@@ -197,6 +197,44 @@ def dense_estimator(records, n_cells, n_lines):
     idx = records["cell"].astype(np.int64) * n_lines + records["line"]
     np.add.at(est, idx, records["value"])
     return est.reshape(n_cells, n_lines)
+
+
+PLANCK_CGS = 6.62607015e-27   # erg s
+LIGHT_CGS = 2.99792458e10     # cm s^-1
+
+
+def spectrum(packets, n_theta, n_phi, n_lambda, lambda_min, lambda_max):
+    """Emergent spectra per viewer (Sec. 2.3: rays leave towards viewers spread
+    evenly in polar and azimuthal angle, 20 x 20 by default; the emergent
+    emission is binned logarithmically in wavelength).
+
+    packets: per-packet results of transport(..., per_packet=True). Every
+    escaped packet (field 0, the escaped weight w, > 0) falls in the viewer
+    bin of its lab-frame direction (fields 8-10): theta = arccos(n_z) in
+    n_theta equal bins of [0, pi], phi = atan2(n_y, n_x) taken into
+    [0, 2 pi) in n_phi equal bins; and in the wavelength bin
+    floor(n_lambda ln(lambda_L / lambda_min) / ln(lambda_max / lambda_min))
+    of its lab wavelength (field 1) when lambda_min <= lambda_L < lambda_max.
+    Returns (photons, energy), each [n_theta, n_phi, n_lambda]: the sums of w
+    and of w h c / lambda_L (erg s^-1), packets in order."""
+    pk = np.asarray(packets, dtype=np.float64)
+    photons = np.zeros((n_theta, n_phi, n_lambda))
+    energy = np.zeros((n_theta, n_phi, n_lambda))
+    inv_dlog = n_lambda / np.log(lambda_max / lambda_min)
+    for r in pk:
+        w, lam = r[0], r[1]
+        if not w > 0.0 or not (lambda_min <= lam < lambda_max):
+            continue
+        b = min(max(int(np.floor(np.log(lam / lambda_min) * inv_dlog)), 0), n_lambda - 1)
+        theta = np.arccos(min(1.0, max(-1.0, r[10])))
+        it = min(max(int(np.floor(theta * (n_theta / np.pi))), 0), n_theta - 1)
+        phi = np.arctan2(r[9], r[8])
+        if phi < 0.0:
+            phi += 2.0 * np.pi
+        ip = min(max(int(np.floor(phi * (n_phi / (2.0 * np.pi)))), 0), n_phi - 1)
+        photons[it, ip, b] += w
+        energy[it, ip, b] += w * (PLANCK_CGS * LIGHT_CGS / lam)
+    return photons, energy
 
 
 def line_tau(pops, atom, t_exp):

@@ -45,8 +45,9 @@ typedef struct {
  * 0 escaped weight, 1 lab wavelength lambda_L, 2 killed weight,
  * 3 absorbed photons (sum of dN), 4 absorbed comoving energy / (hc),
  * 5 adiabatic loss / (hc), 6 emitted comoving energy / (hc),
- * 7 remaining comoving energy / (hc) at escape or kill. */
-enum { OR_PKT_FIELDS = 8 };
+ * 7 remaining comoving energy / (hc) at escape or kill,
+ * 8-10 lab-frame direction (unchanged along the ray). */
+enum { OR_PKT_FIELDS = 11 };
 /* Global stats (doubles): w_emit, w_esc, w_kill, w_abs, n_inter, n_checks,
  * n_cross, n_escaped, n_killed. */
 enum { OR_STATS = 9 };

@@ -218,6 +218,9 @@ done:
   res[3] = w_abs;
   res[4] = e_abs;
   res[5] = e_adiab;
+  res[8] = dir[0];
+  res[9] = dir[1];
+  res[10] = dir[2];
   if (out) memcpy(out, res, sizeof(res));
 }
 
