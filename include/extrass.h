@@ -131,12 +131,45 @@ size_t extrass_transport_workspace(const extrass_grid* g, const extrass_source* 
 /* Runs the packets and OVERWRITES est[C*L] (cell-major, FP64) with their
  * photoexcitation counts (photons s^-1 absorbed per cell and line, divided by
  * f_corr). stats[EXTRASS_STATS] is overwritten. packets_out, if not NULL,
- * receives 4 doubles per packet: escaped weight, lab wavelength, weight at the
- * stop, absorbed photons. Host structs `g` and `s` are read during the call
- * only. */
+ * receives EXTRASS_PACKET_FIELDS doubles per packet, packet first_packet + i
+ * at record i: escaped weight (0 if stopped), lab wavelength (cm), weight at
+ * the stop (0 if escaped), absorbed photons, the lab-frame direction n_x, n_y,
+ * n_z (unchanged along the ray; FP32-rounded with geometry_fp32), and 0.
+ * Packets dropped as bad leave their record untouched. Host structs `g` and
+ * `s` are read during the call only. */
+enum { EXTRASS_PACKET_FIELDS = 8 };
 int extrass_transport(extrass_handle h, const extrass_grid* g, const extrass_source* s,
                       double* est, double* stats, double* packets_out, void* ws,
                       size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Emergent spectra per viewer (Sec. 2.3: rays leave towards 20 x 20 viewers
+ * spread evenly in polar and azimuthal angle; the emission is binned
+ * logarithmically in wavelength; global convergence compares the total
+ * energy in the emergent spectra with the deposition). Each escaped packet
+ * record (escaped weight w > 0) of `packets` (device, the layout
+ * extrass_transport writes) is assigned to the viewer bin of its direction,
+ * theta = acos(n_z) in n_theta equal bins of [0, pi] and
+ * phi = atan2(n_y, n_x) mod 2 pi in n_phi equal bins of [0, 2 pi), and to
+ * the wavelength bin floor(n_lambda ln(lambda_L / lambda_min) /
+ * ln(lambda_max / lambda_min)) when lambda_min <= lambda_L < lambda_max
+ * (others are not binned). photons (if not NULL) receives w, energy (if not
+ * NULL) w h c / lambda_L (erg s^-1), both ADDED at
+ * [(i_theta * n_phi + i_phi) * n_lambda + i_lambda] (device,
+ * n_theta * n_phi * n_lambda doubles; zero them first). Dividing by a
+ * viewer's solid angle, 2 pi / n_phi (cos theta_lo - cos theta_hi), and by
+ * 4 pi gives the isotropic-equivalent rates. Bins: 1..4096 per angle,
+ * 1..2^20 in wavelength, 0 < lambda_min < lambda_max; EXTRASS_EINVAL
+ * otherwise.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  int32_t n_theta, n_phi, n_lambda;
+  double lambda_min, lambda_max;   /* cm */
+} extrass_spectrum_bins;
+
+int extrass_spectrum(extrass_handle h, const double* packets, int64_t n_packets,
+                     const extrass_spectrum_bins* bins, double* photons, double* energy,
+                     void* stream);
 
 /* ------------------------------------------------------------------------
  * Eq. A2: tau_S = (A_ul / 8 pi) (g_u / g_l) lambda^3 n_l (1 - g_l n_u / (g_u n_l)) t

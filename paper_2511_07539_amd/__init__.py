@@ -25,6 +25,7 @@ _lib = C.CDLL(LIB_PATH)
 
 OK, EINVAL, ENOSPACE, EHIP, EUNSUPPORTED = 0, -1, -2, -3, -4
 STATS = 16
+PACKET_FIELDS = 8  # doubles per packet record (EXTRASS_PACKET_FIELDS)
 STAT_NAMES = ["w_emit", "w_esc", "w_kill", "w_abs", "n_inter", "n_checks", "n_cross",
               "n_escaped", "n_killed"]
 STAT_ERROR_FLAG = 15
@@ -36,6 +37,11 @@ class _Grid(C.Structure):
                 ("n_lines", C.c_int32), ("line_lambda", C.c_void_p), ("line_tau0", C.c_void_p),
                 ("line_trans", C.c_void_p), ("n_trans", C.c_int32), ("tau_ct", C.c_void_p),
                 ("fcorr_ct", C.c_void_p)]
+
+
+class _SpecBins(C.Structure):
+    _fields_ = [("n_theta", C.c_int32), ("n_phi", C.c_int32), ("n_lambda", C.c_int32),
+                ("lambda_min", C.c_double), ("lambda_max", C.c_double)]
 
 
 class _Source(C.Structure):
@@ -82,6 +88,7 @@ _lib.extrass_error_string.restype = C.c_char_p
 _lib.extrass_error_string.argtypes = [C.c_int]
 _lib.extrass_last_error.restype = C.c_char_p
 _lib.extrass_last_error.argtypes = [_vp]
+_lib.extrass_spectrum.argtypes = [_vp, _vp, C.c_int64, C.POINTER(_SpecBins), _vp, _vp, _vp]
 _lib.extrass_transport_workspace.restype = C.c_size_t
 _lib.extrass_transport_workspace.argtypes = [C.POINTER(_Grid), C.POINTER(_Source)]
 _lib.extrass_transport.argtypes = [_vp, C.POINTER(_Grid), C.POINTER(_Source), _vp, _vp, _vp, _vp,
@@ -226,7 +233,7 @@ def grid_from_workload(w, device="cuda:0", tau_ct=None, fcorr_ct=None):
 def transport(ctx: Context, grid: Grid, seed, lambda_lo, lambda_hi, n_packets, first_packet=0,
               iteration=0, geometry_fp32=False, explicit_packets=None, est=None, stats=None,
               packets_out=False):
-    """Runs extrass_transport; returns (est [C, L] f64, stats [16] f64, packets [P, 4] or None)."""
+    """Runs extrass_transport; returns (est [C, L] f64, stats [16] f64, packets [P, 8] or None)."""
     dev = grid.line_lambda.device
     expl = _dev(explicit_packets, torch.float64, dev)
     g = grid.struct()
@@ -236,13 +243,33 @@ def transport(ctx: Context, grid: Grid, seed, lambda_lo, lambda_hi, n_packets, f
         est = torch.empty((grid.n_cells, grid.n_lines), dtype=torch.float64, device=dev)
     if stats is None:
         stats = torch.empty(STATS, dtype=torch.float64, device=dev)
-    pk = torch.zeros((n_packets, 4), dtype=torch.float64, device=dev) if packets_out else None
+    pk = (torch.zeros((n_packets, PACKET_FIELDS), dtype=torch.float64, device=dev)
+          if packets_out else None)
     need = _lib.extrass_transport_workspace(C.byref(g), C.byref(s))
     ws = ctx.workspace(need)
     rc = _lib.extrass_transport(ctx.h, C.byref(g), C.byref(s), _ptr(est), _ptr(stats), _ptr(pk),
                                 _ptr(ws), ws.numel(), _stream())
     ctx.check(rc, "extrass_transport")
     return est, stats, pk
+
+
+def spectrum(ctx: Context, packets, n_theta, n_phi, n_lambda, lambda_min, lambda_max,
+             photons=None, energy=None):
+    """Runs extrass_spectrum on per-packet records [P, 8] (device f64, as transport
+    writes them). Adds into photons / energy [n_theta, n_phi, n_lambda] (zeros
+    allocated when None); returns (photons, energy)."""
+    pk = packets.contiguous()
+    dev = pk.device
+    shape = (int(n_theta), int(n_phi), int(n_lambda))
+    if photons is None:
+        photons = torch.zeros(shape, dtype=torch.float64, device=dev)
+    if energy is None:
+        energy = torch.zeros(shape, dtype=torch.float64, device=dev)
+    b = _SpecBins(shape[0], shape[1], shape[2], float(lambda_min), float(lambda_max))
+    rc = _lib.extrass_spectrum(ctx.h, _ptr(pk), pk.shape[0], C.byref(b), _ptr(photons),
+                               _ptr(energy), _stream())
+    ctx.check(rc, "extrass_spectrum")
+    return photons, energy
 
 
 def transport_streamed(ctx: Context, grid: Grid, seed, lambda_lo, lambda_hi, n_packets,

@@ -46,6 +46,7 @@ static inline int lam_bins(int L) {
   return n;
 }
 constexpr int kBlock = 256;
+constexpr int kPkFields = 8;         // doubles per packet record
 
 struct alignas(16) LineRec {
   double inv_lam;
@@ -357,6 +358,21 @@ __device__ __forceinline__ LineRec line_rec(const TArgs& A, int k) {
   return r;
 }
 
+// Per-packet record at the stop: escaped weight, lab wavelength, weight at a
+// kill, absorbed photons, the direction (lab frame; unchanged along the ray),
+// and a zero.
+template <class G>
+__device__ __forceinline__ void put_record(double* o, const Packet<G>& q, double w_esc, double w_kill) {
+  o[0] = w_esc;
+  o[1] = q.lamL;
+  o[2] = w_kill;
+  o[3] = q.wabs;
+  o[4] = (double)q.d[0];
+  o[5] = (double)q.d[1];
+  o[6] = (double)q.d[2];
+  o[7] = 0.0;
+}
+
 template <class G>
 __device__ __forceinline__ G wall(const TArgs& A, int i) {
   return static_cast<G>(-A.beta + static_cast<double>(i) * A.h);
@@ -601,10 +617,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
       if (out) {
         t.w_esc += q.w;
         t.escaped++;
-        if (A.pk_out) {
-          double* o = A.pk_out + 4 * (pid - A.first);
-          o[0] = q.w; o[1] = q.lamL; o[2] = 0.0; o[3] = q.wabs;
-        }
+        if (A.pk_out) put_record<G>(A.pk_out + kPkFields * (pid - A.first), q, q.w, 0.0);
         stop = true;
       } else {
         t.cross++;
@@ -677,10 +690,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
         if (q.w * q.lam_e < (kKillFrac * q.w0) * lam_k) {
           t.w_kill += q.w;
           t.killed++;
-          if (A.pk_out) {
-            double* o = A.pk_out + 4 * (pid - A.first);
-            o[0] = 0.0; o[1] = q.lamL; o[2] = q.w; o[3] = q.wabs;
-          }
+          if (A.pk_out) put_record<G>(A.pk_out + kPkFields * (pid - A.first), q, 0.0, q.w);
           stop = true;
         }
       }
