@@ -71,6 +71,12 @@ __device__ __forceinline__ double read_lane_d(double v, int l) {
   return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
                           __builtin_amdgcn_readlane(__double2loint(v), l));
 }
+// A value every lane holds (a wave reduction, a per-system constant) kept in
+// scalar registers: the vector registers are the scarce ones in the solvers.
+__device__ __forceinline__ double uniform_d(double v) {
+  return __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(v)),
+                          __builtin_amdgcn_readfirstlane(__double2loint(v)));
+}
 constexpr int kDppXor1 = 0xB1;         // quad_perm [1,0,3,2]
 constexpr int kDppXor2 = 0x4E;         // quad_perm [2,3,0,1]
 constexpr int kDppHalfMirror = 0x141;  // lane 7-i within each 8
@@ -81,7 +87,7 @@ __device__ inline double wave_sum(double v) {
   v += dpp_mov<kDppXor2>(v);
   v += dpp_mov<kDppHalfMirror>(v);
   v += dpp_mov<kDppMirror>(v);
-  return (read_lane_d(v, 0) + read_lane_d(v, 16)) + (read_lane_d(v, 32) + read_lane_d(v, 48));
+  return uniform_d((read_lane_d(v, 0) + read_lane_d(v, 16)) + (read_lane_d(v, 32) + read_lane_d(v, 48)));
 }
 __device__ inline float wave_sum(float v) {
   v += dpp_mov<kDppXor1>(v);
@@ -99,7 +105,7 @@ __device__ inline double wave_max(double v) {
   v = fmax(v, dpp_mov<kDppXor2>(v));
   v = fmax(v, dpp_mov<kDppHalfMirror>(v));
   v = fmax(v, dpp_mov<kDppMirror>(v));
-  return fmax(fmax(read_lane_d(v, 0), read_lane_d(v, 16)), fmax(read_lane_d(v, 32), read_lane_d(v, 48)));
+  return uniform_d(fmax(fmax(read_lane_d(v, 0), read_lane_d(v, 16)), fmax(read_lane_d(v, 32), read_lane_d(v, 48))));
 }
 __device__ inline uint64_t wave_sum_u64(uint64_t v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);

@@ -461,12 +461,12 @@ __device__ __forceinline__ bool reduce_blocks(const double* G, const int2* rt, i
   double u[2], d[2], bg[3], pg[3], xg[3];
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
-    u[q] = q + 1 < K ? small[2 * q] : 1.0;
-    d[q] = q + 1 < K ? small[2 * q + 1] : 1.0;
+    u[q] = uniform_d(q + 1 < K ? small[2 * q] : 1.0);
+    d[q] = uniform_d(q + 1 < K ? small[2 * q + 1] : 1.0);
   }
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
-    bg[q] = (rhs && q < K) ? small[6 + 2 * q] + (q > 0 ? small[6 + 2 * (q - 1) + 1] : 0.0) : 0.0;
+    bg[q] = uniform_d((rhs && q < K) ? small[6 + 2 * q] + (q > 0 ? small[6 + 2 * (q - 1) + 1] : 0.0) : 0.0);
     pg[q] = 0.0;
     xg[q] = 0.0;
   }
@@ -620,7 +620,7 @@ __device__ __forceinline__ int solve_system(const NArgs& A, const Sys& y, double
       double best = -1.0;
 #pragma unroll
       for (int q = 0; q < 3; ++q) {
-        const double v = __shfl(n, q < y.nst ? bl.st[q] : 0, 64);
+        const double v = uniform_d(__shfl(n, q < y.nst ? bl.st[q] : 0, 64));
         if (q < y.nst && v > best) {
           best = v;
           pin = q;
@@ -658,7 +658,7 @@ __device__ __forceinline__ int solve_system(const NArgs& A, const Sys& y, double
       const double psum = wave_sum(live ? pp : 0.0);
       const double nw = live ? y.ntot * (pp / psum) : 0.0;
       const double change = wave_max(live ? fabs(log(nw / n)) : 0.0);
-      if (change > 0.999 * prev) omega = omega * 0.5 > 1.0 / 1024 ? omega * 0.5 : 1.0 / 1024;
+      if (change > 0.999 * prev) omega = uniform_d(omega * 0.5 > 1.0 / 1024 ? omega * 0.5 : 1.0 / 1024);
       prev = change;
       const double v = live ? exp((1.0 - omega) * log(n) + omega * log(nw)) : 0.0;
       const double tot = wave_sum(v);
@@ -681,7 +681,7 @@ __device__ __forceinline__ int solve_system(const NArgs& A, const Sys& y, double
         if (phi2 < phi || res2 < 1e-14) {  // accept the trial point
           n = trial;
           h = hv;
-          if (taken >= 0.99 * Delta) Delta = 2.0 * Delta < 30.0 ? 2.0 * Delta : 30.0;
+          if (taken >= 0.99 * Delta) Delta = uniform_d(2.0 * Delta < 30.0 ? 2.0 * Delta : 30.0);
           ++it;
           used = it;
           if (it >= max_iter) return -1;
@@ -698,7 +698,7 @@ __device__ __forceinline__ int solve_system(const NArgs& A, const Sys& y, double
           last_full = taken == step ? step : 0.0;
           phase = NEWTON;
         } else {
-          Delta = (taken < Delta ? taken : Delta) / 4.0;
+          Delta = uniform_d((taken < Delta ? taken : Delta) / 4.0);
           if (++bt >= 40) return (step < 1e-11 || res < 1e-14) ? it + 1 : -1;
         }
       }
@@ -710,7 +710,7 @@ __device__ __forceinline__ int solve_system(const NArgs& A, const Sys& y, double
       double pi = __shfl(xo[1], src, 64);
       if (!live) x = pi = 0.0;
       const double sum_n = wave_sum(n), sum_nx = wave_sum(n * x), sum_npi = wave_sum(n * pi);
-      const double cst = ((y.ntot - sum_n) - sum_nx) / sum_npi;
+      const double cst = uniform_d(((y.ntot - sum_n) - sum_nx) / sum_npi);
       x += cst * pi;
       if (!live) x = 0.0;
       step = wave_max(fabs(x));
@@ -723,8 +723,8 @@ __device__ __forceinline__ int solve_system(const NArgs& A, const Sys& y, double
       phase = TRIAL;
     }
     if (phase == TRIAL) {  // trial point in log(n) within the trust radius
-      const double scale = step > Delta ? Delta / step : 1.0;
-      taken = step * scale;
+      const double scale = uniform_d(step > Delta ? Delta / step : 1.0);
+      taken = uniform_d(step * scale);
       const double v = live ? n * exp(scale * x) : 0.0;
       const double tot = wave_sum(v);
       trial = live ? v * (y.ntot / tot) : 0.0;
@@ -744,10 +744,11 @@ __device__ double cold_start(const Sys& y, bool live) {
     const double rc = y.rec[zz - 1];
     double r = rc > 0.0 ? y.gion[zz - 1] / rc : 1e30;
     r = r < 1e-30 ? 1e-30 : (r > 1e30 ? 1e30 : r);
-    ratio[zz] = ratio[zz - 1] * r;
+    ratio[zz] = uniform_d(ratio[zz - 1] * r);
   }
   double rsum = 0.0;
   for (int zz = 0; zz < y.nst; ++zz) rsum += ratio[zz];
+  rsum = uniform_d(rsum);
   return live ? y.ntot * (ratio[y.z] / rsum) * (w / ss[y.z]) : 0.0;
 }
 
@@ -775,30 +776,34 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 3))) void
     unsigned long long item = 0;
     if (lane == 0) item = atomicAdd(A.queue, 1ull);
     item = __shfl(item, 0, 64);
+    // every lane holds lane 0's value: make it, and what derives from it,
+    // scalar
+    item = ((unsigned long long)__builtin_amdgcn_readfirstlane((unsigned)(item >> 32)) << 32) |
+           (unsigned long long)__builtin_amdgcn_readfirstlane((unsigned)item);
     if (item >= (unsigned long long)items) break;
     Sys y;
     y.c = (int64_t)(item / A.S);
     y.s = (int)(item % A.S);
-    y.base = A.off[y.s];
-    y.Ns = A.off[y.s + 1] - y.base;
-    y.t0 = A.toff[y.s];
-    y.t1 = A.toff[y.s + 1];
-    y.nst = A.nstage[y.s];
-    y.ntot = A.n_species[y.c * A.S + y.s];
+    y.base = __builtin_amdgcn_readfirstlane(A.off[y.s]);
+    y.Ns = __builtin_amdgcn_readfirstlane(A.off[y.s + 1]) - y.base;
+    y.t0 = __builtin_amdgcn_readfirstlane(A.toff[y.s]);
+    y.t1 = __builtin_amdgcn_readfirstlane(A.toff[y.s + 1]);
+    y.nst = __builtin_amdgcn_readfirstlane(A.nstage[y.s]);
+    y.ntot = uniform_d(A.n_species[y.c * A.S + y.s]);
     double* out = A.pops + y.c * A.N + y.base;
     if (!(y.ntot > 0.0)) {
       if (lane < y.Ns) out[lane] = 0.0;
       continue;
     }
-    y.T = A.T_e[y.c];
-    y.ne = A.n_e[y.c];
+    y.T = uniform_d(A.T_e[y.c]);
+    y.ne = uniform_d(A.n_e[y.c]);
     y.kT = kBoltzmann * y.T;
-    y.ikT = 1.0 / y.kT;
-    y.isqT = 1.0 / sqrt(y.T);
-    const double tfac = pow(y.T / 1e4, -0.8);
+    y.ikT = uniform_d(1.0 / y.kT);
+    y.isqT = uniform_d(1.0 / sqrt(y.T));
+    const double tfac = uniform_d(pow(y.T / 1e4, -0.8));
     for (int zz = 0; zz < 3; ++zz) {
-      y.gion[zz] = A.gamma_ion[(y.c * A.S + y.s) * 3 + zz];
-      y.rec[zz] = y.ne * A.alpha0[y.s * 3 + zz] * tfac;
+      y.gion[zz] = uniform_d(A.gamma_ion[(y.c * A.S + y.s) * 3 + zz]);
+      y.rec[zz] = uniform_d(y.ne * A.alpha0[y.s * 3 + zz] * tfac);
     }
     const bool live = lane < y.Ns;
     const int li = live ? y.base + lane : y.base;
