@@ -346,6 +346,9 @@ __device__ __forceinline__ Blocks make_blocks(const Sys& y) {
   return k;
 }
 
+// An int every lane holds, read into a scalar register.
+__device__ __forceinline__ int rfl(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
 // 1/S for a positive normal S: the hardware reciprocal refined by two Newton
 // steps (error within a few ulps), without the scaling a full division does
 // for operands near the ends of the exponent range.
@@ -355,14 +358,6 @@ __device__ __forceinline__ double rcp_pos(double S) {
   r = fma(r, e, r);
   e = fma(-S, r, 1.0);
   return fma(r, e, r);
-}
-
-// Level of position p of block z.
-__device__ __forceinline__ int block_level(const Blocks& k, int z, int p) {
-  const int st = z == 0 ? k.st[0] : (z == 1 ? k.st[1] : k.st[2]);
-  const int nx = z == 0 ? k.nex[0] : (z == 1 ? k.nex[1] : k.nex[2]);
-  const int sn = z == 0 ? k.st[1] : (z == 1 ? k.st[2] : k.st[3]);
-  return p < nx ? st + 1 + p : (p == nx ? st : sn);
 }
 
 // Solves x^T Q = b^T (rhs, with x of the ground `pin` fixed at 0) and the
@@ -381,17 +376,29 @@ __device__ __forceinline__ bool reduce_blocks(const double* G, const int2* rt, i
   // [3][34]: pivot rows with the pivot and right-hand side in slots 32, 33
   double* rows = scratch;
   double* small = scratch + 102;  // reduced rates and right-hand sides of the ground pairs
-  const int z = lane < k.base[1] ? 0 : (lane < k.base[2] ? 1 : 2);
-  const bool live = z < k.nst && lane < k.base[3];
-  const int base = z == 0 ? k.base[0] : (z == 1 ? k.base[1] : k.base[2]);
+  // The lane's block quantities are selected by its block z among values
+  // every lane holds. Selecting among the descriptor's array elements
+  // directly made the compiler index a stack copy of the descriptor (a
+  // scratch load per use); read as scalars first, they are register selects.
+  const int base1 = rfl(k.base[1]), base2 = rfl(k.base[2]);
+  const int z = lane < base1 ? 0 : (lane < base2 ? 1 : 2);
+  const bool live = z < k.nst && lane < rfl(k.base[3]);
+  const int base = z == 0 ? rfl(k.base[0]) : (z == 1 ? base1 : base2);
   const int r = lane - base;
-  const int nex = live ? (z == 0 ? k.nex[0] : (z == 1 ? k.nex[1] : k.nex[2])) : 0;
-  const int B = live ? (z == 0 ? k.B[0] : (z == 1 ? k.B[1] : k.B[2])) : 0;
-  const int my_lev = live ? block_level(k, z, r) : 0;
+  const int nex = live ? (z == 0 ? rfl(k.nex[0]) : (z == 1 ? rfl(k.nex[1]) : rfl(k.nex[2]))) : 0;
+  const int B = live ? (z == 0 ? rfl(k.B[0]) : (z == 1 ? rfl(k.B[1]) : rfl(k.B[2]))) : 0;
+  // the lane's block bounds and row-table entry, once for the unrolled loop
+  const int st0 = rfl(k.st[0]), st1 = rfl(k.st[1]), st2 = rfl(k.st[2]), st3 = rfl(k.st[3]);
+  const int st_z = z == 0 ? st0 : (z == 1 ? st1 : st2);
+  const int sn_z = z == 0 ? st1 : (z == 1 ? st2 : st3);
+  const int my_lev = live ? (r < nex ? st_z + 1 + r : (r == nex ? st_z : sn_z)) : 0;
+  const int2 my_rt = rt[my_lev];
   double g[NTB];
 #pragma unroll
-  for (int b = 0; b < NTB; ++b)
-    g[b] = (live && b < B && b != r) ? G[gat(rt, my_lev, block_level(k, z, b))] : 0.0;
+  for (int b = 0; b < NTB; ++b) {
+    const int lev_b = b < nex ? st_z + 1 + b : (b == nex ? st_z : sn_z);
+    g[b] = (live && b < B && b != r) ? G[my_rt.x + lev_b - my_rt.y] : 0.0;
+  }
   // the scratch below overlays G: keep every row load ahead of its stores
   __asm__ volatile("" ::: "memory");
   // right-hand side: a ground's entry is counted in its own block only
@@ -497,10 +504,12 @@ __device__ __forceinline__ bool reduce_blocks(const double* G, const int2* rt, i
   // needed); then, state by state in reverse elimination order, the state's
   // (x, pi) is published and the rows c < j of its block add x_j * a[j][c];
   // the ground rows first
-  const double gz_x = z == 0 ? xg[0] : (z == 1 ? xg[1] : xg[2]);
-  const double gz_p = z == 0 ? pg[0] : (z == 1 ? pg[1] : pg[2]);
-  const double gn_x = z == 0 ? xg[1] : (z == 1 ? xg[2] : 0.0);
-  const double gn_p = z == 0 ? pg[1] : (z == 1 ? pg[2] : 0.0);
+  const double xg0 = uniform_d(xg[0]), xg1 = uniform_d(xg[1]), xg2 = uniform_d(xg[2]);
+  const double pg0 = uniform_d(pg[0]), pg1 = uniform_d(pg[1]), pg2 = uniform_d(pg[2]);
+  const double gz_x = z == 0 ? xg0 : (z == 1 ? xg1 : xg2);
+  const double gz_p = z == 0 ? pg0 : (z == 1 ? pg1 : pg2);
+  const double gn_x = z == 0 ? xg1 : (z == 1 ? xg2 : 0.0);
+  const double gn_p = z == 0 ? pg1 : (z == 1 ? pg2 : 0.0);
   double xm = 0.0, pm = 0.0;
   if (live && r == nex) { xm = gz_x; pm = gz_p; }
   if (live && r == nex + 1) { xm = gn_x; pm = gn_p; }
