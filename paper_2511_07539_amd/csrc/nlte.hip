@@ -84,9 +84,13 @@ extern "C" int extrass_nlte_solve(extrass_handle h, extrass_atom_handle a, const
   A.gsz = a->maxNs * A.NP;
   A.block_rows = (a->blockLanes + 1) & ~1;
   const bool blocks_fit = !o->factor_fp32 && a->maxBlock <= 32 && a->blockLanes <= 64;
-  // stage blocks: kernels for blocks of at most 12, 16, 22, 24 or 32 states
+  // stage blocks: kernels for blocks of at most 12, 16, 21, 22, 24 or 32
+  // states (the reduction runs NTB - 1 unrolled steps on NTB-entry register
+  // rows, so a bound one above the largest block costs a step and an entry:
+  // 21 is the 20/15/15 atom's largest block)
   const int ntb = a->maxBlock <= 12 ? 12
                 : a->maxBlock <= 16 ? 16
+                : a->maxBlock <= 21 ? 21
                 : a->maxBlock <= 22 ? 22
                 : a->maxBlock <= 24 ? 24 : 32;
   // whole system: kernels for species of at most 16, 24, 32, 40, 50 or 64 levels

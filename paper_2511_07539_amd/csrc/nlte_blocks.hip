@@ -7,6 +7,7 @@ bool launch_nlte_blocks(int ntb, unsigned blocks, size_t lds, hipStream_t st, co
   switch (ntb) {
     case 12: hipLaunchKernelGGL((k_nlte<0, 12>), dim3(blocks), dim3(64), lds, st, A); return true;
     case 16: hipLaunchKernelGGL((k_nlte<0, 16>), dim3(blocks), dim3(64), lds, st, A); return true;
+    case 21: hipLaunchKernelGGL((k_nlte<0, 21>), dim3(blocks), dim3(64), lds, st, A); return true;
     case 22: hipLaunchKernelGGL((k_nlte<0, 22>), dim3(blocks), dim3(64), lds, st, A); return true;
     case 24: hipLaunchKernelGGL((k_nlte<0, 24>), dim3(blocks), dim3(64), lds, st, A); return true;
     case 32: hipLaunchKernelGGL((k_nlte<0, 32>), dim3(blocks), dim3(64), lds, st, A); return true;
