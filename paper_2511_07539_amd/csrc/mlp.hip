@@ -302,6 +302,97 @@ void backward(hipStream_t st, const float* P, const float* x, const float* t, in
 
 // Features of a cell: log10 n_tot, log10 T_e, log10 n_e, log10 deposition and
 // the number fractions of the two species, each normalised by (mean, std).
+// Inference of the whole network, 64 rows per work-group of 4 wavefronts
+// (16 rows each). Layer 1 is computed in FP32 as k_layer1 computes it; the
+// hidden and output layers run on BF16 MFMA 16x16x16 with K taken in chunks
+// of 64 and steps of 16, the order k_gemm takes it, so every output equals
+// forward()'s. The activations stay in LDS as BF16, the value k_gemm rounds
+// them to when it stages its next A tile; the weights are staged as BF16 in
+// 64 x 64 tiles. One launch replaces layer 1 and three GEMMs, and no
+// pre-activation is written.
+constexpr int kIR = 64;           // rows per work-group
+constexpr int kHS = kHid + 8;     // LDS row stride of the activations (bf16)
+
+__device__ __forceinline__ void infer_layer(__bf16 (*H)[kHS], __bf16 (*Ws)[BK + KPAD], const float* W,
+                                            const float* bias, int N, bool silu_out, float* y,
+                                            int64_t row0, int64_t B) {
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int ntile = (N + 15) / 16;  // 16 for the hidden layers, 7 for the output layer
+  f32x4 acc[16];
+#pragma unroll
+  for (int t = 0; t < 16; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int ar = wave * 16 + (lane & 15);
+  for (int kc = 0; kc < kHid; kc += BK) {
+    for (int nc = 0; nc < ntile * 16; nc += 64) {
+      // W tile: rows n in [nc, nc + 64), columns k in [kc, kc + 64); W[n][k] row-major
+      for (int e = tid; e < 64 * BK; e += 256) {
+        const int r = e / BK, kk = e % BK, n = nc + r;
+        Ws[r][kk] = static_cast<__bf16>(n < N ? W[n * kHid + kc + kk] : 0.f);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int ks = 0; ks < BK; ks += 16) {
+        const int kq = ks + 4 * (lane >> 4);
+        bf16x4 a;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) a[q] = H[ar][kc + kq + q];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int tt = nc / 16 + t;
+          if (tt < ntile) {
+            bf16x4 b;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) b[q] = Ws[t * 16 + (lane & 15)][kq + q];
+            acc[tt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[tt], 0, 0, 0);
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // every wave has read its rows of H: write the layer's output in place
+#pragma unroll
+  for (int t = 0; t < 16; ++t) {
+    if (t >= ntile) break;
+    const int n = t * 16 + (lane & 15);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int r = wave * 16 + 4 * (lane >> 4) + q;
+      if (n >= N) continue;
+      const float v = acc[t][q] + bias[n];
+      if (silu_out) {
+        H[r][n] = static_cast<__bf16>(silu(v));
+      } else if (row0 + r < B) {
+        y[(row0 + r) * kOut + n] = v;
+      }
+    }
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void k_mlp_infer(const float* __restrict__ x,
+                                                   const float* __restrict__ P, int64_t B,
+                                                   float* __restrict__ y) {
+  __shared__ __bf16 H[kIR][kHS];
+  __shared__ __bf16 Ws[64][BK + KPAD];
+  const int64_t row0 = (int64_t)blockIdx.x * kIR;
+  // layer 1 (K = 6), as k_layer1
+  for (int e = threadIdx.x; e < kIR * kHid; e += 256) {
+    const int r = e / kHid, o = e % kHid;
+    const int64_t b = row0 + r;
+    float s = P[kOffB1 + o];
+    if (b < B) {
+#pragma unroll
+      for (int i = 0; i < kIn; ++i) s += x[b * kIn + i] * P[kOffW1 + o * kIn + i];
+    }
+    H[r][o] = static_cast<__bf16>(silu(s));
+  }
+  __syncthreads();
+  infer_layer(H, Ws, P + kOffW2, P + kOffB2, kHid, true, nullptr, row0, B);
+  infer_layer(H, Ws, P + kOffW3, P + kOffB3, kHid, true, nullptr, row0, B);
+  infer_layer(H, Ws, P + kOffW4, P + kOffB4, kOut, false, y, row0, B);
+}
+
 __global__ void k_features(int64_t c0, int64_t n, int S, const double* __restrict__ T,
                            const double* __restrict__ ne, const double* __restrict__ ns,
                            const double* __restrict__ dep, const float* __restrict__ norm,
@@ -431,7 +522,8 @@ extern "C" int extrass_nlte_warm_start(extrass_handle h, extrass_atom_handle ato
     const int64_t n = std::min(chunk, C - c0);
     hipLaunchKernelGGL(k_features, dim3(blocks_for(n)), dim3(256), 0, st, c0, n, atom->S,
                        cells->T_e, cells->n_e, cells->n_species, deposition, norm, x);
-    forward(st, params, x, n, a);
+    hipLaunchKernelGGL(k_mlp_infer, dim3((unsigned)((n + kIR - 1) / kIR)), dim3(256), 0, st, x,
+                       params, n, a.y);
     hipLaunchKernelGGL(k_warm_out, dim3((unsigned)((n * atom->S + 3) / 4)), dim3(256), 0, st, c0,
                        n, atom->S, atom->d.off, cells->n_species, norm, a.y, pops);
   }

@@ -140,3 +140,47 @@ def test_warm_start_converges_to_cold_roots(ex, ctx):
         "fallbacks", int((sw == 1).sum()))
     assert rel.max() <= 1e-8
     assert iw.mean() < ic.mean()
+
+
+def test_fused_warm_start_equals_layer_by_layer(ex, ctx):
+    """extrass_nlte_warm_start runs the whole network in one fused kernel. Its
+    populations equal those of the layer-by-layer forward (extrass_mlp_forward)
+    followed by the per-species normalisation, on 13^3 cells (a ragged last
+    work-group of 21 rows). The fused kernel takes K in the same order, so
+    the network outputs agree bit for bit (observed: populations to 8e-16;
+    a feature whose logarithm rounded differently on host and device could
+    move a cell, hence the allowance below)."""
+    from paper_2511_07539_amd import warmstart
+    dev = "cuda:0"
+    w = synth.clumpy(n=13, n_lines=2000, n_packets=10_000, number=3)
+    atom = ex.Atom(ctx, w.atom)
+    cells = ex.cells_from_workload(w)
+    g = np.random.default_rng(7)
+    params = torch.as_tensor(warmstart.init_params(3), device=dev)
+    X = warmstart.features_host(w.T_e, w.n_e, w.n_species, w.deposition)
+    xm, xs = X.mean(0), X.std(0) + 0.1
+    ym, ys = g.normal(-4.0, 1.0, 100), g.uniform(0.5, 2.0, 100)
+    norm_np = np.concatenate([xm, xs, ym, ys]).astype(np.float32)
+    norm = torch.as_tensor(norm_np, device=dev)
+    say("case: fused warm start vs layer-by-layer forward, 2197 cells")
+    xn = ((X - norm_np[:6].astype(np.float64)) / norm_np[6:12].astype(np.float64)).astype(np.float32)
+    y = ex.mlp_forward(ctx, params, torch.as_tensor(xn, device=dev)).cpu().numpy()
+    # y * scale + mean in FP32 with one rounding (the device contracts it into
+    # an FMA), then FP64
+    v = (y.astype(np.float64) * norm_np[112:].astype(np.float64) +
+         norm_np[12:112].astype(np.float64)).astype(np.float32).astype(np.float64)
+    ns = np.asarray(w.n_species).reshape(w.n_cells, -1)
+    ref = np.zeros((w.n_cells, 100))
+    off = w.atom.species_offset
+    for s in range(2):
+        vs = v[:, off[s]:off[s + 1]]
+        e = 10.0 ** (vs - vs.max(1, keepdims=True))
+        ref[:, off[s]:off[s + 1]] = ns[:, s:s + 1] * e / e.sum(1, keepdims=True)
+    pw = ex.nlte_warm_start(ctx, atom, cells, w.deposition, params, norm)
+    torch.cuda.synchronize()
+    pw = pw.cpu().numpy()
+    ok = ref > 0
+    rel = np.abs(pw[ok] - ref[ok]) / ref[ok]
+    say("max rel", rel.max(), "median", np.median(rel))
+    assert np.mean(rel > 1e-13) <= 1e-3
+    assert rel.max() <= 1e-3
