@@ -307,48 +307,89 @@ void backward(hipStream_t st, const float* P, const float* x, const float* t, in
 // hidden and output layers run on BF16 MFMA 16x16x16 with K taken in chunks
 // of 64 and steps of 16, the order k_gemm takes it, so every output equals
 // forward()'s. The activations stay in LDS as BF16, the value k_gemm rounds
-// them to when it stages its next A tile; the weights are staged as BF16 in
-// 64 x 64 tiles. One launch replaces layer 1 and three GEMMs, and no
-// pre-activation is written.
+// them to when it stages its next A tile. The weights, converted to BF16
+// once per call (k_weights_bf16, the same rounding k_gemm applies when it
+// stages them), are staged in 64 x 64 tiles with 16-byte loads. One launch
+// replaces layer 1 and three GEMMs, and no pre-activation is written.
 constexpr int kIR = 64;           // rows per work-group
 constexpr int kHS = kHid + 8;     // LDS row stride of the activations (bf16)
+constexpr int kWS = BK + 8;       // LDS row stride of a weight tile (bf16; rows 16-byte aligned)
+constexpr int64_t kWb2 = 0, kWb3 = kWb2 + kHid * kHid, kWb4 = kWb3 + kHid * kHid,
+                  kWbN = kWb4 + kOut * kHid;  // BF16 copies of W2, W3, W4
 
-__device__ __forceinline__ void infer_layer(__bf16 (*H)[kHS], __bf16 (*Ws)[BK + KPAD], const float* W,
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+__global__ void k_weights_bf16(const float* __restrict__ P, __bf16* __restrict__ Wb) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < kWbN;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t src = i < kWb3 ? kOffW2 + i : (i < kWb4 ? kOffW3 + (i - kWb3) : kOffW4 + (i - kWb4));
+    Wb[i] = static_cast<__bf16>(P[src]);
+  }
+}
+
+// One weight tile: rows n in [nc, nc + 64), columns k in [kc, kc + 64) of
+// W[n][k] (row-major BF16), 8 values per load; two loads per thread.
+__device__ __forceinline__ void load_wtile(const __bf16* W, int N, int nc, int kc, bf16x8 (&v)[2]) {
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int e = threadIdx.x + 256 * i;
+    const int r = e / (BK / 8), kk = 8 * (e % (BK / 8)), n = nc + r;
+    if (n < N) {
+      v[i] = *reinterpret_cast<const bf16x8*>(W + n * kHid + kc + kk);
+    } else {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[i][q] = static_cast<__bf16>(0.f);
+    }
+  }
+}
+__device__ __forceinline__ void store_wtile(__bf16 (*Ws)[kWS], const bf16x8 (&v)[2]) {
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int e = threadIdx.x + 256 * i;
+    *reinterpret_cast<bf16x8*>(&Ws[e / (BK / 8)][8 * (e % (BK / 8))]) = v[i];
+  }
+}
+
+__device__ __forceinline__ void infer_layer(__bf16 (*H)[kHS], __bf16 (*Ws)[64][kWS], const __bf16* W,
                                             const float* bias, int N, bool silu_out, float* y,
                                             int64_t row0, int64_t B) {
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int ntile = (N + 15) / 16;  // 16 for the hidden layers, 7 for the output layer
+  const int ncs = (ntile + 3) / 4;  // 64-column tiles
+  const int stages = (kHid / BK) * ncs;  // (kc, nc) with nc fastest: K stays in order per column
   f32x4 acc[16];
 #pragma unroll
   for (int t = 0; t < 16; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
   const int ar = wave * 16 + (lane & 15);
-  for (int kc = 0; kc < kHid; kc += BK) {
-    for (int nc = 0; nc < ntile * 16; nc += 64) {
-      // W tile: rows n in [nc, nc + 64), columns k in [kc, kc + 64); W[n][k] row-major
-      for (int e = tid; e < 64 * BK; e += 256) {
-        const int r = e / BK, kk = e % BK, n = nc + r;
-        Ws[r][kk] = static_cast<__bf16>(n < N ? W[n * kHid + kc + kk] : 0.f);
-      }
-      __syncthreads();
+  (void)tid;
+  bf16x8 v[2];
+  load_wtile(W, N, 0, 0, v);
+  store_wtile(Ws[0], v);
+  __syncthreads();
+  for (int sg = 0; sg < stages; ++sg) {
+    const int kc = (sg / ncs) * BK, nc = (sg % ncs) * 64;
+    // the next tile's loads are in flight during this tile's products
+    if (sg + 1 < stages) load_wtile(W, N, ((sg + 1) % ncs) * 64, ((sg + 1) / ncs) * BK, v);
+    __bf16 (*Wt)[kWS] = Ws[sg & 1];
 #pragma unroll
-      for (int ks = 0; ks < BK; ks += 16) {
-        const int kq = ks + 4 * (lane >> 4);
-        bf16x4 a;
+    for (int ks = 0; ks < BK; ks += 16) {
+      const int kq = ks + 4 * (lane >> 4);
+      bf16x4 a;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) a[q] = H[ar][kc + kq + q];
+      for (int q = 0; q < 4; ++q) a[q] = H[ar][kc + kq + q];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const int tt = nc / 16 + t;
-          if (tt < ntile) {
-            bf16x4 b;
+      for (int t = 0; t < 4; ++t) {
+        const int tt = nc / 16 + t;
+        if (tt < ntile) {
+          bf16x4 b;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) b[q] = Ws[t * 16 + (lane & 15)][kq + q];
-            acc[tt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[tt], 0, 0, 0);
-          }
+          for (int q = 0; q < 4; ++q) b[q] = Wt[t * 16 + (lane & 15)][kq + q];
+          acc[tt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[tt], 0, 0, 0);
         }
       }
-      __syncthreads();
     }
+    if (sg + 1 < stages) store_wtile(Ws[(sg + 1) & 1], v);
+    __syncthreads();
   }
   // every wave has read its rows of H: write the layer's output in place
 #pragma unroll
@@ -371,10 +412,11 @@ __device__ __forceinline__ void infer_layer(__bf16 (*H)[kHS], __bf16 (*Ws)[BK + 
 }
 
 __global__ __launch_bounds__(256) void k_mlp_infer(const float* __restrict__ x,
-                                                   const float* __restrict__ P, int64_t B,
+                                                   const float* __restrict__ P,
+                                                   const __bf16* __restrict__ Wb, int64_t B,
                                                    float* __restrict__ y) {
   __shared__ __bf16 H[kIR][kHS];
-  __shared__ __bf16 Ws[64][BK + KPAD];
+  __shared__ __align__(16) __bf16 Ws[2][64][kWS];
   const int64_t row0 = (int64_t)blockIdx.x * kIR;
   // layer 1 (K = 6), as k_layer1
   for (int e = threadIdx.x; e < kIR * kHid; e += 256) {
@@ -388,9 +430,9 @@ __global__ __launch_bounds__(256) void k_mlp_infer(const float* __restrict__ x,
     H[r][o] = static_cast<__bf16>(silu(s));
   }
   __syncthreads();
-  infer_layer(H, Ws, P + kOffW2, P + kOffB2, kHid, true, nullptr, row0, B);
-  infer_layer(H, Ws, P + kOffW3, P + kOffB3, kHid, true, nullptr, row0, B);
-  infer_layer(H, Ws, P + kOffW4, P + kOffB4, kOut, false, y, row0, B);
+  infer_layer(H, Ws, Wb + kWb2, P + kOffB2, kHid, true, nullptr, row0, B);
+  infer_layer(H, Ws, Wb + kWb3, P + kOffB3, kHid, true, nullptr, row0, B);
+  infer_layer(H, Ws, Wb + kWb4, P + kOffB4, kOut, false, y, row0, B);
 }
 
 __global__ void k_features(int64_t c0, int64_t n, int S, const double* __restrict__ T,
@@ -497,7 +539,7 @@ extern "C" int extrass_mlp_train_step(extrass_handle h, float* params, float* ad
 
 extern "C" size_t extrass_nlte_warm_start_workspace(int64_t n_cells) {
   const int64_t chunk = std::min<int64_t>(std::max<int64_t>(n_cells, 1), 65536);
-  return acts_bytes(chunk) + carve_bytes<float>(chunk * kIn) + 256;
+  return acts_bytes(chunk) + carve_bytes<float>(chunk * kIn) + kWbN * sizeof(__bf16) + 512;
 }
 
 extern "C" int extrass_nlte_warm_start(extrass_handle h, extrass_atom_handle atom,
@@ -518,12 +560,16 @@ extern "C" int extrass_nlte_warm_start(extrass_handle h, extrass_atom_handle ato
   const int64_t chunk = std::min<int64_t>(C, 65536);
   Acts a = carve_acts(ws, chunk);
   float* x = reinterpret_cast<float*>(static_cast<char*>(ws) + acts_bytes(chunk));
+  // 256-byte aligned, after the features
+  const uintptr_t wb_at = (reinterpret_cast<uintptr_t>(x + chunk * kIn) + 255) & ~uintptr_t(255);
+  __bf16* wb = reinterpret_cast<__bf16*>(wb_at);
+  hipLaunchKernelGGL(k_weights_bf16, dim3(blocks_for(kWbN)), dim3(256), 0, st, params, wb);
   for (int64_t c0 = 0; c0 < C; c0 += chunk) {
     const int64_t n = std::min(chunk, C - c0);
     hipLaunchKernelGGL(k_features, dim3(blocks_for(n)), dim3(256), 0, st, c0, n, atom->S,
                        cells->T_e, cells->n_e, cells->n_species, deposition, norm, x);
     hipLaunchKernelGGL(k_mlp_infer, dim3((unsigned)((n + kIR - 1) / kIR)), dim3(256), 0, st, x,
-                       params, n, a.y);
+                       params, wb, n, a.y);
     hipLaunchKernelGGL(k_warm_out, dim3((unsigned)((n * atom->S + 3) / 4)), dim3(256), 0, st, c0,
                        n, atom->S, atom->d.off, cells->n_species, norm, a.y, pops);
   }
