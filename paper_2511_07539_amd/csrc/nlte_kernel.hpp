@@ -440,9 +440,18 @@ __device__ __forceinline__ bool reduce_blocks(const double* G, const int2* rt, i
       if (r == kk) my_inv = inv;
       const double f = g[kk] * inv;
 #pragma unroll
+      // in chunks of 8: the chunk's pivot-row reads are issued together, then
+      // its updates (left to itself, the scheduler kept the register
+      // pressure down by waiting on each read before the next; 16 or 24 per
+      // chunk spill more and are slower)
       for (int b0 = kk + 1; b0 < NTB; b0 += 8) {
+        double p[8];
 #pragma unroll
-        for (int b = b0; b < b0 + 8 && b < NTB; ++b) g[b] += f * myrow[b];
+        for (int b = b0; b < b0 + 8 && b < NTB; ++b) p[b - b0] = myrow[b];
+        __builtin_amdgcn_sched_group_barrier(0x100, 8, 0);   // LDS reads
+        __builtin_amdgcn_sched_group_barrier(0x002, 16, 0);  // then vector ALU
+#pragma unroll
+        for (int b = b0; b < b0 + 8 && b < NTB; ++b) g[b] += f * p[b - b0];
         __builtin_amdgcn_sched_barrier(0);
       }
       // every lane reads (no branch around the load); only r > kk keeps it
