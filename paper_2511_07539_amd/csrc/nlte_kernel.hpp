@@ -142,7 +142,7 @@ __device__ __forceinline__ void assemble(const NArgs& A, const Sys& y, double* G
   }
   __syncthreads();
   const double* gpe = A.gamma_pe ? A.gamma_pe + y.c * A.T : nullptr;
-#pragma unroll 2
+#pragma unroll 4
   for (int t = y.t0 + lane; t < y.t1; t += 64) {
     const int4 ix = reinterpret_cast<const int4*>(A.t_idx)[t];
     const int l = ix.x, u = ix.y;
@@ -180,7 +180,7 @@ __device__ __forceinline__ void assemble(const NArgs& A, const Sys& y, double* G
   }
   if (jac) {
     __syncthreads();
-#pragma unroll 2
+#pragma unroll 4
     for (int t = y.t0 + lane; t < y.t1; t += 64) {
       const int4 ix = reinterpret_cast<const int4*>(A.t_idx)[t];
       const int l = ix.x, u = ix.y;
