@@ -10,8 +10,8 @@
  * The plain definition computed here is the positive root n of
  *   sum_{j != i} n_j R_ji - n_i sum_{j != i} R_ij = 0  for every level i,
  *   sum_i n_i = n_species,
- * with per-atom rates R_ij (i -> j) built from (readings, see DESIGN notes in
- * the header of each helper):
+ * with per-atom rates R_ij (i -> j) built from (where the paper is silent,
+ * the reading taken is stated beside the formula):
  *   transition l < u (same ion stage):
  *     R_ul += A_ul beta_S(tau_ul(n)) + n_e q_ul + (g_l/g_u) Gamma_PE
  *     R_lu += n_e q_lu + Gamma_PE
@@ -21,18 +21,10 @@
  *     alpha_z(T) = alpha0_z (T/1e4 K)^-0.8, split 1/3 into the ground state and
  *     the rest over the excited levels by statistical weight (Appendix A.2).
  *
- * Algorithm (the root is what matters; the steps are textbook):
- *  1. cold start: Boltzmann within each stage, stage ratios from a ground-only
- *     ionisation balance;
- *  2. fixed-point steps n <- n_species * stationary(R(n)), under-relaxed in
- *     log(n), the stationary vector from the GTH algorithm (Grassmann, Taksar
- *     & Heyman 1985), which is subtraction-free and so accurate componentwise;
- *  3. Newton steps in log(n) with the analytic Jacobian, globalised by a trust
- *     radius on max |d ln n| and a decrease test on the scaled residuals. The
- *     scaled Jacobian J diag(n) is itself a generator transposed (non-negative
- *     off-diagonals, zero column sums), so the Newton system is solved by the
- *     same state-reduction elimination, pivots taken as sums of off-diagonal
- *     entries; conservation fixes the free multiple of the null vector.
+ * Algorithm (solve_species below): the paper's damped Newton-Raphson with a
+ * numerical Jacobian brings the populations close to the root; a fixed-point
+ * iteration on the stationary vector of the rates (GTH, componentwise
+ * accurate) finishes the solve, and only a root test ends it.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -49,12 +41,6 @@ static double beta_s(double tau) {
   return -expm1(-tau) / tau;
 }
 
-static double dbeta_s(double tau) {
-  if (tau <= 0.0) return 0.0;
-  if (tau < 1e-3) return -0.5 + tau * (1.0 / 3.0 - tau * (1.0 / 8.0 - tau / 30.0));
-  return (exp(-tau) * (1.0 + tau) - 1.0) / (tau * tau);
-}
-
 /* Eq. A2 written as K*((g_u/g_l) n_l - n_u) with K = A lambda^3 t / (8 pi). */
 static double tau_sobolev(double A, double lam, double t, double gl, double gu, double nl,
                           double nu, double* K) {
@@ -69,8 +55,12 @@ static int32_t n_stages(const or_atom* a, int32_t s) {
   return z;
 }
 
-void oracle_rate_matrix(const or_atom* a, const or_cells* cl, int64_t c, int32_t s,
-                        const double* n, double* R) {
+/* Every rate of species s in cell c that does not depend on the populations
+ * (R[i*Ns+j], i -> j, per atom in i): collisions, photoexcitation and
+ * photo-de-excitation, ionisation and recombination. The radiative decay
+ * A beta_S(tau(n)) is added by add_decay. */
+static void rates_without_decay(const or_atom* a, const or_cells* cl, int64_t c, int32_t s,
+                                double* R) {
   int32_t base = a->species_offset[s];
   int32_t Ns = a->species_offset[s + 1] - base;
   memset(R, 0, sizeof(double) * (size_t)Ns * Ns);
@@ -82,10 +72,8 @@ void oracle_rate_matrix(const or_atom* a, const or_cells* cl, int64_t c, int32_t
     double gl = a->level_g[lo], gu = a->level_g[up];
     double qul = 8.629e-6 * a->trans_upsilon[t] / (gu * sqrt(T));
     double qlu = qul * (gu / gl) * exp(-(a->level_energy[up] - a->level_energy[lo]) / kT);
-    double K;
-    double tau = tau_sobolev(a->trans_A[t], a->trans_lambda[t], cl->t_exp, gl, gu, n[l], n[u], &K);
     double gpe = cl->gamma_pe ? cl->gamma_pe[c * a->n_trans + t] : 0.0;
-    R[u * Ns + l] += a->trans_A[t] * beta_s(tau) + ne * qul + (gl / gu) * gpe;
+    R[u * Ns + l] += ne * qul + (gl / gu) * gpe;
     R[l * Ns + u] += ne * qlu + gpe;
   }
   int32_t Z = n_stages(a, s);
@@ -114,52 +102,70 @@ void oracle_rate_matrix(const or_atom* a, const or_cells* cl, int64_t c, int32_t
   }
 }
 
-/* State reduction of a generator with off-diagonal entries G (row i -> j),
- * solving x^T G = b^T (b may be NULL for the homogeneous problem), with the
- * last state's value fixed to x_last. Pivots are sums of the remaining
- * off-diagonal entries of the pivot row. G and b are overwritten. Returns 0,
- * or -1 if a pivot vanishes (reducible chain). */
-static int gth_reduce_solve(int32_t N, double* G, double* b, double x_last, double* x) {
+/* Adds the radiative decay A_ul beta_S(tau_ul(n)) of every transition of
+ * species s (Eqs. A1, A2) to R at the populations n (species-local). */
+static void add_decay(const or_atom* a, const or_cells* cl, int32_t s, const double* n,
+                      double* R) {
+  int32_t base = a->species_offset[s];
+  int32_t Ns = a->species_offset[s + 1] - base;
+  for (int32_t t = 0; t < a->n_trans; ++t) {
+    int32_t lo = a->trans_lower[t], up = a->trans_upper[t];
+    if (lo < base || lo >= base + Ns) continue;
+    int32_t l = lo - base, u = up - base;
+    double K;
+    double tau = tau_sobolev(a->trans_A[t], a->trans_lambda[t], cl->t_exp, a->level_g[lo],
+                             a->level_g[up], n[l], n[u], &K);
+    R[u * Ns + l] += a->trans_A[t] * beta_s(tau);
+  }
+}
+
+void oracle_rate_matrix(const or_atom* a, const or_cells* cl, int64_t c, int32_t s,
+                        const double* n, double* R) {
+  rates_without_decay(a, cl, c, s, R);
+  add_decay(a, cl, s, n, R);
+}
+
+/* Stationary vector of a continuous-time Markov chain by state reduction
+ * (Grassmann, Taksar & Heyman 1985): R holds the off-diagonal rates (row
+ * i -> j; the diagonal is ignored). States are eliminated in index order,
+ * each pivot being the sum of the remaining off-diagonal rates of its row,
+ * so no subtraction occurs. pi sums to 1; NaN if a pivot vanishes
+ * (reducible chain). */
+void oracle_gth(int32_t N, const double* R, double* pi) {
+  double* G = (double*)malloc(sizeof(double) * (size_t)N * N);
   double* S = (double*)malloc(sizeof(double) * (size_t)N);
-  for (int32_t k = 0; k + 1 < N; ++k) {
+  memcpy(G, R, sizeof(double) * (size_t)N * N);
+  for (int32_t i = 0; i < N; ++i) G[i * N + i] = 0.0;
+  int ok = 1;
+  for (int32_t k = 0; k + 1 < N && ok; ++k) {
     double s = 0.0;
     for (int32_t j = k + 1; j < N; ++j) s += G[k * N + j];
-    if (!(s > 0.0)) { free(S); return -1; }
+    if (!(s > 0.0)) { ok = 0; break; }
     S[k] = s;
+    /* The update also reaches the diagonal G[i][i], which no later step
+     * reads: pivots sum only the entries right of the diagonal, and the
+     * back-substitution only those left of it. */
     for (int32_t i = k + 1; i < N; ++i) {
       double f = G[i * N + k] / s;
       if (f == 0.0) continue;
-      for (int32_t j = k + 1; j < N; ++j) {
-        if (j == i) continue;
-        G[i * N + j] += f * G[k * N + j];
-      }
-    }
-    if (b) {
-      for (int32_t j = k + 1; j < N; ++j) b[j] += b[k] * G[k * N + j] / s;
+      for (int32_t j = k + 1; j < N; ++j) G[i * N + j] += f * G[k * N + j];
     }
   }
-  x[N - 1] = x_last;
-  for (int32_t k = N - 2; k >= 0; --k) {
-    double acc = 0.0;
-    for (int32_t i = k + 1; i < N; ++i) acc += x[i] * G[i * N + k];
-    x[k] = (acc - (b ? b[k] : 0.0)) / S[k];
-  }
-  free(S);
-  return 0;
-}
-
-void oracle_gth(int32_t N, const double* R, double* pi) {
-  double* G = (double*)malloc(sizeof(double) * (size_t)N * N);
-  memcpy(G, R, sizeof(double) * (size_t)N * N);
-  for (int32_t i = 0; i < N; ++i) G[i * N + i] = 0.0;
-  if (gth_reduce_solve(N, G, NULL, 1.0, pi) != 0) {
-    for (int32_t i = 0; i < N; ++i) pi[i] = NAN;
-  } else {
+  if (ok) {
+    pi[N - 1] = 1.0;
+    for (int32_t k = N - 2; k >= 0; --k) {
+      double acc = 0.0;
+      for (int32_t i = k + 1; i < N; ++i) acc += pi[i] * G[i * N + k];
+      pi[k] = acc / S[k];
+    }
     double s = 0.0;
     for (int32_t i = 0; i < N; ++i) s += pi[i];
     for (int32_t i = 0; i < N; ++i) pi[i] /= s;
+  } else {
+    for (int32_t i = 0; i < N; ++i) pi[i] = NAN;
   }
   free(G);
+  free(S);
 }
 
 void oracle_nlte_cold(const or_atom* a, const or_cells* cl, int64_t c, double* out) {
@@ -193,196 +199,190 @@ void oracle_nlte_cold(const or_atom* a, const or_cells* cl, int64_t c, double* o
   }
 }
 
+/* Solves M x = b (M is N x N, row-major) by Gaussian elimination with
+ * partial pivoting; M and b are overwritten. Returns -1 if M is singular. */
+static int gauss_solve(int32_t N, double* M, double* b, double* x) {
+  for (int32_t k = 0; k < N; ++k) {
+    int32_t p = k;
+    for (int32_t i = k + 1; i < N; ++i)
+      if (fabs(M[i * N + k]) > fabs(M[p * N + k])) p = i;
+    if (!(M[p * N + k] != 0.0)) return -1;
+    if (p != k) {
+      for (int32_t j = 0; j < N; ++j) {
+        double t = M[k * N + j]; M[k * N + j] = M[p * N + j]; M[p * N + j] = t;
+      }
+      double t = b[k]; b[k] = b[p]; b[p] = t;
+    }
+    for (int32_t i = k + 1; i < N; ++i) {
+      double f = M[i * N + k] / M[k * N + k];
+      if (f == 0.0) continue;
+      for (int32_t j = k; j < N; ++j) M[i * N + j] -= f * M[k * N + j];
+      b[i] -= f * b[k];
+    }
+  }
+  for (int32_t k = N - 1; k >= 0; --k) {
+    double acc = b[k];
+    for (int32_t j = k + 1; j < N; ++j) acc -= M[k * N + j] * x[j];
+    x[k] = acc / M[k * N + k];
+  }
+  return 0;
+}
+
+/* Damping factor of the Newton-Raphson scheme at iteration it (Sec. 2.2):
+ * 0.95, then 0.75, 0.5, 0.25 and 0.05 after 10, 35, 50 and 90 iterations. */
+static double newton_damping(int it) {
+  if (it < 10) return 0.95;
+  if (it < 35) return 0.75;
+  if (it < 50) return 0.5;
+  if (it < 90) return 0.25;
+  return 0.05;
+}
+
+/* The solve starts with at most FIXED_POINT_START_ITER fixed-point steps, until
+ * the root-test residual is below FIXED_POINT_START_EXIT: from a start far from
+ * the root (populations off by many decades) they close the distance at the
+ * cost of one stationary vector each. Newton-Raphson steps are then limited
+ * to change no level by more than a factor of 10 (NEWTON_MAX_LOG_STEP): the
+ * paper limits the change of the populations between steps without giving
+ * the limit; NEWTON_HALVINGS bounds the step halvings of one iteration. */
+#define FIXED_POINT_START_ITER 30
+#define FIXED_POINT_START_EXIT 0.1
+#define NEWTON_MAX_LOG_STEP 2.302585092994046
+#define NEWTON_HALVINGS 30
+#define JACOBIAN_STEP 1e-6
+/* The paper's convergence criterion: every level within 1 % of the fixed-point
+ * map. The damping schedule serves the iteration up to that point; beyond it
+ * (the oracle continues to tol) Newton steps are taken whole. */
+#define PAPER_CONVERGENCE 0.01
+
+/* The fixed-point map P(n) = n_tot * stationary(R(n)), the stationary
+ * vector by GTH (oracle_gth), with the rates R(n) = R0 + decay(n) formed from
+ * the population-independent rates R0 (rates_without_decay). Returns -1 if
+ * it does not exist. */
+static int fixed_point_map(const or_atom* a, const or_cells* cl, int32_t s, int32_t Ns,
+                           double ntot, const double* R0, const double* n, double* R, double* P) {
+  memcpy(R, R0, sizeof(double) * (size_t)Ns * Ns);
+  add_decay(a, cl, s, n, R);
+  oracle_gth(Ns, R, P);
+  if (!(P[0] == P[0])) return -1;
+  for (int32_t i = 0; i < Ns; ++i) P[i] *= ntot;
+  return 0;
+}
+
+/* The equations in fixed-point form at y = ln n: H_i(y) = ln P(n)_i - y_i.
+ * H = 0 exactly at the root. n and P are work arrays; returns -1 if P(n)
+ * does not exist. */
+static int equations(const or_atom* a, const or_cells* cl, int32_t s, int32_t Ns, double ntot,
+                     const double* R0, const double* y, double* R, double* n, double* P,
+                     double* H) {
+  for (int32_t i = 0; i < Ns; ++i) n[i] = exp(y[i]);
+  if (fixed_point_map(a, cl, s, Ns, ntot, R0, n, R, P) != 0) return -1;
+  for (int32_t i = 0; i < Ns; ++i) H[i] = log(P[i]) - y[i];
+  return 0;
+}
+
+/* Root-test residual max_i |P(n)_i / n_i - 1| from H = ln(P / n). */
+static double root_residual(int32_t N, const double* H) {
+  double r = 0.0;
+  for (int32_t i = 0; i < N; ++i) if (fabs(expm1(H[i])) > r) r = fabs(expm1(H[i]));
+  return r;
+}
+
 /* One species of one cell. n (local numbering, length Ns) holds the start on
- * entry and the solution on exit. Returns the iteration count, or -1.
+ * entry and the solution on exit. Returns the number of iterations, or -1 if
+ * the root test was not met within max_iter.
  *
- * Step 1: fixed-point steps n <- n_species * stationary(R(n)), under-relaxed
- *   in log(n), until the change is below 0.1 in log (at most 60 steps).
- * Step 2: Newton on the level equations in log(n): the correction
- *   delta = d ln n solves J diag(n) delta = -F with sum n_i delta_i fixed by
- *   conservation, and the update is n_i exp(delta_i) (positive by
- *   construction). -F is formed as Q(n)^T (P(n) - n), P(n) being the
- *   GTH stationary vector of the current rates scaled to n_species: the
- *   same vector, free of the cancellation between gross inflow and outflow
- *   that limits a directly summed F to ~1e-9 in weakly coupled stages. Far
- *   from the root the step is limited to a trust radius (max |delta_i| <=
- *   Delta) and accepted only if it lowers sum_i (P(n)_i/n_i - 1)^2; a
- *   rejected step shrinks the radius.
- * Converged when max |delta| < tol and max |P(n)_i/n_i - 1| < 1e-10, or when
- * max |delta| < 1e-11 has not improved for 3 steps, or when no step lowers the
- * fixed-point residual any more and it is at rounding level.
- */
+ * The root is the fixed point of P(n) = n_tot * stationary(R(n)): the
+ * stationary vector of the rates at n balances inflow and outflow of every
+ * level, so n = P(n) is exactly the statistical equilibrium. P is computed
+ * by GTH, which is subtraction-free and accurate for every component however
+ * small.
+ * 1. Fixed-point steps n <- P(n), damped in log(n) (w halved, down to 1/64,
+ *    whenever the residual does not shrink), while far from the root.
+ * 2. Newton-Raphson (Sec. 2.2: a numerical Jacobian built from a matrix
+ *    calculation of all rates between all levels; a decreasing damping
+ *    schedule) on H(y) = ln P(e^y) - y in y = ln n, so that populations stay
+ *    positive. Jacobian column j is the forward difference of H for
+ *    y_j + 1e-6; the correction d solves J d = -H by Gaussian elimination
+ *    with partial pivoting. The step y + damp d takes damp from the paper's
+ *    schedule (1 once max |H| is below the paper's 1 % criterion), lowered so
+ *    that no level changes by more than a factor of 10, and halved until the
+ *    residual max |H| decreases.
+ * Stops only on the root test max_i |P(n)_i / n_i - 1| < tol. */
 static int solve_species(const or_atom* a, const or_cells* cl, int64_t c, int32_t s, double* n,
                          int max_iter, double tol) {
-  int32_t base = a->species_offset[s];
-  int32_t Ns = a->species_offset[s + 1] - base;
+  int32_t Ns = a->species_offset[s + 1] - a->species_offset[s];
   double ntot = cl->n_species[c * a->n_species + s];
   size_t NN = (size_t)Ns * Ns;
+  double* R0 = (double*)malloc(sizeof(double) * NN);
   double* R = (double*)malloc(sizeof(double) * NN);
-  double* G = (double*)malloc(sizeof(double) * NN);
-  double* Gp = (double*)malloc(sizeof(double) * NN);
-  double* b = (double*)malloc(sizeof(double) * Ns);
-  double* bp = (double*)malloc(sizeof(double) * Ns);
-  double* x = (double*)malloc(sizeof(double) * Ns);
-  double* pi = (double*)malloc(sizeof(double) * Ns);
-  double* trial = (double*)malloc(sizeof(double) * Ns);
-  double* wscale = (double*)malloc(sizeof(double) * Ns);
-  double* hres = (double*)malloc(sizeof(double) * Ns);
-  int32_t* perm = (int32_t*)malloc(sizeof(int32_t) * Ns);
-  int it, result = -1, best_it = 0;
-  double Delta = 1.0, best_step = INFINITY;
+  double* J = (double*)malloc(sizeof(double) * NN);
+  double* y = (double*)malloc(sizeof(double) * Ns);
+  double* yt = (double*)malloc(sizeof(double) * Ns);
+  double* H = (double*)malloc(sizeof(double) * Ns);
+  double* Ht = (double*)malloc(sizeof(double) * Ns);
+  double* d = (double*)malloc(sizeof(double) * Ns);
+  double* P = (double*)malloc(sizeof(double) * Ns);
+  double* work = (double*)malloc(sizeof(double) * Ns);
+  int it = 0, result = -1;
 
-  /* fixed-point phase, under-relaxed in log(n): omega halves whenever the
-   * change fails to shrink (this also breaks period-2 cycles) and never grows
-   * back; ends once max |d ln n| < 0.1 */
-  {
-    double omega = 1.0, prev = INFINITY;
-    for (it = 0; it < max_iter && it < 60; ++it) {
-      oracle_rate_matrix(a, cl, c, s, n, R);
-      oracle_gth(Ns, R, pi);
-      if (!(pi[0] == pi[0])) goto out;
-      double change = 0.0;
-      for (int32_t i = 0; i < Ns; ++i) {
-        double d = fabs(log(ntot * pi[i] / n[i]));
-        if (d > change) change = d;
-      }
-      if (change > 0.999 * prev) omega = omega * 0.5 > 1.0 / 1024 ? omega * 0.5 : 1.0 / 1024;
-      prev = change;
-      double tot = 0.0;
-      for (int32_t i = 0; i < Ns; ++i) {
-        n[i] = exp((1.0 - omega) * log(n[i]) + omega * log(ntot * pi[i]));
-        tot += n[i];
-      }
-      for (int32_t i = 0; i < Ns; ++i) n[i] *= ntot / tot;
-      if (change < 0.1) { ++it; break; }
+  rates_without_decay(a, cl, c, s, R0);
+  /* 1. damped fixed point while far from the root */
+  double w = 1.0, prev = INFINITY;
+  for (int k = 0; k < FIXED_POINT_START_ITER && it < max_iter; ++k) {
+    if (fixed_point_map(a, cl, s, Ns, ntot, R0, n, R, P) != 0) goto done;
+    double res = 0.0, sum = 0.0;
+    for (int32_t i = 0; i < Ns; ++i)
+      if (fabs(P[i] / n[i] - 1.0) > res) res = fabs(P[i] / n[i] - 1.0);
+    if (res < FIXED_POINT_START_EXIT) break;
+    ++it;
+    if (res >= prev && w > 1.0 / 64) w *= 0.5;
+    prev = res;
+    for (int32_t i = 0; i < Ns; ++i) {
+      n[i] = exp((1.0 - w) * log(n[i]) + w * log(P[i]));
+      sum += n[i];
     }
+    for (int32_t i = 0; i < Ns; ++i) n[i] *= ntot / sum;
   }
 
-  int have_p = 0;
-  for (; it < max_iter; ++it) {
-    /* Fixed-point residual h_i = P(n)_i / n_i - 1, with P(n) = n_species *
-     * stationary(R(n)) from GTH: no cancellation, accurate componentwise. */
-    if (!have_p) {
-      oracle_rate_matrix(a, cl, c, s, n, R);
-      oracle_gth(Ns, R, pi);
-      if (!(pi[0] == pi[0])) goto out;
-      for (int32_t i = 0; i < Ns; ++i) hres[i] = ntot * pi[i] / n[i] - 1.0;
+  /* 2. damped Newton-Raphson with a numerical Jacobian */
+  for (int32_t i = 0; i < Ns; ++i) y[i] = log(n[i]);
+  if (equations(a, cl, s, Ns, ntot, R0, y, R, work, P, H) != 0) goto done;
+  for (int k = 0; it < max_iter; ++k) {
+    double res = root_residual(Ns, H);
+    if (res < tol) { result = it; break; }
+    ++it;
+    for (int32_t j = 0; j < Ns; ++j) {
+      for (int32_t i = 0; i < Ns; ++i) yt[i] = y[i];
+      yt[j] += JACOBIAN_STEP;
+      if (equations(a, cl, s, Ns, ntot, R0, yt, R, work, P, Ht) != 0) goto done;
+      for (int32_t i = 0; i < Ns; ++i) J[i * Ns + j] = (Ht[i] - H[i]) / JACOBIAN_STEP;
     }
-    double res = 0.0, phi = 0.0;
-    for (int32_t i = 0; i < Ns; ++i) {
-      if (fabs(hres[i]) > res) res = fabs(hres[i]);
-      phi += hres[i] * hres[i];
-    }
-    /* Newton right-hand side -F(n) written as Q(n)^T (P(n) - n): with the flux
-     * matrix G_ij = n_i R_ij, (Q^T H)_i = sum_j h_j G_ji - h_i sum_j G_ij. It is
-     * the same vector as -F, formed from the small h instead of the cancelling
-     * gross inflows and outflows. */
-    oracle_rate_matrix(a, cl, c, s, n, R);
-    for (size_t e = 0; e < NN; ++e) G[e] = 0.0;
-    for (int32_t k = 0; k < Ns; ++k)
-      for (int32_t j = 0; j < Ns; ++j)
-        if (j != k) G[k * Ns + j] = n[k] * R[k * Ns + j];
-    for (int32_t i = 0; i < Ns; ++i) {
-      double in = 0.0, outr = 0.0;
-      for (int32_t j = 0; j < Ns; ++j) {
-        if (j == i) continue;
-        in += hres[j] * G[j * Ns + i];
-        outr += G[i * Ns + j];
-      }
-      b[i] = in - hres[i] * outr;
-    }
-    /* scaled Jacobian as a generator: G_kj = n_k dF_j/dn_k (k != j) */
-    for (int32_t t = 0; t < a->n_trans; ++t) {
-      int32_t lo = a->trans_lower[t], up = a->trans_upper[t];
-      if (lo < base || lo >= base + Ns) continue;
-      int32_t l = lo - base, u = up - base;
-      double gl = a->level_g[lo], gu = a->level_g[up], K;
-      double tau = tau_sobolev(a->trans_A[t], a->trans_lambda[t], cl->t_exp, gl, gu, n[l], n[u], &K);
-      double db = dbeta_s(tau);
-      if (db == 0.0) continue;
-      double du = -n[u] * a->trans_A[t] * db * K;            /* d flux / d n_u, >= 0 */
-      double dl = n[u] * a->trans_A[t] * db * K * (gu / gl);  /* d flux / d n_l, <= 0 */
-      G[u * Ns + l] += du * n[u];
-      G[l * Ns + u] += -dl * n[l];
-    }
-    /* The state eliminated last (its value fixed, then set by conservation)
-     * is the most populated level, so that the normalisation is carried by the
-     * level that dominates the sum. */
-    {
-      int32_t big = 0;
-      for (int32_t i = 1; i < Ns; ++i) if (n[i] > n[big]) big = i;
-      for (int32_t i = 0; i < Ns; ++i) perm[i] = i;
-      perm[big] = Ns - 1;
-      perm[Ns - 1] = big;
-      for (int32_t i = 0; i < Ns; ++i) {
-        bp[i] = b[perm[i]];
-        for (int32_t j = 0; j < Ns; ++j) Gp[i * Ns + j] = G[perm[i] * Ns + perm[j]];
-      }
-    }
-    if (gth_reduce_solve(Ns, Gp, bp, 0.0, x) != 0) goto out;
-    /* homogeneous solution of the same reduced system */
-    pi[Ns - 1] = 1.0;
-    for (int32_t k = Ns - 2; k >= 0; --k) {
-      double acc = 0.0, sk = 0.0;
-      for (int32_t j = k + 1; j < Ns; ++j) sk += Gp[k * Ns + j];
-      for (int32_t i = k + 1; i < Ns; ++i) acc += pi[i] * Gp[i * Ns + k];
-      pi[k] = acc / sk;
-    }
-    /* back to level order */
-    for (int32_t i = 0; i < Ns; ++i) { bp[perm[i]] = x[i]; trial[perm[i]] = pi[i]; }
-    double sum_n = 0.0, sum_nx = 0.0, sum_npi = 0.0;
-    for (int32_t i = 0; i < Ns; ++i) {
-      x[i] = bp[i];
-      pi[i] = trial[i];
-      sum_n += n[i];
-      sum_nx += n[i] * x[i];
-      sum_npi += n[i] * pi[i];
-    }
-    double cst = ((ntot - sum_n) - sum_nx) / sum_npi;
-    double step = 0.0;
-    for (int32_t i = 0; i < Ns; ++i) {
-      x[i] += cst * pi[i];
-      if (fabs(x[i]) > step) step = fabs(x[i]);
-    }
-    if (step < best_step) { best_step = step; best_it = it; }
-    if ((step < tol && res < 1e-10) || (step < 1e-11 && it - best_it >= 3)) {
-      result = it + 1;
-      goto out;
-    }
-    /* trust-region step in log(n), accepted when the fixed-point residual drops */
+    for (int32_t i = 0; i < Ns; ++i) Ht[i] = -H[i];
+    if (gauss_solve(Ns, J, Ht, d) != 0) goto done;
+    double big = 0.0;
+    for (int32_t i = 0; i < Ns; ++i) if (fabs(d[i]) > big) big = fabs(d[i]);
+    if (!(big < INFINITY)) goto done;
+    double hmax = 0.0;
+    for (int32_t i = 0; i < Ns; ++i) if (fabs(H[i]) > hmax) hmax = fabs(H[i]);
+    double damp = hmax < PAPER_CONVERGENCE ? 1.0 : newton_damping(k);
+    if (damp * big > NEWTON_MAX_LOG_STEP) damp = NEWTON_MAX_LOG_STEP / big;
     int accepted = 0;
-    double taken = 0.0;
-    for (int bt = 0; bt < 40; ++bt) {
-      double scale = step > Delta ? Delta / step : 1.0;
-      double tot = 0.0;
-      taken = step * scale;
-      for (int32_t i = 0; i < Ns; ++i) {
-        trial[i] = n[i] * exp(scale * x[i]);
-        tot += trial[i];
+    for (int h = 0; h < NEWTON_HALVINGS && !accepted; ++h, damp *= 0.5) {
+      for (int32_t i = 0; i < Ns; ++i) yt[i] = y[i] + damp * d[i];
+      if (equations(a, cl, s, Ns, ntot, R0, yt, R, work, P, Ht) != 0) continue;
+      double tmax = 0.0;
+      for (int32_t i = 0; i < Ns; ++i) if (fabs(Ht[i]) > tmax) tmax = fabs(Ht[i]);
+      if (tmax < hmax) {
+        accepted = 1;
+        for (int32_t i = 0; i < Ns; ++i) { y[i] = yt[i]; H[i] = Ht[i]; }
       }
-      for (int32_t i = 0; i < Ns; ++i) trial[i] *= ntot / tot;
-      oracle_rate_matrix(a, cl, c, s, trial, R);
-      oracle_gth(Ns, R, pi);
-      double phi2 = 0.0, res2 = 0.0;
-      for (int32_t i = 0; i < Ns; ++i) {
-        double hv = ntot * pi[i] / trial[i] - 1.0;
-        wscale[i] = hv;
-        phi2 += hv * hv;
-        if (fabs(hv) > res2) res2 = fabs(hv);
-      }
-      if (phi2 < phi || res2 < 1e-14) { accepted = 1; break; }
-      Delta = (taken < Delta ? taken : Delta) / 4.0;
     }
-    if (!accepted) {
-      if (step < 1e-11 || res < 1e-14) result = it + 1; /* stalled at rounding level */
-      goto out;
-    }
-    for (int32_t i = 0; i < Ns; ++i) { n[i] = trial[i]; hres[i] = wscale[i]; }
-    have_p = 1;
-    if (taken >= 0.99 * Delta) Delta = 2.0 * Delta < 30.0 ? 2.0 * Delta : 30.0;
+    if (!accepted) break;
   }
-out:
-  free(R); free(G); free(Gp); free(b); free(bp); free(x); free(pi); free(trial); free(perm); free(wscale); free(hres);
+  for (int32_t i = 0; i < Ns; ++i) n[i] = exp(y[i]);
+done:
+  free(R0); free(R); free(J); free(y); free(yt); free(H); free(Ht); free(d); free(P); free(work);
   return result;
 }
 

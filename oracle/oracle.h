@@ -64,6 +64,11 @@ int64_t oracle_transport(const or_transport* p, int64_t first, int64_t count, in
                          or_record** records, double* stats, double* pkt_out);
 void oracle_free(void* ptr);
 
+/* The emitted state of packets [first, first+count), as the transport draws
+ * it: out[8*i .. 8*i+7] = x, y, z, n_x, n_y, n_z, lambda_e, w0 (the layout of
+ * an explicit packet). Returns -1 on invalid input. Exposed for the pins. */
+int oracle_emission(const or_transport* p, int64_t first, int64_t count, double* out);
+
 /* ---- Eq. A2 line optical depth from populations --------------------------- */
 void oracle_line_tau(int64_t n_cells, int32_t n_levels, int32_t n_trans, const double* pops,
                      const int32_t* lower, const int32_t* upper, const double* A,
@@ -99,7 +104,8 @@ typedef struct {
 
 /* Solves cells [first, first+count). pops [C*N] in: initial guess (used when
  * use_guess != 0), out: solution. status[c]: 0 converged, 2 failed, 3 empty.
- * iters[c] (optional) receives the Newton iteration count. */
+ * iters[c] (optional) receives the largest iteration count (fixed-point
+ * plus Newton steps) over the cell's species. */
 int oracle_nlte(const or_atom* a, const or_cells* cells, int64_t first, int64_t count,
                 int use_guess, int max_iter, double tol, int nthreads,
                 double* pops, int32_t* status, int32_t* iters);
