@@ -75,6 +75,8 @@ def lib():
         L.oracle_transport.argtypes = [C.POINTER(_Transport), C.c_int64, C.c_int64, C.c_int,
                                        C.POINTER(C.POINTER(_Record)), C.c_void_p, C.c_void_p]
         L.oracle_free.argtypes = [C.c_void_p]
+        L.oracle_emission.restype = C.c_int
+        L.oracle_emission.argtypes = [C.POINTER(_Transport), C.c_int64, C.c_int64, C.c_void_p]
         L.oracle_line_tau.argtypes = [C.c_int64, C.c_int32, C.c_int32] + [C.c_void_p] * 6 + \
             [C.c_double, C.c_void_p, C.c_void_p]
         L.oracle_rates.argtypes = [C.c_int64, C.c_int32, C.c_int32, C.c_int32] + [C.c_void_p] * 4 + \
@@ -189,6 +191,17 @@ def transport(inp: TransportInputs, first=0, count=None, nthreads=None, per_pack
         recs = np.zeros(0, dtype=dt)
     lib().oracle_free(ptr)
     return dict(records=recs, stats=dict(zip(STAT_NAMES, stats)), packets=pk)
+
+
+def emission(inp: TransportInputs, first=0, count=None):
+    """Emitted state of packets [first, first+count): [count, 8] rows of
+    (x, y, z, n_x, n_y, n_z, lambda_e, w0), as the transport draws them."""
+    if count is None:
+        count = inp.n_packets - first
+    out = np.zeros((count, 8))
+    if lib().oracle_emission(C.byref(inp.s), first, count, _p(out)) != 0:
+        raise ValueError("oracle_emission: invalid input")
+    return out
 
 
 def dense_estimator(records, n_cells, n_lines):

@@ -275,6 +275,29 @@ int64_t oracle_transport(const or_transport* P, int64_t first, int64_t count, in
   return total;
 }
 
+int oracle_emission(const or_transport* P, int64_t first, int64_t count, double* out) {
+  if (!P || P->n <= 0 || count < 0 || first < 0) return -1;
+  int64_t C = (int64_t)P->n * P->n * P->n;
+  int64_t* start = NULL;
+  if (!P->explicit_packets) {
+    start = (int64_t*)malloc((size_t)(C + 1) * sizeof(int64_t));
+    start[0] = 0;
+    for (int64_t c = 0; c < C; ++c) start[c + 1] = start[c] + P->cell_packets[c];
+    if (first + count > start[C]) { free(start); return -1; }
+  }
+  for (int64_t p = first; p < first + count; ++p) {
+    packet0 q;
+    if (P->explicit_packets) emit_explicit(P, p, &q);
+    else emit_sampled(P, start, C, p, &q);
+    double* o = out + 8 * (p - first);
+    for (int a = 0; a < 3; ++a) { o[a] = q.x[a]; o[3 + a] = q.dir[a]; }
+    o[6] = q.lam_e;
+    o[7] = q.w0;
+  }
+  free(start);
+  return 0;
+}
+
 void oracle_free(void* ptr) { free(ptr); }
 
 /* Eq. A2: tau_S = (A_ul/8pi)(g_u/g_l) lambda^3 n_l (1 - g_l n_u/(g_u n_l)) t.

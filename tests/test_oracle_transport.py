@@ -22,13 +22,18 @@ A = synth.ANGSTROM
 
 
 def _numpy_philox(ctr, key):
-    # numpy advances the 256-bit counter before each block: start one below
+    # numpy advances the 256-bit counter (word 0 least significant) before each
+    # block: start one below, borrowing across words
+    v = sum(int(w) << (64 * i) for i, w in enumerate(ctr)) - 1
+    v %= 1 << 256
+    start = [(v >> (64 * i)) & ((1 << 64) - 1) for i in range(4)]
     bg = np.random.Philox(key=np.array(key, dtype=np.uint64),
-                          counter=np.array([ctr[0] - 1, ctr[1], ctr[2], ctr[3]], dtype=np.uint64))
+                          counter=np.array(start, dtype=np.uint64))
     return bg.random_raw(4)
 
 
 @pytest.mark.parametrize("ctr,key", [((1, 0, 0, 0), (0, 0)), ((5, 7, 1, 0), (2511075391, 3)),
+                                     ((0, 5, 1, 0), (77, 3)),
                                      ((2**63 + 11, 3, 0, 9), (123456789, 987654321))])
 def test_philox_matches_numpy(ctr, key):
     assert np.array_equal(oracle.philox4x64(ctr, key), _numpy_philox(ctr, key))
@@ -283,3 +288,74 @@ def test_line_tau_eq_a2():
     # A/(8 pi) g_u/g_l lambda^3 n_l (1 - g_l n_u / (g_u n_l)) t = 3 n_l - n_u here
     np.testing.assert_allclose(tau, [3.0, 6.0, 0.0, 1.5], rtol=1e-15, atol=1e-15)
     np.testing.assert_allclose(fc, [1.0, 1.0, 0.0, 0.5], rtol=1e-15, atol=1e-15)
+
+
+def _u53(x):
+    return float(int(x) >> 11) * 2.0 ** -53
+
+
+def test_sampled_emission_mapping_matches_numpy_philox():
+    """Each packet's emitted state, recomputed from numpy's own Philox4x64-10
+    and the stated mapping: counters (p, iteration, 0, 0) and (p, iteration,
+    1, 0) under key (seed, 3); uniforms u0..u3 of the first block and u4, u5 of
+    the second; x = corner + h (u0, u1, u2), mu = 2 u3 - 1, phi = 2 pi u4,
+    lambda_e in stratum j of the cell's n_c strata: lambda_lo + (lambda_hi -
+    lambda_lo) (j + u5) / n_c, w0 = cell photons / n_c. Cell-major ids: the
+    cell owning id p is found from the cumulative packet counts. A swapped
+    uniform, axis or stratum formula fails this."""
+    inp = _tiny_workload(1e-9, 5e-5, n=4, n_packets=3000, seed=3)
+    inp.s.iteration = 5
+    cp = inp.arrays["cell_packets"].astype(np.int64)
+    start = np.concatenate([[0], np.cumsum(cp)])
+    ids = [0, 1, 17, 1499, int(start[-1]) - 1] + list(range(700, 705))
+    got = {p: oracle.emission(inp, first=p, count=1)[0] for p in ids}
+    n, beta = 4, 0.01
+    h = 2 * beta / n
+    lo, hi = 4000 * A, 6000 * A
+    for p in ids:
+        c = int(np.searchsorted(start, p, side="right") - 1)
+        j, nc = p - start[c], cp[c]
+        i, jj, k = c % n, (c // n) % n, c // (n * n)
+        r0 = _numpy_philox((p, 5, 0, 0), (77, 3))
+        r1 = _numpy_philox((p, 5, 1, 0), (77, 3))
+        u = [_u53(v) for v in r0] + [_u53(v) for v in r1]
+        corner = [-beta + i * h, -beta + jj * h, -beta + k * h]
+        x = [corner[a] + h * u[a] for a in range(3)]
+        mu = 2.0 * u[3] - 1.0
+        phi = 2.0 * math.pi * u[4]
+        st = math.sqrt(max(0.0, 1.0 - mu * mu))
+        d = [st * math.cos(phi), st * math.sin(phi), mu]
+        lam = lo + (hi - lo) * ((j + u[5]) / nc)
+        w0 = inp.arrays["cell_photons"][c] / nc
+        np.testing.assert_array_equal(got[p][:3], x)
+        np.testing.assert_allclose(got[p][3:6], d, rtol=0, atol=4e-16)
+        assert got[p][6] == lam and got[p][7] == w0
+    # the transport follows exactly these packets: in the thin limit each
+    # escapes with its emitted direction and lambda_L = lambda_e (1 - n.x)
+    r = oracle.transport(inp, per_packet=True, nthreads=1)
+    em = oracle.emission(inp)
+    np.testing.assert_array_equal(r["packets"][:, 8:11], em[:, 3:6])
+    lam_l = em[:, 6] * (1.0 - (em[:, 3:6] * em[:, :3]).sum(1))
+    np.testing.assert_allclose(r["packets"][:, 1], lam_l, rtol=1e-15)
+
+
+def test_rates_hand_computed_two_cells():
+    """Gamma_PE = est[c, line(t)] / (n_lower(c) V) on a 2-cell, 3-line,
+    3-level toy whose values are worked out by hand; a cell whose lower level
+    is empty gets 0."""
+    atom = synth.Atom(species_offset=np.array([0, 3], np.int32),
+                      level_ion=np.zeros(3, np.int32), level_energy=np.zeros(3),
+                      level_g=np.ones(3), trans_lower=np.array([0, 1], np.int32),
+                      trans_upper=np.array([2, 2], np.int32), trans_A=np.ones(2),
+                      trans_lambda=np.ones(2), trans_upsilon=np.ones(2),
+                      trans_line=np.array([2, 0], np.int32), ion_alpha0=np.zeros(3),
+                      species_mass=np.array([1.0]))
+    est = np.array([[3.0, 5.0, 7.0],
+                    [11.0, 13.0, 17.0]])
+    pops = np.array([[2.0, 4.0, 1.0],
+                     [0.0, 8.0, 1.0]])
+    V = 0.5
+    got = oracle.rates(est, pops, atom, V).reshape(2, 2)
+    # cell 0: t0 lower 0 line 2: 7 / (2 * 0.5) = 7; t1 lower 1 line 0: 3 / (4 * 0.5) = 1.5
+    # cell 1: t0 lower level empty -> 0;            t1: 11 / (8 * 0.5) = 2.75
+    np.testing.assert_array_equal(got, [[7.0, 1.5], [0.0, 2.75]])
