@@ -318,7 +318,7 @@ def nlte_inputs_from_workload(w, gamma_pe=None, cells=None):
                       w.gamma_ion.reshape(-1, S, 3)[cells].ravel(), gpe)
 
 
-def nlte(inp: NLTEInputs, guess=None, max_iter=200, tol=1e-13, nthreads=None, first=0,
+def nlte(inp: NLTEInputs, guess=None, max_iter=200, tol=1e-12, nthreads=None, first=0,
          count=None):
     """Solves statistical equilibrium for cells [first, first+count).
 

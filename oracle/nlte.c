@@ -249,7 +249,7 @@ static double newton_damping(int it) {
 #define FIXED_POINT_START_EXIT 0.1
 #define NEWTON_MAX_LOG_STEP 2.302585092994046
 #define NEWTON_HALVINGS 30
-#define JACOBIAN_STEP 1e-6
+#define JACOBIAN_STEP 1e-5
 /* The paper's convergence criterion: every level within 1 % of the fixed-point
  * map. The damping schedule serves the iteration up to that point; beyond it
  * (the oracle continues to tol) Newton steps are taken whole. */
@@ -302,8 +302,8 @@ static double root_residual(int32_t N, const double* H) {
  * 2. Newton-Raphson (Sec. 2.2: a numerical Jacobian built from a matrix
  *    calculation of all rates between all levels; a decreasing damping
  *    schedule) on H(y) = ln P(e^y) - y in y = ln n, so that populations stay
- *    positive. Jacobian column j is the forward difference of H for
- *    y_j + 1e-6; the correction d solves J d = -H by Gaussian elimination
+ *    positive. Jacobian column j is the central difference of H over
+ *    y_j +- 1e-5; the correction d solves J d = -H by Gaussian elimination
  *    with partial pivoting. The step y + damp d takes damp from the paper's
  *    schedule (1 once max |H| is below the paper's 1 % criterion), lowered so
  *    that no level changes by more than a factor of 10, and halved until the
@@ -354,9 +354,12 @@ static int solve_species(const or_atom* a, const or_cells* cl, int64_t c, int32_
     ++it;
     for (int32_t j = 0; j < Ns; ++j) {
       for (int32_t i = 0; i < Ns; ++i) yt[i] = y[i];
-      yt[j] += JACOBIAN_STEP;
+      yt[j] = y[j] + JACOBIAN_STEP;
       if (equations(a, cl, s, Ns, ntot, R0, yt, R, work, P, Ht) != 0) goto done;
-      for (int32_t i = 0; i < Ns; ++i) J[i * Ns + j] = (Ht[i] - H[i]) / JACOBIAN_STEP;
+      for (int32_t i = 0; i < Ns; ++i) J[i * Ns + j] = Ht[i];
+      yt[j] = y[j] - JACOBIAN_STEP;
+      if (equations(a, cl, s, Ns, ntot, R0, yt, R, work, P, Ht) != 0) goto done;
+      for (int32_t i = 0; i < Ns; ++i) J[i * Ns + j] = (J[i * Ns + j] - Ht[i]) / (2.0 * JACOBIAN_STEP);
     }
     for (int32_t i = 0; i < Ns; ++i) Ht[i] = -H[i];
     if (gauss_solve(Ns, J, Ht, d) != 0) goto done;
@@ -404,6 +407,11 @@ int oracle_nlte(const or_atom* a, const or_cells* cl, int64_t first, int64_t cou
       continue;
     }
     if (!use_guess) oracle_nlte_cold(a, cl, c, pc);
+    if (max_iter <= 0) {  /* no iterations: the start is returned, not converged */
+      status[c] = 2;
+      if (iters) iters[c] = 0;
+      continue;
+    }
     int st = 0, itmax = 0;
     for (int32_t s = 0; s < a->n_species; ++s) {
       if (!(cl->n_species[c * a->n_species + s] > 0.0)) continue;

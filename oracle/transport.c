@@ -307,6 +307,7 @@ void oracle_line_tau(int64_t n_cells, int32_t n_levels, int32_t n_trans, const d
                      const int32_t* lower, const int32_t* upper, const double* A,
                      const double* lambda, const double* g, double t_exp,
                      double* tau_ct, double* fcorr_ct) {
+#pragma omp parallel for schedule(static)
   for (int64_t c = 0; c < n_cells; ++c) {
     for (int32_t t = 0; t < n_trans; ++t) {
       double nl = pops[c * n_levels + lower[t]];
