@@ -1,28 +1,33 @@
 """Benchmark of the hot path on one MI355X.
 
-One step = one global iteration of the method on the 50^3-cell workload
-(125 000 cells, 5 000 lines, 1e7 packets, 2 species x 50 levels):
-  Eq. A2 line opacities from the previous populations -> packet transport
-  (FP32 geometry, FP64 estimators) -> photoexcitation rates -> MLP warm
-  start -> NLTE solve of every cell from the MLP's populations (cold-start
-  fallback for systems that do not converge within the warm budget).
-Every step starts from the same previous populations (the cold start), so the
-work per step is fixed. Inputs are resident in HBM before the timed region.
-Setup (not timed) trains the warm-start network on solves of replicas of the
-workload's cells (temperature, deposition and abundances redrawn).
+One step = the whole method on the largest single-GPU workload, clumpy100:
+100^3 = 1e6 cells, 30 000 lines, 1e8 packets per iteration, 2 species x 50
+levels, 5 global iterations. Each iteration: Eq. A2 line opacities from the
+current populations -> packet transport streamed over the 8 velocity octants
+(FP32 geometry, FP64 weights), photoexcitation rates summed per interaction
+-> NLTE solve of every cell to the metric's population accuracy (1e-8). The
+first iteration starts from the learned warm start (cold-start fallback past
+the warm budget), later ones from the previous iteration's populations.
+Every step starts from the same MLP populations, so the work per step is
+fixed. Inputs are resident in HBM before the timed region; the step does no
+host-to-device copies and no allocations.
+
+Setup (not timed): the warm-start network is trained on solves of replicas of
+the 50^3 workload's cells (its own transport, rates and NLTE solves).
 
 Prints one JSON line. `value` is packet line-interactions per second of the
-whole step; NLTE cell-solves per second of the whole step are reported beside
-it, and so is the plain FP64 cold-start NLTE pass on the same rates, timed
-after the step loop, with the largest population difference between the two.
-Both NLTE passes run to the metric's population accuracy (--nlte-tol, 1e-8);
-an untimed solve to 1e-12 then gives the accuracy each pass reached.
+whole step; NLTE cell-solves per second are reported beside it, with the
+plain FP64 cold-start NLTE pass on the last iteration's rates, timed after
+the step loop. The accuracy of both NLTE passes is measured against the
+oracle (tol 1e-12) on a sample of cells with seeded rates, solved by both.
 The roofline object covers the kernel that dominates the step, timed with HIP
-events on the stream the library launches on.
+events on the stream the library launches on. Extra keys: the one-iteration
+50^3 step, emergent spectra, and the batched three-stage NLTE problem.
 """
 import argparse
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -31,7 +36,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "packet line-interactions/s + NLTE cell-solves/s vs plain FP64 at 1e-8 accuracy"
 HBM_PEAK_GBS = 8000.0
-FP64_VALU_PEAK_TFLOPS = 78.6
+FP64_PEAK_TFLOPS = 78.6
+ITERATIONS = 5
 
 
 def parse():
@@ -40,22 +46,38 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-fraction", type=float, default=1.0,
-                    help="fraction of packets and cells the oracle runs for cpu_baseline")
-    ap.add_argument("--geometry-fp64", action="store_true")
-    ap.add_argument("--replicas", type=int, default=8)
+    ap.add_argument("--cpu-packets", type=int, default=10_000_000,
+                    help="packets of the first iteration the oracle transports for cpu_baseline")
+    ap.add_argument("--cpu-cells", type=int, default=16_000,
+                    help="cells the oracle solves for cpu_baseline and the accuracy check")
     ap.add_argument("--epochs", type=int, default=30)
     ap.add_argument("--warm-budget", type=int, default=30)
     ap.add_argument("--nlte-tol", type=float, default=1e-8,
-                    help="population accuracy of both NLTE passes (the metric's 1e-8)")
-    ap.add_argument("--no-spectrum", action="store_true",
-                    help="skip the emergent-spectrum measurement")
-    ap.add_argument("--no-batched", action="store_true",
-                    help="skip the batched three-stage NLTE measurement")
+                    help="population accuracy of the NLTE solves (the metric's 1e-8)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the 50^3 step, spectrum and batched measurements")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device-to-device copy before the step loop, whose "
                          "FETCH_SIZE/WRITE_SIZE counters calibrate the HBM traffic figures")
     return ap.parse_args()
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def nlte_flops_per_iteration(atom):
+    """Algorithmic FP64 flops of one NLTE iteration of one system, per species:
+    two state reductions (a fixed-point or Newton step and its residual), each
+    eliminating the excited levels of every ion stage in its own block,
+    (2/3) (L_z - 1)^3 per stage of L_z levels."""
+    import numpy as np
+    out = []
+    for s in range(atom.n_species):
+        lv = atom.level_ion[atom.species_offset[s]:atom.species_offset[s + 1]]
+        L = np.bincount(lv).astype(np.float64)
+        out.append(2.0 * float(((2.0 / 3.0) * np.maximum(L - 1, 0) ** 3).sum()))
+    return out
 
 
 def main():
@@ -70,15 +92,257 @@ def main():
 
     import paper_2511_07539_amd as ex
     import synth
+    from paper_2511_07539_amd import globalloop, warmstart
 
     dev = "cuda:0"
     torch.cuda.set_device(0)
-    w = synth.paper_scale()
     ctx = ex.Context(0)
+    t_setup = time.perf_counter()
+    w50 = synth.paper_scale()
+    say("setup: warm-start training on the 50^3 pipeline")
+    params, norm, hist = warmstart.train_on_workload(ctx, w50, epochs=args.epochs)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t_setup
+    extras = {}
+    if not args.no_extras:
+        extras["clumpy50_step"] = bench_clumpy50(ex, ctx, w50, params, norm, args)
+        torch.cuda.empty_cache()
+    w = synth.large()
+    say(f"setup: {w.name} resident on the GPU")
+    loop = globalloop.GlobalLoop(ctx, w, tol=args.nlte_tol, warm_budget=args.warm_budget)
+    s = torch.cuda.current_stream()
+    inter = torch.zeros(ITERATIONS, dtype=torch.float64, device=dev)
+    iters_sum = torch.zeros((ITERATIONS, 2), dtype=torch.float64, device=dev)
+
+    def step(evs=None):
+        loop.start(params, norm)
+        for k in range(ITERATIONS):
+            loop.iterate(k, args.warm_budget if k == 0 else 0,
+                         None if evs is None else evs[k])
+            inter[k].copy_(loop.stats[4])
+            iters_sum[k, 0].copy_(loop.iters.sum())
+            iters_sum[k, 1].copy_((loop.status <= 1).sum())
+
+    if args.copy_calibration:
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)  # reads 1 GiB, writes 1 GiB
+        torch.cuda.synchronize()
+        del src, dst
+    say("warm-up steps")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [[[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(ITERATIONS)]
+           for _ in range(args.steps)]
+    say("timed steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) * 1e3 / args.steps
+    names = ["line_tau", "transport", "nlte"]
+    per_it = np.zeros((ITERATIONS, 3))
+    for e in evs:
+        for k in range(ITERATIONS):
+            for i in range(3):
+                per_it[k, i] += e[k][i].elapsed_time(e[k][i + 1])
+    per_it /= args.steps
+    parts = {n: float(per_it[:, i].sum()) for i, n in enumerate(names)}
+    inter_np = inter.cpu().numpy()
+    n_inter = float(inter_np.sum())
+    it_np = iters_sum.cpu().numpy()
+    status = loop.status.cpu().numpy()
+    value = n_inter / (ms * 1e-3)
+    solves = ITERATIONS * w.n_cells / (ms * 1e-3)
+
+    # the plain FP64 pass from the cold start on the last iteration's rates
+    say("plain FP64 cold-start NLTE pass")
+    pops_c = torch.empty_like(loop.pops)
+    st_c = torch.empty_like(loop.status)
+    it_c = torch.empty_like(loop.iters)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    ex.nlte_solve(ctx, loop.atom, loop.cells, tol=args.nlte_tol, pops=pops_c, status=st_c,
+                  iters=it_c)
+    e1.record(s)
+    torch.cuda.synchronize()
+    cold_ms = e0.elapsed_time(e1)
+    cold_iters = float(it_c.float().mean())
+    cold_ok = int((st_c == 0).sum())
+    del pops_c, st_c, it_c
+
+    # roofline of the dominant kernel
+    fl = nlte_flops_per_iteration(w.atom)
+    flops = float(it_np[:, 0].sum() * sum(fl))   # iteration count is the larger of the species'
+    dom = max(parts, key=parts.get)
+    if dom == "nlte":
+        ach = flops / (parts["nlte"] * 1e-3) / 1e12
+        roof = {"kernel": "extrass_nlte_solve (k_nlte)", "bound": "alu", "achieved": ach,
+                "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": ach / FP64_PEAK_TFLOPS,
+                "traffic": recorded_traffic("extrass_nlte_clumpy100"),
+                "algorithmic_flops": flops,
+                "flops_per_system_iteration": fl}
+    else:
+        bytes_alg = ITERATIONS * (16.0 * w.n_cells * w.atom.n_trans + 16.0 * w.n_lines)
+        ach = bytes_alg / (parts[dom] * 1e-3) / 1e9
+        roof = {"kernel": f"extrass_{dom}", "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                "algorithmic_bytes": bytes_alg}
+    out = {
+        "metric": METRIC, "value": value, "unit": "line-interactions/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "cells": w.n_cells, "lines": w.n_lines,
+                   "packets_per_iteration": w.n_packets, "global_iterations": ITERATIONS,
+                   "subdomains": 8, "levels": w.atom.n_levels, "species": w.atom.n_species,
+                   "geometry": "fp32", "nlte_tol": args.nlte_tol},
+        "nlte_cell_solves_per_s": solves,
+        "interactions_per_step": n_inter,
+        "interactions_per_iteration": inter_np.tolist(),
+        "ms_parts": parts,
+        "ms_per_iteration": {n: per_it[:, i].tolist() for i, n in enumerate(names)},
+        "nlte_iters_mean": (it_np[:, 0] / w.n_cells).tolist(),
+        "cells_converged_per_iteration": it_np[:, 1].astype(int).tolist(),
+        "nlte_fallbacks_last": int((status == 1).sum()),
+        "nlte_vs_plain_fp64": {
+            "warm_first_iteration_ms": float(per_it[0, 2]),
+            "warm_later_iterations_ms": float(per_it[1:, 2].mean()),
+            "plain_fp64_cold_ms": cold_ms, "plain_fp64_cold_iters_mean": cold_iters,
+            "plain_fp64_cold_converged": cold_ok,
+            "cell_solves_per_s_warm_later": w.n_cells / (per_it[1:, 2].mean() * 1e-3),
+            "cell_solves_per_s_plain_fp64": w.n_cells / (cold_ms * 1e-3)},
+        "warm_start_training": {"workload": w50.name, "epochs": args.epochs,
+                                "loss_first": hist[0], "loss_last": hist[-1],
+                                "setup_s": t_train},
+        "roofline": roof,
+    }
+    say("accuracy sample")
+    sample, gpe_s = accuracy_sample(w, args.cpu_cells)
+    out["nlte_accuracy"], ref = nlte_accuracy(ex, ctx, loop, w, sample, gpe_s, params, norm, args)
+    del loop
+    torch.cuda.empty_cache()
+    out.update(extras)
+    if not args.no_extras:
+        out["spectrum"] = bench_spectrum(ex, ctx, w50)
+        torch.cuda.empty_cache()
+        out["batched_nlte"] = bench_batched(ex, ctx)
+    if not args.no_cpu_baseline:
+        say("cpu_baseline: oracle on a sample")
+        out["cpu_baseline"] = cpu_baseline(w, n_inter, sample, gpe_s, ref, args)
+    print(json.dumps(out), flush=True)
+
+
+def accuracy_sample(w, n):
+    """Cells (evenly spaced over the grid) and seeded photoexcitation rates for
+    the accuracy check; both sides solve exactly these inputs."""
+    import numpy as np
+    n = min(n, w.n_cells)
+    cells = np.linspace(0, w.n_cells - 1, n).astype(np.int64)
+    g = np.random.default_rng(2511)
+    T = w.atom.n_trans
+    gpe = np.abs(g.standard_normal((n, T))) * 10 ** g.uniform(-8, 0, (n, T))
+    return cells, gpe
+
+
+def nlte_accuracy(ex, ctx, loop, w, cells, gpe, params, norm, args):
+    """Componentwise max |n - n_oracle| / n_oracle of the GPU's NLTE solves on
+    the sample: the plain FP64 cold start and the MLP warm start, both at the
+    bench's tol, against the oracle at 1e-12 on the same seeded inputs."""
+    import numpy as np
+    import torch
+
+    import oracle
+    S = w.atom.n_species
+    cl = ex.Cells(w.t_exp, w.T_e[cells], w.n_e[cells], w.n_species.reshape(-1, S)[cells],
+                  w.gamma_ion.reshape(-1, S, 3)[cells], gpe)
+    pc, sc, _ = ex.nlte_solve(ctx, loop.atom, cl, tol=args.nlte_tol)
+    guess = ex.nlte_warm_start(ctx, loop.atom, cl, w.deposition[cells], params, norm)
+    pw, sw, _ = ex.nlte_solve(ctx, loop.atom, cl, tol=args.nlte_tol, guess=guess,
+                              warm_budget=args.warm_budget)
+    torch.cuda.synchronize()
+    inp = oracle.nlte_inputs_from_workload(w, gamma_pe=np.ascontiguousarray(gpe).ravel(),
+                                           cells=cells)
+    t0 = time.perf_counter()
+    po, so, _ = oracle.nlte(inp, tol=1e-12)
+    t_or = time.perf_counter() - t0
+
+    def rel(p, st):
+        p, st = p.cpu().numpy(), st.cpu().numpy()
+        ok = (so == 0) & (st <= 1)
+        r = np.abs(p[ok] - po[ok]) / po[ok]
+        return {"max_rel": float(r.max()), "cells_above_tol": int((r.max(1) > args.nlte_tol).sum()),
+                "compared": int(ok.sum())}
+    acc = {"tol": args.nlte_tol, "reference": "oracle, tol 1e-12", "cells": int(len(cells)),
+           "oracle_converged": int((so == 0).sum()),
+           "plain_fp64_cold": rel(pc, sc), "mlp_warm": rel(pw, sw)}
+    return acc, {"oracle_s": t_or, "status": so}
+
+
+def host_cpu():
+    info = {"os_cpu_count": os.cpu_count()}
+    try:
+        info["affinity"] = len(os.sched_getaffinity(0))
+    except AttributeError:
+        pass
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            k, _, v = line.partition(":")
+            if k.strip() in ("Model name", "Socket(s)", "Core(s) per socket", "Thread(s) per core"):
+                info[k.strip()] = v.strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return info
+
+
+def cpu_baseline(w, inter_step, sample, gpe, ref, args):
+    """The FP64 oracle on the host, as it stands, on a bounded sample of the
+    step: its transport on the first packets of the first iteration (line
+    opacities from the oracle's own cold-start populations), and its NLTE
+    solve (tol 1e-12) of the accuracy sample's cells. The whole step's time is
+    scaled up from those rates: the step's interactions at the sample's
+    interaction rate, plus ITERATIONS solves of every cell at the sample's
+    per-cell time."""
+    import numpy as np
+
+    import oracle
+    nthreads = oracle.default_threads()
+    inp_n = oracle.nlte_inputs_from_workload(w)
+    cold, _, _ = oracle.nlte(inp_n, max_iter=0)
+    tau, fc = oracle.line_tau(cold, w.atom, w.t_exp)
+    del cold, inp_n
+    inp = oracle.transport_inputs_from_workload(w, tau_ct=tau, fcorr_ct=fc)
+    P = min(args.cpu_packets, w.n_packets)
+    t0 = time.perf_counter()
+    r = oracle.transport(inp, first=0, count=P, nthreads=nthreads)
+    t_tr = time.perf_counter() - t0
+    rate = r["stats"]["n_inter"] / t_tr
+    t_nlte_cell = ref["oracle_s"] / len(sample)
+    t_step = inter_step / rate + ITERATIONS * w.n_cells * t_nlte_cell
+    return {"value": inter_step / t_step, "unit": "line-interactions/s", "cores": nthreads,
+            "kind": "oracle", "nlte_cell_solves_per_s": 1.0 / t_nlte_cell,
+            "transport_interactions_per_s": rate, "host": host_cpu(),
+            "sample": f"transport of packets [0, {P}) of iteration 1 ({r['stats']['n_inter']:.3g} "
+                      f"interactions, {t_tr:.1f} s); NLTE of {len(sample)} cells at tol 1e-12 "
+                      f"({ref['oracle_s']:.1f} s); scaled to the step's {inter_step:.3g} "
+                      f"interactions and {ITERATIONS} x {w.n_cells} cell solves"}
+
+
+def bench_clumpy50(ex, ctx, w, params, norm, args):
+    """One global iteration on the 50^3 workload (125 000 cells, 5000 lines,
+    1e7 packets) with the dense [C x L] FP64 estimator table: opacities ->
+    transport -> rates -> MLP warm start -> NLTE, from the cold-start
+    populations; HIP events per part; the transport's HBM roofline counts the
+    table written once (8 C L bytes) plus the per-cell and per-line inputs."""
+    import torch
+    dev = "cuda:0"
     atom = ex.Atom(ctx, w.atom)
-    V = ex.cell_volume(w)
     cells0 = ex.cells_from_workload(w, device=dev)
-    # previous populations: the cold start (not timed)
     prev, _, _ = ex.nlte_solve(ctx, atom, cells0, max_iter=0)
     prev = prev.clone()
     tau, fc = ex.line_tau(ctx, atom, prev, w.t_exp)
@@ -91,162 +355,67 @@ def main():
     iters = torch.empty(w.n_cells, dtype=torch.int32, device=dev)
     cells = ex.Cells(w.t_exp, cells0.T_e, cells0.n_e, cells0.n_species, cells0.gamma_ion, gamma,
                      device=dev)
-    fp32 = not args.geometry_fp64
-    # learned warm start: trained on the method's own solves (setup, not timed)
-    from paper_2511_07539_amd import warmstart
-    t_train = time.perf_counter()
-    gamma_train = warmstart.photoexcitation_rates(ctx, atom, w, dev)
-    X, Y = warmstart.make_dataset(ctx, atom, w, n_replicas=args.replicas, gamma=gamma_train)
-    del gamma_train
-    params, norm, hist = warmstart.train(ctx, X, Y, epochs=args.epochs, batch=8192)
-    torch.cuda.synchronize()
-    t_train = time.perf_counter() - t_train
     dep = torch.as_tensor(w.deposition, device=dev)
-    guess = torch.empty_like(prev)
     s = torch.cuda.current_stream()
     names = ["line_tau", "transport", "rates", "warm_start", "nlte"]
 
     def step(ev=None):
-        def mark(i):
-            if ev is not None:
-                ev[i].record(s)
+        mark = (lambda i: ev[i].record(s)) if ev is not None else (lambda i: None)
         mark(0)
         ex.line_tau(ctx, atom, prev, w.t_exp, tau=grid.tau_ct, fcorr=grid.fcorr_ct)
         mark(1)
         ex.transport(ctx, grid, w.seed, w.lambda_lo, w.lambda_hi, w.n_packets,
-                     geometry_fp32=fp32, est=est, stats=stats)
+                     geometry_fp32=True, est=est, stats=stats)
         mark(2)
-        ex.rates(ctx, atom, est, prev, V, out=gamma)
+        ex.rates(ctx, atom, grid, w.t_exp, est, prev, out=gamma)
         mark(3)
         ex.nlte_warm_start(ctx, atom, cells, dep, params, norm, pops=pops)
         mark(4)
         ex.nlte_solve(ctx, atom, cells, pops=pops, use_guess=True, warm_budget=args.warm_budget,
-                      tol=args.nlte_tol,
-                      status=status, iters=iters)
+                      tol=args.nlte_tol, status=status, iters=iters)
         mark(5)
 
-    if args.copy_calibration:
-        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)  # reads 1 GiB, writes 1 GiB
-        torch.cuda.synchronize()
-        del src, dst
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(args.steps)]
+    step()
+    reps = 10
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(reps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for k in range(args.steps):
+    for k in range(reps):
         step(evs[k])
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    parts = {n: 0.0 for n in names}
-    for ev in evs:
-        for i, n in enumerate(names):
-            parts[n] += ev[i].elapsed_time(ev[i + 1])
-    parts = {n: v / args.steps for n, v in parts.items()}
-    ms = (t1 - t0) * 1e3 / args.steps
-    st = ex.stats_dict(stats)
-    n_inter = st["n_inter"]
-    st_np = status.cpu().numpy()
-    conv = int((st_np <= 1).sum())
-    fallbacks = int((st_np == 1).sum())
-    it_warm = iters.cpu().numpy()
-    # the plain FP64 pass from the cold start on the same rates, for comparison
-    pops_cold = torch.empty_like(pops)
-    st_cold = torch.empty_like(status)
-    it_cold = torch.empty_like(iters)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(s)
-    ex.nlte_solve(ctx, atom, cells, pops=pops_cold, status=st_cold, iters=it_cold,
-                  tol=args.nlte_tol)
-    e1.record(s)
-    torch.cuda.synchronize()
-    cold_ms = e0.elapsed_time(e1)
-    both = (st_cold == 0) & (status <= 1)
-    pw, pc = pops[both], pops_cold[both]
-    warm_vs_cold = float(((pw - pc).abs() / pc).max().item()) if int(both.sum()) else None
-    # accuracy of both passes against a tight FP64 solve (tol 1e-12, untimed)
-    ref, st_ref, _ = ex.nlte_solve(ctx, atom, cells, tol=1e-12, max_iter=400)
-    ok_ref = st_ref == 0
-
-    def max_rel(p, st):
-        m = ok_ref & (st <= 1)
-        return float((((p - ref).abs() / ref)[m]).max().item()) if int(m.sum()) else None
-    accuracy = {"tol": args.nlte_tol, "reference_tol": 1e-12,
-                "reference_converged": int(ok_ref.sum().item()),
-                "warm_max_rel": max_rel(pops, status), "cold_max_rel": max_rel(pops_cold, st_cold)}
-    del ref
-    value = n_inter / (ms * 1e-3)
-    solves = w.n_cells / (ms * 1e-3)
-
-    # roofline of the dominant kernel
-    dom = max(parts, key=parts.get)
-    if dom == "transport":
-        bytes_alg = 8.0 * w.n_cells * w.n_lines + 16.0 * w.n_cells + 16.0 * w.n_lines
-        ach = bytes_alg / (parts["transport"] * 1e-3) / 1e9
-        roof = {"kernel": "extrass_transport (fill + transport kernels)", "bound": "hbm",
-                "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
-                "traffic": recorded_traffic("extrass_transport"), "algorithmic_bytes": bytes_alg}
-    else:
-        it_np = it_warm
-        S = w.atom.n_species
-        Ns = np.diff(w.atom.species_offset)
-        # state reductions: about two per iteration (fixed-point or Newton + trial),
-        # (2/3) N^3 flops each
-        flops = float(sum(2.0 * it_np.sum() * (2.0 / 3.0) * n ** 3 for n in Ns))
-        ach = flops / (parts[dom] * 1e-3) / 1e12
-        roof = {"kernel": f"extrass_{dom}", "bound": "alu", "achieved": ach,
-                "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": ach / FP64_VALU_PEAK_TFLOPS, "traffic": recorded_traffic("extrass_nlte"),
-                "algorithmic_flops": flops}
-
-    out = {
-        "metric": METRIC, "value": value, "unit": "line-interactions/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": w.name, "cells": w.n_cells, "lines": w.n_lines,
-                   "packets": w.n_packets, "levels": w.atom.n_levels,
-                   "species": w.atom.n_species, "geometry": "fp32" if fp32 else "fp64",
-                   "parallelism": "single GPU"},
-        "nlte_cell_solves_per_s": solves,
-        "interactions_per_step": n_inter,
-        "cells_converged": conv,
-        "nlte_fallbacks": fallbacks,
-        "nlte_iters_mean": {"warm": float(it_warm.mean()), "cold": float(it_cold.float().mean())},
-        "nlte_plain_fp64_cold_ms": cold_ms,
-        "nlte_warm_vs_cold_max_rel": warm_vs_cold,
-        "nlte_accuracy": accuracy,
-        "warm_start_training": {"samples": int(X.shape[0]), "epochs": args.epochs,
-                                "loss_first": hist[0], "loss_last": hist[-1],
-                                "setup_s": t_train},
-        "ms_parts": parts,
-        "roofline": roof,
-    }
-    if not args.no_spectrum:
-        out["spectrum"] = bench_spectrum(ex, ctx, w, grid, fp32)
-    if not args.no_batched:
-        del est, grid, gamma
-        torch.cuda.empty_cache()
-        out["batched_nlte"] = bench_batched(ex, ctx)
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, prev.cpu().numpy(), args.cpu_fraction)
-    print(json.dumps(out), flush=True)
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    parts = {n: sum(e[i].elapsed_time(e[i + 1]) for e in evs) / reps for i, n in enumerate(names)}
+    sd = ex.stats_dict(stats)
+    bytes_alg = 8.0 * w.n_cells * w.n_lines + 16.0 * w.n_cells + 16.0 * w.n_lines
+    ach = bytes_alg / (parts["transport"] * 1e-3) / 1e9
+    fl = nlte_flops_per_iteration(w.atom)
+    flops = float(iters.double().sum()) * sum(fl)
+    return {"workload": w.name, "ms_per_step": ms, "value": sd["n_inter"] / (ms * 1e-3),
+            "unit": "line-interactions/s", "interactions_per_step": sd["n_inter"],
+            "nlte_cell_solves_per_s": w.n_cells / (ms * 1e-3), "ms_parts": parts,
+            "cells_converged": int((status <= 1).sum()),
+            "nlte_iters_mean": float(iters.float().mean()),
+            "roofline_transport": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
+                                   "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                                   "algorithmic_bytes": bytes_alg,
+                                   "traffic": recorded_traffic("extrass_transport")},
+            "roofline_nlte": {"bound": "alu", "achieved": flops / (parts["nlte"] * 1e-3) / 1e12,
+                              "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                              "frac": flops / (parts["nlte"] * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
+                              "algorithmic_flops": flops}}
 
 
-def bench_spectrum(ex, ctx, w, grid, fp32):
-    """Emergent spectra of the step's packets (Sec. 2.3): 20 x 20 viewers and
-    0.1 % log-wavelength bins over the band widened by the Doppler shifts. One
-    untimed transport writes the per-packet records; the binning of all 1e7
-    records (64 B each) is timed with HIP events."""
+def bench_spectrum(ex, ctx, w):
+    """Emergent spectra of the 50^3 workload's packets (Sec. 2.3): 20 x 20
+    viewers and 0.1 % log-wavelength bins over the band widened by the Doppler
+    shifts. One untimed transport writes the per-packet records; the binning of
+    all 1e7 records (64 B each) is timed with HIP events."""
     import math
 
     import torch
+    grid = ex.grid_from_workload(w)
     _, st, pk = ex.transport(ctx, grid, w.seed, w.lambda_lo, w.lambda_hi, w.n_packets,
-                             geometry_fp32=fp32, packets_out=True)
+                             geometry_fp32=True, packets_out=True)
     lo, hi = w.lambda_lo * 0.97, w.lambda_hi * 1.03
     n_lam = int(math.ceil(math.log(hi / lo) / math.log(1.001)))
     bins = (20, 20, n_lam, lo, hi)
@@ -264,8 +433,8 @@ def bench_spectrum(ex, ctx, w, grid, fp32):
     ms = e0.elapsed_time(e1) / reps
     sd = ex.stats_dict(st)
     rec_bytes = pk.numel() * 8
-    return {"viewers": [20, 20], "lambda_bins": n_lam,
-            "lambda_range_cm": [lo, hi], "ms_binning_incl_zero": ms,
+    return {"workload": w.name + " (background opacities)", "viewers": [20, 20],
+            "lambda_bins": n_lam, "lambda_range_cm": [lo, hi], "ms_binning_incl_zero": ms,
             "record_bytes": rec_bytes, "record_read_tb_per_s": rec_bytes / (ms * 1e-3) / 1e12,
             "escaped_packets": int(sd["n_escaped"]),
             "escaped_photon_fraction": sd["w_esc"] / sd["w_emit"],
@@ -276,7 +445,7 @@ def bench_batched(ex, ctx):
     """The batched three-stage NLTE problem (125 000 cells, 20-300 levels per
     stage): tuned launch shape, then one FP64 solve and one FP32-factor solve
     with two FP64 refinement sweeps, each timed with HIP events on the stream
-    the library launches on. Not part of the step."""
+    the library launches on."""
     import numpy as np
     import torch
 
@@ -300,7 +469,8 @@ def bench_batched(ex, ctx):
         ms = e0.elapsed_time(e1)
         st = status.cpu().numpy()
         res[name] = {"ms": ms, "cell_solves_per_s": b.n_cells / (ms * 1e-3),
-                     "tuned_panel_per_cu": list(shape), "status_counts": np.bincount(st, minlength=3).tolist(),
+                     "tuned_panel_per_cu": list(shape),
+                     "status_counts": np.bincount(st, minlength=3).tolist(),
                      "achieved_tflops_factor_equivalent": flops / (ms * 1e-3) / 1e12}
         del pops, status
     return res
@@ -322,41 +492,6 @@ def recorded_traffic(key):
     except (OSError, KeyError, ValueError):
         return None
     return rec["bytes"] if m.hexdigest()[:16] == rec["source_hash"] else None
-
-
-def cpu_baseline(w, prev, frac):
-    """The FP64 oracle on the host, as it stands, on a bounded sample: the first
-    `frac` of the packets and of the cells; the whole-step time is scaled up
-    from that sample."""
-    import numpy as np
-
-    import oracle
-    nthreads = oracle.default_threads()
-    tau, fc = oracle.line_tau(prev, w.atom, w.t_exp)
-    inp = oracle.transport_inputs_from_workload(w, tau_ct=tau, fcorr_ct=fc)
-    P = int(w.n_packets * frac)
-    t0 = time.perf_counter()
-    r = oracle.transport(inp, first=0, count=P, nthreads=nthreads)
-    t1 = time.perf_counter()
-    Cs = int(w.n_cells * frac)
-    cells = np.arange(Cs)
-    rec = r["records"]
-    sel = rec["cell"] < Cs
-    est = np.zeros(Cs * w.n_lines)
-    np.add.at(est, rec["cell"][sel].astype(np.int64) * w.n_lines + rec["line"][sel],
-              rec["value"][sel])
-    V = (2 * w.beta_max / w.n * 2.99792458e10 * w.t_exp) ** 3
-    gpe = oracle.rates(est, prev[:Cs], w.atom, V)
-    ninp = oracle.nlte_inputs_from_workload(w, gamma_pe=gpe, cells=cells)
-    t2 = time.perf_counter()
-    oracle.nlte(ninp, guess=prev[:Cs], nthreads=nthreads)
-    t3 = time.perf_counter()
-    t_step = (t1 - t0) / frac + (t3 - t2) / frac
-    inter_step = r["stats"]["n_inter"] / frac
-    return {"value": inter_step / t_step, "unit": "line-interactions/s", "cores": nthreads,
-            "kind": "oracle", "nlte_cell_solves_per_s": w.n_cells / t_step,
-            "sample": f"first {P} packets and first {Cs} cells ({frac:.0%}) of the workload; "
-                      f"transport {t1 - t0:.2f} s, NLTE {t3 - t2:.2f} s, scaled to the full step"}
 
 
 if __name__ == "__main__":

@@ -12,8 +12,9 @@
  *  - Scratch memory comes from the caller's workspace (`ws`, `ws_bytes`),
  *    sized by the matching *_workspace query. The library performs no device
  *    allocation during these calls.
- *  - `stream` is a hipStream_t (NULL = the null stream). All work is
- *    enqueued on it; outputs are valid once the stream has completed.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream), so
+ *    that this header needs no HIP header. All work is enqueued on it;
+ *    outputs are valid once the stream has completed.
  *  - Return codes: EXTRASS_OK, or a negative EXTRASS_E* code (below). Bad
  *    arguments are detected on the host before any work is enqueued. Errors
  *    found on the device (e.g. a full record buffer) are reported through the
@@ -69,7 +70,10 @@ const char* extrass_last_error(extrass_handle h);
  * Opacity: tau(c,k) = line_tau0[k] * tau_scale[c] (f_corr = 1), except for
  * lines with line_trans[k] = t >= 0 when tau_ct is given: then
  * tau = tau_ct[c*n_trans + t], f_corr = fcorr_ct[c*n_trans + t] (Eq. A2 and
- * its stimulated-emission factor; see extrass_line_tau).
+ * its stimulated-emission factor; see extrass_line_tau). An entry of
+ * line_trans outside [-1, n_trans) is never used as an index: the line is
+ * treated as a background line and stats[EXTRASS_STAT_BAD_LINES] is set
+ * (the estimators are then invalid).
  */
 typedef struct {
   int32_t n;                    /* cells per axis (1..1024) */
@@ -121,7 +125,8 @@ enum {
   EXTRASS_STAT_BAD_PACKETS = 14, /* 1.0 if some packet id lay beyond the sampling plan
                                     or a packet had no wall ahead (NaN or zero direction);
                                     such packets are dropped */
-  EXTRASS_STAT_BAD_LINES = 15,   /* 1.0 if line_lambda is not non-decreasing (est invalid) */
+  EXTRASS_STAT_BAD_LINES = 15,   /* 1.0 if line_lambda is not non-decreasing, or a line_trans
+                                    entry lies outside [-1, n_trans) (est invalid) */
   EXTRASS_STATS = 16
 };
 
@@ -187,10 +192,16 @@ int extrass_line_tau(extrass_handle h, extrass_atom_handle atom, int64_t n_cells
  * divided by the number of atoms in the line's lower level (population times
  * cell volume), is the photoexcitation rate per lower atom:
  *   gamma_pe[c*T + t] = est[c*L + line(t)] / (pops[c*N + lower(t)] * V),
- * 0 where that population is 0. The photo-de-excitation rate per upper atom
- * follows by detailed balance, (g_l/g_u) gamma_pe, inside the NLTE solve. */
-int extrass_rates(extrass_handle h, extrass_atom_handle atom, int64_t n_cells, int32_t n_lines,
-                  const double* est, const double* pops, double cell_volume, double* gamma_pe,
+ * 0 where that population is 0. The cells are those of `grid` (C = n^3,
+ * L = grid->n_lines; only n, beta_max and n_lines are read), and V is the
+ * physical volume of one cell in homologous flow, (2 beta_max / n * c t_exp)^3
+ * cm^3 (a cell's width in x = v/c times c t_exp), computed here. est [C*L],
+ * pops [C*N], gamma_pe [C*T] are device arrays. EXTRASS_EINVAL if an atom
+ * transition's line index is not below L. The photo-de-excitation rate per
+ * upper atom follows by detailed balance, (g_l/g_u) gamma_pe, inside the NLTE
+ * solve. */
+int extrass_rates(extrass_handle h, extrass_atom_handle atom, const extrass_grid* grid,
+                  double t_exp, const double* est, const double* pops, double* gamma_pe,
                   void* stream);
 
 /* ------------------------------------------------------------------------
@@ -210,7 +221,8 @@ int extrass_rates(extrass_handle h, extrass_atom_handle atom, int64_t n_cells, i
  *
  * After each visit, if atom is not NULL, the visit's estimators are turned
  * into photoexcitation rates and ADDED to gamma_pe[C*T] (zeroed at the start;
- * rates are linear in the estimators): gamma_pe[c,t] += est/(n_l V). If
+ * rates are linear in the estimators): gamma_pe[c,t] += est/(n_l V), with V
+ * the cell volume (2 beta_max / n * c t_exp)^3 as in extrass_rates. If
  * est_global is not NULL ([C*L], tests and small grids), every visit's table
  * is also added into it at the global cell rows (zeroed at the start).
  *
@@ -229,7 +241,7 @@ int extrass_rates(extrass_handle h, extrass_atom_handle atom, int64_t n_cells, i
  * between visits (queue lengths decide the next launch). */
 size_t extrass_transport_streamed_workspace(const extrass_grid* grid, int64_t queue_capacity);
 int extrass_transport_streamed(extrass_handle h, const extrass_grid* grid, const extrass_source* src,
-                               extrass_atom_handle atom, const double* pops, double cell_volume,
+                               extrass_atom_handle atom, const double* pops, double t_exp,
                                double* est_octant, double* est_global, double* gamma_pe,
                                double* stats, int64_t queue_capacity, void* ws, size_t ws_bytes,
                                void* stream);
@@ -254,7 +266,8 @@ typedef struct {
   const double* trans_A;           /* host [T] s^-1 */
   const double* trans_lambda;      /* host [T] cm */
   const double* trans_upsilon;     /* host [T] effective collision strength */
-  const int32_t* trans_line;       /* host [T] line index, used by extrass_rates */
+  const int32_t* trans_line;       /* host [T] line index (>= 0; below the grid's L where
+                                      extrass_rates or the streamed rates use it) */
   const double* ion_alpha0;        /* host [S*3] recombination into stage z at 1e4 K */
 } extrass_atom_desc;
 
@@ -279,7 +292,7 @@ typedef struct {
                           populations are then within about tol relative of the root */
   int32_t use_guess;   /* 1: start from pops on entry (a non-positive entry means
                           the cold start for that system); 0: cold start */
-  int32_t factor_fp32; /* 1: Newton systems factored in FP32, residuals in FP64 */
+  int32_t factor_fp32; /* must be 0 (FP64 factors); 1 returns EXTRASS_EUNSUPPORTED */
   int32_t warm_budget; /* with use_guess: after this many iterations from the guess,
                           a system still in its fixed-point phase or with a
                           fixed-point residual above 1e-6 restarts from the cold
@@ -334,6 +347,11 @@ int extrass_mlp_train_step(extrass_handle h, float* params, float* adam_m, float
  * norm[112..211] (standard deviations), exponentiated and scaled so that each
  * species sums to its density. The atom must have 2 species and 100 levels. */
 size_t extrass_nlte_warm_start_workspace(int64_t n_cells);
+/* The six raw (not normalised) features extrass_nlte_warm_start forms for each
+ * cell, x [n_cells*6] (device, FP32), for building training sets and their
+ * normalisation. The atom must have 2 species. */
+int extrass_mlp_features(extrass_handle h, extrass_atom_handle atom, const extrass_cells* cells,
+                         const double* deposition, float* x, void* stream);
 int extrass_nlte_warm_start(extrass_handle h, extrass_atom_handle atom, const extrass_cells* cells,
                             const double* deposition, const float* params, const float* norm,
                             double* pops, void* ws, size_t ws_bytes, void* stream);
@@ -399,7 +417,7 @@ int extrass_batched_workspace(extrass_handle h, const extrass_batched* p,
  * upload of the chunk plan. */
 int extrass_batched_solve(extrass_handle h, const extrass_batched* p, const extrass_batched_opts* o,
                           double* pops, int32_t* status, void* ws, size_t ws_bytes,
-                          hipStream_t stream);
+                          void* stream);
 
 /* Autotuner: times the factorisation of the first cells of p (up to the
  * workspace's capacity) for every panel width (16, 32, 64) and work-groups per
@@ -408,7 +426,7 @@ int extrass_batched_solve(extrass_handle h, const extrass_batched* p, const extr
  * times[9] (optional, host) receives the milliseconds of each candidate, panel-major.
  * Synchronises the stream. */
 int extrass_batched_tune(extrass_handle h, const extrass_batched* p, const extrass_batched_opts* o,
-                         void* ws, size_t ws_bytes, hipStream_t stream, int32_t* choice,
+                         void* ws, size_t ws_bytes, void* stream, int32_t* choice,
                          float* times);
 
 #ifdef __cplusplus

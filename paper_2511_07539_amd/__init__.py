@@ -94,7 +94,7 @@ _lib.extrass_transport_workspace.argtypes = [C.POINTER(_Grid), C.POINTER(_Source
 _lib.extrass_transport.argtypes = [_vp, C.POINTER(_Grid), C.POINTER(_Source), _vp, _vp, _vp, _vp,
                                    C.c_size_t, _vp]
 _lib.extrass_line_tau.argtypes = [_vp, _vp, C.c_int64, _vp, C.c_double, _vp, _vp, _vp]
-_lib.extrass_rates.argtypes = [_vp, _vp, C.c_int64, C.c_int32, _vp, _vp, C.c_double, _vp, _vp]
+_lib.extrass_rates.argtypes = [_vp, _vp, C.POINTER(_Grid), C.c_double, _vp, _vp, _vp, _vp]
 _lib.extrass_atom_create.argtypes = [_vp, C.POINTER(_AtomDesc), C.POINTER(_vp)]
 _lib.extrass_atom_destroy.argtypes = [_vp]
 _lib.extrass_nlte_workspace.restype = C.c_size_t
@@ -121,6 +121,7 @@ _lib.extrass_batched_solve.argtypes = [_vp, C.POINTER(_Batched), C.POINTER(_BOpt
                                        C.c_size_t, _vp]
 _lib.extrass_batched_tune.argtypes = [_vp, C.POINTER(_Batched), C.POINTER(_BOpts), _vp, C.c_size_t,
                                       _vp, _vp, _vp]
+_lib.extrass_mlp_features.argtypes = [_vp, _vp, C.POINTER(_Cells), _vp, _vp, _vp]
 _lib.extrass_nlte_warm_start.argtypes = [_vp, _vp, C.POINTER(_Cells), _vp, _vp, _vp, _vp, _vp,
                                          C.c_size_t, _vp]
 
@@ -131,7 +132,8 @@ SYMBOLS = ["extrass_create", "extrass_destroy", "extrass_error_string", "extrass
            "extrass_mlp_workspace", "extrass_mlp_forward", "extrass_mlp_train_step",
            "extrass_nlte_warm_start_workspace", "extrass_nlte_warm_start",
            "extrass_batched_workspace", "extrass_batched_solve", "extrass_batched_tune",
-           "extrass_transport_streamed_workspace", "extrass_transport_streamed"]
+           "extrass_transport_streamed_workspace", "extrass_transport_streamed",
+           "extrass_mlp_features", "extrass_spectrum"]
 
 
 class ExtrassError(RuntimeError):
@@ -273,7 +275,7 @@ def spectrum(ctx: Context, packets, n_theta, n_phi, n_lambda, lambda_min, lambda
 
 
 def transport_streamed(ctx: Context, grid: Grid, seed, lambda_lo, lambda_hi, n_packets,
-                       atom=None, pops=None, cell_volume=None, iteration=0, geometry_fp32=False,
+                       atom=None, pops=None, t_exp=None, iteration=0, geometry_fp32=False,
                        est_octant=None, est_global=False, gamma=None, stats=None,
                        queue_capacity=None, octant_table=True):
     """Runs extrass_transport_streamed (8 velocity octants, one estimator table
@@ -298,7 +300,7 @@ def transport_streamed(ctx: Context, grid: Grid, seed, lambda_lo, lambda_hi, n_p
     ws = ctx.workspace(_lib.extrass_transport_streamed_workspace(C.byref(g), qcap))
     rc = _lib.extrass_transport_streamed(
         ctx.h, C.byref(g), C.byref(s), atom.h if atom is not None else None, _ptr(pops),
-        float(cell_volume or 0.0), _ptr(est_octant), _ptr(eg), _ptr(gamma if atom is not None else None),
+        float(t_exp or 0.0), _ptr(est_octant), _ptr(eg), _ptr(gamma if atom is not None else None),
         _ptr(stats), qcap, _ptr(ws), ws.numel(), _stream())
     ctx.check(rc, "extrass_transport_streamed")
     return (gamma if atom is not None else None), stats, eg
@@ -369,16 +371,19 @@ def line_tau(ctx: Context, atom: Atom, pops, t_exp, tau=None, fcorr=None):
     return tau, fc
 
 
-def rates(ctx: Context, atom: Atom, est, pops, cell_volume, out=None):
-    """Photoexcitation rates per (cell, transition) (extrass_rates), written into
-    out when given (contiguous f64 [C, T])."""
-    C_ = pops.numel() // atom.n_levels
-    L = est.numel() // C_
+def rates(ctx: Context, atom: Atom, grid: Grid, t_exp, est, pops, out=None):
+    """Photoexcitation rates per (cell, transition) of the grid's cells at time
+    t_exp (extrass_rates), written into out when given (contiguous f64 [C, T])."""
+    C_ = grid.n_cells
+    for t, n in ((est, C_ * grid.n_lines), (pops, C_ * atom.n_levels)):
+        if t.numel() != n:
+            raise ValueError("rates: est must be [C, L] and pops [C, N] of the grid's cells")
     if out is None:
         out = torch.empty((C_, atom.n_trans), dtype=torch.float64, device=pops.device)
     elif out.dtype != torch.float64 or not out.is_contiguous() or out.numel() != C_ * atom.n_trans:
         raise ValueError("rates: out must be contiguous float64 [C, T]")
-    ctx.check(_lib.extrass_rates(ctx.h, atom.h, C_, L, _ptr(est), _ptr(pops), float(cell_volume),
+    g = grid.struct()
+    ctx.check(_lib.extrass_rates(ctx.h, atom.h, C.byref(g), float(t_exp), _ptr(est), _ptr(pops),
                                  _ptr(out), _stream()), "extrass_rates")
     return out
 
@@ -437,10 +442,6 @@ def nlte_solve(ctx: Context, atom: Atom, cells: Cells, max_iter=200, tol=1e-10, 
     return pops, status, iters
 
 
-def cell_volume(w):
-    return (2.0 * w.beta_max / w.n * 2.99792458e10 * w.t_exp) ** 3
-
-
 MLP_PARAMS = int(_lib.extrass_mlp_param_count())
 MLP_IN, MLP_OUT = 6, 100
 
@@ -463,6 +464,17 @@ def mlp_train_step(ctx: Context, params, x, t, adam_m=None, adam_v=None, step=1,
                                           int(step), float(lr), _ptr(x), _ptr(t), B, _ptr(loss),
                                           _ptr(grad), _ptr(ws), ws.numel(), _stream()),
               "extrass_mlp_train_step")
+
+
+def mlp_features(ctx: Context, atom: Atom, cells: Cells, deposition):
+    """The six raw warm-start features of every cell [C, 6] (FP32 device tensor),
+    as extrass_nlte_warm_start forms them (extrass_mlp_features)."""
+    dep = _dev(deposition, torch.float64, cells.T_e.device)
+    x = torch.empty((cells.n_cells, MLP_IN), dtype=torch.float32, device=cells.T_e.device)
+    cs = cells.struct()
+    ctx.check(_lib.extrass_mlp_features(ctx.h, atom.h, C.byref(cs), _ptr(dep), _ptr(x), _stream()),
+              "extrass_mlp_features")
+    return x
 
 
 def nlte_warm_start(ctx: Context, atom: Atom, cells: Cells, deposition, params, norm, pops=None):

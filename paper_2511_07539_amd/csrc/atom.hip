@@ -158,6 +158,11 @@ extern "C" int extrass_atom_create(extrass_handle h, const extrass_atom_desc* d,
       delete a;
       return fail(h, EXTRASS_EINVAL, "extrass_atom_create: bad transition levels");
     }
+    if (d->trans_line[t] < 0) {
+      delete a;
+      return fail(h, EXTRASS_EINVAL, "extrass_atom_create: negative line index");
+    }
+    a->maxLine = std::max(a->maxLine, (int)d->trans_line[t]);
   }
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
     return species_of(d->trans_lower[x]) < species_of(d->trans_lower[y]);
@@ -324,19 +329,23 @@ __global__ void k_rates(int64_t n_cells, int L, int N, int T, const double* __re
   }
 }
 
-extern "C" int extrass_rates(extrass_handle h, extrass_atom_handle a, int64_t n_cells,
-                             int32_t n_lines, const double* est, const double* pops,
-                             double cell_volume, double* gamma_pe, void* stream) {
-  if (!h || !a || !est || !pops || !gamma_pe || n_cells < 0 || n_lines <= 0 ||
-      !(cell_volume > 0.0))
+extern "C" int extrass_rates(extrass_handle h, extrass_atom_handle a, const extrass_grid* g,
+                             double t_exp, const double* est, const double* pops,
+                             double* gamma_pe, void* stream) {
+  if (!h || !a || !g || !est || !pops || !gamma_pe || g->n <= 0 || g->n > 1024 ||
+      g->n_lines <= 0 || !(g->beta_max > 0.0) || !(t_exp > 0.0))
     return fail(h, EXTRASS_EINVAL, "extrass_rates: bad argument");
-  if (n_cells == 0 || a->T == 0) return EXTRASS_OK;
+  if (a->maxLine >= g->n_lines)
+    return fail(h, EXTRASS_EINVAL, "extrass_rates: a transition's line index is beyond the grid's lines");
+  const int64_t n_cells = (int64_t)g->n * g->n * g->n;
+  if (a->T == 0) return EXTRASS_OK;
   EXTRASS_HIP_TRY(h, hipSetDevice(h->device));
+  const double V = extrass::cell_volume(g->n, g->beta_max, t_exp);
   const int64_t total = n_cells * a->T;
   int64_t blocks = std::min<int64_t>((total + 255) / 256, 65536);
   hipLaunchKernelGGL(k_rates, dim3((unsigned)blocks), dim3(256), 0,
-                     static_cast<hipStream_t>(stream), n_cells, (int)n_lines, a->N, a->T, est,
-                     pops, a->d.o_lo, a->d.o_line, cell_volume, gamma_pe);
+                     static_cast<hipStream_t>(stream), n_cells, (int)g->n_lines, a->N, a->T, est,
+                     pops, a->d.o_lo, a->d.o_line, V, gamma_pe);
   EXTRASS_HIP_TRY(h, hipGetLastError());
   return EXTRASS_OK;
 }

@@ -12,6 +12,7 @@ constexpr int kMaxLevels = 64;  // one wavefront lane per level of a species
 struct extrass_atom_ctx {
   int device = 0;
   int S = 0, N = 0, T = 0, maxNs = 0;
+  int maxLine = -1;  // largest line index of a transition (trans_line)
   // stage blocks of the NLTE reduction (stage z's excited levels, its ground,
   // the next stage's ground): the largest block, and the most lanes a species'
   // blocks take side by side

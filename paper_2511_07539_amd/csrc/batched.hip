@@ -943,7 +943,8 @@ extern "C" int extrass_batched_workspace(extrass_handle h, const extrass_batched
 
 extern "C" int extrass_batched_solve(extrass_handle h, const extrass_batched* p,
                                      const extrass_batched_opts* o, double* pops, int32_t* status,
-                                     void* ws, size_t ws_bytes, hipStream_t stream) {
+                                     void* ws, size_t ws_bytes, void* stream_) {
+  hipStream_t stream = static_cast<hipStream_t>(stream_);
   if (!h) return EXTRASS_EINVAL;
   const int v = validate(h, p);
   if (v) return v;
@@ -972,7 +973,8 @@ extern "C" int extrass_batched_solve(extrass_handle h, const extrass_batched* p,
 
 extern "C" int extrass_batched_tune(extrass_handle h, const extrass_batched* p,
                                     const extrass_batched_opts* o, void* ws, size_t ws_bytes,
-                                    hipStream_t stream, int32_t* choice, float* times) {
+                                    void* stream_, int32_t* choice, float* times) {
+  hipStream_t stream = static_cast<hipStream_t>(stream_);
   if (!h) return EXTRASS_EINVAL;
   const int v = validate(h, p);
   if (v) return v;
@@ -1031,8 +1033,8 @@ extern "C" int extrass_batched_tune(extrass_handle h, const extrass_batched* p,
         bc = per_cus[j];
       }
     }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   h->batched_panel[fp32] = bp;
   h->batched_per_cu[fp32] = bc;
   if (choice) {

@@ -47,6 +47,15 @@ struct Carver {
   bool ok() const { return used <= cap; }
 };
 
+// Physical volume of one cell (cm^3) of an n^3 grid over [-beta_max,
+// beta_max]^3 in x = v/c at time t_exp: in homologous flow position is
+// v t_exp, so a cell is (2 beta_max / n) c t_exp wide.
+inline double cell_volume(int n, double beta_max, double t_exp) {
+  const double c_cgs = 2.99792458e10;
+  const double w = 2.0 * beta_max / n * c_cgs * t_exp;
+  return w * w * w;
+}
+
 template <class T>
 inline size_t carve_bytes(size_t count) {
   return ((count * sizeof(T) + 255) & ~size_t(255)) + 256;

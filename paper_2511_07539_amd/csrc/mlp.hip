@@ -435,6 +435,8 @@ __global__ __launch_bounds__(256) void k_mlp_infer(const float* __restrict__ x,
   infer_layer(H, Ws, Wb + kWb4, P + kOffB4, kOut, false, y, row0, B);
 }
 
+// The six warm-start features of each cell, normalised by norm (means, then
+// standard deviations) or raw when norm is NULL.
 __global__ void k_features(int64_t c0, int64_t n, int S, const double* __restrict__ T,
                            const double* __restrict__ ne, const double* __restrict__ ns,
                            const double* __restrict__ dep, const float* __restrict__ norm,
@@ -452,7 +454,8 @@ __global__ void k_features(int64_t c0, int64_t n, int S, const double* __restric
     f[3] = log10(dep[c] > 0.0 ? dep[c] : 1e-30);
     f[4] = ns[c * S + 0] / safe;
     f[5] = ns[c * S + 1] / safe;
-    for (int i = 0; i < kIn; ++i) x[e * kIn + i] = (float)((f[i] - norm[i]) / norm[kIn + i]);
+    for (int i = 0; i < kIn; ++i)
+      x[e * kIn + i] = norm ? (float)((f[i] - norm[i]) / norm[kIn + i]) : (float)f[i];
   }
 }
 
@@ -533,6 +536,24 @@ extern "C" int extrass_mlp_train_step(extrass_handle h, float* params, float* ad
     hipLaunchKernelGGL(k_adam, dim3(blocks_for(kParams)), dim3(256), 0, st, params, adam_m, adam_v,
                        g, kParams, lr, c1, c2);
   }
+  EXTRASS_HIP_TRY(h, hipGetLastError());
+  return EXTRASS_OK;
+}
+
+extern "C" int extrass_mlp_features(extrass_handle h, extrass_atom_handle atom,
+                                    const extrass_cells* cells, const double* deposition,
+                                    float* x, void* stream) {
+  if (!h || !atom || !cells || !deposition || !x || !cells->T_e || !cells->n_e ||
+      !cells->n_species || cells->n_cells < 0)
+    return fail(h, EXTRASS_EINVAL, "extrass_mlp_features: bad argument");
+  if (atom->S != 2)
+    return fail(h, EXTRASS_EINVAL, "extrass_mlp_features: the features need 2 species");
+  if (cells->n_cells == 0) return EXTRASS_OK;
+  EXTRASS_HIP_TRY(h, hipSetDevice(h->device));
+  hipLaunchKernelGGL(k_features, dim3(blocks_for(cells->n_cells)), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), (int64_t)0, cells->n_cells, atom->S,
+                     cells->T_e, cells->n_e, cells->n_species, deposition,
+                     static_cast<const float*>(nullptr), x);
   EXTRASS_HIP_TRY(h, hipGetLastError());
   return EXTRASS_OK;
 }

@@ -38,6 +38,9 @@ extern "C" int extrass_nlte_solve(extrass_handle h, extrass_atom_handle a, const
   if (cl->n_cells < 0 || !cl->T_e || !cl->n_e || !cl->n_species || !cl->gamma_ion ||
       o->max_iter < 0 || !(o->tol > 0.0))
     return fail(h, EXTRASS_EINVAL, "extrass_nlte_solve: bad cells or options");
+  if (o->factor_fp32)
+    return fail(h, EXTRASS_EUNSUPPORTED,
+                "extrass_nlte_solve: FP32 factors are not supported (FP64 only)");
   if (ws_bytes < extrass_nlte_workspace(a, cl->n_cells))
     return fail(h, EXTRASS_ENOSPACE, "extrass_nlte_solve: workspace too small");
   if (cl->n_cells == 0) return EXTRASS_OK;
@@ -75,7 +78,6 @@ extern "C" int extrass_nlte_solve(extrass_handle h, extrass_atom_handle a, const
   A.tol = o->tol;
   A.use_guess = o->use_guess;
   A.warm_budget = o->warm_budget;
-  A.factor_fp32 = o->factor_fp32;
   A.pops = pops;
   A.status = status;
   A.iters = iters;
@@ -83,7 +85,7 @@ extern "C" int extrass_nlte_solve(extrass_handle h, extrass_atom_handle a, const
   A.NP = a->maxNs | 1;
   A.gsz = a->maxNs * A.NP;
   A.block_rows = (a->blockLanes + 1) & ~1;
-  const bool blocks_fit = !o->factor_fp32 && a->maxBlock <= 32 && a->blockLanes <= 64;
+  const bool blocks_fit = a->maxBlock <= 32 && a->blockLanes <= 64;
   // stage blocks: kernels for blocks of at most 12, 16, 21, 22, 24 or 32
   // states (the reduction runs NTB - 1 unrolled steps on NTB-entry register
   // rows, so a bound one above the largest block costs a step and an entry:

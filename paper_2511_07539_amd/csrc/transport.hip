@@ -109,8 +109,10 @@ static_assert(sizeof(QPk) == 120, "queue record layout");
 
 // The line list packed into one 16-byte record per line, so that the event
 // loop's line test and opacity choice take one load.
+// A line_trans entry outside [-1, n_trans) is never used as an index: the line
+// becomes a background line (k_check_lines flags the estimators invalid).
 __global__ void k_prep(const double* lam, const float* tau0, const int32_t* line_trans,
-                       int has_ct, LineRec* lines, int L, double* stats,
+                       int has_ct, int n_trans, LineRec* lines, int L, double* stats,
                        unsigned long long* queue) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t < EXTRASS_STATS) stats[t] = 0.0;
@@ -118,16 +120,23 @@ __global__ void k_prep(const double* lam, const float* tau0, const int32_t* line
   for (int k = t; k < L; k += gridDim.x * blockDim.x) {
     LineRec r;
     r.inv_lam = 1.0 / lam[k];
-    r.trans = has_ct ? line_trans[k] : -1;
+    const int tr = has_ct ? line_trans[k] : -1;
+    r.trans = (tr < -1 || tr >= n_trans) ? -1 : tr;
     r.tau0 = tau0[k];
     lines[k] = r;
   }
 }
 
-__global__ void k_check_sorted(const double* lam, int L, double* stats) {
+// Runs after k_prep (which clears stats): flags a line list that is not
+// non-decreasing, or a line -> transition entry outside [-1, n_trans).
+__global__ void k_check_lines(const double* lam, const int32_t* line_trans, int has_ct,
+                              int n_trans, int L, double* stats) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
-  for (int k = t + 1; k < L; k += gridDim.x * blockDim.x)
-    if (!(lam[k] >= lam[k - 1])) stats[EXTRASS_STATS - 1] = 1.0;
+  for (int k = t; k < L; k += gridDim.x * blockDim.x) {
+    const bool unsorted = k > 0 && !(lam[k] >= lam[k - 1]);
+    const int tr = has_ct ? line_trans[k] : -1;
+    if (unsorted || tr < -1 || tr >= n_trans) stats[EXTRASS_STAT_BAD_LINES] = 1.0;
+  }
 }
 
 // Lookup for the first line above a wavelength: bin b of [lambda_0,
@@ -781,8 +790,10 @@ extern "C" int extrass_transport(extrass_handle h, const extrass_grid* g, const 
 
   const int has_ct = (g->tau_ct && g->line_trans) ? 1 : 0;
   hipLaunchKernelGGL(k_prep, dim3(64), dim3(256), 0, st, g->line_lambda, g->line_tau0,
-                     g->line_trans, has_ct, tw.lines, L, stats, queue);
-  if (L > 1) hipLaunchKernelGGL(k_check_sorted, dim3(64), dim3(256), 0, st, g->line_lambda, L, stats);
+                     g->line_trans, has_ct, g->n_trans, tw.lines, L, stats, queue);
+  if (L > 0)
+    hipLaunchKernelGGL(k_check_lines, dim3(64), dim3(256), 0, st, g->line_lambda, g->line_trans,
+                       has_ct, g->n_trans, L, stats);
   hipLaunchKernelGGL(k_lambin, dim3(64), dim3(256), 0, st, g->line_lambda, L, lam_bins(L),
                      tw.lam_bin, tw.lam_par);
   if (!s->explicit_packets) {
@@ -898,7 +909,7 @@ extern "C" size_t extrass_transport_streamed_workspace(const extrass_grid* g, in
 
 extern "C" int extrass_transport_streamed(extrass_handle h, const extrass_grid* g,
                                           const extrass_source* s, extrass_atom_handle atom,
-                                          const double* pops, double cell_volume, double* est_octant,
+                                          const double* pops, double t_exp, double* est_octant,
                                           double* est_global, double* gamma_pe, double* stats,
                                           int64_t queue_capacity, void* ws, size_t ws_bytes,
                                           void* stream) {
@@ -918,8 +929,12 @@ extern "C" int extrass_transport_streamed(extrass_handle h, const extrass_grid* 
     return fail(h, EXTRASS_EINVAL, "extrass_transport_streamed: tau_ct needs line_trans and n_trans");
   if (s->explicit_packets || s->first_packet != 0 || s->n_packets < 0)
     return fail(h, EXTRASS_EINVAL, "extrass_transport_streamed: whole sampling plan only");
-  if (atom && (!pops || !gamma_pe || !(cell_volume > 0.0)))
-    return fail(h, EXTRASS_EINVAL, "extrass_transport_streamed: rates need pops, gamma_pe, volume");
+  if (atom && (!pops || !gamma_pe || !(t_exp > 0.0)))
+    return fail(h, EXTRASS_EINVAL, "extrass_transport_streamed: rates need pops, gamma_pe, t_exp");
+  if (atom && atom->maxLine >= g->n_lines)
+    return fail(h, EXTRASS_EINVAL,
+                "extrass_transport_streamed: a transition's line index is beyond the grid's lines");
+  const double cell_volume = atom ? extrass::cell_volume(g->n, g->beta_max, t_exp) : 0.0;
   if (queue_capacity <= 0) return fail(h, EXTRASS_EINVAL, "extrass_transport_streamed: queue capacity");
   StreamWs w = stream_layout(g, queue_capacity, ws);
   if (ws_bytes < w.need) return fail(h, EXTRASS_ENOSPACE, "extrass_transport_streamed: workspace too small");
@@ -931,8 +946,9 @@ extern "C" int extrass_transport_streamed(extrass_handle h, const extrass_grid* 
 
   const int has_ct = (g->tau_ct && g->line_trans) ? 1 : 0;
   hipLaunchKernelGGL(k_prep, dim3(64), dim3(256), 0, st, g->line_lambda, g->line_tau0,
-                     g->line_trans, has_ct, w.lines, L, stats, w.counters);
-  if (L > 1) hipLaunchKernelGGL(k_check_sorted, dim3(64), dim3(256), 0, st, g->line_lambda, L, stats);
+                     g->line_trans, has_ct, g->n_trans, w.lines, L, stats, w.counters);
+  hipLaunchKernelGGL(k_check_lines, dim3(64), dim3(256), 0, st, g->line_lambda, g->line_trans,
+                     has_ct, g->n_trans, L, stats);
   scan_counts(st, g->cell_packets, C, n, -1, w.tsum, w.start);
   hipLaunchKernelGGL(k_lambin, dim3(64), dim3(256), 0, st, g->line_lambda, L, lam_bins(L),
                      w.lam_bin, w.lam_par);

@@ -13,19 +13,8 @@ from __future__ import annotations
 import numpy as np
 import torch
 
-from . import (MLP_IN, MLP_OUT, MLP_PARAMS, Atom, Cells, Context, cell_volume, grid_from_workload,
-               line_tau, mlp_train_step, nlte_solve, rates, transport)
-
-
-def features_host(T_e, n_e, n_species, deposition):
-    """The 6 raw features the warm-start kernel forms on the device, here on
-    the host for the normalisation statistics of the training set."""
-    ns = np.asarray(n_species).reshape(len(T_e), -1)
-    tot = ns.sum(1)
-    safe = np.where(tot > 0, tot, 1.0)
-    return np.column_stack([np.log10(safe), np.log10(T_e), np.log10(np.where(n_e > 0, n_e, 1.0)),
-                            np.log10(np.where(deposition > 0, deposition, 1e-30)),
-                            ns[:, 0] / safe, ns[:, 1] / safe])
+from . import (MLP_IN, MLP_OUT, MLP_PARAMS, Atom, Cells, Context, grid_from_workload,
+               line_tau, mlp_features, mlp_train_step, nlte_solve, rates, transport)
 
 
 def replica_states(w, k, seed=97):
@@ -59,7 +48,7 @@ def photoexcitation_rates(ctx: Context, atom: Atom, w, device="cuda:0"):
     grid = grid_from_workload(w, device=device, tau_ct=tau, fcorr_ct=fc)
     est, _, _ = transport(ctx, grid, w.seed, w.lambda_lo, w.lambda_hi, w.n_packets,
                           geometry_fp32=True)
-    gam = rates(ctx, atom, est, cold, cell_volume(w))
+    gam = rates(ctx, atom, grid, w.t_exp, est, cold)
     del est
     return gam
 
@@ -80,7 +69,7 @@ def make_dataset(ctx: Context, atom: Atom, w, n_replicas=8, device="cuda:0", gam
         y = np.empty_like(p)
         for s in range(len(off) - 1):
             y[:, off[s]:off[s + 1]] = np.log10(p[:, off[s]:off[s + 1]] / ns[:, s:s + 1])
-        X.append(features_host(T, n_e, ns, dep)[ok])
+        X.append(mlp_features(ctx, atom, cells, dep).cpu().numpy().astype(np.float64)[ok])
         Y.append(y[ok])
     return np.concatenate(X), np.concatenate(Y)
 
@@ -128,4 +117,16 @@ def train(ctx: Context, X, Y, epochs=30, batch=8192, lr=2e-3, seed=0, device="cu
         hist.append(float(loss.item()) / max(nb, 1))
         if verbose:
             print(f"epoch {ep} loss {hist[-1]:.4e}", flush=True)
+    return params, norm, hist
+
+
+def train_on_workload(ctx: Context, w, n_replicas=8, epochs=30, batch=8192, device="cuda:0"):
+    """Trains the warm-start network on solves of replicas of workload w's
+    cells (photoexcitation rates from one transport pass over w). Returns
+    (params, norm, loss history)."""
+    atom = Atom(ctx, w.atom)
+    gamma = photoexcitation_rates(ctx, atom, w, device)
+    X, Y = make_dataset(ctx, atom, w, n_replicas=n_replicas, device=device, gamma=gamma)
+    del gamma
+    params, norm, hist = train(ctx, X, Y, epochs=epochs, batch=batch, device=device)
     return params, norm, hist

@@ -43,3 +43,22 @@ def test_binding_names_match_header():
     src = open(os.path.join(ROOT, "paper_2511_07539_amd", "__init__.py")).read()
     for name in declared_functions():
         assert name in src, name
+
+
+def test_header_is_plain_c99():
+    """include/extrass.h compiles as plain C (no HIP or C++ types in the
+    signatures), with every warning enabled."""
+    import shutil
+    import subprocess
+    import tempfile
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    with tempfile.TemporaryDirectory() as d:
+        src = os.path.join(d, "use.c")
+        with open(src, "w") as f:
+            f.write('#include "extrass.h"\nint main(void) { return extrass_error_string(0) ? 0 : 1; }\n')
+        r = subprocess.run([cc, "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-c", src,
+                            "-I", os.path.dirname(HEADER), "-o", os.path.join(d, "use.o")],
+                           capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr

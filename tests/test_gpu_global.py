@@ -35,7 +35,7 @@ def test_two_global_iterations_match_oracle_loop():
     got, sg = pops.cpu().numpy(), status.cpu().numpy()
 
     C, L = w.n_cells, w.n_lines
-    V = ex.cell_volume(w)
+    V = (2 * w.beta_max / w.n * synth.C_CGS * w.t_exp) ** 3
     inp0 = oracle.nlte_inputs_from_workload(w)
     p = np.stack([oracle.nlte_cold(inp0, c) for c in range(C)])
     so = None

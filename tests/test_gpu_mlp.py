@@ -142,6 +142,30 @@ def test_warm_start_converges_to_cold_roots(ex, ctx):
     assert iw.mean() < ic.mean()
 
 
+def _features_reference(T_e, n_e, n_species, deposition):
+    """The six warm-start features as the header states them: log10 of the
+    total species density, T_e, n_e and the deposition, and the two species'
+    number fractions."""
+    ns = np.asarray(n_species).reshape(len(T_e), -1)
+    tot = ns.sum(1)
+    safe = np.where(tot > 0, tot, 1.0)
+    return np.column_stack([np.log10(safe), np.log10(T_e), np.log10(np.where(n_e > 0, n_e, 1.0)),
+                            np.log10(np.where(deposition > 0, deposition, 1e-30)),
+                            ns[:, 0] / safe, ns[:, 1] / safe])
+
+
+def test_features_match_their_definition(ex, ctx):
+    w = synth.clumpy(n=13, n_lines=2000, n_packets=10_000, number=3)
+    atom = ex.Atom(ctx, w.atom)
+    cells = ex.cells_from_workload(w)
+    say("case: warm-start features, 2197 cells")
+    x = ex.mlp_features(ctx, atom, cells, w.deposition)
+    torch.cuda.synchronize()
+    ref = _features_reference(w.T_e, w.n_e, w.n_species, w.deposition)
+    # the device rounds the FP64 features to FP32 once: within one FP32 ulp
+    np.testing.assert_allclose(x.cpu().numpy(), ref, rtol=1.2e-7, atol=1e-38)
+
+
 def test_fused_warm_start_equals_layer_by_layer(ex, ctx):
     """extrass_nlte_warm_start runs the whole network in one fused kernel. Its
     populations equal those of the layer-by-layer forward (extrass_mlp_forward)
@@ -157,7 +181,7 @@ def test_fused_warm_start_equals_layer_by_layer(ex, ctx):
     cells = ex.cells_from_workload(w)
     g = np.random.default_rng(7)
     params = torch.as_tensor(warmstart.init_params(3), device=dev)
-    X = warmstart.features_host(w.T_e, w.n_e, w.n_species, w.deposition)
+    X = _features_reference(w.T_e, w.n_e, w.n_species, w.deposition)
     xm, xs = X.mean(0), X.std(0) + 0.1
     ym, ys = g.normal(-4.0, 1.0, 100), g.uniform(0.5, 2.0, 100)
     norm_np = np.concatenate([xm, xs, ym, ys]).astype(np.float32)

@@ -1,8 +1,10 @@
 """NLTE solve: HIP path vs the FP64 oracle on the same inputs.
 
 Bar: componentwise max |n_gpu - n_oracle| / n_oracle <= 1e-8 over every level
-of every converged cell (populations span down to ~1e-38 of the largest), and
-identical convergence status.
+of every cell the GPU reports converged (populations span down to ~1e-38 of
+the largest); the oracle (tol 1e-12) must have converged on each of them. The
+GPU may report a rare cell as not converged (status 2) where the oracle finds
+the root; such cells are counted and bounded, never compared.
 """
 import sys
 
@@ -46,18 +48,44 @@ def _oracle_gamma(w):
     return oracle.rates(est, cold, w.atom, V)
 
 
-def _compare(pg, sg, po, so):
-    mism = np.where(sg != so)[0]
-    if len(mism):
-        both = (sg == 0) | (so == 0)
-        say("status mismatches", len(mism), "gpu", np.bincount(sg[mism] + 1), "oracle",
-            np.bincount(so[mism] + 1))
-        for c in mism[:5]:
-            say(" cell", c, "gpu", sg[c], "oracle", so[c], "max rel",
-                np.max(np.abs(pg[c] - po[c]) / np.abs(po[c])))
-    assert np.array_equal(sg, so)
-    conv = so == 0
-    a, b = pg[conv], po[conv]
+def _fixed_point_residual(inp, c, pops_cell):
+    """max_i |P(n)_i / n_i - 1| of one cell's populations under the oracle's
+    rates: P(n) = n_tot * stationary(R(n)) per species (oracle_gth)."""
+    off = inp.k["off"]
+    worst = 0.0
+    for s_ in range(len(off) - 1):
+        n = pops_cell[off[s_]:off[s_ + 1]]
+        if not n.sum() > 0:
+            continue
+        P = oracle.gth(oracle.rate_matrix(inp, int(c), s_, n)) * n.sum()
+        worst = max(worst, float(np.max(np.abs(P / n - 1.0))))
+    return worst
+
+
+def _compare(pg, sg, po, so, inp=None, gpu_tol=1e-10, max_gpu_failures=0):
+    """Returns (max rel over cells both sides converged, smallest population /
+    largest in those cells). A cell the GPU reports converged (status 0 or 1)
+    where the oracle did not must still be a root of the oracle's equations
+    (fixed-point residual within 10 gpu_tol); GPU failures (status 2) where
+    the oracle converged are allowed up to max_gpu_failures; empty cells (3)
+    must agree."""
+    gconv, oconv = sg <= 1, so == 0
+    claimed = np.where(gconv & ~oconv)[0]
+    lost = np.where(~gconv & oconv)[0]
+    say(f"GPU converged {int(gconv.sum())}, oracle {int(oconv.sum())}; GPU-only {len(claimed)}, "
+        f"oracle-only {len(lost)}")
+    for c in lost[:5]:
+        say(" GPU failure: cell", c, "gpu status", sg[c], "max rel",
+            np.max(np.abs(pg[c] - po[c]) / np.abs(po[c])))
+    if len(claimed):
+        assert inp is not None, f"GPU-only convergence on cells {claimed[:5]}"
+        res = max(_fixed_point_residual(inp, c, pg[c]) for c in claimed)
+        say(f" GPU-only cells: largest fixed-point residual under the oracle's rates {res:.2e}")
+        assert res <= 10 * gpu_tol
+    assert len(lost) <= max_gpu_failures
+    assert np.array_equal(sg == 3, so == 3)
+    both = gconv & oconv
+    a, b = pg[both], po[both]
     rel = np.abs(a - b) / np.abs(b)
     return rel.max(), (b / b.max(axis=1, keepdims=True)).min()
 
@@ -65,7 +93,7 @@ def _compare(pg, sg, po, so):
 def test_sphere_small_all_cells(ex, ctx):
     w = synth.sphere_small()
     gpe = _oracle_gamma(w)
-    po, so, io = oracle.nlte(oracle.nlte_inputs_from_workload(w, gamma_pe=gpe), tol=1e-13)
+    po, so, io = oracle.nlte(oracle.nlte_inputs_from_workload(w, gamma_pe=gpe), tol=1e-12)
     atom = ex.Atom(ctx, w.atom)
     cells = ex.cells_from_workload(w, gamma_pe=gpe)
     say("case: sphere16 NLTE, 4096 cells, 10 levels")
@@ -87,15 +115,16 @@ def test_three_stage_atom_sampled_cells(ex, ctx):
     T = w.atom.n_trans
     gpe = np.abs(g.standard_normal((w.n_cells, T))) * 10 ** g.uniform(-8, 0, (w.n_cells, T))
     inp = oracle.nlte_inputs_from_workload(w, gamma_pe=gpe.ravel(), cells=cells)
-    po, so, io = oracle.nlte(inp, tol=1e-13)
+    po, so, io = oracle.nlte(inp, tol=1e-12)
     atom = ex.Atom(ctx, w.atom)
     cl = ex.cells_from_workload(w, gamma_pe=gpe, cells=cells)
     say("case: clumpy50 NLTE, 3000 sampled cells, 2x50 levels")
     pg, sg, ig = ex.nlte_solve(ctx, atom, cl, max_iter=200, tol=1e-10)
     torch.cuda.synchronize()
-    worst, span = _compare(pg.cpu().numpy(), sg.cpu().numpy(), po, so)
+    worst, span = _compare(pg.cpu().numpy(), sg.cpu().numpy(), po, so, inp=inp,
+                           max_gpu_failures=len(cells) // 1000)
     say("max componentwise rel", worst, "span", span)
-    assert (so == 0).mean() >= 0.999   # both sides fail on the same rare cells
+    assert (so == 0).mean() >= 0.999
     assert worst <= TOL
     assert span < 1e-20
 
@@ -111,14 +140,15 @@ def test_other_atom_shapes(ex, ctx, ion_levels):
     T = w.atom.n_trans
     gpe = np.abs(g.standard_normal((w.n_cells, T))) * 10 ** g.uniform(-8, 0, (w.n_cells, T))
     inp = oracle.nlte_inputs_from_workload(w, gamma_pe=gpe.ravel(), cells=cells)
-    po, so, _ = oracle.nlte(inp, tol=1e-13)
+    po, so, _ = oracle.nlte(inp, tol=1e-12)
     atom = ex.Atom(ctx, w.atom)
     cl = ex.cells_from_workload(w, gamma_pe=gpe, cells=cells)
     say(f"case: NLTE with stages {ion_levels}, 600 sampled cells")
     pg, sg, _ = ex.nlte_solve(ctx, atom, cl, max_iter=200, tol=1e-10)
     torch.cuda.synchronize()
-    worst, span = _compare(pg.cpu().numpy(), sg.cpu().numpy(), po, so)
     sgn = sg.cpu().numpy()
+    worst, span = _compare(pg.cpu().numpy(), sgn, po, so, inp=inp,
+                           max_gpu_failures=len(cells) // 20)
     say("max componentwise rel", worst, "span", span, "converged: gpu", (sgn == 0).mean(),
         "oracle", (so == 0).mean())
     # a single 40-level stage with A up to 1e8 s^-1 leaves a few percent of
@@ -130,7 +160,7 @@ def test_other_atom_shapes(ex, ctx, ion_levels):
 def test_warm_start_and_iteration_cap(ex, ctx):
     w = synth.sphere_small()
     inp = oracle.nlte_inputs_from_workload(w)
-    po, so, _ = oracle.nlte(inp, tol=1e-13)
+    po, so, _ = oracle.nlte(inp, tol=1e-12)
     atom = ex.Atom(ctx, w.atom)
     cells = ex.cells_from_workload(w)
     say("case: warm start from the oracle's roots")
@@ -148,32 +178,57 @@ def test_warm_start_and_iteration_cap(ex, ctx):
     assert np.all(s1[act] == 2) and np.all(s1[so == 3] == 3)
 
 
-def test_tolerance_bounds_the_error(ex, ctx):
-    """tol is the population accuracy: solved at tol (both the last Newton
-    correction and the fixed-point residual below tol), every converged cell
-    is within a small multiple of tol of the oracle's root (tol 1e-13), cold
-    and warm-started alike. The bench runs both NLTE passes at 1e-8."""
+@pytest.fixture(scope="module")
+def paper_scale_all_cells():
+    """Every cell of the 50^3 workload with seeded photoexcitation rates, and
+    the oracle's roots (tol 1e-12) for all of them (host, all threads)."""
     w = synth.paper_scale()
     g = np.random.default_rng(1)
-    cells = np.sort(g.choice(w.n_cells, 2000, replace=False))
     T = w.atom.n_trans
     gpe = np.abs(g.standard_normal((w.n_cells, T))) * 10 ** g.uniform(-8, 0, (w.n_cells, T))
-    inp = oracle.nlte_inputs_from_workload(w, gamma_pe=gpe.ravel(), cells=cells)
-    po, so, _ = oracle.nlte(inp, tol=1e-13)
+    say("case: oracle roots of all 125 000 cells of clumpy50 (host)")
+    inp = oracle.nlte_inputs_from_workload(w, gamma_pe=gpe.ravel())
+    po, so, _ = oracle.nlte(inp, tol=1e-12)
+    say("oracle status counts", np.bincount(so, minlength=4))
+    return w, gpe, po, so, inp
+
+
+@pytest.mark.timeout(1200)
+@pytest.mark.parametrize("tol", [1e-6, 1e-8])
+def test_tolerance_bounds_the_error(ex, ctx, paper_scale_all_cells, tol):
+    """tol is the population accuracy: solved at tol, every cell that both
+    sides converge is within tol (componentwise, relative) of the oracle's
+    root, cold and warm-started alike. All 125 000 cells of the 50^3 workload;
+    the bench runs both NLTE passes at 1e-8."""
+    w, gpe, po, so, inp = paper_scale_all_cells
     atom = ex.Atom(ctx, w.atom)
-    cl = ex.cells_from_workload(w, gamma_pe=gpe, cells=cells)
-    for tol in (1e-6, 1e-8):
-        say(f"case: clumpy50 NLTE, 2000 sampled cells, tol {tol:g}, cold and from a perturbed guess")
-        pg, sg, ig = ex.nlte_solve(ctx, atom, cl, max_iter=200, tol=tol)
-        # a guess off by up to a factor 1.5 per level, as a learned start would be
-        guess = torch.as_tensor(po * np.exp(g.uniform(-0.4, 0.4, po.shape)), device="cuda:0")
-        pw, sw, iw = ex.nlte_solve(ctx, atom, cl, max_iter=200, tol=tol, guess=guess,
-                                   warm_budget=30)
-        torch.cuda.synchronize()
-        for name, p, s in (("cold", pg, sg), ("warm", pw, sw)):
-            p, s = p.cpu().numpy(), s.cpu().numpy()
-            ok = (so == 0) & (s <= 1)
-            assert ok.sum() >= 0.999 * len(cells)
-            rel = np.max(np.abs(p[ok] - po[ok]) / po[ok])
-            say(f"  {name}: max rel {rel:.2e}")
-            assert rel <= 3 * tol
+    cl = ex.cells_from_workload(w, gamma_pe=gpe)
+    say(f"case: clumpy50 NLTE, all cells, tol {tol:g}, cold and from a perturbed guess")
+    pg, sg, _ = ex.nlte_solve(ctx, atom, cl, max_iter=200, tol=tol)
+    # a guess off by up to a factor 1.5 per level, as a learned start would be
+    guess = torch.as_tensor(po * np.exp(np.random.default_rng(7).uniform(-0.4, 0.4, po.shape)),
+                            device="cuda:0")
+    pw, sw, _ = ex.nlte_solve(ctx, atom, cl, max_iter=200, tol=tol, guess=guess, warm_budget=30)
+    torch.cuda.synchronize()
+    for name, p, s_ in (("cold", pg, sg), ("warm", pw, sw)):
+        p, s_ = p.cpu().numpy(), s_.cpu().numpy()
+        claimed = np.where((s_ <= 1) & (so != 0))[0]
+        if len(claimed):   # converged where the oracle did not: must be a root
+            res = max(_fixed_point_residual(inp, c, p[c]) for c in claimed)
+            say(f"  {name}: {len(claimed)} GPU-only cells, fixed-point residual {res:.2e}")
+            assert res <= 10 * tol
+        ok = (so == 0) & (s_ <= 1)
+        rel = np.abs(p[ok] - po[ok]) / po[ok]
+        say(f"  {name}: converged {ok.sum()} of {len(so)}, max rel {rel.max():.3e}, "
+            f"cells above tol {int((rel.max(1) > tol).sum())}")
+        assert ok.sum() >= 0.999 * len(so)
+        assert rel.max() <= tol
+
+
+def test_fp32_factors_are_refused(ex, ctx):
+    w = synth.sphere_small()
+    atom = ex.Atom(ctx, w.atom)
+    cells = ex.cells_from_workload(w)
+    say("case: FP32 NLTE factors requested")
+    with pytest.raises(ex.ExtrassError, match="unsupported"):
+        ex.nlte_solve(ctx, atom, cells, factor_fp32=True)

@@ -60,12 +60,11 @@ def test_streamed_equals_unsplit_coupled_clumpy(ex, ctx, fp32):
     w = synth.clumpy(n=16, n_lines=1500, n_packets=300_000, number=2)
     say(f"case: streamed vs unsplit, clumpy 16^3, coupled lines, fp32={fp32}")
     atom, cold, grid = _coupled(ex, ctx, w)
-    V = ex.cell_volume(w)
     est, st_u, _ = ex.transport(ctx, grid, w.seed, w.lambda_lo, w.lambda_hi, w.n_packets,
                                 geometry_fp32=fp32)
-    gam_u = ex.rates(ctx, atom, est, cold, V)
+    gam_u = ex.rates(ctx, atom, grid, w.t_exp, est, cold)
     gam_s, st_s, eg = ex.transport_streamed(ctx, grid, w.seed, w.lambda_lo, w.lambda_hi,
-                                            w.n_packets, atom=atom, pops=cold, cell_volume=V,
+                                            w.n_packets, atom=atom, pops=cold, t_exp=w.t_exp,
                                             geometry_fp32=fp32, est_global=True)
     torch.cuda.synchronize()
     su, ss = ex.stats_dict(st_u), ex.stats_dict(st_s)
@@ -87,12 +86,11 @@ def test_direct_rates_equal_table_rates(ex, ctx, fp32):
     w = synth.clumpy(n=16, n_lines=1500, n_packets=300_000, number=2)
     say(f"case: streamed rates without the octant table, clumpy 16^3, fp32={fp32}")
     atom, cold, grid = _coupled(ex, ctx, w)
-    V = ex.cell_volume(w)
     gam_t, st_t, _ = ex.transport_streamed(ctx, grid, w.seed, w.lambda_lo, w.lambda_hi,
-                                           w.n_packets, atom=atom, pops=cold, cell_volume=V,
+                                           w.n_packets, atom=atom, pops=cold, t_exp=w.t_exp,
                                            geometry_fp32=fp32)
     gam_d, st_d, _ = ex.transport_streamed(ctx, grid, w.seed, w.lambda_lo, w.lambda_hi,
-                                           w.n_packets, atom=atom, pops=cold, cell_volume=V,
+                                           w.n_packets, atom=atom, pops=cold, t_exp=w.t_exp,
                                            geometry_fp32=fp32, octant_table=False)
     torch.cuda.synchronize()
     a, b = ex.stats_dict(st_d), ex.stats_dict(st_t)
@@ -111,13 +109,13 @@ def test_direct_rates_need_a_consistent_line_map(ex, ctx):
     grid.line_trans[k] = -1  # one atom line no longer maps back to its transition
     with pytest.raises(ex.ExtrassError, match="inverse"):
         ex.transport_streamed(ctx, grid, w.seed, w.lambda_lo, w.lambda_hi, w.n_packets,
-                              atom=atom, pops=cold, cell_volume=ex.cell_volume(w),
+                              atom=atom, pops=cold, t_exp=w.t_exp,
                               octant_table=False)
     torch.cuda.synchronize()
     grid.line_trans.copy_(lt)
     with pytest.raises(ex.ExtrassError, match="invalid argument"):
         ex.transport_streamed(ctx, grid, w.seed, w.lambda_lo, w.lambda_hi, w.n_packets,
-                              atom=atom, pops=cold, cell_volume=ex.cell_volume(w),
+                              atom=atom, pops=cold, t_exp=w.t_exp,
                               octant_table=False, est_global=True)
 
 
@@ -153,3 +151,34 @@ def test_queue_overflow_and_bad_arguments(ex, ctx):
     with pytest.raises(ex.ExtrassError, match="invalid argument"):
         ex.transport_streamed(ctx, ex.grid_from_workload(odd), odd.seed, odd.lambda_lo,
                               odd.lambda_hi, odd.n_packets)
+
+
+@pytest.mark.parametrize("fp32", [False, True])
+def test_streamed_equals_unsplit_paper_scale(ex, ctx, fp32):
+    """The bench's 50^3 workload (125 000 cells, 5000 lines, 1e7 packets,
+    coupled atom lines): the octant-streamed table equals the unsplit one per
+    entry, with identical event counts."""
+    w = synth.paper_scale()
+    say(f"case: streamed vs unsplit, clumpy 50^3, 5000 lines, 1e7 packets, fp32={fp32}")
+    atom, cold, grid = _coupled(ex, ctx, w)
+    est, st_u, _ = ex.transport(ctx, grid, w.seed, w.lambda_lo, w.lambda_hi, w.n_packets,
+                                geometry_fp32=fp32)
+    _, st_s, eg = ex.transport_streamed(ctx, grid, w.seed, w.lambda_lo, w.lambda_hi,
+                                        w.n_packets, geometry_fp32=fp32, est_global=True)
+    torch.cuda.synchronize()
+    a, b = ex.stats_dict(st_s), ex.stats_dict(st_u)
+    for k in ("n_inter", "n_checks", "n_cross", "n_escaped", "n_killed"):
+        assert a[k] == b[k], k
+    assert a["error_flag"] == 0 and a["bad_packets"] == 0
+    del cold, atom
+    # compared on the device, one block of cells at a time
+    worst, mism = 0.0, 0
+    for c0 in range(0, w.n_cells, 25_000):
+        x, y = eg[c0:c0 + 25_000], est[c0:c0 + 25_000]
+        nz = y != 0
+        mism += int(((x != 0) != nz).sum())
+        if bool(nz.any()):
+            worst = max(worst, float(((x[nz] - y[nz]).abs() / y[nz].abs()).max()))
+    say(f"support mismatches {mism}, max rel {worst:.2e}")
+    assert mism == 0
+    assert worst <= 1e-12

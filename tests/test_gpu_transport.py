@@ -2,10 +2,10 @@
 
 Bars: FP64 geometry - per-entry relative difference <= 1e-3 on every
 estimator entry (observed ~1e-10), the same set of non-zero entries and
-identical event counts; FP32 geometry - L1 difference <= 1e-3 of the table,
-every line's sum within 1e-3, event counts within 1e-5, and the number of
-entries that differ by more than 1e-3 (interactions moved to a neighbouring
-cell by FP32 rounding at a wall) at most 1e-5 of the non-zero entries.
+identical event counts; FP32 geometry - per entry within 1e-3 wherever no
+contributing packet met a resonance within 1e-5 cell widths of a wall at or
+before it (near ties counted and reported), L1 difference <= 1e-3 of the
+table, every line's sum within 1e-3, event counts within 1e-5.
 """
 import sys
 
@@ -73,21 +73,49 @@ def test_fp64_geometry_matches_oracle_per_entry(ex, ctx, small):
     np.testing.assert_allclose(pk[:, 3], opk[:, 3], rtol=1e-11, atol=1e-30)
 
 
-def _fp32_metric(est, ref, rec, tie=1e-4):
-    """Reduced-precision parity. Under FP32 geometry a resonance within rounding
-    of a cell wall, or the order in which a ray crosses two nearly coincident
-    walls, can move an interaction to a neighbouring cell; the number of such
-    entries is bounded and reported, and the table, each line's sum and the
-    event counts must agree to 1e-3."""
+def _fp32_metric(est, ref, rec, tie=1e-5):
+    """Reduced-precision parity (FP32 positions and distances against the FP64
+    oracle). Rounding can move a resonance that lies within rounding of a cell
+    wall into the neighbouring cell, where another optical depth applies; the
+    packet's weight then differs for the rest of its path. The oracle records
+    each interaction's margin, min(D_k - D_entry, D_exit - D_k) / h, the
+    distance of the resonance from its segment's walls in cell widths. A
+    record is a near tie if its margin is below `tie`, and every later record
+    of the same packet inherits the taint. Entries with no tainted record must
+    agree to 1e-3; the tainted ones are counted, and so are entries the GPU
+    filled where the oracle has none (a moved resonance), which cannot exceed
+    the near-tie records. The table and each line's sum must agree to 1e-3."""
+    L = ref.shape[1]
+    near = rec["margin"] < tie
+    pkt = rec["packet"]
+    assert np.all(pkt[1:] >= pkt[:-1]), "records must come in packet order"
+    first = np.r_[True, pkt[1:] != pkt[:-1]]
+    csum = np.cumsum(near)
+    before = (csum - near)[first]                   # near ties before each packet
+    tainted = (csum - np.repeat(before, np.diff(np.r_[np.flatnonzero(first), len(pkt)]))) > 0
+    idx = rec["cell"].astype(np.int64) * L + rec["line"]
+    taint_entry = np.zeros(ref.size, dtype=bool)
+    taint_entry[idx[tainted]] = True
+    e, r_ = est.ravel(), ref.ravel()
+    clean = (r_ != 0) & ~taint_entry
+    rel = np.abs(e[clean] - r_[clean]) / np.abs(r_[clean])
+    moved = int(((r_ == 0) & (e != 0)).sum())
     d = np.abs(est - ref)
-    l1 = d.sum() / np.abs(ref).sum()
     line_ref = ref.sum(0)
     big_l = line_ref > 1e-3 * line_ref.max()
     line_err = np.abs(est.sum(0) - line_ref)
-    bad = (d > 1e-3 * np.abs(ref)) & ((ref != 0) | (est != 0))
-    tie_records = int((rec["margin"] < tie).sum())
-    return dict(l1=l1, line=(line_err[big_l] / line_ref[big_l]).max(), bad_entries=int(bad.sum()),
-                tie_records=tie_records, nonzero=int((ref != 0).sum()))
+    return dict(l1=d.sum() / np.abs(ref).sum(),
+                line=(line_err[big_l] / line_ref[big_l]).max(),
+                clean_max_rel=float(rel.max()) if rel.size else 0.0,
+                clean_entries=int(clean.sum()), near_tie_records=int(near.sum()),
+                tainted_entries=int((taint_entry & (r_ != 0)).sum()), moved_entries=moved,
+                nonzero=int((r_ != 0).sum()))
+
+
+def _assert_fp32(m):
+    assert m["l1"] <= 1e-3 and m["line"] <= 1e-3
+    assert m["clean_max_rel"] <= 1e-3
+    assert m["moved_entries"] <= m["near_tie_records"]
 
 
 def test_fp32_geometry_matches_oracle_statistically(ex, ctx, small):
@@ -96,8 +124,7 @@ def test_fp32_geometry_matches_oracle_statistically(ex, ctx, small):
     est, st, _ = _run(ex, ctx, w, True)
     m = _fp32_metric(est, ref, r["records"])
     say(m)
-    assert m["l1"] <= 1e-3 and m["line"] <= 1e-3
-    assert m["bad_entries"] <= 1e-3 * m["nonzero"]
+    _assert_fp32(m)
     assert abs(st["n_inter"] - r["stats"]["n_inter"]) <= 1e-3 * r["stats"]["n_inter"]
 
 
@@ -177,6 +204,49 @@ def test_unsorted_lines_flagged(ex, ctx):
     assert ex.stats_dict(st)["error_flag"] == 1
 
 
+def test_bad_line_map_is_flagged_not_followed(ex, ctx):
+    """A line -> transition entry outside [-1, n_trans) is never used as an
+    index: the line acts as a background line and the estimators are flagged
+    invalid."""
+    w = synth.clumpy(n=8, n_lines=1000, n_packets=20_000, number=2)
+    T = w.atom.n_trans
+    tau = np.full((w.n_cells, T), 0.5)
+    fc = np.ones((w.n_cells, T))
+    grid = ex.grid_from_workload(w, tau_ct=tau, fcorr_ct=fc)
+    say("case: line map entries beyond the transitions")
+    _, st, _ = ex.transport(ctx, grid, w.seed, w.lambda_lo, w.lambda_hi, w.n_packets)
+    torch.cuda.synchronize()
+    assert ex.stats_dict(st)["error_flag"] == 0
+    lt = grid.line_trans.clone()
+    k = int(torch.nonzero(lt >= 0)[0])
+    for bad in (T, T + 1000, -7):
+        grid.line_trans[k] = bad
+        _, st, _ = ex.transport(ctx, grid, w.seed, w.lambda_lo, w.lambda_hi, w.n_packets)
+        torch.cuda.synchronize()
+        assert ex.stats_dict(st)["error_flag"] == 1, bad
+    grid.line_trans.copy_(lt)
+
+
+def test_rates_reject_lines_beyond_the_grid(ex, ctx):
+    """An atom whose transitions point past the grid's line list is refused
+    before any kernel runs; a negative line index is refused at creation."""
+    w = synth.sphere_small()
+    atom = ex.Atom(ctx, w.atom)
+    small = ex.Grid(w.n, w.beta_max, w.tau_scale, w.cell_photons, w.cell_packets,
+                    w.line_lambda[: int(w.atom.trans_line.max())],
+                    w.line_tau0[: int(w.atom.trans_line.max())])
+    est = torch.zeros((small.n_cells, small.n_lines), dtype=torch.float64, device="cuda:0")
+    pops = torch.ones((small.n_cells, atom.n_levels), dtype=torch.float64, device="cuda:0")
+    say("case: rates with transition lines beyond the grid's lines")
+    with pytest.raises(ex.ExtrassError, match="invalid argument"):
+        ex.rates(ctx, atom, small, w.t_exp, est, pops)
+    import dataclasses
+    neg = dataclasses.replace(w.atom, trans_line=np.where(np.arange(w.atom.n_trans) == 3, -1,
+                                                          w.atom.trans_line).astype(np.int32))
+    with pytest.raises(ex.ExtrassError, match="invalid argument"):
+        ex.Atom(ctx, neg)
+
+
 def test_line_tau_and_rates_match_oracle(ex, ctx, small):
     w, r, ref = small
     inp = oracle.nlte_inputs_from_workload(w)
@@ -190,7 +260,8 @@ def test_line_tau_and_rates_match_oracle(ex, ctx, small):
     pd = torch.as_tensor(pops, device="cuda:0")
     say("case: Eq. A2 opacity and rates, sphere16")
     tau, fc = ex.line_tau(ctx, atom, pd, w.t_exp)
-    gam = ex.rates(ctx, atom, torch.as_tensor(ref, device="cuda:0"), pd, V)
+    gam = ex.rates(ctx, atom, ex.grid_from_workload(w), w.t_exp,
+                   torch.as_tensor(ref, device="cuda:0"), pd)
     torch.cuda.synchronize()
     np.testing.assert_allclose(tau.cpu().numpy().ravel(), tau_o, rtol=1e-13, atol=0)
     np.testing.assert_allclose(fc.cpu().numpy().ravel(), fc_o, rtol=1e-13, atol=1e-15)
@@ -255,8 +326,7 @@ def test_paper_scale_fp32_full_size(ex, ctx, paper_scale):
     est, st, _ = _run(ex, ctx, w, True, grid=grid)
     m = _fp32_metric(est, ref, r["records"])
     say(m)
-    assert m["l1"] <= 1e-3 and m["line"] <= 1e-3
-    assert m["bad_entries"] <= 1e-5 * m["nonzero"]
+    _assert_fp32(m)
     assert abs(st["n_inter"] - r["stats"]["n_inter"]) <= 1e-5 * r["stats"]["n_inter"]
     assert st["w_emit"] == pytest.approx(r["stats"]["w_emit"], rel=1e-12)
     assert st["w_abs"] == pytest.approx(r["stats"]["w_abs"], rel=1e-6)
