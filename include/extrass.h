@@ -147,6 +147,19 @@ int extrass_transport(extrass_handle h, const extrass_grid* g, const extrass_sou
                       double* est, double* stats, double* packets_out, void* ws,
                       size_t ws_bytes, void* stream);
 
+/* extrass_transport without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc). Same arguments, outputs and errors as
+ * extrass_transport; the scratch is a 16 MiB array the library keeps on each
+ * GPU for the life of the process (set up by extrass_create), and
+ * EXTRASS_ENOSPACE is returned when extrass_transport_workspace(g, s) exceeds
+ * it (a 100^3 grid with 30000 lines and 1e8 packets needs 10.1 MiB; 120^3
+ * fits, 125^3 does not). Allocates nothing. Every call on a
+ * GPU shares that GPU's array: calls that overlap on one GPU (other streams,
+ * other handles, other threads) race and must be serialised by the caller. */
+int extrass_transport_noalloc(extrass_handle h, const extrass_grid* g, const extrass_source* s,
+                              double* est, double* stats, double* packets_out, void* stream);
+
 /* ------------------------------------------------------------------------
  * Emergent spectra per viewer (Sec. 2.3: rays leave towards 20 x 20 viewers
  * spread evenly in polar and azimuthal angle; the emission is binned

@@ -93,6 +93,8 @@ _lib.extrass_transport_workspace.restype = C.c_size_t
 _lib.extrass_transport_workspace.argtypes = [C.POINTER(_Grid), C.POINTER(_Source)]
 _lib.extrass_transport.argtypes = [_vp, C.POINTER(_Grid), C.POINTER(_Source), _vp, _vp, _vp, _vp,
                                    C.c_size_t, _vp]
+_lib.extrass_transport_noalloc.argtypes = [_vp, C.POINTER(_Grid), C.POINTER(_Source), _vp, _vp,
+                                           _vp, _vp]
 _lib.extrass_line_tau.argtypes = [_vp, _vp, C.c_int64, _vp, C.c_double, _vp, _vp, _vp]
 _lib.extrass_rates.argtypes = [_vp, _vp, C.POINTER(_Grid), C.c_double, _vp, _vp, _vp, _vp]
 _lib.extrass_atom_create.argtypes = [_vp, C.POINTER(_AtomDesc), C.POINTER(_vp)]
@@ -133,7 +135,7 @@ SYMBOLS = ["extrass_create", "extrass_destroy", "extrass_error_string", "extrass
            "extrass_nlte_warm_start_workspace", "extrass_nlte_warm_start",
            "extrass_batched_workspace", "extrass_batched_solve", "extrass_batched_tune",
            "extrass_transport_streamed_workspace", "extrass_transport_streamed",
-           "extrass_mlp_features", "extrass_spectrum"]
+           "extrass_mlp_features", "extrass_spectrum", "extrass_transport_noalloc"]
 
 
 class ExtrassError(RuntimeError):
@@ -253,6 +255,22 @@ def transport(ctx: Context, grid: Grid, seed, lambda_lo, lambda_hi, n_packets, f
                                 _ptr(ws), ws.numel(), _stream())
     ctx.check(rc, "extrass_transport")
     return est, stats, pk
+
+
+def transport_noalloc(ctx: Context, grid: Grid, seed, lambda_lo, lambda_hi, n_packets, est, stats,
+                      first_packet=0, iteration=0, geometry_fp32=False, packets_out=None):
+    """Runs extrass_transport_noalloc (no workspace; the library's per-GPU
+    scratch) into the caller's est [C, L], stats [16] and optional per-packet
+    records; returns the library's return code (0, or ENOSPACE when the problem
+    needs more scratch than it holds) without raising on ENOSPACE."""
+    g = grid.struct()
+    s = _Source(int(seed), int(iteration), int(first_packet), int(n_packets), float(lambda_lo),
+                float(lambda_hi), None, 1 if geometry_fp32 else 0)
+    rc = _lib.extrass_transport_noalloc(ctx.h, C.byref(g), C.byref(s), _ptr(est), _ptr(stats),
+                                        _ptr(packets_out), _stream())
+    if rc not in (OK, ENOSPACE):
+        ctx.check(rc, "extrass_transport_noalloc")
+    return rc
 
 
 def spectrum(ctx: Context, packets, n_theta, n_phi, n_lambda, lambda_min, lambda_max,

@@ -26,6 +26,11 @@ extern "C" int extrass_create(extrass_handle* out, int device) {
     return EXTRASS_EHIP;
   }
   h->num_cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  // the allocation-free transport's scratch on this device
+  if (hipSetDevice(device) != hipSuccess || noalloc_init(device) != hipSuccess) {
+    delete h;
+    return EXTRASS_EHIP;
+  }
   *out = h;
   return EXTRASS_OK;
 }

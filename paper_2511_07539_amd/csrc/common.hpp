@@ -20,6 +20,9 @@ struct extrass_ctx {
 
 namespace extrass {
 
+// Sets up the allocation-free transport's per-GPU scratch (transport.hip).
+hipError_t noalloc_init(int device);
+
 inline int fail(extrass_handle h, int code, const std::string& what) {
   if (h) h->last_error = what;
   return code;

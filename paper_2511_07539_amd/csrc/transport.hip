@@ -27,6 +27,8 @@
 #include <cmath>
 #include <cstdint>
 
+#include <mutex>
+
 #include "atom.hpp"
 #include "common.hpp"
 #include "philox.hpp"
@@ -729,6 +731,32 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
 
 using namespace extrass;
 
+// Scratch of extrass_transport_noalloc: one array per GPU, held until the
+// process ends. Host code never uses its name as an address (on the host it
+// is only a stand-in): the device address comes from hipGetSymbolAddress,
+// once per device, and is kept in noalloc_ptr.
+constexpr size_t kNoAllocBytes = size_t(16) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex noalloc_mutex;
+void* noalloc_ptr[kMaxDevices] = {};
+}  // namespace
+
+namespace extrass {
+// Looks up this device's scratch address once (the device must be current).
+hipError_t noalloc_init(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(noalloc_mutex);
+  if (noalloc_ptr[device]) return hipSuccess;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e == hipSuccess) noalloc_ptr[device] = p;
+  return e;
+}
+}  // namespace extrass
+
 struct TransportWs {
   int64_t* start = nullptr;
   LineRec* lines = nullptr;
@@ -856,6 +884,24 @@ extern "C" int extrass_transport(extrass_handle h, const extrass_grid* g, const 
     hipLaunchKernelGGL(k_transport<double>, dim3((unsigned)blocks), dim3(kBlock), 0, st, A);
   EXTRASS_HIP_TRY(h, hipGetLastError());
   return EXTRASS_OK;
+}
+
+extern "C" int extrass_transport_noalloc(extrass_handle h, const extrass_grid* g,
+                                         const extrass_source* s, double* est, double* stats,
+                                         double* packets_out, void* stream) {
+  if (!h || !g || !s) return fail(h, EXTRASS_EINVAL, "extrass_transport_noalloc: null argument");
+  if (h->device < 0 || h->device >= kMaxDevices)
+    return fail(h, EXTRASS_EINVAL, "extrass_transport_noalloc: device index");
+  void* ws = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(noalloc_mutex);
+    ws = noalloc_ptr[h->device];
+  }
+  if (!ws) return fail(h, EXTRASS_EHIP, "extrass_transport_noalloc: scratch not set up");
+  if (g->n <= 0 || s->n_packets < 0 || extrass_transport_workspace(g, s) > kNoAllocBytes)
+    return fail(h, EXTRASS_ENOSPACE,
+                "extrass_transport_noalloc: the problem needs more than the 16 MiB scratch");
+  return extrass_transport(h, g, s, est, stats, packets_out, ws, kNoAllocBytes, stream);
 }
 
 // ---- streamed transport over velocity octants --------------------------------
