@@ -89,6 +89,13 @@ def lib():
         L.oracle_rate_matrix.argtypes = [C.POINTER(_Atom), C.POINTER(_Cells), C.c_int64, C.c_int32,
                                          C.c_void_p, C.c_void_p]
         L.oracle_gth.argtypes = [C.c_int32, C.c_void_p, C.c_void_p]
+        L.oracle_emission_bins.argtypes = [C.POINTER(_Atom), C.c_int64, C.c_void_p, C.c_double,
+                                           C.c_double, C.c_double, C.c_double, C.c_int32,
+                                           C.c_void_p, C.c_void_p, C.c_void_p]
+        L.oracle_ray_packets.restype = C.c_int64
+        L.oracle_ray_packets.argtypes = [C.c_int32, C.c_double, C.c_int64, C.c_int64, C.c_int32,
+                                         C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
+                                         C.POINTER(C.POINTER(C.c_double))]
         L.oracle_batched_matrix.argtypes = [C.POINTER(_Batched), C.c_int64, C.c_void_p]
         L.oracle_batched.restype = C.c_int64
         L.oracle_batched.argtypes = [C.POINTER(_Batched), C.c_void_p, C.c_int64, C.c_int64,
@@ -358,6 +365,41 @@ def gth(R):
     pi = np.zeros(len(R))
     lib().oracle_gth(len(R), _p(R), _p(pi))
     return pi
+
+
+def emission_bins(inp: "NLTEInputs", pops, t_exp, cell_volume, lambda_min, lambda_max, n_lambda):
+    """Line emission per cell and logarithmic wavelength bin (Sec. 2.3, Eq. A3):
+    returns (energy [C, n_lambda] erg s^-1, reddest line wavelength per bin
+    [n_lambda] (0 where empty), energy outside the range [C])."""
+    pops = np.ascontiguousarray(pops, dtype=np.float64)
+    C_ = pops.size // inp.n_levels
+    E = np.zeros((C_, n_lambda))
+    lam = np.zeros(n_lambda)
+    out = np.zeros(C_)
+    lib().oracle_emission_bins(C.byref(inp.atom), C_, _p(pops), t_exp, cell_volume, lambda_min,
+                               lambda_max, n_lambda, _p(E), _p(lam), _p(out))
+    return E, lam, out
+
+
+def ray_packets(n, beta_max, bin_energy, bin_lambda, n_theta, n_phi, first=0, count=None):
+    """The deterministic rays of cells [first, first+count) as explicit packets
+    [R, 8] (x, y, z, n_x, n_y, n_z, lambda_e, w0), cell by cell, bin by bin,
+    viewer by viewer (theta-major)."""
+    E = np.ascontiguousarray(bin_energy, dtype=np.float64)
+    lam = np.ascontiguousarray(bin_lambda, dtype=np.float64)
+    n_lambda = lam.size
+    if count is None:
+        count = E.size // n_lambda - first
+    ptr = C.POINTER(C.c_double)()
+    nr = lib().oracle_ray_packets(n, beta_max, first, count, n_lambda, _p(E), _p(lam), n_theta,
+                                  n_phi, C.byref(ptr))
+    if nr > 0:
+        buf = (C.c_double * (8 * nr)).from_address(C.addressof(ptr.contents))
+        out = np.frombuffer(buf, dtype=np.float64).reshape(nr, 8).copy()
+    else:
+        out = np.zeros((0, 8))
+    lib().oracle_free(ptr)
+    return out
 
 
 class BatchedInputs:
