@@ -73,19 +73,24 @@ def test_fp64_geometry_matches_oracle_per_entry(ex, ctx, small):
     np.testing.assert_allclose(pk[:, 3], opk[:, 3], rtol=1e-11, atol=1e-30)
 
 
-def _fp32_metric(est, ref, rec, tie=1e-5):
+def _fp32_metric(est, ref, rec, tie=1e-4):
     """Reduced-precision parity (FP32 positions and distances against the FP64
     oracle). Rounding can move a resonance that lies within rounding of a cell
     wall into the neighbouring cell, where another optical depth applies; the
     packet's weight then differs for the rest of its path. The oracle records
     each interaction's margin, min(D_k - D_entry, D_exit - D_k) / h, the
     distance of the resonance from its segment's walls in cell widths. A
-    record is a near tie if its margin is below `tie`, and every later record
-    of the same packet inherits the taint. Entries with no tainted record must
-    agree to 1e-3; the tainted ones are counted, and so are entries the GPU
-    filled where the oracle has none (a moved resonance), which cannot exceed
-    the near-tie records. The table and each line's sum must agree to 1e-3."""
+    record is a near tie if its margin is below `tie`: D is held in FP32,
+    whose unit roundoff 6e-8 times |D| <= sqrt(3) beta_max is 2.6e-6 cell
+    widths per rounding at 50^3, and a path takes a few tens of roundings
+    (wall crossings, D_k to FP32), so 1e-4. A near tie taints every later
+    record of its packet, and its line's entries in the 27 cells around it
+    (where the moved resonance can land). Entries with no taint must agree to
+    1e-3; the tainted ones are counted, and so are entries the GPU filled where
+    the oracle has none, which cannot exceed the near-tie records. The table
+    and each line's sum must agree to 1e-3."""
     L = ref.shape[1]
+    n = int(round(ref.shape[0] ** (1.0 / 3.0)))
     near = rec["margin"] < tie
     pkt = rec["packet"]
     assert np.all(pkt[1:] >= pkt[:-1]), "records must come in packet order"
@@ -96,10 +101,30 @@ def _fp32_metric(est, ref, rec, tie=1e-5):
     idx = rec["cell"].astype(np.int64) * L + rec["line"]
     taint_entry = np.zeros(ref.size, dtype=bool)
     taint_entry[idx[tainted]] = True
+    c = rec["cell"][near].astype(np.int64)
+    ci = np.stack([c % n, (c // n) % n, c // (n * n)], axis=1)
+    for dz in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                q = ci + np.array([dx, dy, dz])
+                ok = np.all((q >= 0) & (q < n), axis=1)
+                cc = q[ok, 0] + n * (q[ok, 1] + n * q[ok, 2])
+                taint_entry[cc * L + rec["line"][near][ok]] = True
     e, r_ = est.ravel(), ref.ravel()
     clean = (r_ != 0) & ~taint_entry
     rel = np.abs(e[clean] - r_[clean]) / np.abs(r_[clean])
     moved = int(((r_ == 0) & (e != 0)).sum())
+    bad = np.flatnonzero(clean)[rel > 1e-3]
+    if len(bad):   # diagnostics: the records and packets behind the worst entries
+        say(f"clean entries off by > 1e-3: {len(bad)}")
+        pmin = np.minimum.reduceat(rec["margin"], np.flatnonzero(first))
+        pk_first = np.flatnonzero(first)
+        for b in bad[:8]:
+            ri = np.flatnonzero(idx == b)
+            pk = np.unique(pkt[ri])
+            gi = np.searchsorted(pkt[pk_first], pk)
+            say(f"  entry {b}: ref {r_[b]:.4e} est {e[b]:.4e} records {len(ri)} "
+                f"min margin {rec['margin'][ri].min():.2e} packet min margin {pmin[gi].min():.2e}")
     d = np.abs(est - ref)
     line_ref = ref.sum(0)
     big_l = line_ref > 1e-3 * line_ref.max()
