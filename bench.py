@@ -228,6 +228,8 @@ def main():
     torch.cuda.empty_cache()
     out.update(extras)
     if not args.no_extras:
+        out["deterministic_rays"] = bench_rays(ex, ctx, w50)
+        torch.cuda.empty_cache()
         out["spectrum"] = bench_spectrum(ex, ctx, w50)
         torch.cuda.empty_cache()
         out["batched_nlte"] = bench_batched(ex, ctx)
@@ -265,8 +267,9 @@ def nlte_accuracy(ex, ctx, loop, w, cells, gpe, params, norm, args):
     pw, sw, _ = ex.nlte_solve(ctx, loop.atom, cl, tol=args.nlte_tol, guess=guess,
                               warm_budget=args.warm_budget)
     torch.cuda.synchronize()
-    inp = oracle.nlte_inputs_from_workload(w, gamma_pe=np.ascontiguousarray(gpe).ravel(),
-                                           cells=cells)
+    inp = oracle.NLTEInputs(w.atom, w.t_exp, w.T_e[cells], w.n_e[cells],
+                            w.n_species.reshape(-1, S)[cells].ravel(),
+                            w.gamma_ion.reshape(-1, S, 3)[cells].ravel(), gpe.ravel())
     t0 = time.perf_counter()
     po, so, _ = oracle.nlte(inp, tol=1e-12)
     t_or = time.perf_counter() - t0
@@ -403,6 +406,45 @@ def bench_clumpy50(ex, ctx, w, params, norm, args):
                               "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                               "frac": flops / (parts["nlte"] * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
                               "algorithmic_flops": flops}}
+
+
+def bench_rays(ex, ctx, w, n_rays=2_000_000_000):
+    """The paper's deterministic rays (Sec. 2.3) on the 50^3 workload at its
+    cold-start populations: line emission (Eq. A3) into 0.1 % logarithmic bins
+    over the atom's lines, one ray per (cell, occupied bin, viewer) towards
+    20 x 20 viewers (FP32 geometry). The first n_rays rays (cell-major, so a
+    slab of cells with all their bins and viewers) are timed with HIP events;
+    the rate is projected to the whole ray set."""
+    import math
+
+    import torch
+    atom = ex.Atom(ctx, w.atom)
+    cells0 = ex.cells_from_workload(w)
+    pops, _, _ = ex.nlte_solve(ctx, atom, cells0, max_iter=0)
+    tau, fc = ex.line_tau(ctx, atom, pops, w.t_exp)
+    grid = ex.grid_from_workload(w, tau_ct=tau, fcorr_ct=fc)
+    lo, hi = 0.97 * float(w.atom.trans_lambda.min()), 1.03 * float(w.atom.trans_lambda.max())
+    n_lam = int(math.ceil(math.log(hi / lo) / math.log(1.001)))
+    plan = ex.EmissionPlan(ctx, atom, lo, hi, n_lam)
+    s = torch.cuda.current_stream()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    e[0].record(s)
+    ph, _ = ex.emission(ctx, plan, atom, grid, w.t_exp, pops)
+    e[1].record(s)
+    total = w.n_cells * plan.n_bins * 400
+    n = min(n_rays, total)
+    est, st, _ = ex.transport_rays(ctx, grid, plan, ph, 20, 20, n_rays=n, geometry_fp32=True)
+    e[2].record(s)
+    torch.cuda.synchronize()
+    ms_em, ms_rays = e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2])
+    sd = ex.stats_dict(st)
+    return {"workload": w.name, "viewers": [20, 20], "lambda_bins": n_lam,
+            "occupied_bins": plan.n_bins, "rays_total": total, "rays_timed": n,
+            "ms_emission": ms_em, "ms_rays_incl_table_fill": ms_rays,
+            "rays_per_s": n / (ms_rays * 1e-3), "interactions": sd["n_inter"],
+            "projected_s_all_rays": total / (n / (ms_rays * 1e-3)),
+            "paper_context": "2.5e10 rays per iteration in about 70 min on 768 CPU cores "
+                             "(includes the NLTE solve)"}
 
 
 def bench_spectrum(ex, ctx, w):

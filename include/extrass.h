@@ -100,6 +100,7 @@ typedef struct {
  * cell_photons[c] / n_c. Explicit mode: packet p is the row
  * explicit_packets[8p .. 8p+7] = (x, y, z, nx, ny, nz, lambda_e, w0).
  * Runs packets [first_packet, first_packet + n_packets). */
+typedef struct extrass_rays extrass_rays;  /* deterministic rays, below */
 typedef struct {
   uint64_t seed;
   int32_t iteration;
@@ -108,7 +109,29 @@ typedef struct {
   double lambda_lo, lambda_hi;      /* emission band, cm */
   const double* explicit_packets;   /* [P*8] or NULL */
   int32_t geometry_fp32;            /* 0: FP64 positions and distances; 1: FP32 */
+  const extrass_rays* rays;         /* host struct: deterministic rays instead of sampled
+                                       packets (explicit_packets NULL), or NULL */
 } extrass_source;
+
+/* Deterministic emission (Sec. 2.3): every cell sends one ray per wavelength
+ * bin with emission and per viewer, from the middle of the cell, starting at
+ * the reddest wavelength of the bin's lines (no absorption in its own line)
+ * and carrying the bin's photons times the viewer's share of the sphere.
+ * Viewers: n_theta x n_phi, theta_a = (a + 1/2) pi / n_theta, phi_b =
+ * (b + 1/2) 2 pi / n_phi, solid angle dOmega = (2 pi / n_phi)(cos(a pi /
+ * n_theta) - cos((a + 1) pi / n_theta)). Ray r (packet id) of cell
+ * c = r / (B V), bin slot j = (r / V) mod B, viewer k = r mod V (theta-major,
+ * k = a n_phi + b), V = n_theta n_phi, carries
+ * bin_photons[c*B + j] * dOmega_k / (4 pi) photons s^-1 (the reading of the
+ * weight E_bin / dOmega_k / E_phot as E_bin (dOmega_k / 4 pi) / E_phot, so a
+ * bin's rays carry its photons once over the sphere); rays of zero weight are
+ * skipped (no events, not tallied). Valid ray ids are [0, C B V). */
+struct extrass_rays {
+  int32_t n_theta, n_phi;       /* viewers, 1..4096 each */
+  int32_t n_bins;               /* B, occupied wavelength bins */
+  const double* bin_lambda;     /* device [B] starting (comoving) wavelength of each bin, cm */
+  const double* bin_photons;    /* device [C*B] photons s^-1 each cell emits in each bin */
+};
 
 /* Transport statistics, written to `stats` (device, EXTRASS_STATS doubles). */
 enum {
@@ -121,6 +144,8 @@ enum {
   EXTRASS_STAT_N_CROSS = 6,  /* cell-to-cell crossings */
   EXTRASS_STAT_N_ESCAPED = 7,
   EXTRASS_STAT_N_KILLED = 8,
+  EXTRASS_STAT_E_ESC = 9,    /* escaped weight over lab wavelength, sum of w / lambda_L
+                                (cm^-1 s^-1): h c times it is the escaping luminosity */
   EXTRASS_STAT_QUEUE_FULL = 13,  /* streamed transport: 1.0 if an octant queue overflowed */
   EXTRASS_STAT_BAD_PACKETS = 14, /* 1.0 if some packet id lay beyond the sampling plan
                                     or a packet had no wall ahead (NaN or zero direction);
@@ -188,6 +213,34 @@ typedef struct {
 int extrass_spectrum(extrass_handle h, const double* packets, int64_t n_packets,
                      const extrass_spectrum_bins* bins, double* photons, double* energy,
                      void* stream);
+
+/* ------------------------------------------------------------------------
+ * Line emission for the deterministic rays (Sec. 2.3; Eq. A3): the
+ * bound-bound emissivity A_ul Delta E_ul beta_S N_u of every atom transition,
+ * N_u = n_u V the cell's atoms in the upper level, beta_S from Eqs. A1-A2 at
+ * the cell's populations, Delta E_ul = h c / lambda_ul, binned by wavelength
+ * in n_lambda logarithmic bins over [lambda_min, lambda_max) (bin
+ * floor(n_lambda ln(lambda / lambda_min) / ln(lambda_max / lambda_min))).
+ * A plan fixes the binning for an atom: its occupied bins (those holding at
+ * least one transition), in increasing order, each starting its rays at the
+ * reddest transition wavelength in it. */
+typedef struct extrass_emission_ctx* extrass_emission_plan;
+int extrass_emission_plan_create(extrass_handle h, extrass_atom_handle atom, double lambda_min,
+                                 double lambda_max, int32_t n_lambda, extrass_emission_plan* out);
+int extrass_emission_plan_destroy(extrass_emission_plan p);
+/* B, and (host arrays of capacity B, either may be NULL) each occupied bin's
+ * number in the n_lambda grid and its starting wavelength; *device_lambda
+ * (may be NULL) receives the plan's device copy of the wavelengths [B], for
+ * extrass_rays.bin_lambda (owned by the plan). */
+int extrass_emission_plan_info(extrass_emission_plan p, int32_t* n_bins, int32_t* bin_number,
+                               double* bin_lambda, const double** device_lambda);
+/* For the grid's cells (C = n^3, V = (2 beta_max / n c t_exp)^3) at
+ * populations pops [C*N]: bin_photons [C*B] (device, overwritten) photons
+ * s^-1 per occupied bin, E_bin / (h c / lambda_bin); outside [C] (device, may
+ * be NULL) erg s^-1 emitted in lines outside [lambda_min, lambda_max). */
+int extrass_emission(extrass_handle h, extrass_emission_plan p, extrass_atom_handle atom,
+                     const extrass_grid* grid, double t_exp, const double* pops,
+                     double* bin_photons, double* outside, void* stream);
 
 /* ------------------------------------------------------------------------
  * Eq. A2: tau_S = (A_ul / 8 pi) (g_u / g_l) lambda^3 n_l (1 - g_l n_u / (g_u n_l)) t

@@ -27,7 +27,7 @@ OK, EINVAL, ENOSPACE, EHIP, EUNSUPPORTED = 0, -1, -2, -3, -4
 STATS = 16
 PACKET_FIELDS = 8  # doubles per packet record (EXTRASS_PACKET_FIELDS)
 STAT_NAMES = ["w_emit", "w_esc", "w_kill", "w_abs", "n_inter", "n_checks", "n_cross",
-              "n_escaped", "n_killed"]
+              "n_escaped", "n_killed", "e_esc"]
 STAT_ERROR_FLAG = 15
 
 
@@ -47,7 +47,13 @@ class _SpecBins(C.Structure):
 class _Source(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("iteration", C.c_int32), ("first_packet", C.c_int64),
                 ("n_packets", C.c_int64), ("lambda_lo", C.c_double), ("lambda_hi", C.c_double),
-                ("explicit_packets", C.c_void_p), ("geometry_fp32", C.c_int32)]
+                ("explicit_packets", C.c_void_p), ("geometry_fp32", C.c_int32),
+                ("rays", C.c_void_p)]
+
+
+class _Rays(C.Structure):
+    _fields_ = [("n_theta", C.c_int32), ("n_phi", C.c_int32), ("n_bins", C.c_int32),
+                ("bin_lambda", C.c_void_p), ("bin_photons", C.c_void_p)]
 
 
 class _AtomDesc(C.Structure):
@@ -95,6 +101,12 @@ _lib.extrass_transport.argtypes = [_vp, C.POINTER(_Grid), C.POINTER(_Source), _v
                                    C.c_size_t, _vp]
 _lib.extrass_transport_noalloc.argtypes = [_vp, C.POINTER(_Grid), C.POINTER(_Source), _vp, _vp,
                                            _vp, _vp]
+_lib.extrass_emission_plan_create.argtypes = [_vp, _vp, C.c_double, C.c_double, C.c_int32,
+                                              C.POINTER(_vp)]
+_lib.extrass_emission_plan_destroy.argtypes = [_vp]
+_lib.extrass_emission_plan_info.argtypes = [_vp, C.POINTER(C.c_int32), _vp, _vp,
+                                            C.POINTER(C.c_void_p)]
+_lib.extrass_emission.argtypes = [_vp, _vp, _vp, C.POINTER(_Grid), C.c_double, _vp, _vp, _vp, _vp]
 _lib.extrass_line_tau.argtypes = [_vp, _vp, C.c_int64, _vp, C.c_double, _vp, _vp, _vp]
 _lib.extrass_rates.argtypes = [_vp, _vp, C.POINTER(_Grid), C.c_double, _vp, _vp, _vp, _vp]
 _lib.extrass_atom_create.argtypes = [_vp, C.POINTER(_AtomDesc), C.POINTER(_vp)]
@@ -135,7 +147,9 @@ SYMBOLS = ["extrass_create", "extrass_destroy", "extrass_error_string", "extrass
            "extrass_nlte_warm_start_workspace", "extrass_nlte_warm_start",
            "extrass_batched_workspace", "extrass_batched_solve", "extrass_batched_tune",
            "extrass_transport_streamed_workspace", "extrass_transport_streamed",
-           "extrass_mlp_features", "extrass_spectrum", "extrass_transport_noalloc"]
+           "extrass_mlp_features", "extrass_spectrum", "extrass_transport_noalloc",
+           "extrass_emission_plan_create", "extrass_emission_plan_destroy",
+           "extrass_emission_plan_info", "extrass_emission"]
 
 
 class ExtrassError(RuntimeError):
@@ -271,6 +285,82 @@ def transport_noalloc(ctx: Context, grid: Grid, seed, lambda_lo, lambda_hi, n_pa
     if rc not in (OK, ENOSPACE):
         ctx.check(rc, "extrass_transport_noalloc")
     return rc
+
+
+class EmissionPlan:
+    """The wavelength binning of an atom's line emission for deterministic rays
+    (extrass_emission_plan_create): n_lambda logarithmic bins over
+    [lambda_min, lambda_max); the occupied ones, each with its starting
+    (reddest) wavelength."""
+
+    def __init__(self, ctx: Context, atom, lambda_min, lambda_max, n_lambda):
+        h = _vp()
+        ctx.check(_lib.extrass_emission_plan_create(ctx.h, atom.h, float(lambda_min),
+                                                    float(lambda_max), int(n_lambda), C.byref(h)),
+                  "extrass_emission_plan_create")
+        self.h = h
+        nb = C.c_int32(0)
+        _lib.extrass_emission_plan_info(h, C.byref(nb), None, None, None)
+        self.n_bins = int(nb.value)
+        self.bin_number = np.zeros(self.n_bins, dtype=np.int32)
+        self.bin_lambda = np.zeros(self.n_bins)
+        dptr = C.c_void_p()
+        _lib.extrass_emission_plan_info(h, None, self.bin_number.ctypes.data,
+                                        self.bin_lambda.ctypes.data, C.byref(dptr))
+        self.device_lambda = dptr.value
+
+    def close(self):
+        if self.h:
+            _lib.extrass_emission_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def emission(ctx: Context, plan: EmissionPlan, atom, grid: Grid, t_exp, pops, bin_photons=None,
+             outside=None):
+    """Line emission of the grid's cells (extrass_emission): photons s^-1 per
+    occupied bin [C, B] and erg s^-1 outside the binned range [C]."""
+    dev = pops.device
+    if bin_photons is None:
+        bin_photons = torch.empty((grid.n_cells, plan.n_bins), dtype=torch.float64, device=dev)
+    if outside is None:
+        outside = torch.empty(grid.n_cells, dtype=torch.float64, device=dev)
+    g = grid.struct()
+    ctx.check(_lib.extrass_emission(ctx.h, plan.h, atom.h, C.byref(g), float(t_exp), _ptr(pops),
+                                    _ptr(bin_photons), _ptr(outside), _stream()),
+              "extrass_emission")
+    return bin_photons, outside
+
+
+def transport_rays(ctx: Context, grid: Grid, plan: EmissionPlan, bin_photons, n_theta, n_phi,
+                   first_ray=0, n_rays=None, geometry_fp32=False, est=None, stats=None,
+                   packets_out=False):
+    """Deterministic rays (extrass_transport with extrass_rays): one ray per
+    (cell, occupied bin, viewer). Returns (est [C, L], stats [16], packets [R, 8]
+    or None)."""
+    dev = grid.line_lambda.device
+    total = grid.n_cells * plan.n_bins * int(n_theta) * int(n_phi)
+    if n_rays is None:
+        n_rays = total - first_ray
+    rays = _Rays(int(n_theta), int(n_phi), plan.n_bins, plan.device_lambda, _ptr(bin_photons))
+    g = grid.struct()
+    s = _Source(0, 0, int(first_ray), int(n_rays), 0.0, 0.0, None, 1 if geometry_fp32 else 0,
+                C.cast(C.pointer(rays), C.c_void_p))
+    if est is None:
+        est = torch.empty((grid.n_cells, grid.n_lines), dtype=torch.float64, device=dev)
+    if stats is None:
+        stats = torch.empty(STATS, dtype=torch.float64, device=dev)
+    pk = (torch.zeros((n_rays, PACKET_FIELDS), dtype=torch.float64, device=dev)
+          if packets_out else None)
+    ws = ctx.workspace(_lib.extrass_transport_workspace(C.byref(g), C.byref(s)))
+    ctx.check(_lib.extrass_transport(ctx.h, C.byref(g), C.byref(s), _ptr(est), _ptr(stats),
+                                     _ptr(pk), _ptr(ws), ws.numel(), _stream()), "extrass_transport")
+    return est, stats, pk
 
 
 def spectrum(ctx: Context, packets, n_theta, n_phi, n_lambda, lambda_min, lambda_max,

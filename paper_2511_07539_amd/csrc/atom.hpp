@@ -23,7 +23,8 @@ struct extrass_atom_ctx {
   int maxPacked = 0;
   std::vector<int> off;   // host copy of species_offset
   std::vector<int> toff;  // host: transitions of species s are [toff[s], toff[s+1])
-  struct {
+  std::vector<double> lam_host;  // host copy of the transition wavelengths (caller's order)
+  struct Dev {
     int32_t* off = nullptr;       // [S+1]
     int32_t* toff = nullptr;      // [S+1]
     int32_t* nstage = nullptr;    // [S]

@@ -73,6 +73,10 @@ struct TArgs {
   int64_t first, count;
   double lam_lo, lam_hi;
   const double* explicit_pk;
+  // deterministic rays (ray_ph not NULL): B occupied bins, viewers nt x np
+  const double* ray_lam;   // [B]
+  const double* ray_ph;    // [C*B]
+  int ray_B, ray_nt, ray_np;
   const int64_t* start;  // [C+1] exclusive prefix of cell_packets
   const int32_t* lam_bin;   // [nbin] first line above each log-lambda bin edge (lowered)
   const double* lam_par;    // lambda_0, bins per unit lambda
@@ -400,7 +404,9 @@ __device__ __forceinline__ int first_line_above(const TArgs& A, double lam) {
   return k;
 }
 
-template <class G>
+// RAYS: the deterministic-ray kernel, compiled apart so that the sampled
+// kernels keep their register allocation.
+template <class G, bool RAYS>
 __device__ void emit(const TArgs& A, int64_t p, Packet<G>& q) {
   double x[3], d[3], lam_e, w0;
   int ci[3];
@@ -415,6 +421,35 @@ __device__ void emit(const TArgs& A, int64_t p, Packet<G>& q) {
     }
     lam_e = e[6];
     w0 = e[7];
+  } else if (RAYS) {
+    // ray r = (c B + j) V + k from the middle of cell c towards viewer k,
+    // starting at bin j's wavelength with the viewer's share of its photons
+    const int64_t V = (int64_t)A.ray_nt * A.ray_np;
+    if (p >= A.C * A.ray_B * V) {
+      q.bad = true;
+      return;
+    }
+    const int64_t cb = p / V;
+    const int k = static_cast<int>(p - cb * V);
+    const int64_t c = cb / A.ray_B;
+    const int j = static_cast<int>(cb - c * A.ray_B);
+    ci[0] = static_cast<int>(c % A.n);
+    ci[1] = static_cast<int>((c / A.n) % A.n);
+    ci[2] = static_cast<int>(c / ((int64_t)A.n * A.n));
+    for (int a = 0; a < 3; ++a) x[a] = -A.beta + (static_cast<double>(ci[a]) + 0.5) * A.h;
+    const int it = k / A.ray_np, ip = k - it * A.ray_np;
+    const double th = (it + 0.5) * M_PI / A.ray_nt;
+    const double ph = (ip + 0.5) * 2.0 * M_PI / A.ray_np;
+    const double dom = (2.0 * M_PI / A.ray_np) *
+                       (cos(it * M_PI / A.ray_nt) - cos((it + 1) * M_PI / A.ray_nt));
+    double st, ct, sp, cp;
+    sincos(th, &st, &ct);
+    sincos(ph, &sp, &cp);
+    d[0] = st * cp;
+    d[1] = st * sp;
+    d[2] = ct;
+    lam_e = A.ray_lam[j];
+    w0 = A.ray_ph[cb] * dom / (4.0 * M_PI);
   } else {
     if (p >= A.start[A.C]) {  // id beyond the sampling plan
       q.bad = true;
@@ -475,6 +510,7 @@ __device__ void emit(const TArgs& A, int64_t p, Packet<G>& q) {
 
 struct Tally {
   double w_emit = 0, w_esc = 0, w_kill = 0, w_abs = 0;
+  double e_esc = 0;  // escaped weight over lab wavelength: h c e_esc is the escaping erg s^-1
   uint32_t inter = 0, checks = 0, cross = 0, escaped = 0, killed = 0;  // per lane
   bool bad = false;
   bool overflow = false;
@@ -535,7 +571,7 @@ __device__ int64_t resume(const QPk& r, Packet<G>& q) {
 // Three waves per SIMD: the kernel is bound by the latency of its gathers and
 // scattered atomics, and the third wave (a few dwords of rarely used state
 // spilled) is worth more than the spill.
-template <class G>
+template <class G, bool RAYS>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_transport(TArgs A) {
   const int lane = threadIdx.x & 63;
   Packet<G> q;
@@ -580,9 +616,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
             nxt = line_rec(A, q.k);
           } else {  // one emission site for both modes keeps the register peak down
             const int64_t p = A.oct < 0 ? A.first + idx : octant_packet(A, idx);
-            emit<G>(A, p, q);
+            emit<G, RAYS>(A, p, q);
             if (q.bad) {
               t.bad = true;
+              pid = -1;
+            } else if (RAYS && !(q.w0 > 0.0)) {  // a ray with no photons: skipped
               pid = -1;
             } else {
               pid = p;
@@ -627,6 +665,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
       q.have_exit = false;
       if (out) {
         t.w_esc += q.w;
+        t.e_esc += q.w / q.lamL;
         t.escaped++;
         if (A.pk_out) put_record<G>(A.pk_out + kPkFields * (pid - A.first), q, q.w, 0.0);
         stop = true;
@@ -713,10 +752,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
   }
 
   // ---- per-wave reduction of the tallies, one atomic per wave and field
-  double v[9] = {t.w_emit, t.w_esc, t.w_kill, t.w_abs, (double)t.inter, (double)t.checks,
-                 (double)t.cross, (double)t.escaped, (double)t.killed};
+  double v[10] = {t.w_emit, t.w_esc, t.w_kill, t.w_abs, (double)t.inter, (double)t.checks,
+                  (double)t.cross, (double)t.escaped, (double)t.killed, t.e_esc};
 #pragma unroll
-  for (int f = 0; f < 9; ++f) {
+  for (int f = 0; f < 10; ++f) {
     double s = wave_sum(v[f]);
     if (lane == 0 && s != 0.0) atomicAdd(A.stats + f, s);
   }
@@ -803,7 +842,12 @@ extern "C" int extrass_transport(extrass_handle h, const extrass_grid* g, const 
     return fail(h, EXTRASS_EINVAL, "extrass_transport: tau_ct needs line_trans and n_trans");
   if (s->n_packets < 0 || s->first_packet < 0)
     return fail(h, EXTRASS_EINVAL, "extrass_transport: bad packet range");
-  if (!s->explicit_packets && (!g->cell_packets || !g->cell_photons))
+  const extrass_rays* rays = s->rays;
+  if (rays && (s->explicit_packets || rays->n_theta < 1 || rays->n_phi < 1 ||
+               rays->n_theta > 4096 || rays->n_phi > 4096 || rays->n_bins < 0 ||
+               (rays->n_bins > 0 && (!rays->bin_lambda || !rays->bin_photons))))
+    return fail(h, EXTRASS_EINVAL, "extrass_transport: bad deterministic rays");
+  if (!s->explicit_packets && !rays && (!g->cell_packets || !g->cell_photons))
     return fail(h, EXTRASS_EINVAL, "extrass_transport: sampled mode needs cell_packets/photons");
   TransportWs tw;
   const size_t need = ws_layout(g, s, &tw, ws);
@@ -824,7 +868,7 @@ extern "C" int extrass_transport(extrass_handle h, const extrass_grid* g, const 
                        has_ct, g->n_trans, L, stats);
   hipLaunchKernelGGL(k_lambin, dim3(64), dim3(256), 0, st, g->line_lambda, L, lam_bins(L),
                      tw.lam_bin, tw.lam_par);
-  if (!s->explicit_packets) {
+  if (!s->explicit_packets && !rays) {
     scan_counts(st, g->cell_packets, C, g->n, -1, tw.tsum, start);
     const int64_t b2 = std::min<int64_t>((tw.nchunk + 255) / 256, 4096);
     hipLaunchKernelGGL(k_chunk_cells, dim3((unsigned)std::max<int64_t>(b2, 1)), dim3(256), 0, st,
@@ -864,7 +908,15 @@ extern "C" int extrass_transport(extrass_handle h, const extrass_grid* g, const 
   A.lam_bin = tw.lam_bin;
   A.lam_par = tw.lam_par;
   A.nbin = lam_bins(L);
-  A.chunk_cell = s->explicit_packets ? nullptr : tw.chunk_cell;
+  A.chunk_cell = (s->explicit_packets || rays) ? nullptr : tw.chunk_cell;
+  if (rays) {
+    A.ray_lam = rays->bin_lambda;
+    A.ray_ph = rays->n_bins > 0 ? rays->bin_photons : nullptr;
+    A.ray_B = rays->n_bins;
+    A.ray_nt = rays->n_theta;
+    A.ray_np = rays->n_phi;
+    if (rays->n_bins == 0) return EXTRASS_OK;  // no bins: no rays
+  }
   A.nchunk = tw.nchunk;
   A.C = C;
   A.est = est;
@@ -878,10 +930,14 @@ extern "C" int extrass_transport(extrass_handle h, const extrass_grid* g, const 
   const int64_t max_blocks = (s->n_packets + kBlock - 1) / kBlock;
   if (blocks > max_blocks) blocks = max_blocks;
   if (blocks < 1) blocks = 1;
-  if (s->geometry_fp32)
-    hipLaunchKernelGGL(k_transport<float>, dim3((unsigned)blocks), dim3(kBlock), 0, st, A);
+  if (rays && s->geometry_fp32)
+    hipLaunchKernelGGL((k_transport<float, true>), dim3((unsigned)blocks), dim3(kBlock), 0, st, A);
+  else if (rays)
+    hipLaunchKernelGGL((k_transport<double, true>), dim3((unsigned)blocks), dim3(kBlock), 0, st, A);
+  else if (s->geometry_fp32)
+    hipLaunchKernelGGL((k_transport<float, false>), dim3((unsigned)blocks), dim3(kBlock), 0, st, A);
   else
-    hipLaunchKernelGGL(k_transport<double>, dim3((unsigned)blocks), dim3(kBlock), 0, st, A);
+    hipLaunchKernelGGL((k_transport<double, false>), dim3((unsigned)blocks), dim3(kBlock), 0, st, A);
   EXTRASS_HIP_TRY(h, hipGetLastError());
   return EXTRASS_OK;
 }
@@ -973,7 +1029,7 @@ extern "C" int extrass_transport_streamed(extrass_handle h, const extrass_grid* 
     return fail(h, EXTRASS_EINVAL, "extrass_transport_streamed: bad grid (n must be even)");
   if (g->tau_ct && (!g->line_trans || g->n_trans <= 0))
     return fail(h, EXTRASS_EINVAL, "extrass_transport_streamed: tau_ct needs line_trans and n_trans");
-  if (s->explicit_packets || s->first_packet != 0 || s->n_packets < 0)
+  if (s->explicit_packets || s->rays || s->first_packet != 0 || s->n_packets < 0)
     return fail(h, EXTRASS_EINVAL, "extrass_transport_streamed: whole sampling plan only");
   if (atom && (!pops || !gamma_pe || !(t_exp > 0.0)))
     return fail(h, EXTRASS_EINVAL, "extrass_transport_streamed: rates need pops, gamma_pe, t_exp");
@@ -1094,9 +1150,9 @@ extern "C" int extrass_transport_streamed(extrass_handle h, const extrass_grid* 
       const int64_t max_blocks = (A.count + kBlock - 1) / kBlock;
       if (blocks > max_blocks) blocks = max_blocks;
       if (s->geometry_fp32)
-        hipLaunchKernelGGL(k_transport<float>, dim3((unsigned)blocks), dim3(kBlock), 0, st, A);
+        hipLaunchKernelGGL((k_transport<float, false>), dim3((unsigned)blocks), dim3(kBlock), 0, st, A);
       else
-        hipLaunchKernelGGL(k_transport<double>, dim3((unsigned)blocks), dim3(kBlock), 0, st, A);
+        hipLaunchKernelGGL((k_transport<double, false>), dim3((unsigned)blocks), dim3(kBlock), 0, st, A);
       EXTRASS_HIP_TRY(h, hipGetLastError());
       if (!direct)
         hipLaunchKernelGGL(k_octant_flush, dim3((unsigned)Co), dim3(256), 0, st, est_octant,
