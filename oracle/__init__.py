@@ -18,10 +18,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 _lib = None
 
-PKT_FIELDS = 11
-N_STATS = 9
+PKT_FIELDS = 12
+N_STATS = 10
 STAT_NAMES = ["w_emit", "w_esc", "w_kill", "w_abs", "n_inter", "n_checks", "n_cross",
-              "n_escaped", "n_killed"]
+              "n_escaped", "n_killed", "w_pi"]
 
 
 class _Transport(C.Structure):
@@ -32,6 +32,9 @@ class _Transport(C.Structure):
         ("line_trans", C.c_void_p), ("n_trans", C.c_int32), ("tau_ct", C.c_void_p),
         ("fcorr_ct", C.c_void_p), ("lambda_lo", C.c_double), ("lambda_hi", C.c_double),
         ("seed", C.c_uint64), ("iteration", C.c_int32), ("explicit_packets", C.c_void_p),
+        ("pi_levels", C.c_int32), ("pi_lambda", C.c_void_p), ("pi_sigma0", C.c_void_p),
+        ("pi_level", C.c_void_p), ("pi_nlev", C.c_int32), ("pi_pops", C.c_void_p),
+        ("pi_length", C.c_double), ("pi_absorbed", C.c_void_p),
     ]
 
 
@@ -54,6 +57,7 @@ class _Cells(C.Structure):
     _fields_ = [
         ("t_exp", C.c_double), ("T_e", C.c_void_p), ("n_e", C.c_void_p),
         ("n_species", C.c_void_p), ("gamma_ion", C.c_void_p), ("gamma_pe", C.c_void_p),
+        ("gamma_pi", C.c_void_p),
     ]
 
 
@@ -96,6 +100,9 @@ def lib():
         L.oracle_ray_packets.argtypes = [C.c_int32, C.c_double, C.c_int64, C.c_int64, C.c_int32,
                                          C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
                                          C.POINTER(C.POINTER(C.c_double))]
+        L.oracle_pi_levels.restype = C.c_int32
+        L.oracle_pi_levels.argtypes = [C.POINTER(_Atom), C.c_void_p, C.c_int32, C.c_void_p,
+                                       C.c_void_p, C.c_void_p]
         L.oracle_batched_matrix.argtypes = [C.POINTER(_Batched), C.c_int64, C.c_void_p]
         L.oracle_batched.restype = C.c_int64
         L.oracle_batched.argtypes = [C.POINTER(_Batched), C.c_void_p, C.c_int64, C.c_int64,
@@ -132,7 +139,11 @@ class TransportInputs:
 
     def __init__(self, n, beta_max, tau_scale, cell_photons, cell_packets, line_lambda, line_tau0,
                  lambda_lo, lambda_hi, seed, iteration=0, line_trans=None, tau_ct=None,
-                 fcorr_ct=None, explicit_packets=None):
+                 fcorr_ct=None, explicit_packets=None, photoion=None):
+        """photoion: None, or a dict with the photoionising levels of
+        pi_levels() (level, lambda, sigma0), the populations pops [C, N] in
+        cm^-3 and length = c t_exp; transport() then also returns each
+        (cell, level)'s absorbed photons."""
         self.arrays = dict(
             tau_scale=np.ascontiguousarray(tau_scale, dtype=np.float32),
             cell_photons=np.ascontiguousarray(cell_photons, dtype=np.float64),
@@ -154,6 +165,23 @@ class TransportInputs:
                             _p(a["line_tau0"]), _p(a["line_trans"]), n_trans, _p(a["tau_ct"]),
                             _p(a["fcorr_ct"]), lambda_lo, lambda_hi, seed, iteration,
                             _p(a["explicit"]))
+        self.pi_levels = 0
+        if photoion is not None:
+            a["pi_lambda"] = np.ascontiguousarray(photoion["lambda"], np.float64)
+            a["pi_sigma0"] = np.ascontiguousarray(photoion["sigma0"], np.float64)
+            a["pi_level"] = np.ascontiguousarray(photoion["level"], np.int32)
+            pops = np.ascontiguousarray(photoion["pops"], np.float64).reshape(self.n_cells, -1)
+            a["pi_pops"] = pops
+            self.pi_levels = len(a["pi_lambda"])
+            a["pi_absorbed"] = np.zeros((self.n_cells, self.pi_levels))
+            self.s.pi_levels = self.pi_levels
+            self.s.pi_lambda = _p(a["pi_lambda"])
+            self.s.pi_sigma0 = _p(a["pi_sigma0"])
+            self.s.pi_level = _p(a["pi_level"])
+            self.s.pi_nlev = pops.shape[1]
+            self.s.pi_pops = _p(pops)
+            self.s.pi_length = float(photoion["length"])
+            self.s.pi_absorbed = _p(a["pi_absorbed"])
 
     @property
     def n_packets(self):
@@ -176,7 +204,9 @@ def transport(inp: TransportInputs, first=0, count=None, nthreads=None, per_pack
     """Runs the oracle over packets [first, first+count).
 
     Returns dict(records=(packet, cell, line, value) structured array in packet
-    order, stats=dict, packets=[count, 11] per-packet results if per_packet).
+    order, stats=dict, packets=[count, 12] per-packet results if per_packet,
+    pi_absorbed=[C, M] photons absorbed per (cell, photoionising level) when the
+    inputs have photoionisation; the run is then serial).
     """
     if count is None:
         count = inp.n_packets - first
@@ -197,7 +227,11 @@ def transport(inp: TransportInputs, first=0, count=None, nthreads=None, per_pack
     else:
         recs = np.zeros(0, dtype=dt)
     lib().oracle_free(ptr)
-    return dict(records=recs, stats=dict(zip(STAT_NAMES, stats)), packets=pk)
+    out = dict(records=recs, stats=dict(zip(STAT_NAMES, stats)), packets=pk)
+    if inp.pi_levels:
+        out["pi_absorbed"] = inp.arrays["pi_absorbed"].copy()
+        inp.arrays["pi_absorbed"][:] = 0.0
+    return out
 
 
 def emission(inp: TransportInputs, first=0, count=None):
@@ -208,6 +242,30 @@ def emission(inp: TransportInputs, first=0, count=None):
     out = np.zeros((count, 8))
     if lib().oracle_emission(C.byref(inp.s), first, count, _p(out)) != 0:
         raise ValueError("oracle_emission: invalid input")
+    return out
+
+
+def pi_levels(inp: "NLTEInputs", ion_energy, max_per_stage=25):
+    """Photoionising levels (Sec. 2.3.1; Eq. A5): dict(level, lambda, sigma0)
+    as oracle_pi_levels selects them (oracle.h). ion_energy [S*3] erg."""
+    ie = np.ascontiguousarray(ion_energy, np.float64)
+    n = lib().oracle_pi_levels(C.byref(inp.atom), _p(ie), max_per_stage, None, None, None)
+    level = np.zeros(n, np.int32)
+    lam = np.zeros(n)
+    sig = np.zeros(n)
+    lib().oracle_pi_levels(C.byref(inp.atom), _p(ie), max_per_stage, _p(level), _p(lam), _p(sig))
+    return {"level": level, "lambda": lam, "sigma0": sig}
+
+
+def pi_rates(pi_absorbed, pops, level, n_levels, cell_volume):
+    """Photoionisation rate of each level, Gamma_PI = N_abs / (n V) (Sec.
+    2.3.1): [C, N], zero for levels that do not photoionise."""
+    ab = np.asarray(pi_absorbed, np.float64)
+    P = np.asarray(pops, np.float64).reshape(len(ab), -1)
+    out = np.zeros((len(ab), n_levels))
+    for j, lv in enumerate(level):
+        n = P[:, lv]
+        out[:, lv] = np.where(n > 0, ab[:, j] / np.where(n > 0, n, 1.0) / cell_volume, 0.0)
     return out
 
 
@@ -283,7 +341,7 @@ def rates(est, pops, atom, cell_volume):
 
 
 class NLTEInputs:
-    def __init__(self, atom, t_exp, T_e, n_e, n_species, gamma_ion, gamma_pe=None):
+    def __init__(self, atom, t_exp, T_e, n_e, n_species, gamma_ion, gamma_pe=None, gamma_pi=None):
         self.k = dict(
             off=np.ascontiguousarray(atom.species_offset, np.int32),
             ion=np.ascontiguousarray(atom.level_ion, np.int32),
@@ -299,6 +357,7 @@ class NLTEInputs:
             ns=np.ascontiguousarray(n_species, np.float64),
             gion=np.ascontiguousarray(gamma_ion, np.float64),
             gpe=None if gamma_pe is None else np.ascontiguousarray(gamma_pe, np.float64),
+            gpi=None if gamma_pi is None else np.ascontiguousarray(gamma_pi, np.float64),
         )
         k = self.k
         self.n_levels = len(k["ion"])
@@ -307,22 +366,23 @@ class NLTEInputs:
                           _p(k["g"]), len(k["A"]), _p(k["lo"]), _p(k["up"]), _p(k["A"]),
                           _p(k["lam"]), _p(k["ups"]), _p(k["alpha"]))
         self.cells = _Cells(t_exp, _p(k["T"]), _p(k["ne"]), _p(k["ns"]), _p(k["gion"]),
-                            _p(k["gpe"]))
+                            _p(k["gpe"]), _p(k["gpi"]))
 
 
-def nlte_inputs_from_workload(w, gamma_pe=None, cells=None):
+def nlte_inputs_from_workload(w, gamma_pe=None, cells=None, gamma_pi=None):
     """NLTE inputs for all cells (or the given cell indices) of a workload."""
     if cells is None:
-        sel = slice(None)
-        S = w.atom.n_species
-        return NLTEInputs(w.atom, w.t_exp, w.T_e, w.n_e, w.n_species, w.gamma_ion, gamma_pe)
+        return NLTEInputs(w.atom, w.t_exp, w.T_e, w.n_e, w.n_species, w.gamma_ion, gamma_pe,
+                          gamma_pi)
     cells = np.asarray(cells)
     S = w.atom.n_species
     T = w.atom.n_trans
+    N = w.atom.n_levels
     gpe = None if gamma_pe is None else gamma_pe.reshape(-1, T)[cells].ravel()
+    gpi = None if gamma_pi is None else gamma_pi.reshape(-1, N)[cells].ravel()
     return NLTEInputs(w.atom, w.t_exp, w.T_e[cells], w.n_e[cells],
                       w.n_species.reshape(-1, S)[cells].ravel(),
-                      w.gamma_ion.reshape(-1, S, 3)[cells].ravel(), gpe)
+                      w.gamma_ion.reshape(-1, S, 3)[cells].ravel(), gpe, gpi)
 
 
 def nlte(inp: NLTEInputs, guess=None, max_iter=200, tol=1e-12, nthreads=None, first=0,

@@ -4,7 +4,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["philox.c", "transport.c", "nlte.c", "batched.c", "emission.c"]
+SOURCES = ["philox.c", "transport.c", "nlte.c", "batched.c", "emission.c", "photoion.c"]
 LIB = os.path.join(HERE, "liboracle.so")
 
 

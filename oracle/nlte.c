@@ -57,7 +57,8 @@ static int32_t n_stages(const or_atom* a, int32_t s) {
 
 /* Every rate of species s in cell c that does not depend on the populations
  * (R[i*Ns+j], i -> j, per atom in i): collisions, photoexcitation and
- * photo-de-excitation, ionisation and recombination. The radiative decay
+ * photo-de-excitation, ionisation (the stage's rate plus each level's
+ * photoionisation rate, when given) and recombination. The radiative decay
  * A beta_S(tau(n)) is added by add_decay. */
 static void rates_without_decay(const or_atom* a, const or_cells* cl, int64_t c, int32_t s,
                                 double* R) {
@@ -90,7 +91,8 @@ static void rates_without_decay(const or_atom* a, const or_cells* cl, int64_t c,
     double rec = ne * a->ion_alpha0[s * 3 + z] * pow(T / 1e4, -0.8);
     for (int32_t i = 0; i < Ns; ++i) {
       if (a->level_ion[base + i] != z) continue;
-      R[i * Ns + gnext] += gion;
+      /* stage ionisation rate plus the level's own photoionisation (Sec. 2.3.1) */
+      R[i * Ns + gnext] += gion + (cl->gamma_pi ? cl->gamma_pi[c * a->n_levels + base + i] : 0.0);
       if (sumg == 0.0) {
         R[gnext * Ns + i] += rec;
       } else if (i == g0) {

@@ -39,18 +39,33 @@ typedef struct {
   uint64_t seed;
   int32_t iteration;
   const double* explicit_packets; /* [P*8] x,y,z,nx,ny,nz,lambda_e,w0; NULL = sampled */
+  /* Photoionisation (Sec. 2.3.1; Eq. A5), or pi_levels = 0. Level i (of
+   * oracle_pi_levels) with threshold pi_lambda[i] and threshold cross section
+   * pi_sigma0[i] absorbs along every move of the ray while the comoving
+   * wavelength is below its threshold, with population pi_pops[c*pi_nlev +
+   * pi_level[i]] (cm^-3). pi_absorbed [C*M] accumulates the photons each level
+   * absorbs in each cell; it needs nthreads == 1 (one table, packet order). */
+  int32_t pi_levels;
+  const double* pi_lambda;        /* [M] cm */
+  const double* pi_sigma0;        /* [M] cm^2 */
+  const int32_t* pi_level;        /* [M] */
+  int32_t pi_nlev;
+  const double* pi_pops;          /* [C*pi_nlev] */
+  double pi_length;               /* cm per unit of path, c t_exp */
+  double* pi_absorbed;            /* [C*M] out, accumulated */
 } or_transport;
 
-/* Per-packet results (8 doubles per packet):
+/* Per-packet results (12 doubles per packet):
  * 0 escaped weight, 1 lab wavelength lambda_L, 2 killed weight,
- * 3 absorbed photons (sum of dN), 4 absorbed comoving energy / (hc),
- * 5 adiabatic loss / (hc), 6 emitted comoving energy / (hc),
+ * 3 photons absorbed in lines (sum of dN), 4 comoving energy / (hc) absorbed
+ * in lines, 5 adiabatic loss / (hc), 6 emitted comoving energy / (hc),
  * 7 remaining comoving energy / (hc) at escape or kill,
- * 8-10 lab-frame direction (unchanged along the ray). */
-enum { OR_PKT_FIELDS = 11 };
+ * 8-10 lab-frame direction (unchanged along the ray),
+ * 11 photons absorbed by photoionisation. */
+enum { OR_PKT_FIELDS = 12 };
 /* Global stats (doubles): w_emit, w_esc, w_kill, w_abs, n_inter, n_checks,
- * n_cross, n_escaped, n_killed. */
-enum { OR_STATS = 9 };
+ * n_cross, n_escaped, n_killed, w_pi (photons absorbed by photoionisation). */
+enum { OR_STATS = 10 };
 
 /* One line interaction: packet, cell, line, photons added to est (dN / f_corr),
  * and the margin of the resonance inside its segment, min(D_k - D_entry,
@@ -100,7 +115,19 @@ typedef struct {
   const double* n_species;        /* [C*S] */
   const double* gamma_ion;        /* [C*S*3] */
   const double* gamma_pe;         /* [C*T] or NULL */
+  const double* gamma_pi;         /* [C*N] or NULL: photoionisation of each level to
+                                     the next stage's ground, s^-1, added to gamma_ion */
 } or_cells;
+
+/* ---- Photoionising levels (Sec. 2.3.1; Eq. A5) ------------------------------
+ * For every species, stages 0 and 1 below its top stage (no ionisation from
+ * the doubly ionised stage): the first max_per_stage levels of the stage, in
+ * level order, that lie below the stage's ionisation energy ion_energy[s*3+z]
+ * (erg). Writes (when not NULL) the global level, the threshold wavelength
+ * h c / (E_ion - E_i) in cm and the hydrogenic cross section at threshold
+ * 7.9e-18 (1 - E_i / E_ion)^-1/2 / (z + 1)^2 cm^2 of each; returns how many. */
+int32_t oracle_pi_levels(const or_atom* a, const double* ion_energy, int32_t max_per_stage,
+                         int32_t* level, double* lambda_thr, double* sigma0);
 
 /* Solves cells [first, first+count). pops [C*N] in: initial guess (used when
  * use_guess != 0), out: solution. status[c]: 0 converged, 2 failed, 3 empty.

@@ -20,6 +20,16 @@
  *  - the kill test compares comoving energies: w*lambda_e < 1e-6*w0*lambda_k;
  *  - axes whose wall distances tie exactly are stepped together;
  *  - the packet's position on the crossed wall is set exactly to that wall.
+ * Photoionisation (Sec. 2.3.1): every move of the ray -- to a wall, or to a
+ * line that interacts -- also passes through the continuum of the
+ * photoionising levels. Level i absorbs while the comoving wavelength is below
+ * its threshold (the move is cut where the ray redshifts past it), with
+ * tau_i = integral of sigma_i(lambda) n_i ds over that part; the move absorbs
+ * N (1 - e^-tau), tau = sum_i tau_i, shared among the levels in proportion to
+ * tau_i. Readings: sigma_i follows the ray's comoving wavelength along the
+ * move (Eq. A5's lambda^3 law integrated exactly), and after a move that ends
+ * at a wall the packet also stops once its comoving energy is below 1e-6 of
+ * its start (the rule the paper states for the ray as a whole).
  * Emission (sampled mode): cell c emits cell_packets[c] packets with ids in
  * cell-major order; packet id p draws two Philox4x64-10 blocks with counters
  * (p, iteration, 0, 0) and (p, iteration, 1, 0) under key (seed, 3): uniform
@@ -136,7 +146,48 @@ static void emit_explicit(const or_transport* P, int64_t p, packet0* q) {
   q->w0 = e[7];
 }
 
-/* Follows one packet; returns nothing, fills out[8], stats, records. */
+/* Integral of lambda(D)^3 dD from D_a to D_b, lambda(D) = lambda_L / (1 - D),
+ * given lambda_a = lambda(D_a), lambda_b = lambda(D_b): the antiderivative
+ * lambda_L^3 / (2 (1 - D)^2) differenced, written as
+ * (1/2) lambda_a lambda_b (lambda_a + lambda_b) (D_b - D_a), which has no
+ * cancellation for short moves. */
+static double lambda_cubed_integral(double lam_a, double lam_b, double dD) {
+  return 0.5 * lam_a * lam_b * (lam_a + lam_b) * dD;
+}
+
+/* Photoionisation over the move D_a -> D_b of the ray in cell c with w
+ * photons: returns the move's optical depth tau, sets *absorbed to
+ * w (1 - e^-tau) and adds each level's share to pi_absorbed. */
+static double photoionise(const or_transport* P, int64_t c, double lamL, double Da, double Db,
+                          double w, double* absorbed) {
+  *absorbed = 0.0;
+  if (P->pi_levels <= 0 || !(Db > Da)) return 0.0;
+  const int32_t M = P->pi_levels;
+  double tau_i[M];
+  double tau = 0.0;
+  const double lam_a = lamL / (1.0 - Da);
+  for (int32_t i = 0; i < M; ++i) {
+    tau_i[i] = 0.0;
+    const double lam_t = P->pi_lambda[i];
+    if (!(lam_a < lam_t)) continue; /* already redward of the threshold */
+    const double Dt = 1.0 - lamL / lam_t; /* where the ray reaches the threshold */
+    double lam_b, dD;
+    if (Dt < Db) { lam_b = lam_t; dD = Dt - Da; }
+    else { lam_b = lamL / (1.0 - Db); dD = Db - Da; }
+    const double n_i = P->pi_pops[c * P->pi_nlev + P->pi_level[i]];
+    const double k = n_i * P->pi_sigma0[i] / (lam_t * lam_t * lam_t);
+    tau_i[i] = k * lambda_cubed_integral(lam_a, lam_b, dD) * P->pi_length;
+    tau += tau_i[i];
+  }
+  if (!(tau > 0.0)) return 0.0;
+  const double N = w * (-expm1(-tau));
+  for (int32_t i = 0; i < M; ++i)
+    if (tau_i[i] > 0.0) P->pi_absorbed[c * M + i] += N * (tau_i[i] / tau);
+  *absorbed = N;
+  return tau;
+}
+
+/* Follows one packet; returns nothing, fills out[12], stats, records. */
 static void follow(const or_transport* P, int64_t p, const packet0* q, recbuf* rb, double* st,
                    double* out) {
   int32_t n = P->n;
@@ -148,7 +199,7 @@ static void follow(const or_transport* P, int64_t p, const packet0* q, recbuf* r
   int32_t k = first_line_above(P, q->lam_e);  /* no absorption at the emission wavelength */
   double h = 2.0 * P->beta_max / n;
   double w = q->w0, Dcur = D;
-  double e_abs = 0.0, e_adiab = 0.0, w_abs = 0.0;
+  double e_abs = 0.0, e_adiab = 0.0, w_abs = 0.0, w_pi = 0.0;
   double res[OR_PKT_FIELDS] = {0};
   res[1] = lamL;
   res[6] = q->w0 / q->lam_e;
@@ -174,6 +225,14 @@ static void follow(const or_transport* P, int64_t p, const packet0* q, recbuf* r
       if (tau > TAU_MIN) {
         st[4] += 1.0;
         e_adiab += w * (Dk - Dcur) / lamL;
+        if (P->pi_levels > 0) {
+          double Npi;
+          const double tpi = photoionise(P, c, lamL, Dcur, Dk, w, &Npi);
+          if (tpi > 0.0) {
+            w_pi += Npi;
+            w = w * exp(-tpi);
+          }
+        }
         Dcur = Dk;
         double dN = w * (-expm1(-tau));
         double m1 = Dk - D, m2 = Dexit - Dk;
@@ -192,6 +251,22 @@ static void follow(const or_transport* P, int64_t p, const packet0* q, recbuf* r
       ++k;
     }
     e_adiab += w * (Dexit - Dcur) / lamL;
+    if (P->pi_levels > 0) {
+      double Npi;
+      const double tpi = photoionise(P, c, lamL, Dcur, Dexit, w, &Npi);
+      if (tpi > 0.0) {
+        w_pi += Npi;
+        w = w * exp(-tpi);
+        /* comoving energy left at the wall against 1e-6 of the start */
+        if (w * q->lam_e * (1.0 - Dexit) < (KILL_FRAC * q->w0) * lamL) {
+          res[2] = w;
+          res[7] = w * (1.0 - Dexit) / lamL;
+          st[2] += w;
+          st[8] += 1.0;
+          goto done;
+        }
+      }
+    }
     Dcur = Dexit;
     D = Dexit;
     int out_of_grid = 0;
@@ -215,6 +290,8 @@ static void follow(const or_transport* P, int64_t p, const packet0* q, recbuf* r
   }
 done:
   st[3] += w_abs;
+  st[9] += w_pi;
+  res[11] = w_pi;
   res[3] = w_abs;
   res[4] = e_abs;
   res[5] = e_adiab;
@@ -227,6 +304,11 @@ done:
 int64_t oracle_transport(const or_transport* P, int64_t first, int64_t count, int nthreads,
                          or_record** records, double* stats, double* pkt_out) {
   if (!P || P->n <= 0 || P->n_lines < 0 || count < 0) return -1;
+  if (P->pi_levels > 0) {
+    if (!P->pi_lambda || !P->pi_sigma0 || !P->pi_level || !P->pi_pops || !P->pi_absorbed)
+      return -1;
+    nthreads = 1; /* one absorption table, filled in packet order */
+  }
   for (int32_t k = 1; k < P->n_lines; ++k)
     if (!(P->line_lambda[k] >= P->line_lambda[k - 1])) return -1;
   int64_t C = (int64_t)P->n * P->n * P->n;

@@ -36,6 +36,8 @@ SEED_BASE = 2511075390
 STREAM_GRID, STREAM_LINES, STREAM_ATOM, STREAM_PACKETS, STREAM_CELLS, STREAM_MLP = range(6)
 # Key word 1 of the per-level and per-pair draws of the batched NLTE problem.
 STREAM_BATCHED = 6
+# Key word 1 of the ionisation energies drawn for photoionisation.
+STREAM_PHOTOION = 7
 
 
 def rng(workload: int, stream: int) -> np.random.Generator:
@@ -211,6 +213,28 @@ def make_atom(workload: int, ion_levels, masses, e_max_ev, lines_available: int,
         species_mass=np.array(masses, dtype=np.float64),
     )
     return atom
+
+
+def ion_energies(workload: int, atom: Atom, chi_lo_ev: float = 0.5,
+                 chi_hi_ev: float = 2.0) -> np.ndarray:
+    """Ionisation energy (erg) of each (species, stage) [S*3], from the stage's
+    ground to the next stage's ground, for photoionisation: the stage's highest
+    level plus a binding energy log-uniform in [chi_lo_ev, chi_hi_ev] eV, so
+    that the thresholds of the stage's levels spread from the far ultraviolet
+    (the ground) into the optical and near infrared (the highest levels). The
+    top stage of each species gets 0 (no ionisation from it). Drawn from its
+    own Philox stream, so the other inputs of the workload are unchanged."""
+    g = rng(workload, STREAM_PHOTOION)
+    S = atom.n_species
+    out = np.zeros(S * 3)
+    for s in range(S):
+        b, e = atom.species_offset[s], atom.species_offset[s + 1]
+        ion = atom.level_ion[b:e]
+        top = int(ion.max())
+        for z in range(top):
+            e_top = atom.level_energy[b:e][ion == z].max()
+            out[s * 3 + z] = e_top + _log_uniform(g, chi_lo_ev, chi_hi_ev, 1)[0] * EV
+    return out
 
 
 def _finish(name, number, n, beta_max, t_exp, rho, lines_lo_A, lines_hi_A, n_lines,
