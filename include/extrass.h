@@ -88,7 +88,36 @@ typedef struct {
   int32_t n_trans;              /* T (only with tau_ct) */
   const double* tau_ct;         /* [C*T] or NULL */
   const double* fcorr_ct;       /* [C*T] or NULL (then f_corr = 1) */
+  const struct extrass_photoion* photoion;  /* host struct: photoionisation opacity of the
+                                               cells (below), or NULL for none */
 } extrass_grid;
+
+/* Photoionisation in the transport (Sec. 2.3.1; Eq. A5). M photoionising
+ * levels, numbered in order of non-decreasing threshold wavelength lambda_j;
+ * level j has the hydrogenic cross section sigma_j(lambda) = sigma0_j
+ * (lambda / lambda_j)^3 blueward of its threshold and zero redward. Every
+ * move of a packet -- to a wall, or to a line that interacts (tau > 1e-4) --
+ * passes through the continuum: level j absorbs while the comoving wavelength
+ * is below lambda_j (the move is cut where the packet redshifts past it),
+ * tau_j = a_j integral(lambda^3 ds) times `length`, a_j = n_j sigma0_j /
+ * lambda_j^3 with n_j the level's population density in the cell. The move
+ * absorbs w (1 - e^-tau), tau = sum_j tau_j, shared in proportion to tau_j,
+ * and leaves w e^-tau. After a move that ends at a wall the packet stops when
+ * its comoving energy is below 1e-6 of its start (w lambda_e < 1e-6 w0
+ * lambda_comoving), as after a line. Photons absorbed by photoionisation are
+ * counted in stats[EXTRASS_STAT_W_PI].
+ * opacity (extrass_pi_opacity writes it): per cell, 2M + 1 doubles: the
+ * suffix sums S_j = sum_{k >= j} a_k for j = 0..M (S_M = 0), then a_0..a_{M-1}
+ * (cm^-4). tally: per cell 2M doubles accumulated into: T_0..T_{M-1}, then
+ * Q_0..Q_{M-1}, such that level j absorbed a_j (sum_{k <= j} T_k + Q_j)
+ * photons s^-1 in the cell (extrass_pi_rates turns them into rates). */
+typedef struct extrass_photoion {
+  int32_t n_levels;             /* M, 1..4096 */
+  const double* lambda_thr;     /* device [M] threshold wavelengths, cm, non-decreasing */
+  const double* opacity;        /* device [C*(2M+1)] */
+  double length;                /* cm per unit of path (x = v/c): c t_exp */
+  double* tally;                /* device [C*2M], accumulated into */
+} extrass_photoion;
 
 /* Emission. Sampled mode (explicit_packets == NULL): packet ids are cell-major,
  * cell c owning ids [sum_{c'<c} cell_packets[c'], ... + cell_packets[c]).
@@ -146,6 +175,7 @@ enum {
   EXTRASS_STAT_N_KILLED = 8,
   EXTRASS_STAT_E_ESC = 9,    /* escaped weight over lab wavelength, sum of w / lambda_L
                                 (cm^-1 s^-1): h c times it is the escaping luminosity */
+  EXTRASS_STAT_W_PI = 10,    /* absorbed by photoionisation (grid.photoion) */
   EXTRASS_STAT_QUEUE_FULL = 13,  /* streamed transport: 1.0 if an octant queue overflowed */
   EXTRASS_STAT_BAD_PACKETS = 14, /* 1.0 if some packet id lay beyond the sampling plan
                                     or a packet had no wall ahead (NaN or zero direction);
@@ -241,6 +271,40 @@ int extrass_emission_plan_info(extrass_emission_plan p, int32_t* n_bins, int32_t
 int extrass_emission(extrass_handle h, extrass_emission_plan p, extrass_atom_handle atom,
                      const extrass_grid* grid, double t_exp, const double* pops,
                      double* bin_photons, double* outside, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Photoionising levels and their opacity (Sec. 2.3.1; Eq. A5). Ionisation is
+ * taken from stages 0 and 1 of each species (none from the doubly ionised
+ * stage upwards), from the first max_per_stage levels of each such stage (in
+ * level order) that lie below the stage's ionisation energy ion_energy[s*3+z]
+ * (erg, host [S*3]; from the stage's ground to the next stage's ground). Each
+ * takes the hydrogenic cross section of Eq. A5 (Verner and TOPBASE data are
+ * not used): at threshold lambda_j = h c / (E_ion - E_j),
+ * sigma0_j = 7.9e-18 (1 - E_j / E_ion)^-1/2 / (z + 1)^2 cm^2. A plan holds
+ * them in order of non-decreasing threshold (equal thresholds in level order).
+ * EXTRASS_EINVAL if no level qualifies or max_per_stage < 1. */
+typedef struct extrass_pi_ctx* extrass_pi_plan;
+int extrass_pi_plan_create(extrass_handle h, extrass_atom_handle atom, const double* ion_energy,
+                           int32_t max_per_stage, extrass_pi_plan* out);
+int extrass_pi_plan_destroy(extrass_pi_plan p);
+/* M, and (host arrays of capacity M, each may be NULL) each level's global
+ * index, threshold wavelength (cm) and sigma0 (cm^2), in the plan's order;
+ * *device_lambda (may be NULL): the plan's device copy of the thresholds,
+ * for extrass_photoion.lambda_thr (owned by the plan). */
+int extrass_pi_plan_info(extrass_pi_plan p, int32_t* n_levels, int32_t* level, double* lambda_thr,
+                         double* sigma0, const double** device_lambda);
+/* The opacity table of extrass_photoion for n_cells cells at populations
+ * pops [C*N] (cm^-3): opacity [C*(2M+1)] (device, overwritten). */
+int extrass_pi_opacity(extrass_handle h, extrass_pi_plan p, int64_t n_cells, const double* pops,
+                       double* opacity, void* stream);
+/* Photoionisation rates per atom of each level from a transport's tally:
+ * gamma_pi[c*N + i] = N_abs / (n_i V) = sigma0_j / lambda_j^3 (sum_{k <= j}
+ * T_k + Q_j) / V for the plan's level j = i, 0 for levels outside the plan
+ * (the population cancels). V as in extrass_rates, from grid (n, beta_max)
+ * and t_exp. tally [C*2M], gamma_pi [C*N] (device, overwritten). For
+ * extrass_cells.gamma_pi. */
+int extrass_pi_rates(extrass_handle h, extrass_pi_plan p, const extrass_grid* grid, double t_exp,
+                     const double* tally, double* gamma_pi, void* stream);
 
 /* ------------------------------------------------------------------------
  * Eq. A2: tau_S = (A_ul / 8 pi) (g_u / g_l) lambda^3 n_l (1 - g_l n_u / (g_u n_l)) t
@@ -349,6 +413,9 @@ typedef struct {
   const double* n_species;      /* [C*S] cm^-3 */
   const double* gamma_ion;      /* [C*S*3] s^-1, stage z -> z+1 from any level */
   const double* gamma_pe;       /* [C*T] s^-1 per lower atom, or NULL */
+  const double* gamma_pi;       /* [C*N] s^-1 per atom: photoionisation of each level to the
+                                   next stage's ground (extrass_pi_rates), added to
+                                   gamma_ion for that level; or NULL */
 } extrass_cells;
 
 typedef struct {
@@ -372,7 +439,8 @@ typedef struct {
  *   R_ul += A_ul beta_S(tau_ul(n)) + n_e q_ul + (g_l/g_u) Gamma_PE,
  *   R_lu += n_e q_lu + Gamma_PE,  q_ul = 8.629e-6 Upsilon / (g_u sqrt(T)),
  *   q_lu = q_ul (g_u/g_l) exp(-(E_u - E_l)/kT),
- *   ionisation stage z -> ground of z+1 at gamma_ion, recombination from the
+ *   ionisation stage z -> ground of z+1 at gamma_ion (plus gamma_pi of the
+ *   level when given), recombination from the
  *   ground of z+1 at n_e alpha0 (T/1e4)^-0.8, 1/3 to the ground state of z and
  *   2/3 over its excited levels by statistical weight (Appendix A.2).
  * pops [C*N]: in = guess (if use_guess), out = solution. status [C]: 0

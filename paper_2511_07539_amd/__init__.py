@@ -27,7 +27,7 @@ OK, EINVAL, ENOSPACE, EHIP, EUNSUPPORTED = 0, -1, -2, -3, -4
 STATS = 16
 PACKET_FIELDS = 8  # doubles per packet record (EXTRASS_PACKET_FIELDS)
 STAT_NAMES = ["w_emit", "w_esc", "w_kill", "w_abs", "n_inter", "n_checks", "n_cross",
-              "n_escaped", "n_killed", "e_esc"]
+              "n_escaped", "n_killed", "e_esc", "w_pi"]
 STAT_ERROR_FLAG = 15
 
 
@@ -36,7 +36,12 @@ class _Grid(C.Structure):
                 ("cell_photons", C.c_void_p), ("cell_packets", C.c_void_p),
                 ("n_lines", C.c_int32), ("line_lambda", C.c_void_p), ("line_tau0", C.c_void_p),
                 ("line_trans", C.c_void_p), ("n_trans", C.c_int32), ("tau_ct", C.c_void_p),
-                ("fcorr_ct", C.c_void_p)]
+                ("fcorr_ct", C.c_void_p), ("photoion", C.c_void_p)]
+
+
+class _Photoion(C.Structure):
+    _fields_ = [("n_levels", C.c_int32), ("lambda_thr", C.c_void_p), ("opacity", C.c_void_p),
+                ("length", C.c_double), ("tally", C.c_void_p)]
 
 
 class _SpecBins(C.Structure):
@@ -68,7 +73,7 @@ class _AtomDesc(C.Structure):
 class _Cells(C.Structure):
     _fields_ = [("n_cells", C.c_int64), ("t_exp", C.c_double), ("T_e", C.c_void_p),
                 ("n_e", C.c_void_p), ("n_species", C.c_void_p), ("gamma_ion", C.c_void_p),
-                ("gamma_pe", C.c_void_p)]
+                ("gamma_pe", C.c_void_p), ("gamma_pi", C.c_void_p)]
 
 
 class _Opts(C.Structure):
@@ -107,6 +112,12 @@ _lib.extrass_emission_plan_destroy.argtypes = [_vp]
 _lib.extrass_emission_plan_info.argtypes = [_vp, C.POINTER(C.c_int32), _vp, _vp,
                                             C.POINTER(C.c_void_p)]
 _lib.extrass_emission.argtypes = [_vp, _vp, _vp, C.POINTER(_Grid), C.c_double, _vp, _vp, _vp, _vp]
+_lib.extrass_pi_plan_create.argtypes = [_vp, _vp, _vp, C.c_int32, C.POINTER(_vp)]
+_lib.extrass_pi_plan_destroy.argtypes = [_vp]
+_lib.extrass_pi_plan_info.argtypes = [_vp, C.POINTER(C.c_int32), _vp, _vp, _vp,
+                                      C.POINTER(C.c_void_p)]
+_lib.extrass_pi_opacity.argtypes = [_vp, _vp, C.c_int64, _vp, _vp, _vp]
+_lib.extrass_pi_rates.argtypes = [_vp, _vp, C.POINTER(_Grid), C.c_double, _vp, _vp, _vp]
 _lib.extrass_line_tau.argtypes = [_vp, _vp, C.c_int64, _vp, C.c_double, _vp, _vp, _vp]
 _lib.extrass_rates.argtypes = [_vp, _vp, C.POINTER(_Grid), C.c_double, _vp, _vp, _vp, _vp]
 _lib.extrass_atom_create.argtypes = [_vp, C.POINTER(_AtomDesc), C.POINTER(_vp)]
@@ -149,7 +160,9 @@ SYMBOLS = ["extrass_create", "extrass_destroy", "extrass_error_string", "extrass
            "extrass_transport_streamed_workspace", "extrass_transport_streamed",
            "extrass_mlp_features", "extrass_spectrum", "extrass_transport_noalloc",
            "extrass_emission_plan_create", "extrass_emission_plan_destroy",
-           "extrass_emission_plan_info", "extrass_emission"]
+           "extrass_emission_plan_info", "extrass_emission", "extrass_pi_plan_create",
+           "extrass_pi_plan_destroy", "extrass_pi_plan_info", "extrass_pi_opacity",
+           "extrass_pi_rates"]
 
 
 class ExtrassError(RuntimeError):
@@ -230,12 +243,15 @@ class Grid:
         self.n_cells = self.n ** 3
         self.n_lines = int(self.line_lambda.numel())
         self.n_trans = 0 if self.tau_ct is None else self.tau_ct.numel() // self.n_cells
+        self.photoion = None  # a Photoion: the transport then also photoionises
 
     def struct(self):
+        self._pi = self.photoion.struct() if self.photoion is not None else None
         return _Grid(self.n, self.beta_max, _ptr(self.tau_scale), _ptr(self.cell_photons),
                      _ptr(self.cell_packets), self.n_lines, _ptr(self.line_lambda),
                      _ptr(self.line_tau0), _ptr(self.line_trans), self.n_trans,
-                     _ptr(self.tau_ct), _ptr(self.fcorr_ct))
+                     _ptr(self.tau_ct), _ptr(self.fcorr_ct),
+                     C.addressof(self._pi) if self._pi is not None else None)
 
 
 def grid_from_workload(w, device="cuda:0", tau_ct=None, fcorr_ct=None):
@@ -246,6 +262,81 @@ def grid_from_workload(w, device="cuda:0", tau_ct=None, fcorr_ct=None):
         line_trans = lt
     return Grid(w.n, w.beta_max, w.tau_scale, w.cell_photons, w.cell_packets, w.line_lambda,
                 w.line_tau0, device, line_trans, tau_ct, fcorr_ct)
+
+
+class PiPlan:
+    """The photoionising levels of an atom (extrass_pi_plan_create; Sec.
+    2.3.1, Eq. A5): stages 0 and 1, the first max_per_stage levels of each
+    below its ionisation energy ion_energy [S*3] (erg), in threshold order."""
+
+    def __init__(self, ctx: Context, atom, ion_energy, max_per_stage=25):
+        ie = np.ascontiguousarray(ion_energy, np.float64)
+        h = _vp()
+        ctx.check(_lib.extrass_pi_plan_create(ctx.h, atom.h, ie.ctypes.data, int(max_per_stage),
+                                              C.byref(h)), "extrass_pi_plan_create")
+        self.h = h
+        self.ctx = ctx
+        self.n_levels_atom = atom.n_levels
+        m = C.c_int32(0)
+        _lib.extrass_pi_plan_info(h, C.byref(m), None, None, None, None)
+        self.M = int(m.value)
+        self.level = np.zeros(self.M, np.int32)
+        self.lambda_thr = np.zeros(self.M)
+        self.sigma0 = np.zeros(self.M)
+        dptr = C.c_void_p()
+        _lib.extrass_pi_plan_info(h, None, self.level.ctypes.data, self.lambda_thr.ctypes.data,
+                                  self.sigma0.ctypes.data, C.byref(dptr))
+        self.device_lambda = dptr.value
+
+    def opacity(self, pops, out=None):
+        """extrass_pi_opacity: [C, 2M+1] per-cell rows from populations [C, N]."""
+        C_ = pops.numel() // self.n_levels_atom
+        if out is None:
+            out = torch.empty((C_, 2 * self.M + 1), dtype=torch.float64, device=pops.device)
+        self.ctx.check(_lib.extrass_pi_opacity(self.ctx.h, self.h, C_, _ptr(pops), _ptr(out),
+                                               _stream()), "extrass_pi_opacity")
+        return out
+
+    def rates(self, grid: "Grid", t_exp, tally, out=None):
+        """extrass_pi_rates: photoionisation rate per atom of each level [C, N]."""
+        if out is None:
+            out = torch.empty((grid.n_cells, self.n_levels_atom), dtype=torch.float64,
+                              device=tally.device)
+        g = grid.struct()
+        self.ctx.check(_lib.extrass_pi_rates(self.ctx.h, self.h, C.byref(g), float(t_exp),
+                                             _ptr(tally), _ptr(out), _stream()), "extrass_pi_rates")
+        return out
+
+    def close(self):
+        if self.h:
+            _lib.extrass_pi_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Photoion:
+    """Photoionisation for a grid's transport (extrass_photoion): the plan's
+    thresholds, an opacity table and a tally [C, 2M] the transport adds into
+    (zeroed here). Set grid.photoion to it."""
+
+    LIGHT = 2.99792458e10
+
+    def __init__(self, plan: PiPlan, opacity, t_exp, tally=None):
+        self.plan = plan
+        self.opacity = opacity
+        self.length = self.LIGHT * float(t_exp)
+        C_ = opacity.shape[0]
+        self.tally = (torch.zeros((C_, 2 * plan.M), dtype=torch.float64, device=opacity.device)
+                      if tally is None else tally)
+
+    def struct(self):
+        return _Photoion(self.plan.M, self.plan.device_lambda, _ptr(self.opacity), self.length,
+                         _ptr(self.tally))
 
 
 def transport(ctx: Context, grid: Grid, seed, lambda_lo, lambda_hi, n_packets, first_packet=0,
@@ -497,18 +588,21 @@ def rates(ctx: Context, atom: Atom, grid: Grid, t_exp, est, pops, out=None):
 
 
 class Cells:
-    def __init__(self, t_exp, T_e, n_e, n_species, gamma_ion, gamma_pe=None, device="cuda:0"):
+    def __init__(self, t_exp, T_e, n_e, n_species, gamma_ion, gamma_pe=None, device="cuda:0",
+                 gamma_pi=None):
         self.t_exp = float(t_exp)
         self.T_e = _dev(T_e, torch.float64, device)
         self.n_e = _dev(n_e, torch.float64, device)
         self.n_species = _dev(n_species, torch.float64, device)
         self.gamma_ion = _dev(gamma_ion, torch.float64, device)
         self.gamma_pe = _dev(gamma_pe, torch.float64, device)
+        self.gamma_pi = _dev(gamma_pi, torch.float64, device)
         self.n_cells = int(self.T_e.numel())
 
     def struct(self):
         return _Cells(self.n_cells, self.t_exp, _ptr(self.T_e), _ptr(self.n_e),
-                      _ptr(self.n_species), _ptr(self.gamma_ion), _ptr(self.gamma_pe))
+                      _ptr(self.n_species), _ptr(self.gamma_ion), _ptr(self.gamma_pe),
+                      _ptr(self.gamma_pi))
 
 
 def cells_from_workload(w, gamma_pe=None, device="cuda:0", cells=None):

@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libextrass.so")
 OBJ = os.path.join(HERE, "_build")
 SOURCES = ["atom.hip", "transport.hip", "spectrum.hip", "nlte.hip", "nlte_blocks.hip", "nlte_whole.hip", "mlp.hip",
-           "batched.hip", "emission.hip"]
+           "batched.hip", "emission.hip", "photoion.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -170,6 +170,8 @@ extern "C" int extrass_atom_create(extrass_handle h, const extrass_atom_desc* d,
     a->maxLine = std::max(a->maxLine, (int)d->trans_line[t]);
   }
   a->lam_host.assign(d->trans_lambda, d->trans_lambda + T);
+  a->lv_ion_host.assign(d->level_ion, d->level_ion + N);
+  a->lv_E_host.assign(d->level_energy, d->level_energy + N);
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
     return species_of(d->trans_lower[x]) < species_of(d->trans_lower[y]);
   });

@@ -24,6 +24,8 @@ struct extrass_atom_ctx {
   std::vector<int> off;   // host copy of species_offset
   std::vector<int> toff;  // host: transitions of species s are [toff[s], toff[s+1])
   std::vector<double> lam_host;  // host copy of the transition wavelengths (caller's order)
+  std::vector<int> lv_ion_host;   // host copy of each level's ion stage
+  std::vector<double> lv_E_host;  // host copy of each level's energy above its stage's ground
   struct Dev {
     int32_t* off = nullptr;       // [S+1]
     int32_t* toff = nullptr;      // [S+1]

@@ -74,6 +74,7 @@ extern "C" int extrass_nlte_solve(extrass_handle h, extrass_atom_handle a, const
   A.n_species = cl->n_species;
   A.gamma_ion = cl->gamma_ion;
   A.gamma_pe = cl->gamma_pe;
+  A.gamma_pi = cl->gamma_pi;
   A.max_iter = o->max_iter;
   A.tol = o->tol;
   A.use_guess = o->use_guess;

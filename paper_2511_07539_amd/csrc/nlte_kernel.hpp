@@ -63,6 +63,7 @@ struct NArgs {
   const double* n_species;
   const double* gamma_ion;
   const double* gamma_pe;
+  const double* gamma_pi;  // [C*N] photoionisation per level, or NULL
   int max_iter;
   double tol;
   int use_guess;
@@ -163,7 +164,9 @@ __device__ __forceinline__ void assemble(const NArgs& A, const Sys& y, double* G
   if (lane < Ns && y.gnext >= 0) {
     const double rs = rowscale ? n_mine : 1.0;
     const double rsg = rowscale ? nb[y.gnext] : 1.0;
-    myrow[y.gnext] += rs * y.gion[y.z];
+    // the stage's ionisation rate plus the level's photoionisation rate
+    const double gpi = A.gamma_pi ? A.gamma_pi[y.c * A.N + y.base + lane] : 0.0;
+    myrow[y.gnext] += rs * (y.gion[y.z] + gpi);
     G[gat(rt, y.gnext, lane)] += rsg * y.rec[y.z] * y.share;
   }
   __syncthreads();

@@ -101,6 +101,13 @@ struct TArgs {
   uint8_t* touched;          // [Coct] rows that received an estimator this visit
   double* gdirect;           // octant mode without a table: [C*T] sums of dN / f_corr per
                              // (cell, atom transition); other lines are not recorded
+  // photoionisation (the PI kernels): M thresholds, per-cell opacity rows and
+  // tally rows (the layout of extrass_photoion), cm per unit of path
+  int pi_M;
+  const double* pi_lam;
+  const double* pi_opac;
+  double* pi_tally;
+  double pi_len;
 };
 
 // A packet in flight between octants: the whole state after a wall crossing.
@@ -361,6 +368,11 @@ struct Packet {
   int k;
   bool have_exit;
   bool bad;
+  // photoionisation (PI kernels only): D where the continuum absorption last
+  // stopped, the first threshold redward of the comoving wavelength there,
+  // and the photons absorbed
+  double Dp, wpi;
+  int jpi;
 };
 
 // The record of line k, or an empty one past the red end of the list.
@@ -374,9 +386,9 @@ __device__ __forceinline__ LineRec line_rec(const TArgs& A, int k) {
 }
 
 // Per-packet record at the stop: escaped weight, lab wavelength, weight at a
-// kill, absorbed photons, the direction (lab frame; unchanged along the ray),
-// and a zero.
-template <class G>
+// kill, photons absorbed in lines, the direction (lab frame; unchanged along
+// the ray), and the photons absorbed by photoionisation (0 without it).
+template <class G, bool PI = false>
 __device__ __forceinline__ void put_record(double* o, const Packet<G>& q, double w_esc, double w_kill) {
   o[0] = w_esc;
   o[1] = q.lamL;
@@ -385,7 +397,7 @@ __device__ __forceinline__ void put_record(double* o, const Packet<G>& q, double
   o[4] = (double)q.d[0];
   o[5] = (double)q.d[1];
   o[6] = (double)q.d[2];
-  o[7] = 0.0;
+  o[7] = PI ? q.wpi : 0.0;
 }
 
 template <class G>
@@ -509,7 +521,7 @@ __device__ void emit(const TArgs& A, int64_t p, Packet<G>& q) {
 }
 
 struct Tally {
-  double w_emit = 0, w_esc = 0, w_kill = 0, w_abs = 0;
+  double w_emit = 0, w_esc = 0, w_kill = 0, w_abs = 0, w_pi = 0;
   double e_esc = 0;  // escaped weight over lab wavelength: h c e_esc is the escaping erg s^-1
   uint32_t inter = 0, checks = 0, cross = 0, escaped = 0, killed = 0;  // per lane
   bool bad = false;
@@ -568,10 +580,74 @@ __device__ int64_t resume(const QPk& r, Packet<G>& q) {
   return r.pid;
 }
 
+// First photoionisation threshold above the comoving wavelength lam.
+__device__ __forceinline__ int pi_first_above(const TArgs& A, double lam) {
+  int lo = 0, hi = A.pi_M;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (A.pi_lam[mid] > lam) hi = mid; else lo = mid + 1;
+  }
+  return lo;
+}
+
+// Integral of lambda^3 dD over a move D_a -> D_b of the ray, lambda(D) =
+// lambda_L / (1 - D), lambda_a and lambda_b its ends: (1/2) lambda_a lambda_b
+// (lambda_a + lambda_b) (D_b - D_a), the antiderivative lambda_L^3 / (2 (1 -
+// D)^2) differenced without cancellation.
+__device__ __forceinline__ double lam3_integral(double la, double lb, double dD) {
+  return 0.5 * la * lb * (la + lb) * dD;
+}
+
+// Photoionisation over the move of the packet from q.Dp to Db in cell c (Sec.
+// 2.3.1): the levels whose thresholds lie redward of the comoving wavelength
+// absorb, those the packet redshifts past during the move only up to where it
+// reaches them. Levels absorbing over the whole move share the suffix sum
+// S_jb of the cell's opacity row; the cut ones (rare) are added one by one.
+// Returns the move's optical depth (0: nothing absorbed).
+template <class G>
+__device__ __forceinline__ double pi_move(const TArgs& A, Packet<G>& q, int64_t c, double Db,
+                                          Tally& t) {
+  const double Da = q.Dp;
+  q.Dp = Db;
+  const int M = A.pi_M;
+  if (!(Db > Da) || q.jpi >= M) return 0.0;
+  const double lamL = q.lamL;
+  const double la = lamL / (1.0 - Da);
+  int j = q.jpi;
+  while (j < M && A.pi_lam[j] <= la) ++j;
+  const double lb = lamL / (1.0 - Db);
+  int jb = j;
+  while (jb < M && A.pi_lam[jb] < lb) ++jb;
+  q.jpi = jb;
+  if (j >= M) return 0.0;
+  const double* row = A.pi_opac + c * (2 * M + 1);
+  const double full = lam3_integral(la, lb, Db - Da) * A.pi_len;
+  const double Sjb = jb < M ? row[jb] : 0.0;
+  double tau = Sjb * full;
+  for (int i = j; i < jb; ++i) {
+    const double li = A.pi_lam[i];
+    tau += row[M + 1 + i] * (lam3_integral(la, li, (1.0 - lamL / li) - Da) * A.pi_len);
+  }
+  if (!(tau > 0.0)) return 0.0;
+  const double Nabs = q.w * (-expm1(-tau));
+  const double r = Nabs / tau;
+  double* tl = A.pi_tally + c * 2 * M;
+  if (jb < M && Sjb > 0.0) atomicAdd(tl + jb, r * full);
+  for (int i = j; i < jb; ++i) {
+    const double li = A.pi_lam[i];
+    if (row[M + 1 + i] > 0.0)
+      atomicAdd(tl + M + i, r * (lam3_integral(la, li, (1.0 - lamL / li) - Da) * A.pi_len));
+  }
+  q.w = q.w * exp(-tau);
+  q.wpi += Nabs;
+  t.w_pi += Nabs;
+  return tau;
+}
+
 // Three waves per SIMD: the kernel is bound by the latency of its gathers and
 // scattered atomics, and the third wave (a few dwords of rarely used state
 // spilled) is worth more than the spill.
-template <class G, bool RAYS>
+template <class G, bool RAYS, bool PI>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_transport(TArgs A) {
   const int lane = threadIdx.x & 63;
   Packet<G> q;
@@ -614,6 +690,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
           if (A.oct >= 0 && idx >= A.n_emit) {
             pid = resume<G>(A.inbox[idx - A.n_emit], q);
             nxt = line_rec(A, q.k);
+            if constexpr (PI) {  // absorbed up to the wall it came through
+              q.Dp = (double)q.D;
+              q.jpi = pi_first_above(A, q.lamL / (1.0 - q.Dp));
+              q.wpi = 0.0;
+            }
           } else {  // one emission site for both modes keeps the register peak down
             const int64_t p = A.oct < 0 ? A.first + idx : octant_packet(A, idx);
             emit<G, RAYS>(A, p, q);
@@ -626,6 +707,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
               pid = p;
               t.w_emit += q.w0;
               nxt = line_rec(A, q.k);
+              if constexpr (PI) {
+                q.Dp = (double)q.D;
+                q.jpi = pi_first_above(A, q.lam_e);
+                q.wpi = 0.0;
+              }
             }
           }
         } else if (exhausted) {
@@ -645,7 +731,21 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     // order of events of each packet is unchanged.
     bool stop = false;
     bool line_event = q.have_exit && q.k < A.L && static_cast<G>(1.0 - q.lamL * nxt.inv_lam) <= q.Dexit;
-    if (q.have_exit && !line_event) {
+    if constexpr (PI) {
+      if (q.have_exit && !line_event) {
+        // the continuum up to the wall, in the cell being left; then the
+        // 1e-6 rule on the comoving energy left there
+        const int64_t c = q.ci[0] + (int64_t)A.n * (q.ci[1] + (int64_t)A.n * q.ci[2]);
+        const double Db = (double)q.Dexit;
+        if (pi_move<G>(A, q, c, Db, t) > 0.0 && q.w * q.lam_e * (1.0 - Db) < (kKillFrac * q.w0) * q.lamL) {
+          t.w_kill += q.w;
+          t.killed++;
+          if (A.pk_out) put_record<G, PI>(A.pk_out + kPkFields * (pid - A.first), q, 0.0, q.w);
+          stop = true;
+        }
+      }
+    }
+    if (q.have_exit && !line_event && !stop) {
       bool out = false;
       for (int a = 0; a < 3; ++a) {
         if (q.dist[a] == q.smin) {
@@ -667,7 +767,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
         t.w_esc += q.w;
         t.e_esc += q.w / q.lamL;
         t.escaped++;
-        if (A.pk_out) put_record<G>(A.pk_out + kPkFields * (pid - A.first), q, q.w, 0.0);
+        if (A.pk_out) put_record<G, PI>(A.pk_out + kPkFields * (pid - A.first), q, q.w, 0.0);
         stop = true;
       } else {
         t.cross++;
@@ -728,6 +828,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
       if (tau > kTauMin) {
         t.inter++;
         const double lam_k = A.lam[k];
+        // the continuum up to the resonance, then the line
+        if constexpr (PI) pi_move<G>(A, q, c, 1.0 - q.lamL / lam_k, t);
         const double dN = q.w * (-expm1(-tau));
         q.wabs += dN;
         q.w = q.w * exp(-tau);
@@ -740,7 +842,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
         if (q.w * q.lam_e < (kKillFrac * q.w0) * lam_k) {
           t.w_kill += q.w;
           t.killed++;
-          if (A.pk_out) put_record<G>(A.pk_out + kPkFields * (pid - A.first), q, 0.0, q.w);
+          if (A.pk_out) put_record<G, PI>(A.pk_out + kPkFields * (pid - A.first), q, 0.0, q.w);
           stop = true;
         }
       }
@@ -752,10 +854,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
   }
 
   // ---- per-wave reduction of the tallies, one atomic per wave and field
-  double v[10] = {t.w_emit, t.w_esc, t.w_kill, t.w_abs, (double)t.inter, (double)t.checks,
-                  (double)t.cross, (double)t.escaped, (double)t.killed, t.e_esc};
+  double v[11] = {t.w_emit, t.w_esc, t.w_kill, t.w_abs, (double)t.inter, (double)t.checks,
+                  (double)t.cross, (double)t.escaped, (double)t.killed, t.e_esc, t.w_pi};
 #pragma unroll
-  for (int f = 0; f < 10; ++f) {
+  for (int f = 0; f < (PI ? 11 : 10); ++f) {
     double s = wave_sum(v[f]);
     if (lane == 0 && s != 0.0) atomicAdd(A.stats + f, s);
   }
@@ -823,6 +925,41 @@ static size_t ws_layout(const extrass_grid* g, const extrass_source* s, Transpor
   return cv.used + 256;
 }
 
+// Photoionisation fields of A from the grid's photoion (none when NULL);
+// false when they are invalid.
+static bool set_photoion(const extrass_grid* g, TArgs& A) {
+  const extrass_photoion* p = g->photoion;
+  A.pi_M = 0;
+  if (!p) return true;
+  if (p->n_levels < 1 || p->n_levels > 4096 || !p->lambda_thr || !p->opacity || !p->tally ||
+      !(p->length > 0.0))
+    return false;
+  A.pi_M = p->n_levels;
+  A.pi_lam = p->lambda_thr;
+  A.pi_opac = p->opacity;
+  A.pi_tally = p->tally;
+  A.pi_len = p->length;
+  return true;
+}
+
+// The transport kernel for the geometry precision, emission kind and
+// photoionisation.
+static void launch_transport(bool fp32, bool rays, bool pi, unsigned blocks, hipStream_t st,
+                             const TArgs& A) {
+  const dim3 g(blocks), b(kBlock);
+  if (pi) {
+    if (rays && fp32) hipLaunchKernelGGL((k_transport<float, true, true>), g, b, 0, st, A);
+    else if (rays) hipLaunchKernelGGL((k_transport<double, true, true>), g, b, 0, st, A);
+    else if (fp32) hipLaunchKernelGGL((k_transport<float, false, true>), g, b, 0, st, A);
+    else hipLaunchKernelGGL((k_transport<double, false, true>), g, b, 0, st, A);
+  } else {
+    if (rays && fp32) hipLaunchKernelGGL((k_transport<float, true, false>), g, b, 0, st, A);
+    else if (rays) hipLaunchKernelGGL((k_transport<double, true, false>), g, b, 0, st, A);
+    else if (fp32) hipLaunchKernelGGL((k_transport<float, false, false>), g, b, 0, st, A);
+    else hipLaunchKernelGGL((k_transport<double, false, false>), g, b, 0, st, A);
+  }
+}
+
 extern "C" size_t extrass_transport_workspace(const extrass_grid* g, const extrass_source* s) {
   if (!g || !s || g->n <= 0 || s->n_packets < 0) return 0;
   return ws_layout(g, s, nullptr, nullptr);
@@ -849,6 +986,8 @@ extern "C" int extrass_transport(extrass_handle h, const extrass_grid* g, const 
     return fail(h, EXTRASS_EINVAL, "extrass_transport: bad deterministic rays");
   if (!s->explicit_packets && !rays && (!g->cell_packets || !g->cell_photons))
     return fail(h, EXTRASS_EINVAL, "extrass_transport: sampled mode needs cell_packets/photons");
+  TArgs A{};
+  if (!set_photoion(g, A)) return fail(h, EXTRASS_EINVAL, "extrass_transport: bad photoion");
   TransportWs tw;
   const size_t need = ws_layout(g, s, &tw, ws);
   if (ws_bytes < need) return fail(h, EXTRASS_ENOSPACE, "extrass_transport: workspace too small");
@@ -884,7 +1023,6 @@ extern "C" int extrass_transport(extrass_handle h, const extrass_grid* g, const 
   EXTRASS_HIP_TRY(h, hipGetLastError());
   if (s->n_packets == 0) return EXTRASS_OK;
 
-  TArgs A{};
   A.n = g->n;
   A.beta = g->beta_max;
   A.h = 2.0 * g->beta_max / g->n;
@@ -930,14 +1068,7 @@ extern "C" int extrass_transport(extrass_handle h, const extrass_grid* g, const 
   const int64_t max_blocks = (s->n_packets + kBlock - 1) / kBlock;
   if (blocks > max_blocks) blocks = max_blocks;
   if (blocks < 1) blocks = 1;
-  if (rays && s->geometry_fp32)
-    hipLaunchKernelGGL((k_transport<float, true>), dim3((unsigned)blocks), dim3(kBlock), 0, st, A);
-  else if (rays)
-    hipLaunchKernelGGL((k_transport<double, true>), dim3((unsigned)blocks), dim3(kBlock), 0, st, A);
-  else if (s->geometry_fp32)
-    hipLaunchKernelGGL((k_transport<float, false>), dim3((unsigned)blocks), dim3(kBlock), 0, st, A);
-  else
-    hipLaunchKernelGGL((k_transport<double, false>), dim3((unsigned)blocks), dim3(kBlock), 0, st, A);
+  launch_transport(s->geometry_fp32 != 0, rays != nullptr, A.pi_M > 0, (unsigned)blocks, st, A);
   EXTRASS_HIP_TRY(h, hipGetLastError());
   return EXTRASS_OK;
 }
@@ -1038,6 +1169,8 @@ extern "C" int extrass_transport_streamed(extrass_handle h, const extrass_grid* 
                 "extrass_transport_streamed: a transition's line index is beyond the grid's lines");
   const double cell_volume = atom ? extrass::cell_volume(g->n, g->beta_max, t_exp) : 0.0;
   if (queue_capacity <= 0) return fail(h, EXTRASS_EINVAL, "extrass_transport_streamed: queue capacity");
+  TArgs A{};
+  if (!set_photoion(g, A)) return fail(h, EXTRASS_EINVAL, "extrass_transport_streamed: bad photoion");
   StreamWs w = stream_layout(g, queue_capacity, ws);
   if (ws_bytes < w.need) return fail(h, EXTRASS_ENOSPACE, "extrass_transport_streamed: workspace too small");
 
@@ -1087,7 +1220,6 @@ extern "C" int extrass_transport_streamed(extrass_handle h, const extrass_grid* 
   if (total != s->n_packets)
     return fail(h, EXTRASS_EINVAL, "extrass_transport_streamed: n_packets differs from the plan");
 
-  TArgs A{};
   A.n = n;
   A.beta = g->beta_max;
   A.h = 2.0 * g->beta_max / n;
@@ -1149,10 +1281,7 @@ extern "C" int extrass_transport_streamed(extrass_handle h, const extrass_grid* 
       int64_t blocks = (int64_t)h->num_cus * 8;
       const int64_t max_blocks = (A.count + kBlock - 1) / kBlock;
       if (blocks > max_blocks) blocks = max_blocks;
-      if (s->geometry_fp32)
-        hipLaunchKernelGGL((k_transport<float, false>), dim3((unsigned)blocks), dim3(kBlock), 0, st, A);
-      else
-        hipLaunchKernelGGL((k_transport<double, false>), dim3((unsigned)blocks), dim3(kBlock), 0, st, A);
+      launch_transport(s->geometry_fp32 != 0, false, A.pi_M > 0, (unsigned)blocks, st, A);
       EXTRASS_HIP_TRY(h, hipGetLastError());
       if (!direct)
         hipLaunchKernelGGL(k_octant_flush, dim3((unsigned)Co), dim3(256), 0, st, est_octant,
