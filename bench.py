@@ -230,6 +230,8 @@ def main():
     if not args.no_extras:
         out["deterministic_rays"] = bench_rays(ex, ctx, w50)
         torch.cuda.empty_cache()
+        out["photoionisation"] = bench_photoion(ex, ctx, w50)
+        torch.cuda.empty_cache()
         out["spectrum"] = bench_spectrum(ex, ctx, w50)
         torch.cuda.empty_cache()
         out["batched_nlte"] = bench_batched(ex, ctx)
@@ -406,6 +408,68 @@ def bench_clumpy50(ex, ctx, w, params, norm, args):
                               "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                               "frac": flops / (parts["nlte"] * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
                               "algorithmic_flops": flops}}
+
+
+def bench_photoion(ex, ctx, w):
+    """Photoionisation in the transport (Sec. 2.3.1) on the 50^3 workload at
+    its cold-start populations: the 70 photoionising levels of the two species
+    (stages 0 and 1, hydrogenic cross sections, synthetic ionisation energies),
+    the continuum opacity table, the 1e7-packet transport with and without the
+    continuum (FP32 geometry, the atom's lines at Eq. A2 opacities), and the
+    per-level rates; HIP events, median of 5."""
+    import numpy as np
+    import torch
+    import synth
+    dev = "cuda:0"
+    atom = ex.Atom(ctx, w.atom)
+    cold, _, _ = ex.nlte_solve(ctx, atom, ex.cells_from_workload(w, device=dev), max_iter=0)
+    tau, fc = ex.line_tau(ctx, atom, cold, w.t_exp)
+    grid = ex.grid_from_workload(w, device=dev, tau_ct=tau, fcorr_ct=fc)
+    plan = ex.PiPlan(ctx, atom, synth.ion_energies(w.number, w.atom), 25)
+    opac = plan.opacity(cold)
+    photo = ex.Photoion(plan, opac, w.t_exp)
+    est = torch.empty((w.n_cells, w.n_lines), dtype=torch.float64, device=dev)
+    stats = torch.empty(ex.STATS, dtype=torch.float64, device=dev)
+    gpi = torch.empty((w.n_cells, w.atom.n_levels), dtype=torch.float64, device=dev)
+    s = torch.cuda.current_stream()
+    res = {}
+    for name, on in (("plain", False), ("photoion", True)):
+        grid.photoion = photo if on else None
+        times, topac, trates = [], [], []
+        for _ in range(6):
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+            e[0].record(s)
+            if on:
+                plan.opacity(cold, out=opac)
+                photo.tally.zero_()
+            e[1].record(s)
+            ex.transport(ctx, grid, w.seed, w.lambda_lo, w.lambda_hi, w.n_packets,
+                         geometry_fp32=True, est=est, stats=stats)
+            e[2].record(s)
+            if on:
+                plan.rates(grid, w.t_exp, photo.tally, out=gpi)
+            e[3].record(s)
+            torch.cuda.synchronize()
+            topac.append(e[0].elapsed_time(e[1]))
+            times.append(e[1].elapsed_time(e[2]))
+            trates.append(e[2].elapsed_time(e[3]))
+        sd = ex.stats_dict(stats)
+        res[name] = {"ms_transport": float(np.median(times[1:])),
+                     "interactions": sd["n_inter"], "crossings": sd["n_cross"],
+                     "photoionised_fraction": sd["w_pi"] / sd["w_emit"],
+                     "line_absorbed_fraction": sd["w_abs"] / sd["w_emit"],
+                     "escaped_fraction": sd["w_esc"] / sd["w_emit"]}
+        if on:
+            res[name]["ms_opacity_table"] = float(np.median(topac[1:]))
+            res[name]["ms_rates"] = float(np.median(trates[1:]))
+    grid.photoion = None
+    g = gpi.cpu().numpy()
+    res.update({"workload": w.name + " (cold-start populations)", "levels": plan.M,
+                "threshold_range_A": [float(plan.lambda_thr.min() * 1e8),
+                                      float(plan.lambda_thr.max() * 1e8)],
+                "rate_range_s": [float(g[g > 0].min()), float(g.max())] if (g > 0).any() else None,
+                "slowdown": res["photoion"]["ms_transport"] / res["plain"]["ms_transport"]})
+    return res
 
 
 def bench_rays(ex, ctx, w, n_rays=2_000_000_000):

@@ -23,9 +23,9 @@ import time
 import numpy as np
 import torch
 
-from . import (Atom, Cells, Context, EmissionPlan, cells_from_workload, emission,
-               grid_from_workload, line_tau, nlte_solve, nlte_warm_start, rates, stats_dict,
-               transport_rays, transport_streamed)
+from . import (Atom, Cells, Context, EmissionPlan, Photoion, PiPlan, cells_from_workload,
+               emission, grid_from_workload, line_tau, nlte_solve, nlte_warm_start, rates,
+               stats_dict, transport_rays, transport_streamed)
 
 HC = 6.62607015e-27 * 2.99792458e10  # h c, erg cm
 
@@ -35,10 +35,14 @@ class GlobalLoop:
 
     tol is the population accuracy each NLTE solve runs to; the streamed
     transport sums the rates per interaction (no octant estimator table)
-    unless octant_table is set."""
+    unless octant_table is set. With ion_energy [S*3] (erg) the transport also
+    photoionises (Sec. 2.3.1): each iteration builds the continuum opacity from
+    the current populations, and the NLTE solve takes the photoionisation
+    rates the transport measured."""
 
     def __init__(self, ctx: Context, w, device="cuda:0", geometry_fp32=True, queue_capacity=None,
-                 max_iter=200, tol=1e-10, warm_budget=30, octant_table=False):
+                 max_iter=200, tol=1e-10, warm_budget=30, octant_table=False, ion_energy=None,
+                 pi_levels_per_stage=25):
         self.ctx, self.w, self.device = ctx, w, device
         self.geometry_fp32, self.queue_capacity = geometry_fp32, queue_capacity
         self.max_iter, self.tol, self.warm_budget = max_iter, tol, warm_budget
@@ -47,12 +51,23 @@ class GlobalLoop:
         self.cells0 = cells_from_workload(w, device=device)
         C, T, N = w.n_cells, w.atom.n_trans, w.atom.n_levels
         self.gamma = torch.zeros((C, T), dtype=torch.float64, device=device)
+        self.pi_plan = None
+        self.gamma_pi = None
+        if ion_energy is not None:
+            self.pi_plan = PiPlan(ctx, self.atom, ion_energy, pi_levels_per_stage)
+            self.gamma_pi = torch.zeros((C, N), dtype=torch.float64, device=device)
         self.cells = Cells(w.t_exp, self.cells0.T_e, self.cells0.n_e, self.cells0.n_species,
-                           self.cells0.gamma_ion, self.gamma, device=device)
+                           self.cells0.gamma_ion, self.gamma, device=device,
+                           gamma_pi=self.gamma_pi)
         self.deposition = torch.as_tensor(w.deposition, device=device)
         tau = torch.empty((C, T), dtype=torch.float64, device=device)
         self.grid = grid_from_workload(w, device=device, tau_ct=tau, fcorr_ct=torch.empty_like(tau))
         del tau
+        if self.pi_plan is not None:
+            M = self.pi_plan.M
+            self.grid.photoion = Photoion(
+                self.pi_plan, torch.empty((C, 2 * M + 1), dtype=torch.float64, device=device),
+                w.t_exp)
         self.pops = torch.empty((C, N), dtype=torch.float64, device=device)
         self.new = torch.empty_like(self.pops)
         self.status = torch.empty(C, dtype=torch.int32, device=device)
@@ -83,12 +98,18 @@ class GlobalLoop:
         rec(0)
         line_tau(self.ctx, self.atom, self.pops, w.t_exp, tau=self.grid.tau_ct,
                  fcorr=self.grid.fcorr_ct)
+        pi = self.grid.photoion
+        if pi is not None:
+            self.pi_plan.opacity(self.pops, out=pi.opacity)
+            pi.tally.zero_()
         rec(1)
         transport_streamed(self.ctx, self.grid, w.seed, w.lambda_lo, w.lambda_hi, w.n_packets,
                            atom=self.atom, pops=self.pops, t_exp=w.t_exp, iteration=k,
                            geometry_fp32=self.geometry_fp32, est_octant=self.est_oct,
                            gamma=self.gamma, stats=self.stats,
                            queue_capacity=self.queue_capacity, octant_table=self.octant_table)
+        if pi is not None:
+            self.pi_plan.rates(self.grid, w.t_exp, pi.tally, out=self.gamma_pi)
         rec(2)
         nlte_solve(self.ctx, self.atom, self.cells, max_iter=self.max_iter, tol=self.tol,
                    guess=self.pops, warm_budget=warm_budget, pops=self.new, status=self.status,
@@ -126,6 +147,7 @@ class GlobalLoop:
         return {"iteration": k + 1, "ms_line_tau": ev[0].elapsed_time(ev[1]),
                 "ms_transport": ev[1].elapsed_time(ev[2]), "ms_nlte": ev[2].elapsed_time(ev[3]),
                 "interactions": sd["n_inter"], "escaped_fraction": sd["w_esc"] / sd["w_emit"],
+                "photoionised_fraction": sd["w_pi"] / sd["w_emit"],
                 "cells_converged": int(ok.sum()), "fallbacks": int((st == 1).sum()),
                 "nlte_iters_mean": float(self.iters.float().mean()),
                 "max_rel_change": float(d.max().item()) if d.numel() else None,
@@ -161,8 +183,14 @@ class RayLoop:
         C, T = w.n_cells, w.atom.n_trans
         self.cells0 = cells_from_workload(w, device=device)
         self.gamma = torch.zeros((C, T), dtype=torch.float64, device=device)
+        self.pi_plan = None
+        self.gamma_pi = None
+        if ion_energy is not None:
+            self.pi_plan = PiPlan(ctx, self.atom, ion_energy, pi_levels_per_stage)
+            self.gamma_pi = torch.zeros((C, N), dtype=torch.float64, device=device)
         self.cells = Cells(w.t_exp, self.cells0.T_e, self.cells0.n_e, self.cells0.n_species,
-                           self.cells0.gamma_ion, self.gamma, device=device)
+                           self.cells0.gamma_ion, self.gamma, device=device,
+                           gamma_pi=self.gamma_pi)
         tau = torch.empty((C, T), dtype=torch.float64, device=device)
         self.grid = grid_from_workload(w, device=device, tau_ct=tau, fcorr_ct=torch.empty_like(tau))
         self.est = torch.empty((C, w.n_lines), dtype=torch.float64, device=device)
@@ -235,12 +263,12 @@ class RayLoop:
 
 def run(ctx: Context, w, iterations=5, params=None, norm=None, warm_budget=30, geometry_fp32=True,
         queue_capacity=None, max_iter=200, tol=1e-10, device="cuda:0", log=None,
-        octant_table=False):
+        octant_table=False, ion_energy=None):
     """Returns (pops [C, N], status [C], history) of `iterations` global
     iterations over workload w (see GlobalLoop)."""
     loop = GlobalLoop(ctx, w, device=device, geometry_fp32=geometry_fp32,
                       queue_capacity=queue_capacity, max_iter=max_iter, tol=tol,
-                      warm_budget=warm_budget, octant_table=octant_table)
+                      warm_budget=warm_budget, octant_table=octant_table, ion_energy=ion_energy)
     pops, status, hist = loop.run(iterations, params, norm, log=log)
     return pops.clone(), status.clone(), hist
 

@@ -58,3 +58,57 @@ def test_two_global_iterations_match_oracle_loop():
     rel = np.max(np.abs(g[pos] - ref[pos]) / ref[pos])
     say(f"populations after 2 iterations: max rel {rel:.2e}")
     assert rel <= 1e-8
+
+
+def test_two_global_iterations_with_photoionisation_match_oracle_loop():
+    """The same loop with photoionisation (Sec. 2.3.1): each side builds the
+    continuum opacity from its own populations, and its NLTE solve takes the
+    photoionisation rates its transport measured."""
+    import paper_2511_07539_amd as ex
+    from paper_2511_07539_amd import globalloop
+    ctx = ex.Context(0)
+    w = synth.clumpy(n=16, n_lines=1500, n_packets=200_000, number=2)
+    ie = synth.ion_energies(2, w.atom)
+    say("case: two global iterations with photoionisation, clumpy 16^3, streamed FP64")
+    pops, status, hist = globalloop.run(ctx, w, iterations=2, geometry_fp32=False,
+                                        ion_energy=ie, log=lambda r: say(r))
+    torch.cuda.synchronize()
+    got, sg = pops.cpu().numpy(), status.cpu().numpy()
+
+    C, L, N = w.n_cells, w.n_lines, w.atom.n_levels
+    V = (2 * w.beta_max / w.n * synth.C_CGS * w.t_exp) ** 3
+    inp0 = oracle.nlte_inputs_from_workload(w)
+    pl = oracle.pi_levels(inp0, ie, 25)
+    p = np.stack([oracle.nlte_cold(inp0, c) for c in range(C)])
+    so = None
+    for k in range(2):
+        tau, fc = oracle.line_tau(p, w.atom, w.t_exp)
+        base = oracle.transport_inputs_from_workload(w, iteration=k, tau_ct=tau, fcorr_ct=fc)
+        photo = dict(level=pl["level"], sigma0=pl["sigma0"], pops=p,
+                     length=synth.C_CGS * w.t_exp, **{"lambda": pl["lambda"]})
+        inp = oracle.TransportInputs(w.n, w.beta_max, w.tau_scale, w.cell_photons, w.cell_packets,
+                                     w.line_lambda, w.line_tau0, w.lambda_lo, w.lambda_hi, w.seed,
+                                     k, base.arrays["line_trans"], tau, fc, photoion=photo)
+        r = oracle.transport(inp)
+        est = oracle.dense_estimator(r["records"], C, L)
+        gam = oracle.rates(est, p, w.atom, V)
+        gpi = oracle.pi_rates(r["pi_absorbed"], p, pl["level"], N, V)
+        say(f"oracle iteration {k + 1}: interactions {r['stats']['n_inter']:.0f}, "
+            f"GPU {hist[k]['interactions']:.0f}; photoionised fraction "
+            f"{r['stats']['w_pi'] / r['stats']['w_emit']:.3e}, GPU "
+            f"{hist[k]['photoionised_fraction']:.3e}")
+        assert r["stats"]["n_inter"] == hist[k]["interactions"]
+        assert hist[k]["photoionised_fraction"] == pytest.approx(
+            r["stats"]["w_pi"] / r["stats"]["w_emit"], rel=1e-10)
+        p, so, _ = oracle.nlte(oracle.nlte_inputs_from_workload(w, gamma_pe=gam, gamma_pi=gpi),
+                               guess=p)
+    assert r["stats"]["w_pi"] > 0
+    both = (sg <= 1) & (so == 0)
+    say(f"converged: GPU {(sg <= 1).sum()}, oracle {(so == 0).sum()}, both {both.sum()} of {C}")
+    assert both.sum() >= 0.999 * C
+    ref = p[both]
+    g = got[both]
+    pos = ref > 0
+    rel = np.max(np.abs(g[pos] - ref[pos]) / ref[pos])
+    say(f"populations after 2 iterations: max rel {rel:.2e}")
+    assert rel <= 1e-8
