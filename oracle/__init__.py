@@ -24,6 +24,11 @@ STAT_NAMES = ["w_emit", "w_esc", "w_kill", "w_abs", "n_inter", "n_checks", "n_cr
               "n_escaped", "n_killed", "w_pi"]
 
 
+class _Sphere(C.Structure):
+    _fields_ = [("n_r", C.c_int32), ("n_theta", C.c_int32), ("n_phi", C.c_int32),
+                ("r_edge", C.c_void_p), ("theta_edge", C.c_void_p)]
+
+
 class _Transport(C.Structure):
     _fields_ = [
         ("n", C.c_int32), ("beta_max", C.c_double),
@@ -35,6 +40,7 @@ class _Transport(C.Structure):
         ("pi_levels", C.c_int32), ("pi_lambda", C.c_void_p), ("pi_sigma0", C.c_void_p),
         ("pi_level", C.c_void_p), ("pi_nlev", C.c_int32), ("pi_pops", C.c_void_p),
         ("pi_length", C.c_double), ("pi_absorbed", C.c_void_p),
+        ("sphere", C.c_void_p),
     ]
 
 
@@ -100,6 +106,11 @@ def lib():
         L.oracle_ray_packets.argtypes = [C.c_int32, C.c_double, C.c_int64, C.c_int64, C.c_int32,
                                          C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
                                          C.POINTER(C.POINTER(C.c_double))]
+        L.oracle_sphere_cell.restype = C.c_int64
+        L.oracle_sphere_cell.argtypes = [C.POINTER(_Sphere), C.c_void_p]
+        L.oracle_sphere_crossings.restype = C.c_int32
+        L.oracle_sphere_crossings.argtypes = [C.POINTER(_Sphere), C.c_void_p, C.c_void_p,
+                                              C.c_void_p, C.c_int32]
         L.oracle_pi_levels.restype = C.c_int32
         L.oracle_pi_levels.argtypes = [C.POINTER(_Atom), C.c_void_p, C.c_int32, C.c_void_p,
                                        C.c_void_p, C.c_void_p]
@@ -139,11 +150,12 @@ class TransportInputs:
 
     def __init__(self, n, beta_max, tau_scale, cell_photons, cell_packets, line_lambda, line_tau0,
                  lambda_lo, lambda_hi, seed, iteration=0, line_trans=None, tau_ct=None,
-                 fcorr_ct=None, explicit_packets=None, photoion=None):
+                 fcorr_ct=None, explicit_packets=None, photoion=None, sphere=None):
         """photoion: None, or a dict with the photoionising levels of
         pi_levels() (level, lambda, sigma0), the populations pops [C, N] in
         cm^-3 and length = c t_exp; transport() then also returns each
-        (cell, level)'s absorbed photons."""
+        (cell, level)'s absorbed photons. sphere: None, or a Sphere (the
+        spherical grid; n and beta_max are then unused)."""
         self.arrays = dict(
             tau_scale=np.ascontiguousarray(tau_scale, dtype=np.float32),
             cell_photons=np.ascontiguousarray(cell_photons, dtype=np.float64),
@@ -157,14 +169,17 @@ class TransportInputs:
             np.ascontiguousarray(explicit_packets, np.float64).reshape(-1, 8),
         )
         a = self.arrays
-        n_trans = 0 if a["tau_ct"] is None else a["tau_ct"].size // (n ** 3)
-        self.n_cells = n ** 3
+        self.sphere = sphere
+        self.n_cells = sphere.n_cells if sphere is not None else n ** 3
+        n_trans = 0 if a["tau_ct"] is None else a["tau_ct"].size // self.n_cells
         self.n_lines = len(a["line_lambda"])
         self.s = _Transport(n, beta_max, _p(a["tau_scale"]), _p(a["cell_photons"]),
                             _p(a["cell_packets"]), self.n_lines, _p(a["line_lambda"]),
                             _p(a["line_tau0"]), _p(a["line_trans"]), n_trans, _p(a["tau_ct"]),
                             _p(a["fcorr_ct"]), lambda_lo, lambda_hi, seed, iteration,
                             _p(a["explicit"]))
+        if sphere is not None:
+            self.s.sphere = C.addressof(sphere.s)
         self.pi_levels = 0
         if photoion is not None:
             a["pi_lambda"] = np.ascontiguousarray(photoion["lambda"], np.float64)
@@ -188,6 +203,40 @@ class TransportInputs:
         if self.arrays["explicit"] is not None:
             return len(self.arrays["explicit"])
         return int(self.arrays["cell_packets"].astype(np.int64).sum())
+
+
+class Sphere:
+    """Spherical grid (the paper's (r, theta, phi) cells): shell edges r_edge
+    [n_r + 1] in x = v/c from 0, polar edges theta_edge [n_theta + 1] from 0
+    to pi, n_phi equal azimuthal slices; cell i_r + n_r (i_theta + n_theta
+    i_phi)."""
+
+    def __init__(self, r_edge, theta_edge, n_phi):
+        self.r_edge = np.ascontiguousarray(r_edge, np.float64)
+        self.theta_edge = np.ascontiguousarray(theta_edge, np.float64)
+        self.n_r, self.n_theta, self.n_phi = len(self.r_edge) - 1, len(self.theta_edge) - 1, int(n_phi)
+        self.n_cells = self.n_r * self.n_theta * self.n_phi
+        self.s = _Sphere(self.n_r, self.n_theta, self.n_phi, _p(self.r_edge), _p(self.theta_edge))
+
+    def cell(self, x):
+        xx = np.ascontiguousarray(x, np.float64)
+        return int(lib().oracle_sphere_cell(C.byref(self.s), _p(xx)))
+
+    def crossings(self, x0, n):
+        a = np.ascontiguousarray(x0, np.float64)
+        b = np.ascontiguousarray(n, np.float64)
+        cap = 2 * self.n_r + 2 * self.n_theta + self.n_phi + 4
+        out = np.zeros(cap)
+        m = lib().oracle_sphere_crossings(C.byref(self.s), _p(a), _p(b), _p(out), cap)
+        return out[:m].copy()
+
+    def volumes(self, scale=1.0):
+        """Cell volumes [C] in (scale x)^3 units: (r_b^3 - r_a^3)/3 (cos th_a -
+        cos th_b) dphi."""
+        r3 = (self.r_edge[1:] ** 3 - self.r_edge[:-1] ** 3) / 3.0
+        ct = np.cos(self.theta_edge[:-1]) - np.cos(self.theta_edge[1:])
+        v = r3[:, None, None] * ct[None, :, None] * np.full(self.n_phi, 2 * np.pi / self.n_phi)
+        return (v.transpose(2, 1, 0).ravel()) * scale ** 3
 
 
 def transport_inputs_from_workload(w, iteration=0, tau_ct=None, fcorr_ct=None):

@@ -22,6 +22,17 @@ void oracle_philox4x64(const uint64_t ctr[4], const uint64_t key[2], uint64_t ou
  * tau(c,k) = line_tau0[k]*tau_scale[c] for background lines (line_trans[k] < 0
  * or line_trans == NULL); tau_ct[c*n_trans + t] for line k = transition t.
  */
+/* Spherical grid (the paper's (r, theta, phi) cells, Sec. 2): n_r shells with
+ * edges r_edge[0] = 0 < ... < r_edge[n_r] in x = v/c, n_theta polar bins with
+ * edges theta_edge[0] = 0 < ... < theta_edge[n_theta] = pi, n_phi equal
+ * azimuthal slices of 2 pi / n_phi starting at phi = 0. Cell
+ * c = i_r + n_r (i_theta + n_theta i_phi): a phi slice is a contiguous range. */
+typedef struct {
+  int32_t n_r, n_theta, n_phi;
+  const double* r_edge;         /* [n_r + 1] */
+  const double* theta_edge;     /* [n_theta + 1] */
+} or_sphere;
+
 typedef struct {
   int32_t n;
   double beta_max;
@@ -53,6 +64,13 @@ typedef struct {
   const double* pi_pops;          /* [C*pi_nlev] */
   double pi_length;               /* cm per unit of path, c t_exp */
   double* pi_absorbed;            /* [C*M] out, accumulated */
+  /* Spherical grid instead of the cube (n and beta_max unused), or NULL.
+   * Sampled emission in cell (i_r, i_theta, i_phi) takes r^3 uniform in the
+   * shell (u0), cos(theta) uniform in the polar bin (u1) and phi uniform in
+   * the slice (u2); direction, wavelength and weight as in the cube. The
+   * path is cut at every crossing of a sphere, cone or half-plane of the
+   * grid; each piece lies in the cell its midpoint falls in. */
+  const or_sphere* sphere;
 } or_transport;
 
 /* Per-packet results (12 doubles per packet):
@@ -78,6 +96,14 @@ typedef struct { int64_t packet; int32_t cell, line; double value, margin; } or_
 int64_t oracle_transport(const or_transport* p, int64_t first, int64_t count, int nthreads,
                          or_record** records, double* stats, double* pkt_out);
 void oracle_free(void* ptr);
+
+/* Cell of point x on a spherical grid, -1 outside (exposed for the pins). */
+int64_t oracle_sphere_cell(const or_sphere* g, const double x[3]);
+/* Path lengths s > 0 (ascending, at most cap) at which the ray x0 + s n meets
+ * a surface of the spherical grid, up to its last exit from the outer sphere.
+ * Returns how many (exposed for the pins). */
+int32_t oracle_sphere_crossings(const or_sphere* g, const double x0[3], const double n[3],
+                                double* s_out, int32_t cap);
 
 /* The emitted state of packets [first, first+count), as the transport draws
  * it: out[8*i .. 8*i+7] = x, y, z, n_x, n_y, n_z, lambda_e, w0 (the layout of
