@@ -90,7 +90,32 @@ typedef struct {
   const double* fcorr_ct;       /* [C*T] or NULL (then f_corr = 1) */
   const struct extrass_photoion* photoion;  /* host struct: photoionisation opacity of the
                                                cells (below), or NULL for none */
+  const struct extrass_spherical* spherical; /* host struct: a spherical grid instead of the
+                                                cube (below; n and beta_max are then not
+                                                read), or NULL */
 } extrass_grid;
+
+/* Spherical grid (Sec. 2: the paper's (r, theta, phi) cells, larger at large
+ * radii). Shells between r_edge[i] and r_edge[i+1] (x = v/c, r_edge[0] = 0),
+ * polar bins between theta_edge[j] and theta_edge[j+1] (0 = theta_0 < ... <
+ * theta_{n_theta} = pi), n_phi equal azimuthal slices [2 pi k / n_phi,
+ * 2 pi (k+1) / n_phi). Cell c = i_r + n_r (i_theta + n_theta i_phi), so a phi
+ * slice is a contiguous range of cells; C = n_r n_theta n_phi for every [C]
+ * array of the grid. A packet leaves its cell where its straight path first
+ * meets a bounding sphere, cone or half-plane while moving out of the cell,
+ * steps to the neighbour across it (phi wraps around), and escapes beyond the
+ * outer sphere. Sampled emission in a cell takes r^3 uniform between the
+ * shell's edges (u0), cos(theta) uniform in the polar bin (u1) and phi
+ * uniform in the slice (u2) for the position; the direction, wavelength and
+ * weight are drawn as in the cube. Explicit packets start in the cell their
+ * position falls in. Spherical grids run with FP64 positions and distances
+ * (geometry_fp32 is ignored), sampled or explicit packets (no rays), and
+ * extrass_transport only (not the streamed entry). */
+typedef struct extrass_spherical {
+  int32_t n_r, n_theta, n_phi;  /* each >= 1; C at most 2^31 - 1 */
+  const double* r_edge;         /* device [n_r + 1], increasing */
+  const double* theta_edge;     /* device [n_theta + 1], increasing */
+} extrass_spherical;
 
 /* Photoionisation in the transport (Sec. 2.3.1; Eq. A5). M photoionising
  * levels, numbered in order of non-decreasing threshold wavelength lambda_j;

@@ -36,7 +36,12 @@ class _Grid(C.Structure):
                 ("cell_photons", C.c_void_p), ("cell_packets", C.c_void_p),
                 ("n_lines", C.c_int32), ("line_lambda", C.c_void_p), ("line_tau0", C.c_void_p),
                 ("line_trans", C.c_void_p), ("n_trans", C.c_int32), ("tau_ct", C.c_void_p),
-                ("fcorr_ct", C.c_void_p), ("photoion", C.c_void_p)]
+                ("fcorr_ct", C.c_void_p), ("photoion", C.c_void_p), ("spherical", C.c_void_p)]
+
+
+class _Spherical(C.Structure):
+    _fields_ = [("n_r", C.c_int32), ("n_theta", C.c_int32), ("n_phi", C.c_int32),
+                ("r_edge", C.c_void_p), ("theta_edge", C.c_void_p)]
 
 
 class _Photoion(C.Structure):
@@ -244,14 +249,48 @@ class Grid:
         self.n_lines = int(self.line_lambda.numel())
         self.n_trans = 0 if self.tau_ct is None else self.tau_ct.numel() // self.n_cells
         self.photoion = None  # a Photoion: the transport then also photoionises
+        self.spherical = None  # a Spherical: (r, theta, phi) cells instead of the cube
 
     def struct(self):
         self._pi = self.photoion.struct() if self.photoion is not None else None
+        self._sph = self.spherical.struct() if self.spherical is not None else None
         return _Grid(self.n, self.beta_max, _ptr(self.tau_scale), _ptr(self.cell_photons),
                      _ptr(self.cell_packets), self.n_lines, _ptr(self.line_lambda),
                      _ptr(self.line_tau0), _ptr(self.line_trans), self.n_trans,
                      _ptr(self.tau_ct), _ptr(self.fcorr_ct),
-                     C.addressof(self._pi) if self._pi is not None else None)
+                     C.addressof(self._pi) if self._pi is not None else None,
+                     C.addressof(self._sph) if self._sph is not None else None)
+
+
+class Spherical:
+    """A spherical grid (extrass_spherical): shell edges r_edge [n_r + 1] in
+    x = v/c from 0, polar edges theta_edge [n_theta + 1] from 0 to pi, n_phi
+    equal azimuthal slices; cell i_r + n_r (i_theta + n_theta i_phi)."""
+
+    def __init__(self, r_edge, theta_edge, n_phi, device="cuda:0"):
+        self.r_edge = _dev(r_edge, torch.float64, device)
+        self.theta_edge = _dev(theta_edge, torch.float64, device)
+        self.n_r = int(self.r_edge.numel()) - 1
+        self.n_theta = int(self.theta_edge.numel()) - 1
+        self.n_phi = int(n_phi)
+        self.n_cells = self.n_r * self.n_theta * self.n_phi
+
+    def struct(self):
+        return _Spherical(self.n_r, self.n_theta, self.n_phi, _ptr(self.r_edge),
+                          _ptr(self.theta_edge))
+
+
+def spherical_grid(r_edge, theta_edge, n_phi, tau_scale, cell_photons, cell_packets, line_lambda,
+                   line_tau0, device="cuda:0", line_trans=None, tau_ct=None, fcorr_ct=None):
+    """A Grid whose cells are those of a spherical grid (the per-cell arrays
+    have n_r n_theta n_phi entries)."""
+    sph = Spherical(r_edge, theta_edge, n_phi, device)
+    g = Grid(1, 1.0, tau_scale, cell_photons, cell_packets, line_lambda, line_tau0, device,
+             line_trans, tau_ct, fcorr_ct)
+    g.spherical = sph
+    g.n_cells = sph.n_cells
+    g.n_trans = 0 if g.tau_ct is None else g.tau_ct.numel() // g.n_cells
+    return g
 
 
 def grid_from_workload(w, device="cuda:0", tau_ct=None, fcorr_ct=None):

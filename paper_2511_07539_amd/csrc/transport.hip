@@ -108,6 +108,13 @@ struct TArgs {
   const double* pi_opac;
   double* pi_tally;
   double pi_len;
+  // spherical grid (the SPH kernels): shell and polar edges, slice width
+  int sph_nr, sph_nt, sph_np;
+  const double* sph_r;   // [nr + 1]
+  const double* sph_th;  // [nt + 1]
+  const double* sph_cth; // [nt + 1] cos of the polar edges (workspace)
+  const double* sph_cs;  // [2 (np + 1)] cos, sin of the azimuthal edges (workspace)
+  double sph_dphi;
 };
 
 // A packet in flight between octants: the whole state after a wall crossing.
@@ -344,6 +351,19 @@ __global__ void k_check_map(const int32_t* __restrict__ line_trans, int L,
   }
 }
 
+// Cosines of a spherical grid's polar edges, and cosines and sines of its
+// azimuthal edges 2 pi k / np, k = 0..np.
+__global__ void k_sph_trig(const double* th, int nt, int np, double* cth, double* cs) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t <= nt) cth[t] = cos(th[t]);
+  if (t <= np) {
+    double sp, cp;
+    sincos(2.0 * M_PI * t / np, &sp, &cp);
+    cs[2 * t] = cp;
+    cs[2 * t + 1] = sp;
+  }
+}
+
 __global__ void k_reset_u64(unsigned long long* p, int n) {
   if ((int)threadIdx.x < n) p[threadIdx.x] = 0ull;
 }
@@ -373,6 +393,7 @@ struct Packet {
   // and the photons absorbed
   double Dp, wpi;
   int jpi;
+  int sbits;  // spherical grid: the boundaries the current segment ends on
 };
 
 // The record of line k, or an empty one past the red end of the list.
@@ -416,9 +437,126 @@ __device__ __forceinline__ int first_line_above(const TArgs& A, double lam) {
   return k;
 }
 
+// ---- spherical grid ---------------------------------------------------------
+
+// Cell of point x on the spherical grid: the shell and polar bin whose lower
+// edges lie at or below r and theta, and the slice holding phi; false beyond
+// the outer sphere.
+__device__ __forceinline__ bool sph_locate(const TArgs& A, const double x[3], int ci[3]) {
+  const double r = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+  if (!(r < A.sph_r[A.sph_nr])) return false;
+  int lo = 0, hi = A.sph_nr;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (A.sph_r[mid] <= r) lo = mid; else hi = mid;
+  }
+  ci[0] = lo;
+  const double th = r > 0.0 ? acos(fmin(1.0, fmax(-1.0, x[2] / r))) : 0.0;
+  lo = 0;
+  hi = A.sph_nt;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (A.sph_th[mid] <= th) lo = mid; else hi = mid;
+  }
+  ci[1] = lo;
+  double ph = atan2(x[1], x[0]);
+  if (ph < 0.0) ph += 2.0 * M_PI;
+  int k = static_cast<int>(floor(ph / A.sph_dphi));
+  ci[2] = k < 0 ? 0 : (k > A.sph_np - 1 ? A.sph_np - 1 : k);
+  return true;
+}
+
+// Path length s >= 0 from x along n to where the ray leaves spherical cell
+// ci: the first root of one of its bounding surfaces at which the ray moves
+// out of the cell (roots where it moves in, such as the surface it just
+// crossed, do not count); `which` receives the surfaces met there (1 inner
+// sphere, 2 outer sphere, 4 lower cone, 8 upper cone, 16 lower half-plane,
+// 32 upper half-plane). A root within eps behind x counts as at x (x sits on
+// that surface up to rounding).
+__device__ __forceinline__ double sph_exit(const TArgs& A, const double x[3], const double n[3], const int ci[3],
+                           int& which) {
+  const double xx = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
+  const double b = x[0] * n[0] + x[1] * n[1] + x[2] * n[2];
+  const double eps = 1e-14 * A.sph_r[A.sph_nr];
+  double best = INFINITY;
+  which = 0;
+  auto take = [&](double s, int bit) {
+    if (!(s >= -eps)) return;
+    s = s > 0.0 ? s : 0.0;
+    if (s < best) {
+      best = s;
+      which = bit;
+    } else if (s == best) {
+      which |= bit;
+    }
+  };
+  {  // outer sphere: the larger root of |x + s n| = r
+    const double r = A.sph_r[ci[0] + 1];
+    const double disc = b * b - (xx - r * r);
+    take(-b + sqrt(disc > 0.0 ? disc : 0.0), 2);
+  }
+  if (ci[0] > 0) {  // inner sphere: the smaller root
+    const double r = A.sph_r[ci[0]];
+    const double disc = b * b - (xx - r * r);
+    if (disc >= 0.0) take(-b - sqrt(disc), 1);
+  }
+  // cones: the lower edge theta_lo bounds z <= cos(theta_lo) |x|, the upper
+  // edge z >= cos(theta_hi) |x|; roots of (z + s n_z)^2 = c^2 |x + s n|^2 on
+  // the cone's own nappe (z of the sign of c), or of z = 0 for theta = pi/2
+  for (int side = 0; side < 2; ++side) {
+    const int j = ci[1] + side;
+    if (j == 0 || j == A.sph_nt) continue;
+    const double c = A.sph_cth[j];
+    const double sgn = side == 0 ? 1.0 : -1.0;  // g = sgn (c |x| - z) >= 0 inside
+    if (fabs(c) < 1e-12) {
+      // the equatorial plane: g = -sgn z, decreasing when sgn n_z > 0
+      if (sgn * n[2] > 0.0) take(-x[2] / n[2], 4 << side);
+      continue;
+    }
+    const double Aq = n[2] * n[2] - c * c;
+    const double Bq = x[2] * n[2] - c * c * b;
+    const double Cq = x[2] * x[2] - c * c * xx;
+    double rt[2];
+    int nr = 0;
+    if (fabs(Aq) < 1e-300) {
+      if (Bq != 0.0) rt[nr++] = -Cq / (2.0 * Bq);
+    } else {
+      const double disc = Bq * Bq - Aq * Cq;
+      if (disc >= 0.0) {
+        const double q = sqrt(disc);
+        rt[nr++] = (-Bq - q) / Aq;
+        rt[nr++] = (-Bq + q) / Aq;
+      }
+    }
+    for (int i = 0; i < nr; ++i) {
+      const double sr = rt[i];
+      const double p[3] = {x[0] + sr * n[0], x[1] + sr * n[1], x[2] + sr * n[2]};
+      if ((p[2] > 0.0) != (c > 0.0)) continue;  // the other nappe
+      const double pr = sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
+      if (!(pr > 0.0)) continue;
+      const double dg = sgn * (c * (p[0] * n[0] + p[1] * n[1] + p[2] * n[2]) / pr - n[2]);
+      if (dg < 0.0) take(sr, 4 << side);
+    }
+  }
+  if (A.sph_np > 1) {  // half-planes through the z axis
+    for (int side = 0; side < 2; ++side) {
+      const double cp = A.sph_cs[2 * (ci[2] + side)], sp = A.sph_cs[2 * (ci[2] + side) + 1];
+      // inside: counter-clockwise of the lower edge, clockwise of the upper
+      const double sgn = side == 0 ? 1.0 : -1.0;
+      const double g0 = sgn * (-sp * x[0] + cp * x[1]);
+      const double g1 = sgn * (-sp * n[0] + cp * n[1]);
+      if (!(g1 < 0.0)) continue;
+      const double sr = -g0 / g1;
+      const double px = x[0] + sr * n[0], py = x[1] + sr * n[1];
+      if (cp * px + sp * py > 0.0) take(sr, 16 << side);
+    }
+  }
+  return best;
+}
+
 // RAYS: the deterministic-ray kernel, compiled apart so that the sampled
-// kernels keep their register allocation.
-template <class G, bool RAYS>
+// kernels keep their register allocation. SPH: the spherical grid.
+template <class G, bool RAYS, bool SPH>
 __device__ void emit(const TArgs& A, int64_t p, Packet<G>& q) {
   double x[3], d[3], lam_e, w0;
   int ci[3];
@@ -430,6 +568,10 @@ __device__ void emit(const TArgs& A, int64_t p, Packet<G>& q) {
       d[a] = e[3 + a];
       int i = static_cast<int>(floor((e[a] + A.beta) / A.h));
       ci[a] = i < 0 ? 0 : (i > A.n - 1 ? A.n - 1 : i);
+    }
+    if (SPH && !sph_locate(A, x, ci)) {  // starts beyond the outer sphere
+      q.bad = true;
+      return;
     }
     lam_e = e[6];
     w0 = e[7];
@@ -487,12 +629,32 @@ __device__ void emit(const TArgs& A, int64_t p, Packet<G>& q) {
       q.bad = true;
       return;
     }
-    ci[0] = static_cast<int>(c % A.n);
-    ci[1] = static_cast<int>((c / A.n) % A.n);
-    ci[2] = static_cast<int>(c / ((int64_t)A.n * A.n));
     const u64x4 r0 = philox4x64_10((uint64_t)p, A.iteration, 0, 0, A.seed, 3);
     const u64x4 r1 = philox4x64_10((uint64_t)p, A.iteration, 1, 0, A.seed, 3);
-    for (int a = 0; a < 3; ++a) x[a] = (-A.beta + static_cast<double>(ci[a]) * A.h) + A.h * unit53(r0.v[a]);
+    if constexpr (SPH) {
+      // uniform in the cell's volume: r^3 over the shell, cos(theta) over the
+      // polar bin, phi over the slice
+      ci[0] = static_cast<int>(c % A.sph_nr);
+      ci[1] = static_cast<int>((c / A.sph_nr) % A.sph_nt);
+      ci[2] = static_cast<int>(c / ((int64_t)A.sph_nr * A.sph_nt));
+      const double ra = A.sph_r[ci[0]], rb = A.sph_r[ci[0] + 1];
+      const double r = cbrt(ra * ra * ra + unit53(r0.v[0]) * (rb * rb * rb - ra * ra * ra));
+      const double ca = A.sph_cth[ci[1]], cb = A.sph_cth[ci[1] + 1];
+      const double mu_x = ca + unit53(r0.v[1]) * (cb - ca);
+      const double ph_x = 2.0 * M_PI * (ci[2] + unit53(r0.v[2])) / A.sph_np;
+      const double sx = sqrt(fmax(0.0, 1.0 - mu_x * mu_x));
+      double spx, cpx;
+      sincos(ph_x, &spx, &cpx);
+      x[0] = r * sx * cpx;
+      x[1] = r * sx * spx;
+      x[2] = r * mu_x;
+    } else {
+      ci[0] = static_cast<int>(c % A.n);
+      ci[1] = static_cast<int>((c / A.n) % A.n);
+      ci[2] = static_cast<int>(c / ((int64_t)A.n * A.n));
+      for (int a = 0; a < 3; ++a)
+        x[a] = (-A.beta + static_cast<double>(ci[a]) * A.h) + A.h * unit53(r0.v[a]);
+    }
     const double mu = 2.0 * unit53(r0.v[3]) - 1.0;
     const double phi = 2.0 * M_PI * unit53(r1.v[0]);
     const double st = sqrt(fmax(0.0, 1.0 - mu * mu));
@@ -647,8 +809,8 @@ __device__ __forceinline__ double pi_move(const TArgs& A, Packet<G>& q, int64_t 
 // Three waves per SIMD: the kernel is bound by the latency of its gathers and
 // scattered atomics, and the third wave (a few dwords of rarely used state
 // spilled) is worth more than the spill.
-template <class G, bool RAYS, bool PI>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_transport(TArgs A) {
+template <class G, bool RAYS, bool PI, bool SPH>
+__device__ __forceinline__ void transport_body(const TArgs& A) {
   const int lane = threadIdx.x & 63;
   Packet<G> q;
   LineRec nxt;  // record of line q.k, loaded ahead so that the event does not wait for it
@@ -697,7 +859,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
             }
           } else {  // one emission site for both modes keeps the register peak down
             const int64_t p = A.oct < 0 ? A.first + idx : octant_packet(A, idx);
-            emit<G, RAYS>(A, p, q);
+            emit<G, RAYS, SPH>(A, p, q);
             if (q.bad) {
               t.bad = true;
               pid = -1;
@@ -735,7 +897,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
       if (q.have_exit && !line_event) {
         // the continuum up to the wall, in the cell being left; then the
         // 1e-6 rule on the comoving energy left there
-        const int64_t c = q.ci[0] + (int64_t)A.n * (q.ci[1] + (int64_t)A.n * q.ci[2]);
+        const int64_t c = SPH ? q.ci[0] + (int64_t)A.sph_nr * (q.ci[1] + (int64_t)A.sph_nt * q.ci[2])
+                              : q.ci[0] + (int64_t)A.n * (q.ci[1] + (int64_t)A.n * q.ci[2]);
         const double Db = (double)q.Dexit;
         if (pi_move<G>(A, q, c, Db, t) > 0.0 && q.w * q.lam_e * (1.0 - Db) < (kKillFrac * q.w0) * q.lamL) {
           t.w_kill += q.w;
@@ -747,6 +910,22 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     }
     if (q.have_exit && !line_event && !stop) {
       bool out = false;
+      if constexpr (SPH) {
+        // move to the exit point and across the surfaces met there
+        for (int a = 0; a < 3; ++a) q.x[a] = q.x[a] + q.s * q.d[a];
+        const int w = q.sbits;
+        if (w & 1) q.ci[0] -= 1;
+        if (w & 2) q.ci[0] += 1;
+        if (w & 4) q.ci[1] -= 1;
+        if (w & 8) q.ci[1] += 1;
+        if (w & 16) q.ci[2] = q.ci[2] == 0 ? A.sph_np - 1 : q.ci[2] - 1;
+        if (w & 32) q.ci[2] = q.ci[2] == A.sph_np - 1 ? 0 : q.ci[2] + 1;
+        out = q.ci[0] >= A.sph_nr;
+        if (q.ci[0] < 0 || q.ci[1] < 0 || q.ci[1] >= A.sph_nt) {  // rounding at the origin or a pole
+          q.ci[0] = q.ci[0] < 0 ? 0 : q.ci[0];
+          q.ci[1] = q.ci[1] < 0 ? 0 : (q.ci[1] >= A.sph_nt ? A.sph_nt - 1 : q.ci[1]);
+        }
+      } else {
       for (int a = 0; a < 3; ++a) {
         if (q.dist[a] == q.smin) {
           if (q.d[a] > G(0)) {
@@ -760,6 +939,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
         } else {
           q.x[a] = q.x[a] + q.s * q.d[a];
         }
+      }
       }
       q.D = q.Dexit;
       q.have_exit = false;
@@ -785,12 +965,18 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     }
     if (!stop && !q.have_exit) {  // a new packet, or a new segment after a crossing
       G smin = static_cast<G>(INFINITY);
+      if constexpr (SPH) {
+        const double xd[3] = {(double)q.x[0], (double)q.x[1], (double)q.x[2]};
+        const double nd[3] = {(double)q.d[0], (double)q.d[1], (double)q.d[2]};
+        smin = static_cast<G>(sph_exit(A, xd, nd, q.ci, q.sbits));
+      } else {
       for (int a = 0; a < 3; ++a) {
         G dd = static_cast<G>(INFINITY);
         if (q.d[a] > G(0)) dd = (wall<G>(A, q.ci[a] + 1) - q.x[a]) / q.d[a];
         else if (q.d[a] < G(0)) dd = (wall<G>(A, q.ci[a]) - q.x[a]) / q.d[a];
         q.dist[a] = dd;
         smin = dd < smin ? dd : smin;
+      }
       }
       q.smin = smin;
       q.s = smin > G(0) ? smin : G(0);
@@ -805,7 +991,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     }
     if (line_event) {
       const LineRec lr = nxt;
-      const int64_t c = q.ci[0] + (int64_t)A.n * (q.ci[1] + (int64_t)A.n * q.ci[2]);
+      const int64_t c = SPH ? q.ci[0] + (int64_t)A.sph_nr * (q.ci[1] + (int64_t)A.sph_nt * q.ci[2])
+                            : q.ci[0] + (int64_t)A.n * (q.ci[1] + (int64_t)A.n * q.ci[2]);
       const int64_t row = A.oct < 0 ? c
           : (q.ci[0] - A.lo[0]) + (int64_t)A.half * ((q.ci[1] - A.lo[1]) + (int64_t)A.half * (q.ci[2] - A.lo[2]));
       const int k = q.k;
@@ -867,6 +1054,19 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
   if (__ballot(t.overflow) != 0ull && lane == 0) A.stats[EXTRASS_STAT_QUEUE_FULL] = 1.0;
 }
 
+template <class G, bool RAYS, bool PI, bool SPH>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_transport(TArgs A) {
+  transport_body<G, RAYS, PI, SPH>(A);
+}
+
+// The spherical grid's exit search (three surfaces of each kind, square
+// roots, the cone quadratics) needs more registers than three wavefronts per
+// SIMD leave: two per SIMD.
+template <bool PI>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void k_transport_sph(TArgs A) {
+  transport_body<double, false, PI, true>(A);
+}
+
 }  // namespace
 }  // namespace extrass
 
@@ -907,10 +1107,37 @@ struct TransportWs {
   int32_t* chunk_cell = nullptr;
   int64_t nchunk = 0;
   int64_t* tsum = nullptr;  // tile sums of the packet-count scan
+  double* sph_cth = nullptr;  // spherical grid: cos of the polar edges
+  double* sph_cs = nullptr;   // spherical grid: cos, sin of the azimuthal edges
 };
 
+// Cells of the grid: n^3 for the cube, n_r n_theta n_phi for a spherical grid.
+static int64_t grid_cells(const extrass_grid* g) {
+  if (g->spherical)
+    return (int64_t)g->spherical->n_r * g->spherical->n_theta * g->spherical->n_phi;
+  return (int64_t)g->n * g->n * g->n;
+}
+
+// Spherical-grid fields of A from the grid (none for the cube); false when
+// they are invalid.
+static bool set_spherical(const extrass_grid* g, TArgs& A) {
+  const extrass_spherical* p = g->spherical;
+  A.sph_nr = 0;
+  if (!p) return true;
+  if (p->n_r < 1 || p->n_theta < 1 || p->n_phi < 1 || !p->r_edge || !p->theta_edge ||
+      (int64_t)p->n_r * p->n_theta * p->n_phi > INT32_MAX)
+    return false;
+  A.sph_nr = p->n_r;
+  A.sph_nt = p->n_theta;
+  A.sph_np = p->n_phi;
+  A.sph_r = p->r_edge;
+  A.sph_th = p->theta_edge;
+  A.sph_dphi = 2.0 * M_PI / p->n_phi;
+  return true;
+}
+
 static size_t ws_layout(const extrass_grid* g, const extrass_source* s, TransportWs* w, void* ws) {
-  const int64_t C = (int64_t)g->n * g->n * g->n;
+  const int64_t C = grid_cells(g);
   Carver cv(ws, ~size_t(0));
   TransportWs t;
   t.start = cv.take<int64_t>(C + 1);
@@ -921,6 +1148,10 @@ static size_t ws_layout(const extrass_grid* g, const extrass_source* s, Transpor
   t.nchunk = s->n_packets > 0 ? (s->n_packets + 255) / 256 + 1 : 1;
   t.chunk_cell = cv.take<int32_t>(t.nchunk);
   t.tsum = cv.take<int64_t>((C + kScanTile - 1) / kScanTile + 1);
+  if (g->spherical) {
+    t.sph_cth = cv.take<double>(g->spherical->n_theta + 1);
+    t.sph_cs = cv.take<double>(2 * (g->spherical->n_phi + 1));
+  }
   if (w) *w = t;
   return cv.used + 256;
 }
@@ -942,26 +1173,29 @@ static bool set_photoion(const extrass_grid* g, TArgs& A) {
   return true;
 }
 
-// The transport kernel for the geometry precision, emission kind and
-// photoionisation.
-static void launch_transport(bool fp32, bool rays, bool pi, unsigned blocks, hipStream_t st,
-                             const TArgs& A) {
+// The transport kernel for the geometry precision, emission kind,
+// photoionisation and grid (spherical grids: FP64 geometry, no rays).
+static void launch_transport(bool fp32, bool rays, bool pi, bool sph, unsigned blocks,
+                             hipStream_t st, const TArgs& A) {
   const dim3 g(blocks), b(kBlock);
-  if (pi) {
-    if (rays && fp32) hipLaunchKernelGGL((k_transport<float, true, true>), g, b, 0, st, A);
-    else if (rays) hipLaunchKernelGGL((k_transport<double, true, true>), g, b, 0, st, A);
-    else if (fp32) hipLaunchKernelGGL((k_transport<float, false, true>), g, b, 0, st, A);
-    else hipLaunchKernelGGL((k_transport<double, false, true>), g, b, 0, st, A);
+  if (sph) {
+    if (pi) hipLaunchKernelGGL((k_transport_sph<true>), g, b, 0, st, A);
+    else hipLaunchKernelGGL((k_transport_sph<false>), g, b, 0, st, A);
+  } else if (pi) {
+    if (rays && fp32) hipLaunchKernelGGL((k_transport<float, true, true, false>), g, b, 0, st, A);
+    else if (rays) hipLaunchKernelGGL((k_transport<double, true, true, false>), g, b, 0, st, A);
+    else if (fp32) hipLaunchKernelGGL((k_transport<float, false, true, false>), g, b, 0, st, A);
+    else hipLaunchKernelGGL((k_transport<double, false, true, false>), g, b, 0, st, A);
   } else {
-    if (rays && fp32) hipLaunchKernelGGL((k_transport<float, true, false>), g, b, 0, st, A);
-    else if (rays) hipLaunchKernelGGL((k_transport<double, true, false>), g, b, 0, st, A);
-    else if (fp32) hipLaunchKernelGGL((k_transport<float, false, false>), g, b, 0, st, A);
-    else hipLaunchKernelGGL((k_transport<double, false, false>), g, b, 0, st, A);
+    if (rays && fp32) hipLaunchKernelGGL((k_transport<float, true, false, false>), g, b, 0, st, A);
+    else if (rays) hipLaunchKernelGGL((k_transport<double, true, false, false>), g, b, 0, st, A);
+    else if (fp32) hipLaunchKernelGGL((k_transport<float, false, false, false>), g, b, 0, st, A);
+    else hipLaunchKernelGGL((k_transport<double, false, false, false>), g, b, 0, st, A);
   }
 }
 
 extern "C" size_t extrass_transport_workspace(const extrass_grid* g, const extrass_source* s) {
-  if (!g || !s || g->n <= 0 || s->n_packets < 0) return 0;
+  if (!g || !s || (!g->spherical && g->n <= 0) || s->n_packets < 0) return 0;
   return ws_layout(g, s, nullptr, nullptr);
 }
 
@@ -970,8 +1204,9 @@ extern "C" int extrass_transport(extrass_handle h, const extrass_grid* g, const 
                                  size_t ws_bytes, void* stream) {
   if (!h || !g || !s || !est || !stats || !ws)
     return fail(h, EXTRASS_EINVAL, "extrass_transport: null argument");
-  if (g->n <= 0 || g->n > 1024 || g->n_lines < 0 || !(g->beta_max > 0.0))
+  if (!g->spherical && (g->n <= 0 || g->n > 1024 || !(g->beta_max > 0.0)))
     return fail(h, EXTRASS_EINVAL, "extrass_transport: bad grid size");
+  if (g->n_lines < 0) return fail(h, EXTRASS_EINVAL, "extrass_transport: bad line count");
   if (g->n_lines > 0 && (!g->line_lambda || !g->line_tau0))
     return fail(h, EXTRASS_EINVAL, "extrass_transport: missing line arrays");
   if (!g->tau_scale) return fail(h, EXTRASS_EINVAL, "extrass_transport: tau_scale is NULL");
@@ -988,6 +1223,9 @@ extern "C" int extrass_transport(extrass_handle h, const extrass_grid* g, const 
     return fail(h, EXTRASS_EINVAL, "extrass_transport: sampled mode needs cell_packets/photons");
   TArgs A{};
   if (!set_photoion(g, A)) return fail(h, EXTRASS_EINVAL, "extrass_transport: bad photoion");
+  if (!set_spherical(g, A)) return fail(h, EXTRASS_EINVAL, "extrass_transport: bad spherical grid");
+  if (g->spherical && rays)
+    return fail(h, EXTRASS_EINVAL, "extrass_transport: deterministic rays need the cube");
   TransportWs tw;
   const size_t need = ws_layout(g, s, &tw, ws);
   if (ws_bytes < need) return fail(h, EXTRASS_ENOSPACE, "extrass_transport: workspace too small");
@@ -996,7 +1234,7 @@ extern "C" int extrass_transport(extrass_handle h, const extrass_grid* g, const 
 
   hipStream_t st = static_cast<hipStream_t>(stream);
   EXTRASS_HIP_TRY(h, hipSetDevice(h->device));
-  const int64_t C = (int64_t)g->n * g->n * g->n;
+  const int64_t C = grid_cells(g);
   const int L = g->n_lines;
 
   const int has_ct = (g->tau_ct && g->line_trans) ? 1 : 0;
@@ -1023,9 +1261,9 @@ extern "C" int extrass_transport(extrass_handle h, const extrass_grid* g, const 
   EXTRASS_HIP_TRY(h, hipGetLastError());
   if (s->n_packets == 0) return EXTRASS_OK;
 
-  A.n = g->n;
-  A.beta = g->beta_max;
-  A.h = 2.0 * g->beta_max / g->n;
+  A.n = g->spherical ? 1 : g->n;
+  A.beta = g->spherical ? 1.0 : g->beta_max;
+  A.h = 2.0 * A.beta / A.n;
   A.tau_scale = g->tau_scale;
   A.cell_photons = g->cell_photons;
   A.cell_packets = g->cell_packets;
@@ -1047,6 +1285,13 @@ extern "C" int extrass_transport(extrass_handle h, const extrass_grid* g, const 
   A.lam_par = tw.lam_par;
   A.nbin = lam_bins(L);
   A.chunk_cell = (s->explicit_packets || rays) ? nullptr : tw.chunk_cell;
+  if (g->spherical) {
+    const int m = std::max(A.sph_nt, A.sph_np) + 1;
+    hipLaunchKernelGGL(k_sph_trig, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st,
+                       A.sph_th, A.sph_nt, A.sph_np, tw.sph_cth, tw.sph_cs);
+    A.sph_cth = tw.sph_cth;
+    A.sph_cs = tw.sph_cs;
+  }
   if (rays) {
     A.ray_lam = rays->bin_lambda;
     A.ray_ph = rays->n_bins > 0 ? rays->bin_photons : nullptr;
@@ -1068,7 +1313,8 @@ extern "C" int extrass_transport(extrass_handle h, const extrass_grid* g, const 
   const int64_t max_blocks = (s->n_packets + kBlock - 1) / kBlock;
   if (blocks > max_blocks) blocks = max_blocks;
   if (blocks < 1) blocks = 1;
-  launch_transport(s->geometry_fp32 != 0, rays != nullptr, A.pi_M > 0, (unsigned)blocks, st, A);
+  launch_transport(s->geometry_fp32 != 0, rays != nullptr, A.pi_M > 0, A.sph_nr > 0, (unsigned)blocks,
+                   st, A);
   EXTRASS_HIP_TRY(h, hipGetLastError());
   return EXTRASS_OK;
 }
@@ -1085,7 +1331,8 @@ extern "C" int extrass_transport_noalloc(extrass_handle h, const extrass_grid* g
     ws = noalloc_ptr[h->device];
   }
   if (!ws) return fail(h, EXTRASS_EHIP, "extrass_transport_noalloc: scratch not set up");
-  if (g->n <= 0 || s->n_packets < 0 || extrass_transport_workspace(g, s) > kNoAllocBytes)
+  if ((!g->spherical && g->n <= 0) || s->n_packets < 0 ||
+      extrass_transport_workspace(g, s) > kNoAllocBytes)
     return fail(h, EXTRASS_ENOSPACE,
                 "extrass_transport_noalloc: the problem needs more than the 16 MiB scratch");
   return extrass_transport(h, g, s, est, stats, packets_out, ws, kNoAllocBytes, stream);
@@ -1162,6 +1409,8 @@ extern "C" int extrass_transport_streamed(extrass_handle h, const extrass_grid* 
     return fail(h, EXTRASS_EINVAL, "extrass_transport_streamed: tau_ct needs line_trans and n_trans");
   if (s->explicit_packets || s->rays || s->first_packet != 0 || s->n_packets < 0)
     return fail(h, EXTRASS_EINVAL, "extrass_transport_streamed: whole sampling plan only");
+  if (g->spherical)
+    return fail(h, EXTRASS_EINVAL, "extrass_transport_streamed: the cube only");
   if (atom && (!pops || !gamma_pe || !(t_exp > 0.0)))
     return fail(h, EXTRASS_EINVAL, "extrass_transport_streamed: rates need pops, gamma_pe, t_exp");
   if (atom && atom->maxLine >= g->n_lines)
@@ -1281,7 +1530,7 @@ extern "C" int extrass_transport_streamed(extrass_handle h, const extrass_grid* 
       int64_t blocks = (int64_t)h->num_cus * 8;
       const int64_t max_blocks = (A.count + kBlock - 1) / kBlock;
       if (blocks > max_blocks) blocks = max_blocks;
-      launch_transport(s->geometry_fp32 != 0, false, A.pi_M > 0, (unsigned)blocks, st, A);
+      launch_transport(s->geometry_fp32 != 0, false, A.pi_M > 0, false, (unsigned)blocks, st, A);
       EXTRASS_HIP_TRY(h, hipGetLastError());
       if (!direct)
         hipLaunchKernelGGL(k_octant_flush, dim3((unsigned)Co), dim3(256), 0, st, est_octant,

@@ -427,6 +427,100 @@ def large() -> Workload:
     return clumpy(100, 30000, 100_000_000, number=5)
 
 
+@dataclasses.dataclass
+class SphericalWorkload:
+    """Inputs on a spherical (r, theta, phi) grid (Sec. 2): shell edges r_edge
+    (x = v/c, from 0), polar edges theta_edge, n_phi equal azimuthal slices;
+    cell c = i_r + n_r (i_theta + n_theta i_phi). Per-cell arrays have
+    n_r n_theta n_phi entries; no atom (background lines only)."""
+    name: str
+    number: int
+    r_edge: np.ndarray
+    theta_edge: np.ndarray
+    n_phi: int
+    t_exp: float
+    rho: np.ndarray
+    tau_scale: np.ndarray
+    cell_photons: np.ndarray
+    cell_packets: np.ndarray
+    line_lambda: np.ndarray
+    line_tau0: np.ndarray
+    lambda_lo: float
+    lambda_hi: float
+    n_packets: int
+    seed: int
+
+    @property
+    def n_r(self) -> int:
+        return len(self.r_edge) - 1
+
+    @property
+    def n_theta(self) -> int:
+        return len(self.theta_edge) - 1
+
+    @property
+    def n_cells(self) -> int:
+        return self.n_r * self.n_theta * self.n_phi
+
+    @property
+    def n_lines(self) -> int:
+        return len(self.line_lambda)
+
+    def cell_volumes(self) -> np.ndarray:
+        """Physical cell volumes (cm^3) in cell order."""
+        r3 = (self.r_edge[1:] ** 3 - self.r_edge[:-1] ** 3) / 3.0
+        ct = np.cos(self.theta_edge[:-1]) - np.cos(self.theta_edge[1:])
+        v = (r3[:, None, None] * ct[None, :, None] * np.full(self.n_phi, 2 * np.pi / self.n_phi))
+        return v.transpose(2, 1, 0).ravel() * (C_CGS * self.t_exp) ** 3
+
+
+def spherical(n_r: int = 40, n_theta: int = 30, n_phi: int = 60, n_lines: int = 5000,
+              n_packets: int = 10_000_000, number: int = 8, power: float = 1.5) -> SphericalWorkload:
+    """Clumped homologous ejecta on a spherical grid, v_max 5000 km/s, t = 200 d.
+
+    Shell edges r_i = R (i / n_r)^power (cells grow outwards, as the paper's
+    grid does), polar edges uniform in theta, n_phi equal slices. rho ~
+    |v|^-2 at the cell's middle radius; clumps with filling factor 0.2
+    (multiplier lognormal, median 10, sigma_ln 0.5) renormalised per shell to
+    conserve its mass, times 10 % noise; 1 M_sun in all. Lines in
+    2000-25000 A with tau0 log-uniform in 1e-4..1e4 scaled by rho/rho_bar;
+    emission proportional to mass; packets by largest remainder."""
+    R = 5000.0 / C_KMS
+    t_exp = 200.0 * DAY
+    r_edge = R * (np.arange(n_r + 1) / n_r) ** power
+    theta_edge = np.linspace(0.0, np.pi, n_theta + 1)
+    g = rng(number, STREAM_GRID)
+    C = n_r * n_theta * n_phi
+    ir = np.arange(C) % n_r
+    rm = 0.5 * (r_edge[ir] + r_edge[ir + 1])
+    base = 1.0 / rm ** 2
+    clump = g.random(C) < 0.2
+    mult = np.where(clump, 10.0 * np.exp(0.5 * g.standard_normal(C)), 1.0)
+    dens = base * mult
+    sw = SphericalWorkload("", number, r_edge, theta_edge, n_phi, t_exp, np.zeros(C),
+                           np.zeros(C, np.float32), np.zeros(C), np.zeros(C, np.int32),
+                           np.zeros(0), np.zeros(0, np.float32), 2000e-8, 25000e-8, n_packets,
+                           packet_seed(number))
+    V = sw.cell_volumes()
+    for i in range(n_r):
+        m = ir == i
+        dens[m] *= (base[m] * V[m]).sum() / (dens[m] * V[m]).sum()
+    dens *= _lognormal_unit_mean(g, 0.10, C)
+    rho = dens * (M_SUN / (dens * V).sum())
+    gl = rng(number, STREAM_LINES)
+    lam = np.sort(gl.uniform(2000.0, 25000.0, size=n_lines)) * ANGSTROM
+    tau0 = _log_uniform(gl, 1e-4, 1e4, n_lines).astype(np.float32)
+    mass = rho * V
+    sw.name = f"sphere{n_r}x{n_theta}x{n_phi}_l{n_lines}_p{n_packets:.0e}".replace("+0", "")
+    sw.rho = rho
+    sw.tau_scale = (rho / rho.mean()).astype(np.float32)
+    sw.cell_photons = 2.5e52 * mass / mass.sum()
+    sw.cell_packets = largest_remainder(mass / mass.sum(), n_packets)
+    sw.line_lambda = lam
+    sw.line_tau0 = tau0
+    return sw
+
+
 def workload_by_name(name: str) -> Workload:
     table = {"sphere16": sphere_small, "clumpy50": paper_scale, "clumpy100": large}
     return table[name]()

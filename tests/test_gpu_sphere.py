@@ -1,0 +1,215 @@
+"""Transport on the spherical (r, theta, phi) grid (Sec. 2): HIP path vs the
+FP64 oracle on the same inputs.
+
+The two sides find the cells differently: the kernel walks from cell to
+neighbour through the surface where the ray first moves out of its cell; the
+oracle cuts the ray at every crossing of every grid surface and classifies the
+midpoint of each piece. Both in FP64, so every estimator entry agrees to 1e-9
+unless a resonance lies within rounding of a surface (margin below 1e-10 cell
+widths): such a near tie taints the rest of its packet and its line in the
+cells around it, and is counted. Event counts agree up to the near ties.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+A = synth.ANGSTROM
+C_LIGHT = 2.99792458e10
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ex():
+    import paper_2511_07539_amd as ex
+    return ex
+
+
+@pytest.fixture(scope="module")
+def ctx(ex):
+    return ex.Context(0)
+
+
+@pytest.fixture(scope="module")
+def sph():
+    return synth.spherical(12, 8, 16, 300, 100_000, number=9)
+
+
+def _oracle_inputs(w, explicit=None, tau0=None, scale=None, photoion=None):
+    S = oracle.Sphere(w.r_edge, w.theta_edge, w.n_phi)
+    inp = oracle.TransportInputs(1, 1.0, w.tau_scale if scale is None else scale, w.cell_photons,
+                                 w.cell_packets, w.line_lambda,
+                                 w.line_tau0 if tau0 is None else tau0, w.lambda_lo, w.lambda_hi,
+                                 w.seed, explicit_packets=explicit, sphere=S, photoion=photoion)
+    return inp, S
+
+
+def _gpu_grid(ex, w, tau0=None, scale=None):
+    return ex.spherical_grid(w.r_edge, w.theta_edge, w.n_phi,
+                             w.tau_scale if scale is None else scale, w.cell_photons,
+                             w.cell_packets, w.line_lambda, w.line_tau0 if tau0 is None else tau0)
+
+
+def _near_tie_metric(est, ref, rec, w, tie=1e-10):
+    L = ref.shape[1]
+    near = rec["margin"] < tie
+    pkt = rec["packet"]
+    tainted = np.zeros(len(rec), dtype=bool)
+    if near.any():
+        bad_pk = np.unique(pkt[near])
+        first_near = {p: rec_i for rec_i, p in zip(np.flatnonzero(near)[::-1], pkt[near][::-1])}
+        for i in np.flatnonzero(np.isin(pkt, bad_pk)):
+            tainted[i] = i >= first_near[pkt[i]]
+    taint = np.zeros(ref.size, dtype=bool)
+    idx = rec["cell"].astype(np.int64) * L + rec["line"]
+    taint[idx[tainted]] = True
+    nr, nt, npf = w.n_r, w.n_theta, w.n_phi
+    for c, k in zip(rec["cell"][near].astype(np.int64), rec["line"][near]):
+        ir, it, ip = c % nr, (c // nr) % nt, c // (nr * nt)
+        for dr in (-1, 0, 1):
+            for dt in (-1, 0, 1):
+                for dp in (-1, 0, 1):
+                    a, b = ir + dr, it + dt
+                    if 0 <= a < nr and 0 <= b < nt:
+                        taint[(a + nr * (b + nt * ((ip + dp) % npf))) * L + k] = True
+    e, r_ = est.ravel(), ref.ravel()
+    clean = (r_ != 0) & ~taint
+    rel = np.abs(e[clean] - r_[clean]) / np.abs(r_[clean])
+    return dict(clean_max_rel=float(rel.max()) if rel.size else 0.0, clean=int(clean.sum()),
+                near_ties=int(near.sum()), tainted=int((taint & (r_ != 0)).sum()),
+                moved=int(((r_ == 0) & (e != 0) & ~taint).sum()),
+                l1=float(np.abs(est - ref).sum() / np.abs(ref).sum()))
+
+
+def test_sampled_packets_match_oracle(ex, ctx, sph):
+    w = sph
+    say(f"case: {w.name}: {w.n_cells} cells, sampled packets, FP64")
+    inp, _ = _oracle_inputs(w)
+    r = oracle.transport(inp, per_packet=True)
+    ref = oracle.dense_estimator(r["records"], w.n_cells, w.n_lines)
+    grid = _gpu_grid(ex, w)
+    est, st, pk = ex.transport(ctx, grid, w.seed, w.lambda_lo, w.lambda_hi, w.n_packets,
+                               packets_out=True)
+    torch.cuda.synchronize()
+    sd = ex.stats_dict(st)
+    m = _near_tie_metric(est.cpu().numpy(), ref, r["records"], w)
+    say(m, {k: (sd[k], r["stats"][k]) for k in ("n_inter", "n_cross", "n_escaped", "n_killed")})
+    assert sd["error_flag"] == 0 and sd["bad_packets"] == 0
+    assert m["clean_max_rel"] <= 1e-9 and m["moved"] == 0
+    assert m["tainted"] <= 1e-4 * m["clean"]
+    for k in ("n_inter", "n_checks", "n_cross", "n_escaped", "n_killed"):
+        assert abs(sd[k] - r["stats"][k]) <= m["near_ties"], k
+    assert sd["w_emit"] == pytest.approx(r["stats"]["w_emit"], rel=1e-12)
+    assert sd["w_abs"] == pytest.approx(r["stats"]["w_abs"], rel=1e-9)
+    pk = pk.cpu().numpy()
+    np.testing.assert_allclose(pk[:, 1], r["packets"][:, 1], rtol=1e-13)
+    both = (pk[:, 0] > 0) & (r["packets"][:, 0] > 0)
+    assert both.sum() >= 0.999 * (r["packets"][:, 0] > 0).sum()
+    np.testing.assert_allclose(pk[both, 0], r["packets"][both, 0], rtol=1e-9)
+
+
+def test_uniform_sphere_inward_packets_match_oracle(ex, ctx, sph):
+    """Explicit packets entering through the outer sphere (the closed-form
+    pin's setup), one line of uniform tau: per entry against the oracle."""
+    w = sph
+    R = w.r_edge[-1]
+    P = 50_000
+    g = np.random.default_rng(21)
+    m = g.standard_normal((P, 3))
+    m /= np.linalg.norm(m, axis=1, keepdims=True)
+    x0 = R * (1 - 1e-12) * m
+    d = g.standard_normal((P, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    d = np.where(((d * m).sum(1) > 0)[:, None], -d, d)  # inward
+    lam_k = 5000 * A
+    lamL = 1.0 / g.uniform((1 / lam_k) / (1 + R), (1 / lam_k) / (1 - R), P)
+    lam_e = lamL / (1 - (d * x0).sum(1))
+    pk = np.column_stack([x0, d, lam_e, np.full(P, 1.0 / P)])
+    C = w.n_cells
+    line = np.array([lam_k])
+    tau0 = np.array([0.7], np.float32)
+    ones = np.ones(C, np.float32)
+    say("case: explicit inward packets through the outer sphere, one line")
+    S = oracle.Sphere(w.r_edge, w.theta_edge, w.n_phi)
+    inp = oracle.TransportInputs(1, 1.0, ones, np.zeros(C), np.zeros(C, np.int32), line, tau0,
+                                 0, 0, 1, explicit_packets=pk, sphere=S)
+    r = oracle.transport(inp)
+    ref = oracle.dense_estimator(r["records"], C, 1)
+    grid = ex.spherical_grid(w.r_edge, w.theta_edge, w.n_phi, ones, np.zeros(C),
+                             np.zeros(C, np.int32), line, tau0)
+    est, st, _ = ex.transport(ctx, grid, 1, 0, 0, P, explicit_packets=pk)
+    torch.cuda.synchronize()
+    met = _near_tie_metric(est.cpu().numpy(), ref, r["records"], w)
+    sd = ex.stats_dict(st)
+    say(met)
+    assert sd["bad_packets"] == 0
+    assert met["clean_max_rel"] <= 1e-9 and met["moved"] == 0
+    assert abs(sd["n_inter"] - r["stats"]["n_inter"]) <= met["near_ties"]
+
+
+def test_photoionisation_on_spherical_grid(ex, ctx, sph):
+    w = sph
+    aw = synth.clumpy(n=16, n_lines=1000, n_packets=1000, number=12)
+    ie = synth.ion_energies(12, aw.atom)
+    g = np.random.default_rng(6)
+    pops = 10 ** g.uniform(0.0, 2.0, (w.n_cells, aw.atom.n_levels))
+    pl = oracle.pi_levels(oracle.nlte_inputs_from_workload(aw), ie, 25)
+    photo = dict(level=pl["level"], sigma0=pl["sigma0"], pops=pops, length=C_LIGHT * w.t_exp,
+                 **{"lambda": pl["lambda"]})
+    inp, _ = _oracle_inputs(w, photoion=photo)
+    say("case: spherical grid with photoionisation (oracle serial)")
+    r = oracle.transport(inp)
+    V = w.cell_volumes()
+    gamma_ref = np.zeros((w.n_cells, aw.atom.n_levels))
+    for j, lv in enumerate(pl["level"]):
+        gamma_ref[:, lv] = r["pi_absorbed"][:, j] / pops[:, lv] / V
+    atom = ex.Atom(ctx, aw.atom)
+    plan = ex.PiPlan(ctx, atom, ie, 25)
+    grid = _gpu_grid(ex, w)
+    opac = plan.opacity(torch.as_tensor(pops, device="cuda:0"))
+    grid.photoion = ex.Photoion(plan, opac, w.t_exp)
+    est, st, _ = ex.transport(ctx, grid, w.seed, w.lambda_lo, w.lambda_hi, w.n_packets)
+    torch.cuda.synchronize()
+    sd = ex.stats_dict(st)
+    say(f"photoionised fraction {sd['w_pi'] / sd['w_emit']:.3f}")
+    assert sd["w_pi"] == pytest.approx(r["stats"]["w_pi"], rel=1e-9)
+    # per level: the tally's shares against the oracle's absorbed photons
+    tally = grid.photoion.tally.cpu().numpy()
+    M = plan.M
+    a = opac.cpu().numpy()[:, M + 1:]
+    got = a * (np.cumsum(tally[:, :M], axis=1) + tally[:, M:])
+    order = np.argsort(pl["lambda"], kind="stable")
+    ref_ab = r["pi_absorbed"][:, order]
+    on = ref_ab > 1e-12 * ref_ab.max()
+    rel = np.abs(got[on] - ref_ab[on]) / ref_ab[on]
+    say(f"absorbed per (cell, level): max rel {rel.max():.2e} over {int(on.sum())}")
+    assert rel.max() <= 1e-8
+
+
+def test_spherical_arguments(ex, ctx, sph):
+    w = sph
+    grid = _gpu_grid(ex, w)
+    say("case: spherical grid with the streamed entry, rays, a bad grid")
+    with pytest.raises(ex.ExtrassError, match="invalid argument"):
+        ex.transport_streamed(ctx, grid, w.seed, w.lambda_lo, w.lambda_hi, w.n_packets)
+    bad = ex.spherical_grid(w.r_edge, w.theta_edge, w.n_phi, w.tau_scale, w.cell_photons,
+                            w.cell_packets, w.line_lambda, w.line_tau0)
+    bad.spherical.n_phi = 0
+    with pytest.raises(ex.ExtrassError, match="invalid argument"):
+        ex.transport(ctx, bad, w.seed, w.lambda_lo, w.lambda_hi, 1000)
+    # an explicit packet beyond the outer sphere is dropped and flagged
+    R = w.r_edge[-1]
+    pk = np.array([[2 * R, 0, 0, -1, 0, 0, 5000 * A, 1.0], [0.5 * R, 0, 0, 1, 0, 0, 5000 * A, 1.0]])
+    _, st, _ = ex.transport(ctx, grid, 1, 0, 0, 2, explicit_packets=pk)
+    torch.cuda.synchronize()
+    sd = ex.stats_dict(st)
+    assert sd["bad_packets"] == 1.0 and sd["w_emit"] == pytest.approx(1.0)
