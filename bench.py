@@ -232,6 +232,8 @@ def main():
         torch.cuda.empty_cache()
         out["photoionisation"] = bench_photoion(ex, ctx, w50)
         torch.cuda.empty_cache()
+        out["spherical_grid"] = bench_spherical(ex, ctx)
+        torch.cuda.empty_cache()
         out["spectrum"] = bench_spectrum(ex, ctx, w50)
         torch.cuda.empty_cache()
         out["batched_nlte"] = bench_batched(ex, ctx)
@@ -470,6 +472,46 @@ def bench_photoion(ex, ctx, w):
                 "rate_range_s": [float(g[g > 0].min()), float(g.max())] if (g > 0).any() else None,
                 "slowdown": res["photoion"]["ms_transport"] / res["plain"]["ms_transport"]})
     return res
+
+
+def bench_spherical(ex, ctx):
+    """Transport on the paper's spherical (r, theta, phi) grid: 48 x 32 x 64 =
+    98 304 cells (shells growing outwards), 5000 background lines, 1e7
+    sampled packets, FP64 geometry; the estimator table [C x L] written as in
+    the cube's step; unsplit, and streamed over 8 phi domains (the paper's
+    decomposition). HIP events, median of 5."""
+    import numpy as np
+    import torch
+    import synth
+    dev = "cuda:0"
+    w = synth.spherical(48, 32, 64, 5000, 10_000_000, number=8)
+    grid = ex.spherical_grid(w.r_edge, w.theta_edge, w.n_phi, w.tau_scale, w.cell_photons,
+                             w.cell_packets, w.line_lambda, w.line_tau0, device=dev, n_domains=8)
+    est = torch.empty((w.n_cells, w.n_lines), dtype=torch.float64, device=dev)
+    stats = torch.empty(ex.STATS, dtype=torch.float64, device=dev)
+    s = torch.cuda.current_stream()
+    out = {"workload": w.name, "cells": w.n_cells, "lines": w.n_lines, "packets": w.n_packets}
+    for name in ("unsplit", "streamed_8_phi_domains"):
+        times = []
+        for _ in range(6):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            if name == "unsplit":
+                ex.transport(ctx, grid, w.seed, w.lambda_lo, w.lambda_hi, w.n_packets, est=est,
+                             stats=stats)
+            else:
+                ex.transport_streamed(ctx, grid, w.seed, w.lambda_lo, w.lambda_hi, w.n_packets,
+                                      stats=stats)
+            e1.record(s)
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+        sd = ex.stats_dict(stats)
+        ms = float(np.median(times[1:]))
+        out[name] = {"ms": ms, "interactions": sd["n_inter"],
+                     "line_interactions_per_s": sd["n_inter"] / (ms * 1e-3),
+                     "crossings_per_packet": sd["n_cross"] / w.n_packets,
+                     "escaped_fraction": sd["w_esc"] / sd["w_emit"]}
+    return out
 
 
 def bench_rays(ex, ctx, w, n_rays=2_000_000_000):

@@ -108,13 +108,17 @@ typedef struct {
  * shell's edges (u0), cos(theta) uniform in the polar bin (u1) and phi
  * uniform in the slice (u2) for the position; the direction, wavelength and
  * weight are drawn as in the cube. Explicit packets start in the cell their
- * position falls in. Spherical grids run with FP64 positions and distances
- * (geometry_fp32 is ignored), sampled or explicit packets (no rays), and
- * extrass_transport only (not the streamed entry). */
+ * position falls in; one beyond the outer sphere is dropped and flagged
+ * (EXTRASS_STAT_BAD_PACKETS). Spherical grids run with FP64 positions and
+ * distances (geometry_fp32 is ignored) and sampled or explicit packets (no
+ * rays). extrass_transport_streamed splits them into n_domains equal ranges of
+ * phi (Sec. 2.4.1's phi decomposition; each a contiguous range of cells). */
 typedef struct extrass_spherical {
   int32_t n_r, n_theta, n_phi;  /* each >= 1; C at most 2^31 - 1 */
   const double* r_edge;         /* device [n_r + 1], increasing */
   const double* theta_edge;     /* device [n_theta + 1], increasing */
+  int32_t n_domains;            /* streamed transport: phi subdomains, >= 2, dividing n_phi
+                                   (not read elsewhere) */
 } extrass_spherical;
 
 /* Photoionisation in the transport (Sec. 2.3.1; Eq. A5). M photoionising
@@ -383,6 +387,10 @@ int extrass_rates(extrass_handle h, extrass_atom_handle atom, const extrass_grid
  *
  * n: even. est_octant: device [(n/2)^3 * L] (local cell i + (n/2)(j + (n/2) k)
  * within the octant, octant o = (i >= n/2) + 2 (j >= n/2) + 4 (k >= n/2)).
+ * A spherical grid is split instead into its n_domains equal phi ranges (the
+ * paper's phi decomposition), visited in order for at most n_domains rounds
+ * (each range is convex); est_octant is then [C / n_domains * L], the
+ * subdomain's cells in their global order, and V is each cell's own volume.
  * est_octant may be NULL when only the rates are wanted (atom given,
  * est_global NULL, the grid's tau_ct/line_trans set and line_trans the
  * inverse of the atom's transition -> line map, else EXTRASS_EINVAL): each
@@ -390,8 +398,8 @@ int extrass_rates(extrass_handle h, extrass_atom_handle atom, const extrass_grid
  * gamma_pe[c,t], which is divided by n_l V at the end. No octant table is
  * kept and no flush runs; lines of no atom transition are not recorded. The
  * rates equal the table path's up to the order of the additions.
- * queue_capacity: packets each octant's queue holds; the workspace holds 8
- * queues of 120-byte records. A full queue loses packets: stats[QUEUE_FULL]
+ * queue_capacity: packets each subdomain's queue holds; the workspace holds one
+ * queue of 120-byte records per subdomain. A full queue loses packets: stats[QUEUE_FULL]
  * is set and the call returns EXTRASS_ENOSPACE. The host waits for the stream
  * between visits (queue lengths decide the next launch). */
 size_t extrass_transport_streamed_workspace(const extrass_grid* grid, int64_t queue_capacity);

@@ -41,7 +41,7 @@ class _Grid(C.Structure):
 
 class _Spherical(C.Structure):
     _fields_ = [("n_r", C.c_int32), ("n_theta", C.c_int32), ("n_phi", C.c_int32),
-                ("r_edge", C.c_void_p), ("theta_edge", C.c_void_p)]
+                ("r_edge", C.c_void_p), ("theta_edge", C.c_void_p), ("n_domains", C.c_int32)]
 
 
 class _Photoion(C.Structure):
@@ -267,7 +267,8 @@ class Spherical:
     x = v/c from 0, polar edges theta_edge [n_theta + 1] from 0 to pi, n_phi
     equal azimuthal slices; cell i_r + n_r (i_theta + n_theta i_phi)."""
 
-    def __init__(self, r_edge, theta_edge, n_phi, device="cuda:0"):
+    def __init__(self, r_edge, theta_edge, n_phi, device="cuda:0", n_domains=0):
+        self.n_domains = int(n_domains)  # phi subdomains of the streamed transport
         self.r_edge = _dev(r_edge, torch.float64, device)
         self.theta_edge = _dev(theta_edge, torch.float64, device)
         self.n_r = int(self.r_edge.numel()) - 1
@@ -277,14 +278,16 @@ class Spherical:
 
     def struct(self):
         return _Spherical(self.n_r, self.n_theta, self.n_phi, _ptr(self.r_edge),
-                          _ptr(self.theta_edge))
+                          _ptr(self.theta_edge), self.n_domains)
 
 
 def spherical_grid(r_edge, theta_edge, n_phi, tau_scale, cell_photons, cell_packets, line_lambda,
-                   line_tau0, device="cuda:0", line_trans=None, tau_ct=None, fcorr_ct=None):
+                   line_tau0, device="cuda:0", line_trans=None, tau_ct=None, fcorr_ct=None,
+                   n_domains=0):
     """A Grid whose cells are those of a spherical grid (the per-cell arrays
-    have n_r n_theta n_phi entries)."""
-    sph = Spherical(r_edge, theta_edge, n_phi, device)
+    have n_r n_theta n_phi entries); n_domains phi subdomains for the
+    streamed transport."""
+    sph = Spherical(r_edge, theta_edge, n_phi, device, n_domains)
     g = Grid(1, 1.0, tau_scale, cell_photons, cell_packets, line_lambda, line_tau0, device,
              line_trans, tau_ct, fcorr_ct)
     g.spherical = sph
@@ -525,9 +528,10 @@ def transport_streamed(ctx: Context, grid: Grid, seed, lambda_lo, lambda_hi, n_p
     g = grid.struct()
     s = _Source(int(seed), int(iteration), 0, int(n_packets), float(lambda_lo), float(lambda_hi),
                 None, 1 if geometry_fp32 else 0)
-    half = grid.n // 2
+    sub_cells = (grid.n_cells // max(1, grid.spherical.n_domains) if grid.spherical is not None
+                 else (grid.n // 2) ** 3)
     if est_octant is None and octant_table:
-        est_octant = torch.empty((half ** 3, grid.n_lines), dtype=torch.float64, device=dev)
+        est_octant = torch.empty((sub_cells, grid.n_lines), dtype=torch.float64, device=dev)
     eg = (torch.empty((grid.n_cells, grid.n_lines), dtype=torch.float64, device=dev)
           if est_global else None)
     if stats is None:

@@ -325,13 +325,13 @@ extern "C" int extrass_line_tau(extrass_handle h, extrass_atom_handle a, int64_t
 // ---------------------------------------------------------------- rates
 __global__ void k_rates(int64_t n_cells, int L, int N, int T, const double* __restrict__ est,
                         const double* __restrict__ pops, const int32_t* __restrict__ lo,
-                        const int32_t* __restrict__ line, double V, double* __restrict__ gamma) {
+                        const int32_t* __restrict__ line, CellVolume V, double* __restrict__ gamma) {
   const int64_t total = n_cells * T;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t c = e / T;
     const int t = static_cast<int>(e - c * T);
-    const double Nl = pops[c * N + lo[t]] * V;
+    const double Nl = pops[c * N + lo[t]] * V(c);
     const double x = est[c * L + line[t]];
     gamma[e] = Nl > 0.0 ? x / Nl : 0.0;
   }
@@ -340,15 +340,15 @@ __global__ void k_rates(int64_t n_cells, int L, int N, int T, const double* __re
 extern "C" int extrass_rates(extrass_handle h, extrass_atom_handle a, const extrass_grid* g,
                              double t_exp, const double* est, const double* pops,
                              double* gamma_pe, void* stream) {
-  if (!h || !a || !g || !est || !pops || !gamma_pe || g->n <= 0 || g->n > 1024 ||
-      g->n_lines <= 0 || !(g->beta_max > 0.0) || !(t_exp > 0.0))
+  if (!h || !a || !g || !est || !pops || !gamma_pe || !grid_shape_ok(g) || g->n_lines <= 0 ||
+      !(t_exp > 0.0))
     return fail(h, EXTRASS_EINVAL, "extrass_rates: bad argument");
   if (a->maxLine >= g->n_lines)
     return fail(h, EXTRASS_EINVAL, "extrass_rates: a transition's line index is beyond the grid's lines");
-  const int64_t n_cells = (int64_t)g->n * g->n * g->n;
+  const int64_t n_cells = grid_cell_count(g);
   if (a->T == 0) return EXTRASS_OK;
   EXTRASS_HIP_TRY(h, hipSetDevice(h->device));
-  const double V = extrass::cell_volume(g->n, g->beta_max, t_exp);
+  const CellVolume V = grid_volumes(g, t_exp);
   const int64_t total = n_cells * a->T;
   int64_t blocks = std::min<int64_t>((total + 255) / 256, 65536);
   hipLaunchKernelGGL(k_rates, dim3((unsigned)blocks), dim3(256), 0,

@@ -59,6 +59,61 @@ inline double cell_volume(int n, double beta_max, double t_exp) {
   return w * w * w;
 }
 
+// The cells' volumes of a grid: one value for the cube, or per cell from the
+// edges of a spherical grid, (r_b^3 - r_a^3)/3 (cos theta_a - cos theta_b)
+// (2 pi / n_phi) (c t)^3 for cell c = i_r + n_r (i_theta + n_theta i_phi).
+struct CellVolume {
+  double cube = 0.0;            // the cube's cell volume (sph == false)
+  bool sph = false;
+  int nr = 0, nt = 0, np = 0;
+  const double* r = nullptr;    // device [nr + 1]
+  const double* th = nullptr;   // device [nt + 1]
+  double ct3 = 0.0;             // (c t)^3
+  __device__ double operator()(int64_t c) const {
+    if (!sph) return cube;
+    const int ir = (int)(c % nr);
+    const int it = (int)((c / nr) % nt);
+    const double ra = r[ir], rb = r[ir + 1];
+    return (rb * rb * rb - ra * ra * ra) / 3.0 * (cos(th[it]) - cos(th[it + 1])) *
+           (2.0 * M_PI / np) * ct3;
+  }
+};
+
+// The grid's cell count and volumes at time t_exp (host).
+inline int64_t grid_cell_count(const extrass_grid* g) {
+  if (g->spherical)
+    return (int64_t)g->spherical->n_r * g->spherical->n_theta * g->spherical->n_phi;
+  return (int64_t)g->n * g->n * g->n;
+}
+
+inline CellVolume grid_volumes(const extrass_grid* g, double t_exp) {
+  CellVolume v;
+  if (g->spherical) {
+    const double ct = 2.99792458e10 * t_exp;
+    v.sph = true;
+    v.nr = g->spherical->n_r;
+    v.nt = g->spherical->n_theta;
+    v.np = g->spherical->n_phi;
+    v.r = g->spherical->r_edge;
+    v.th = g->spherical->theta_edge;
+    v.ct3 = ct * ct * ct;
+  } else {
+    v.cube = cell_volume(g->n, g->beta_max, t_exp);
+  }
+  return v;
+}
+
+// A grid's shape is valid: a cube of 1..1024 cells per axis with beta_max > 0,
+// or a spherical grid with every count >= 1, edge arrays and C < 2^31.
+inline bool grid_shape_ok(const extrass_grid* g) {
+  if (g->spherical) {
+    const extrass_spherical* p = g->spherical;
+    return p->n_r >= 1 && p->n_theta >= 1 && p->n_phi >= 1 && p->r_edge && p->theta_edge &&
+           (int64_t)p->n_r * p->n_theta * p->n_phi <= 2147483647LL;
+  }
+  return g->n > 0 && g->n <= 1024 && g->beta_max > 0.0;
+}
+
 template <class T>
 inline size_t carve_bytes(size_t count) {
   return ((count * sizeof(T) + 255) & ~size_t(255)) + 256;

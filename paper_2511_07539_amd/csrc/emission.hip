@@ -174,7 +174,7 @@ extern "C" int extrass_emission_plan_info(extrass_emission_plan p, int32_t* n_bi
 extern "C" int extrass_emission(extrass_handle h, extrass_emission_plan p, extrass_atom_handle a,
                                 const extrass_grid* g, double t_exp, const double* pops,
                                 double* bin_photons, double* outside, void* stream) {
-  if (!h || !p || !a || !g || !pops || !bin_photons || g->n <= 0 || g->n > 1024 ||
+  if (!h || !p || !a || !g || !pops || !bin_photons || g->spherical || g->n <= 0 || g->n > 1024 ||
       !(g->beta_max > 0.0) || !(t_exp > 0.0) || p->T != a->T || p->device != h->device)
     return fail(h, EXTRASS_EINVAL, "extrass_emission: bad argument");
   const int64_t C = (int64_t)g->n * g->n * g->n;

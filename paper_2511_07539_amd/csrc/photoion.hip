@@ -66,9 +66,10 @@ __global__ void k_pi_opacity(int64_t C, int N, int M, const int32_t* __restrict_
 // full-move absorptions; Q_j adds the moves cut at the level's threshold.
 __global__ void k_pi_rates(int64_t C, int N, int M, const int32_t* __restrict__ level,
                            const double* __restrict__ coef, const double* __restrict__ tally,
-                           double inv_V, double* __restrict__ gamma_pi) {
+                           CellVolume V, double* __restrict__ gamma_pi) {
   for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < C;
        c += (int64_t)gridDim.x * blockDim.x) {
+    const double inv_V = 1.0 / V(c);
     double* out = gamma_pi + c * N;
     for (int i = 0; i < N; ++i) out[i] = 0.0;
     const double* tc = tally + c * 2 * M;
@@ -173,14 +174,14 @@ extern "C" int extrass_pi_opacity(extrass_handle h, extrass_pi_plan p, int64_t n
 extern "C" int extrass_pi_rates(extrass_handle h, extrass_pi_plan p, const extrass_grid* g,
                                 double t_exp, const double* tally, double* gamma_pi,
                                 void* stream) {
-  if (!h || !p || !g || !tally || !gamma_pi || g->n <= 0 || g->n > 1024 ||
-      !(g->beta_max > 0.0) || !(t_exp > 0.0) || p->device != h->device)
+  if (!h || !p || !g || !tally || !gamma_pi || !grid_shape_ok(g) || !(t_exp > 0.0) ||
+      p->device != h->device)
     return fail(h, EXTRASS_EINVAL, "extrass_pi_rates: bad argument");
-  const int64_t C = (int64_t)g->n * g->n * g->n;
+  const int64_t C = grid_cell_count(g);
   EXTRASS_HIP_TRY(h, hipSetDevice(h->device));
   hipLaunchKernelGGL(k_pi_rates, dim3(grid_for(C)), dim3(256), 0, static_cast<hipStream_t>(stream),
-                     C, p->N, p->M, p->d.level, p->d.coef, tally,
-                     1.0 / cell_volume(g->n, g->beta_max, t_exp), gamma_pi);
+                     C, p->N, p->M, p->d.level, p->d.coef, tally, grid_volumes(g, t_exp),
+                     gamma_pi);
   EXTRASS_HIP_TRY(h, hipGetLastError());
   return EXTRASS_OK;
 }

@@ -91,6 +91,8 @@ struct TArgs {
   // octant mode (oct >= 0)
   int oct, half;
   int lo[3];                 // first cell index of the octant per axis
+  int sub_slices;            // spherical grid: phi slices per subdomain (0: octants of the cube)
+  int64_t sub_c0;            // spherical grid: first cell of the current subdomain
   int64_t n_emit;            // packets emitted in this visit (first visit only)
   const int64_t* ostart;     // [Coct+1] prefix of cell_packets over the octant's cells
   const struct QPk* inbox;   // packets entering this octant
@@ -302,22 +304,26 @@ void scan_counts(hipStream_t st, const int32_t* counts, int64_t m, int n, int oc
 // the row, so that the octant table is all zero again for the next visit.
 // One work-group per row; untouched rows return at once.
 __global__ __launch_bounds__(256) void k_octant_flush(double* __restrict__ eo, uint8_t* touched,
-                                                      int n, int oct, int L, int N, int T,
-                                                      const int32_t* __restrict__ lo,
+                                                      int n, int oct, int64_t c0, int L, int N,
+                                                      int T, const int32_t* __restrict__ lo,
                                                       const int32_t* __restrict__ line,
-                                                      const double* __restrict__ pops, double V,
-                                                      double* __restrict__ gamma,
+                                                      const double* __restrict__ pops,
+                                                      CellVolume V, double* __restrict__ gamma,
                                                       double* __restrict__ eg) {
   const int64_t r = blockIdx.x;
   if (!touched[r]) return;
-  const int half = n / 2;
-  const int o0 = (oct & 1) ? half : 0, o1 = (oct & 2) ? half : 0, o2 = (oct & 4) ? half : 0;
-  const int i = (int)(r % half), j = (int)((r / half) % half), k = (int)(r / ((int64_t)half * half));
-  const int64_t c = (i + o0) + (int64_t)n * ((j + o1) + (int64_t)n * (k + o2));
+  int64_t c = c0 + r;  // a phi subdomain (c0 >= 0): contiguous cells
+  if (c0 < 0) {        // an octant of the cube
+    const int half = n / 2;
+    const int o0 = (oct & 1) ? half : 0, o1 = (oct & 2) ? half : 0, o2 = (oct & 4) ? half : 0;
+    const int i = (int)(r % half), j = (int)((r / half) % half), k = (int)(r / ((int64_t)half * half));
+    c = (i + o0) + (int64_t)n * ((j + o1) + (int64_t)n * (k + o2));
+  }
   double* row = eo + r * L;
+  const double Vc = gamma ? V(c) : 0.0;
   if (gamma)
     for (int t = threadIdx.x; t < T; t += blockDim.x) {
-      const double Nl = pops[c * N + lo[t]] * V;
+      const double Nl = pops[c * N + lo[t]] * Vc;
       if (Nl > 0.0) gamma[c * T + t] += row[line[t]] / Nl;
     }
   if (eg)
@@ -329,14 +335,14 @@ __global__ __launch_bounds__(256) void k_octant_flush(double* __restrict__ eo, u
 
 // Rates from the direct sums: gamma_pe[c,t] = sum(dN / f_corr) / (n_l V).
 __global__ void k_rates_direct(int64_t C, int N, int T, const int32_t* __restrict__ lo,
-                               const double* __restrict__ pops, double V,
+                               const double* __restrict__ pops, CellVolume V,
                                double* __restrict__ gamma) {
   const int64_t total = C * T;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t c = e / T;
     const int t = (int)(e - c * T);
-    const double Nl = pops[c * N + lo[t]] * V;
+    const double Nl = pops[c * N + lo[t]] * V(c);
     gamma[e] = Nl > 0.0 ? gamma[e] / Nl : 0.0;
   }
 }
@@ -693,6 +699,8 @@ struct Tally {
 // Octant mode: the idx-th packet emitted in the octant (its cells in local
 // order, each cell's packets in id order) is global packet start[c] + j.
 __device__ __forceinline__ int64_t octant_packet(const TArgs& A, int64_t idx) {
+  // a phi subdomain's cells are contiguous, and so are their packet ids
+  if (A.sub_slices) return A.start[A.sub_c0] + idx;
   const int64_t Co = (int64_t)A.half * A.half * A.half;
   int64_t lo = 0, hi = Co;
   while (hi - lo > 1) {
@@ -952,7 +960,9 @@ __device__ __forceinline__ void transport_body(const TArgs& A) {
       } else {
         t.cross++;
         if (A.oct >= 0) {
-          const int dst = (q.ci[0] >= A.half) | ((q.ci[1] >= A.half) << 1) | ((q.ci[2] >= A.half) << 2);
+          const int dst = A.sub_slices ? q.ci[2] / A.sub_slices
+                                       : (q.ci[0] >= A.half) | ((q.ci[1] >= A.half) << 1) |
+                                             ((q.ci[2] >= A.half) << 2);
           if (dst != A.oct) {  // hand the packet to its next octant
             const unsigned long long slot = atomicAdd(A.qtail + dst, 1ull);
             if ((int64_t)slot < A.qcap) store<G>(A.qbase + (int64_t)dst * A.qcap + (int64_t)slot, q, pid);
@@ -994,6 +1004,7 @@ __device__ __forceinline__ void transport_body(const TArgs& A) {
       const int64_t c = SPH ? q.ci[0] + (int64_t)A.sph_nr * (q.ci[1] + (int64_t)A.sph_nt * q.ci[2])
                             : q.ci[0] + (int64_t)A.n * (q.ci[1] + (int64_t)A.n * q.ci[2]);
       const int64_t row = A.oct < 0 ? c
+          : A.sub_slices ? c - A.sub_c0
           : (q.ci[0] - A.lo[0]) + (int64_t)A.half * ((q.ci[1] - A.lo[1]) + (int64_t)A.half * (q.ci[2] - A.lo[2]));
       const int k = q.k;
       t.checks++;
@@ -1111,13 +1122,6 @@ struct TransportWs {
   double* sph_cs = nullptr;   // spherical grid: cos, sin of the azimuthal edges
 };
 
-// Cells of the grid: n^3 for the cube, n_r n_theta n_phi for a spherical grid.
-static int64_t grid_cells(const extrass_grid* g) {
-  if (g->spherical)
-    return (int64_t)g->spherical->n_r * g->spherical->n_theta * g->spherical->n_phi;
-  return (int64_t)g->n * g->n * g->n;
-}
-
 // Spherical-grid fields of A from the grid (none for the cube); false when
 // they are invalid.
 static bool set_spherical(const extrass_grid* g, TArgs& A) {
@@ -1137,7 +1141,7 @@ static bool set_spherical(const extrass_grid* g, TArgs& A) {
 }
 
 static size_t ws_layout(const extrass_grid* g, const extrass_source* s, TransportWs* w, void* ws) {
-  const int64_t C = grid_cells(g);
+  const int64_t C = grid_cell_count(g);
   Carver cv(ws, ~size_t(0));
   TransportWs t;
   t.start = cv.take<int64_t>(C + 1);
@@ -1234,7 +1238,7 @@ extern "C" int extrass_transport(extrass_handle h, const extrass_grid* g, const 
 
   hipStream_t st = static_cast<hipStream_t>(stream);
   EXTRASS_HIP_TRY(h, hipSetDevice(h->device));
-  const int64_t C = grid_cells(g);
+  const int64_t C = grid_cell_count(g);
   const int L = g->n_lines;
 
   const int has_ct = (g->tau_ct && g->line_trans) ? 1 : 0;
@@ -1341,34 +1345,64 @@ extern "C" int extrass_transport_noalloc(extrass_handle h, const extrass_grid* g
 // ---- streamed transport over velocity octants --------------------------------
 
 namespace {
+// Subdomains of the streamed transport: the cube's 8 velocity octants, or a
+// spherical grid's n_domains equal ranges of phi (contiguous cells). Both are
+// convex, so a straight ray enters each at most once.
+struct Domains {
+  int n = 8;         // subdomains
+  int64_t Co = 0;    // cells per subdomain
+  int slices = 0;    // spherical grid: phi slices per subdomain (0: octants)
+  int rounds = 5;    // passes over the subdomains that drain every queue
+};
+
+Domains domains_of(const extrass_grid* g) {
+  Domains d;
+  if (g->spherical) {
+    d.n = g->spherical->n_domains;
+    d.slices = d.n > 0 ? g->spherical->n_phi / d.n : 0;
+    d.Co = d.n > 0 ? grid_cell_count(g) / d.n : 0;
+    d.rounds = d.n + 1;
+  } else {
+    const int64_t half = g->n / 2;
+    d.Co = half * half * half;
+  }
+  return d;
+}
+
 struct StreamWs {
   int64_t* start;
   LineRec* lines;
-  unsigned long long* counters;  // [0] packet pool, [1..8] queue tails
-  int64_t* ostart;               // 8 x (Co + 1)
-  QPk* queues;                   // 8 x qcap
+  unsigned long long* counters;  // [0] packet pool, [1..n] queue tails, [n + 1] map flag
+  int64_t* ostart;               // octants: 8 x (Co + 1)
+  QPk* queues;                   // n x qcap
   uint8_t* touched;              // [Co]
   int64_t* tsum;                 // tile sums of the packet-count scans
   int32_t* lam_bin;              // [lam_bins(L)]
   double* lam_par;               // [2]
+  double* sph_cth;               // spherical grid: cos of the polar edges
+  double* sph_cs;                // spherical grid: cos, sin of the azimuthal edges
   size_t need;
 };
 
 StreamWs stream_layout(const extrass_grid* g, int64_t qcap, void* ws) {
-  const int64_t C = (int64_t)g->n * g->n * g->n;
-  const int64_t half = g->n / 2;
-  const int64_t Co = half * half * half;
+  const int64_t C = grid_cell_count(g);
+  const Domains dm = domains_of(g);
+  const int64_t Co = dm.Co;
   Carver cv(ws, ~size_t(0));
-  StreamWs w;
+  StreamWs w{};
   w.start = cv.take<int64_t>(C + 1);
   w.lines = cv.take<LineRec>(g->n_lines > 0 ? g->n_lines : 1);
-  w.counters = cv.take<unsigned long long>(16);
-  w.ostart = cv.take<int64_t>(8 * (Co + 1));
-  w.queues = cv.take<QPk>((size_t)(8 * (qcap > 0 ? qcap : 1)));
+  w.counters = cv.take<unsigned long long>(dm.n + 8);
+  if (!dm.slices) w.ostart = cv.take<int64_t>(8 * (Co + 1));
+  w.queues = cv.take<QPk>((size_t)(dm.n * (qcap > 0 ? qcap : 1)));
   w.touched = cv.take<uint8_t>(Co);
   w.tsum = cv.take<int64_t>((C + kScanTile - 1) / kScanTile + 1);
   w.lam_bin = cv.take<int32_t>(lam_bins(g->n_lines));
   w.lam_par = cv.take<double>(2);
+  if (g->spherical) {
+    w.sph_cth = cv.take<double>(g->spherical->n_theta + 1);
+    w.sph_cs = cv.take<double>(2 * (g->spherical->n_phi + 1));
+  }
   w.need = cv.used + 256;
   return w;
 }
@@ -1382,8 +1416,17 @@ void zero_doubles(double* p, int64_t n, hipStream_t st) {
 }
 }  // namespace
 
+// A grid the streamed transport can split: an even cube, or a spherical grid
+// whose n_phi slices divide into n_domains >= 2 equal subdomains.
+static bool streamable(const extrass_grid* g) {
+  if (!grid_shape_ok(g)) return false;
+  if (g->spherical)
+    return g->spherical->n_domains >= 2 && g->spherical->n_phi % g->spherical->n_domains == 0;
+  return (g->n & 1) == 0;
+}
+
 extern "C" size_t extrass_transport_streamed_workspace(const extrass_grid* g, int64_t queue_capacity) {
-  if (!g || g->n <= 0 || (g->n & 1) || queue_capacity < 0) return 0;
+  if (!g || !streamable(g) || queue_capacity < 0) return 0;
   return stream_layout(g, queue_capacity, nullptr).need;
 }
 
@@ -1402,31 +1445,33 @@ extern "C" int extrass_transport_streamed(extrass_handle h, const extrass_grid* 
     return fail(h, EXTRASS_EINVAL,
                 "extrass_transport_streamed: without est_octant, rates need the atom, the grid's "
                 "transition opacities and no est_global");
-  if (g->n <= 0 || g->n > 1024 || (g->n & 1) || g->n_lines <= 0 || !(g->beta_max > 0.0) ||
-      !g->line_lambda || !g->line_tau0 || !g->tau_scale || !g->cell_packets || !g->cell_photons)
-    return fail(h, EXTRASS_EINVAL, "extrass_transport_streamed: bad grid (n must be even)");
+  if (!streamable(g) || g->n_lines <= 0 || !g->line_lambda || !g->line_tau0 || !g->tau_scale ||
+      !g->cell_packets || !g->cell_photons)
+    return fail(h, EXTRASS_EINVAL,
+                "extrass_transport_streamed: bad grid (an even cube, or n_domains dividing n_phi)");
   if (g->tau_ct && (!g->line_trans || g->n_trans <= 0))
     return fail(h, EXTRASS_EINVAL, "extrass_transport_streamed: tau_ct needs line_trans and n_trans");
   if (s->explicit_packets || s->rays || s->first_packet != 0 || s->n_packets < 0)
     return fail(h, EXTRASS_EINVAL, "extrass_transport_streamed: whole sampling plan only");
-  if (g->spherical)
-    return fail(h, EXTRASS_EINVAL, "extrass_transport_streamed: the cube only");
   if (atom && (!pops || !gamma_pe || !(t_exp > 0.0)))
     return fail(h, EXTRASS_EINVAL, "extrass_transport_streamed: rates need pops, gamma_pe, t_exp");
   if (atom && atom->maxLine >= g->n_lines)
     return fail(h, EXTRASS_EINVAL,
                 "extrass_transport_streamed: a transition's line index is beyond the grid's lines");
-  const double cell_volume = atom ? extrass::cell_volume(g->n, g->beta_max, t_exp) : 0.0;
+  const CellVolume cell_volume = grid_volumes(g, atom ? t_exp : 1.0);
   if (queue_capacity <= 0) return fail(h, EXTRASS_EINVAL, "extrass_transport_streamed: queue capacity");
   TArgs A{};
   if (!set_photoion(g, A)) return fail(h, EXTRASS_EINVAL, "extrass_transport_streamed: bad photoion");
+  if (!set_spherical(g, A)) return fail(h, EXTRASS_EINVAL, "extrass_transport_streamed: bad spherical grid");
   StreamWs w = stream_layout(g, queue_capacity, ws);
   if (ws_bytes < w.need) return fail(h, EXTRASS_ENOSPACE, "extrass_transport_streamed: workspace too small");
 
   hipStream_t st = static_cast<hipStream_t>(stream);
   EXTRASS_HIP_TRY(h, hipSetDevice(h->device));
-  const int n = g->n, half = n / 2, L = g->n_lines;
-  const int64_t C = (int64_t)n * n * n, Co = (int64_t)half * half * half;
+  const Domains dm = domains_of(g);
+  const int ND = dm.n;
+  const int n = g->spherical ? 1 : g->n, half = n / 2, L = g->n_lines;
+  const int64_t C = grid_cell_count(g), Co = dm.Co;
 
   const int has_ct = (g->tau_ct && g->line_trans) ? 1 : 0;
   hipLaunchKernelGGL(k_prep, dim3(64), dim3(256), 0, st, g->line_lambda, g->line_tau0,
@@ -1436,13 +1481,21 @@ extern "C" int extrass_transport_streamed(extrass_handle h, const extrass_grid* 
   scan_counts(st, g->cell_packets, C, n, -1, w.tsum, w.start);
   hipLaunchKernelGGL(k_lambin, dim3(64), dim3(256), 0, st, g->line_lambda, L, lam_bins(L),
                      w.lam_bin, w.lam_par);
-  for (int o = 0; o < 8; ++o)
-    scan_counts(st, g->cell_packets, Co, n, o, w.tsum, w.ostart + o * (Co + 1));
-  hipLaunchKernelGGL(k_reset_u64, dim3(1), dim3(64), 0, st, w.counters, 16);
+  if (!dm.slices)
+    for (int o = 0; o < 8; ++o)
+      scan_counts(st, g->cell_packets, Co, n, o, w.tsum, w.ostart + o * (Co + 1));
+  if (g->spherical) {
+    const int m = std::max(A.sph_nt, A.sph_np) + 1;
+    hipLaunchKernelGGL(k_sph_trig, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st,
+                       A.sph_th, A.sph_nt, A.sph_np, w.sph_cth, w.sph_cs);
+    A.sph_cth = w.sph_cth;
+    A.sph_cs = w.sph_cs;
+  }
+  hipLaunchKernelGGL(k_reset_u64, dim3(1), dim3(64), 0, st, w.counters, ND + 8);
   if (atom) zero_doubles(gamma_pe, C * (int64_t)atom->T, st);
   if (est_global) zero_doubles(est_global, C * (int64_t)L, st);
   if (direct) {
-    unsigned long long* flag = w.counters + 15;  // zeroed with the counters above
+    unsigned long long* flag = w.counters + ND + 1;  // zeroed with the counters above
     hipLaunchKernelGGL(k_check_map, dim3(16), dim3(256), 0, st, g->line_trans, L, atom->d.o_line,
                        atom->T, flag);
     unsigned long long bad = 0;
@@ -1458,20 +1511,29 @@ extern "C" int extrass_transport_streamed(extrass_handle h, const extrass_grid* 
   }
   EXTRASS_HIP_TRY(h, hipGetLastError());
 
-  // packets each octant emits, and the plan's total
-  int64_t n_emit[8];
-  for (int o = 0; o < 8; ++o)
-    EXTRASS_HIP_TRY(h, hipMemcpyAsync(&n_emit[o], w.ostart + o * (Co + 1) + Co, sizeof(int64_t),
-                                      hipMemcpyDeviceToHost, st));
-  EXTRASS_HIP_TRY(h, hipStreamSynchronize(st));
+  // packets each subdomain emits, and the plan's total
+  std::vector<int64_t> n_emit(ND, 0);
+  if (dm.slices) {  // contiguous cells: differences of the global prefix
+    std::vector<int64_t> edge(ND + 1, 0);
+    for (int o = 0; o <= ND; ++o)
+      EXTRASS_HIP_TRY(h, hipMemcpyAsync(&edge[o], w.start + o * Co, sizeof(int64_t),
+                                        hipMemcpyDeviceToHost, st));
+    EXTRASS_HIP_TRY(h, hipStreamSynchronize(st));
+    for (int o = 0; o < ND; ++o) n_emit[o] = edge[o + 1] - edge[o];
+  } else {
+    for (int o = 0; o < 8; ++o)
+      EXTRASS_HIP_TRY(h, hipMemcpyAsync(&n_emit[o], w.ostart + o * (Co + 1) + Co, sizeof(int64_t),
+                                        hipMemcpyDeviceToHost, st));
+    EXTRASS_HIP_TRY(h, hipStreamSynchronize(st));
+  }
   int64_t total = 0;
-  for (int o = 0; o < 8; ++o) total += n_emit[o];
+  for (int o = 0; o < ND; ++o) total += n_emit[o];
   if (total != s->n_packets)
     return fail(h, EXTRASS_EINVAL, "extrass_transport_streamed: n_packets differs from the plan");
 
   A.n = n;
-  A.beta = g->beta_max;
-  A.h = 2.0 * g->beta_max / n;
+  A.beta = g->spherical ? 1.0 : g->beta_max;
+  A.h = 2.0 * A.beta / n;
   A.tau_scale = g->tau_scale;
   A.cell_photons = g->cell_photons;
   A.cell_packets = g->cell_packets;
@@ -1498,19 +1560,22 @@ extern "C" int extrass_transport_streamed(extrass_handle h, const extrass_grid* 
   A.pk_out = nullptr;
   A.queue = w.counters;
   A.half = half;
+  A.sub_slices = dm.slices;
   A.qbase = w.queues;
   A.qtail = w.counters + 1;
   A.qcap = queue_capacity;
   A.touched = direct ? nullptr : w.touched;
   A.gdirect = direct ? gamma_pe : nullptr;
 
-  int64_t head[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  unsigned long long tail[8];
-  // a ray crosses each coordinate plane at most once: <= 4 octants, <= 4 rounds
-  for (int round = 0; round < 5; ++round) {
+  std::vector<int64_t> head(ND, 0);
+  std::vector<unsigned long long> tail(ND, 0);
+  // a ray enters each convex subdomain at most once: the cube's octants take
+  // at most 4 rounds, a spherical grid's phi ranges at most n_domains
+  for (int round = 0; round < dm.rounds; ++round) {
     bool any = false;
-    for (int o = 0; o < 8; ++o) {
-      EXTRASS_HIP_TRY(h, hipMemcpyAsync(tail, w.counters + 1, sizeof(tail), hipMemcpyDeviceToHost, st));
+    for (int o = 0; o < ND; ++o) {
+      EXTRASS_HIP_TRY(h, hipMemcpyAsync(tail.data(), w.counters + 1, ND * sizeof(unsigned long long),
+                                        hipMemcpyDeviceToHost, st));
       EXTRASS_HIP_TRY(h, hipStreamSynchronize(st));
       const int64_t avail = std::min<int64_t>((int64_t)tail[o], queue_capacity);
       const int64_t n_in = avail - head[o];
@@ -1522,7 +1587,8 @@ extern "C" int extrass_transport_streamed(extrass_handle h, const extrass_grid* 
       A.lo[0] = (o & 1) ? half : 0;
       A.lo[1] = (o & 2) ? half : 0;
       A.lo[2] = (o & 4) ? half : 0;
-      A.ostart = w.ostart + o * (Co + 1);
+      A.ostart = dm.slices ? nullptr : w.ostart + o * (Co + 1);
+      A.sub_c0 = dm.slices ? (int64_t)o * Co : 0;
       A.n_emit = ne;
       A.inbox = w.queues + (int64_t)o * queue_capacity + head[o];
       A.n_in = n_in;
@@ -1530,11 +1596,13 @@ extern "C" int extrass_transport_streamed(extrass_handle h, const extrass_grid* 
       int64_t blocks = (int64_t)h->num_cus * 8;
       const int64_t max_blocks = (A.count + kBlock - 1) / kBlock;
       if (blocks > max_blocks) blocks = max_blocks;
-      launch_transport(s->geometry_fp32 != 0, false, A.pi_M > 0, false, (unsigned)blocks, st, A);
+      launch_transport(s->geometry_fp32 != 0, false, A.pi_M > 0, g->spherical != nullptr,
+                       (unsigned)blocks, st, A);
       EXTRASS_HIP_TRY(h, hipGetLastError());
       if (!direct)
         hipLaunchKernelGGL(k_octant_flush, dim3((unsigned)Co), dim3(256), 0, st, est_octant,
-                           w.touched, n, o, L, atom ? atom->N : 0, atom ? atom->T : 0,
+                           w.touched, n, o, dm.slices ? (int64_t)o * Co : (int64_t)-1, L,
+                           atom ? atom->N : 0, atom ? atom->T : 0,
                            atom ? atom->d.o_lo : nullptr, atom ? atom->d.o_line : nullptr, pops,
                            cell_volume, atom ? gamma_pe : nullptr, est_global);
       EXTRASS_HIP_TRY(h, hipGetLastError());
@@ -1543,13 +1611,14 @@ extern "C" int extrass_transport_streamed(extrass_handle h, const extrass_grid* 
     if (!any && round > 0) break;
   }
   double full = 0.0;
-  EXTRASS_HIP_TRY(h, hipMemcpyAsync(tail, w.counters + 1, sizeof(tail), hipMemcpyDeviceToHost, st));
+  EXTRASS_HIP_TRY(h, hipMemcpyAsync(tail.data(), w.counters + 1, ND * sizeof(unsigned long long),
+                                    hipMemcpyDeviceToHost, st));
   EXTRASS_HIP_TRY(h, hipMemcpyAsync(&full, stats + EXTRASS_STAT_QUEUE_FULL, sizeof(double),
                                     hipMemcpyDeviceToHost, st));
   EXTRASS_HIP_TRY(h, hipStreamSynchronize(st));
   if (full != 0.0)
-    return fail(h, EXTRASS_ENOSPACE, "extrass_transport_streamed: an octant queue overflowed");
-  for (int o = 0; o < 8; ++o)
+    return fail(h, EXTRASS_ENOSPACE, "extrass_transport_streamed: a subdomain queue overflowed");
+  for (int o = 0; o < ND; ++o)
     if ((int64_t)tail[o] != head[o])
       return fail(h, EXTRASS_EHIP, "extrass_transport_streamed: packets left in a queue");
   if (direct) {

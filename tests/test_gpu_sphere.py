@@ -198,9 +198,7 @@ def test_photoionisation_on_spherical_grid(ex, ctx, sph):
 def test_spherical_arguments(ex, ctx, sph):
     w = sph
     grid = _gpu_grid(ex, w)
-    say("case: spherical grid with the streamed entry, rays, a bad grid")
-    with pytest.raises(ex.ExtrassError, match="invalid argument"):
-        ex.transport_streamed(ctx, grid, w.seed, w.lambda_lo, w.lambda_hi, w.n_packets)
+    say("case: a bad spherical grid; a packet beyond the outer sphere")
     bad = ex.spherical_grid(w.r_edge, w.theta_edge, w.n_phi, w.tau_scale, w.cell_photons,
                             w.cell_packets, w.line_lambda, w.line_tau0)
     bad.spherical.n_phi = 0
@@ -213,3 +211,56 @@ def test_spherical_arguments(ex, ctx, sph):
     torch.cuda.synchronize()
     sd = ex.stats_dict(st)
     assert sd["bad_packets"] == 1.0 and sd["w_emit"] == pytest.approx(1.0)
+
+
+@pytest.mark.parametrize("n_domains", [2, 4, 16])
+def test_streamed_phi_domains_equal_unsplit(ex, ctx, sph, n_domains):
+    """The paper's phi decomposition: the grid split into n_domains equal phi
+    ranges, visited one after another with one range's table resident; the
+    events and estimators equal the unsplit run's (1e-12, the order of the
+    additions)."""
+    w = sph
+    say(f"case: spherical grid streamed over {n_domains} phi domains")
+    grid = ex.spherical_grid(w.r_edge, w.theta_edge, w.n_phi, w.tau_scale, w.cell_photons,
+                             w.cell_packets, w.line_lambda, w.line_tau0, n_domains=n_domains)
+    est, st_u, _ = ex.transport(ctx, grid, w.seed, w.lambda_lo, w.lambda_hi, w.n_packets)
+    _, st_s, eg = ex.transport_streamed(ctx, grid, w.seed, w.lambda_lo, w.lambda_hi, w.n_packets,
+                                        est_global=True)
+    torch.cuda.synchronize()
+    su, ss = ex.stats_dict(st_u), ex.stats_dict(st_s)
+    for k in ("n_inter", "n_checks", "n_cross", "n_escaped", "n_killed"):
+        assert su[k] == ss[k], k
+    for k in ("w_emit", "w_esc", "w_kill", "w_abs"):
+        assert ss[k] == pytest.approx(su[k], rel=1e-12), k
+    a, b = eg.cpu().numpy(), est.cpu().numpy()
+    nz = b != 0
+    assert np.array_equal(a != 0, nz)
+    rel = np.max(np.abs(a[nz] - b[nz]) / b[nz])
+    say(f"estimators max rel {rel:.2e}")
+    assert rel <= 1e-12
+
+
+def test_rates_use_each_spherical_cells_volume(ex, ctx, sph):
+    w = sph
+    aw = synth.clumpy(n=16, n_lines=1000, n_packets=1000, number=12)
+    g = np.random.default_rng(8)
+    pops = 10 ** g.uniform(0.0, 3.0, (w.n_cells, aw.atom.n_levels))
+    est = 10 ** g.uniform(20.0, 30.0, (w.n_cells, 1000))
+    atom = ex.Atom(ctx, aw.atom)
+    grid = ex.spherical_grid(w.r_edge, w.theta_edge, w.n_phi, w.tau_scale, w.cell_photons,
+                             w.cell_packets, np.sort(g.uniform(2000, 25000, 1000)) * A,
+                             np.ones(1000, np.float32))
+    gam = ex.rates(ctx, atom, grid, w.t_exp, torch.as_tensor(est, device="cuda:0"),
+                   torch.as_tensor(pops, device="cuda:0")).cpu().numpy()
+    V = w.cell_volumes()
+    ref = est[:, aw.atom.trans_line] / (pops[:, aw.atom.trans_lower] * V[:, None])
+    np.testing.assert_allclose(gam, ref, rtol=1e-13)
+
+
+def test_streamed_phi_domains_arguments(ex, ctx, sph):
+    w = sph
+    for nd in (0, 1, 3):
+        grid = ex.spherical_grid(w.r_edge, w.theta_edge, w.n_phi, w.tau_scale, w.cell_photons,
+                                 w.cell_packets, w.line_lambda, w.line_tau0, n_domains=nd)
+        with pytest.raises(ex.ExtrassError, match="invalid argument"):
+            ex.transport_streamed(ctx, grid, w.seed, w.lambda_lo, w.lambda_hi, w.n_packets)
