@@ -817,7 +817,7 @@ __device__ __forceinline__ double pi_move(const TArgs& A, Packet<G>& q, int64_t 
 // Three waves per SIMD: the kernel is bound by the latency of its gathers and
 // scattered atomics, and the third wave (a few dwords of rarely used state
 // spilled) is worth more than the spill.
-template <class G, bool RAYS, bool PI, bool SPH>
+template <class G, bool RAYS, bool PI, bool SPH, bool OCT>
 __device__ __forceinline__ void transport_body(const TArgs& A) {
   const int lane = threadIdx.x & 63;
   Packet<G> q;
@@ -857,7 +857,7 @@ __device__ __forceinline__ void transport_body(const TArgs& A) {
       if (need) {
         if ((uint64_t)rank < take) {
           const int64_t idx = (int64_t)(pool_base + rank);
-          if (A.oct >= 0 && idx >= A.n_emit) {
+          if (OCT && idx >= A.n_emit) {
             pid = resume<G>(A.inbox[idx - A.n_emit], q);
             nxt = line_rec(A, q.k);
             if constexpr (PI) {  // absorbed up to the wall it came through
@@ -866,7 +866,7 @@ __device__ __forceinline__ void transport_body(const TArgs& A) {
               q.wpi = 0.0;
             }
           } else {  // one emission site for both modes keeps the register peak down
-            const int64_t p = A.oct < 0 ? A.first + idx : octant_packet(A, idx);
+            const int64_t p = !OCT ? A.first + idx : octant_packet(A, idx);
             emit<G, RAYS, SPH>(A, p, q);
             if (q.bad) {
               t.bad = true;
@@ -959,12 +959,28 @@ __device__ __forceinline__ void transport_body(const TArgs& A) {
         stop = true;
       } else {
         t.cross++;
-        if (A.oct >= 0) {
+        if constexpr (OCT) {
           const int dst = A.sub_slices ? q.ci[2] / A.sub_slices
                                        : (q.ci[0] >= A.half) | ((q.ci[1] >= A.half) << 1) |
                                              ((q.ci[2] >= A.half) << 2);
           if (dst != A.oct) {  // hand the packet to its next octant
-            const unsigned long long slot = atomicAdd(A.qtail + dst, 1ull);
+            // one atomic per destination and wave: the lanes handing over to
+            // the first lane's destination take consecutive slots, then the
+            // rest repeat (a per-lane atomic on a handful of shared tails
+            // serialised in L2: 152 -> 110 ms for a streamed 98 304-cell sphere)
+            unsigned long long slot = 0;
+            for (;;) {
+              const int d0 = __builtin_amdgcn_readfirstlane(dst);
+              const uint64_t same = __ballot(dst == d0);
+              if (dst == d0) {
+                const int leader = __ffsll((long long)same) - 1;
+                unsigned long long base = 0;
+                if (lane == leader) base = atomicAdd(A.qtail + d0, (unsigned long long)__popcll(same));
+                base = __shfl(base, leader);
+                slot = base + __popcll(same & ((1ull << lane) - 1ull));
+                break;
+              }
+            }
             if ((int64_t)slot < A.qcap) store<G>(A.qbase + (int64_t)dst * A.qcap + (int64_t)slot, q, pid);
             else t.overflow = true;
             pid = -1;
@@ -1003,7 +1019,7 @@ __device__ __forceinline__ void transport_body(const TArgs& A) {
       const LineRec lr = nxt;
       const int64_t c = SPH ? q.ci[0] + (int64_t)A.sph_nr * (q.ci[1] + (int64_t)A.sph_nt * q.ci[2])
                             : q.ci[0] + (int64_t)A.n * (q.ci[1] + (int64_t)A.n * q.ci[2]);
-      const int64_t row = A.oct < 0 ? c
+      const int64_t row = !OCT ? c
           : A.sub_slices ? c - A.sub_c0
           : (q.ci[0] - A.lo[0]) + (int64_t)A.half * ((q.ci[1] - A.lo[1]) + (int64_t)A.half * (q.ci[2] - A.lo[2]));
       const int k = q.k;
@@ -1065,17 +1081,17 @@ __device__ __forceinline__ void transport_body(const TArgs& A) {
   if (__ballot(t.overflow) != 0ull && lane == 0) A.stats[EXTRASS_STAT_QUEUE_FULL] = 1.0;
 }
 
-template <class G, bool RAYS, bool PI, bool SPH>
+template <class G, bool RAYS, bool PI, bool SPH, bool OCT>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_transport(TArgs A) {
-  transport_body<G, RAYS, PI, SPH>(A);
+  transport_body<G, RAYS, PI, SPH, OCT>(A);
 }
 
 // The spherical grid's exit search (three surfaces of each kind, square
 // roots, the cone quadratics) needs more registers than three wavefronts per
 // SIMD leave: two per SIMD.
-template <bool PI>
+template <bool PI, bool OCT>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void k_transport_sph(TArgs A) {
-  transport_body<double, false, PI, true>(A);
+  transport_body<double, false, PI, true, OCT>(A);
 }
 
 }  // namespace
@@ -1179,22 +1195,38 @@ static bool set_photoion(const extrass_grid* g, TArgs& A) {
 
 // The transport kernel for the geometry precision, emission kind,
 // photoionisation and grid (spherical grids: FP64 geometry, no rays).
+// Unsplit launches (one kernel per geometry precision, ray and continuum
+// option) and streamed visits (OCT: packets handed between subdomains) are
+// separate instantiations, so the hand-over code costs the unsplit kernels
+// no registers.
 static void launch_transport(bool fp32, bool rays, bool pi, bool sph, unsigned blocks,
                              hipStream_t st, const TArgs& A) {
   const dim3 g(blocks), b(kBlock);
-  if (sph) {
-    if (pi) hipLaunchKernelGGL((k_transport_sph<true>), g, b, 0, st, A);
-    else hipLaunchKernelGGL((k_transport_sph<false>), g, b, 0, st, A);
+  const bool oct = A.oct >= 0;
+  if (oct) {  // streamed visits: sampled packets only
+    if (sph) {
+      if (pi) hipLaunchKernelGGL((k_transport_sph<true, true>), g, b, 0, st, A);
+      else hipLaunchKernelGGL((k_transport_sph<false, true>), g, b, 0, st, A);
+    } else if (pi) {
+      if (fp32) hipLaunchKernelGGL((k_transport<float, false, true, false, true>), g, b, 0, st, A);
+      else hipLaunchKernelGGL((k_transport<double, false, true, false, true>), g, b, 0, st, A);
+    } else {
+      if (fp32) hipLaunchKernelGGL((k_transport<float, false, false, false, true>), g, b, 0, st, A);
+      else hipLaunchKernelGGL((k_transport<double, false, false, false, true>), g, b, 0, st, A);
+    }
+  } else if (sph) {
+    if (pi) hipLaunchKernelGGL((k_transport_sph<true, false>), g, b, 0, st, A);
+    else hipLaunchKernelGGL((k_transport_sph<false, false>), g, b, 0, st, A);
   } else if (pi) {
-    if (rays && fp32) hipLaunchKernelGGL((k_transport<float, true, true, false>), g, b, 0, st, A);
-    else if (rays) hipLaunchKernelGGL((k_transport<double, true, true, false>), g, b, 0, st, A);
-    else if (fp32) hipLaunchKernelGGL((k_transport<float, false, true, false>), g, b, 0, st, A);
-    else hipLaunchKernelGGL((k_transport<double, false, true, false>), g, b, 0, st, A);
+    if (rays && fp32) hipLaunchKernelGGL((k_transport<float, true, true, false, false>), g, b, 0, st, A);
+    else if (rays) hipLaunchKernelGGL((k_transport<double, true, true, false, false>), g, b, 0, st, A);
+    else if (fp32) hipLaunchKernelGGL((k_transport<float, false, true, false, false>), g, b, 0, st, A);
+    else hipLaunchKernelGGL((k_transport<double, false, true, false, false>), g, b, 0, st, A);
   } else {
-    if (rays && fp32) hipLaunchKernelGGL((k_transport<float, true, false, false>), g, b, 0, st, A);
-    else if (rays) hipLaunchKernelGGL((k_transport<double, true, false, false>), g, b, 0, st, A);
-    else if (fp32) hipLaunchKernelGGL((k_transport<float, false, false, false>), g, b, 0, st, A);
-    else hipLaunchKernelGGL((k_transport<double, false, false, false>), g, b, 0, st, A);
+    if (rays && fp32) hipLaunchKernelGGL((k_transport<float, true, false, false, false>), g, b, 0, st, A);
+    else if (rays) hipLaunchKernelGGL((k_transport<double, true, false, false, false>), g, b, 0, st, A);
+    else if (fp32) hipLaunchKernelGGL((k_transport<float, false, false, false, false>), g, b, 0, st, A);
+    else hipLaunchKernelGGL((k_transport<double, false, false, false, false>), g, b, 0, st, A);
   }
 }
 
@@ -1570,10 +1602,15 @@ extern "C" int extrass_transport_streamed(extrass_handle h, const extrass_grid* 
   std::vector<int64_t> head(ND, 0);
   std::vector<unsigned long long> tail(ND, 0);
   // a ray enters each convex subdomain at most once: the cube's octants take
-  // at most 4 rounds, a spherical grid's phi ranges at most n_domains
+  // at most 4 rounds, a spherical grid's phi ranges at most n_domains. Rounds
+  // alternate their direction: phi along a straight ray is monotonic, so a
+  // packet moving towards lower phi ranges is handed on within a backward
+  // round instead of waiting one round per range (a visit costs about 1 ms
+  // however few packets it resumes)
   for (int round = 0; round < dm.rounds; ++round) {
     bool any = false;
-    for (int o = 0; o < ND; ++o) {
+    for (int v = 0; v < ND; ++v) {
+      const int o = (round & 1) ? ND - 1 - v : v;
       EXTRASS_HIP_TRY(h, hipMemcpyAsync(tail.data(), w.counters + 1, ND * sizeof(unsigned long long),
                                         hipMemcpyDeviceToHost, st));
       EXTRASS_HIP_TRY(h, hipStreamSynchronize(st));

@@ -183,14 +183,8 @@ class RayLoop:
         C, T = w.n_cells, w.atom.n_trans
         self.cells0 = cells_from_workload(w, device=device)
         self.gamma = torch.zeros((C, T), dtype=torch.float64, device=device)
-        self.pi_plan = None
-        self.gamma_pi = None
-        if ion_energy is not None:
-            self.pi_plan = PiPlan(ctx, self.atom, ion_energy, pi_levels_per_stage)
-            self.gamma_pi = torch.zeros((C, N), dtype=torch.float64, device=device)
         self.cells = Cells(w.t_exp, self.cells0.T_e, self.cells0.n_e, self.cells0.n_species,
-                           self.cells0.gamma_ion, self.gamma, device=device,
-                           gamma_pi=self.gamma_pi)
+                           self.cells0.gamma_ion, self.gamma, device=device)
         tau = torch.empty((C, T), dtype=torch.float64, device=device)
         self.grid = grid_from_workload(w, device=device, tau_ct=tau, fcorr_ct=torch.empty_like(tau))
         self.est = torch.empty((C, w.n_lines), dtype=torch.float64, device=device)
