@@ -86,6 +86,9 @@ bool launch_nlte_whole(int nt, unsigned blocks, size_t lds, hipStream_t st, cons
 namespace {
 
 constexpr double kBoltzmann = 1.380649e-16;  // erg/K
+// A warm guess whose first fixed-point step changes no population by more
+// than this factor in log n goes straight to Newton.
+constexpr double kNearRoot = 1e-2;
 
 // Everything one system needs, held per wave (uniform values) or per lane.
 struct Sys {
@@ -664,6 +667,17 @@ __device__ __forceinline__ int solve_system(const NArgs& A, const Sys& y, double
       const double psum = wave_sum(live ? pp : 0.0);
       const double nw = live ? y.ntot * (pp / psum) : 0.0;
       const double change = wave_max(live ? fabs(log(nw / n)) : 0.0);
+      if (warm && it == 0 && change < kNearRoot) {
+        // a guess this close to the root (the previous global iteration's
+        // solution): this solve is already the residual at the guess, and
+        // Newton starts from the guess itself
+        h = live ? nw / n - 1.0 : 0.0;
+        ++it;
+        used = it;
+        if (it >= max_iter || (check_at > 0 && it == check_at)) return -1;
+        phase = NEWTON;
+        continue;
+      }
       if (change > 0.999 * prev) omega = uniform_d(omega * 0.5 > 1.0 / 1024 ? omega * 0.5 : 1.0 / 1024);
       prev = change;
       const double v = live ? exp((1.0 - omega) * log(n) + omega * log(nw)) : 0.0;
@@ -694,11 +708,14 @@ __device__ __forceinline__ int solve_system(const NArgs& A, const Sys& y, double
           // warm-start check: still far from the root after the budget
           if (check_at > 0 && it == check_at && !(res2 < 1e-6)) return -1;
           // In the quadratic end game the next full Newton step is about
-          // (s / s_prev^2) s^2 for this full step s and the one before it;
-          // when that is far below tol and the residual is already below
-          // tol, the verifying Newton step is skipped.
-          if (taken == step && last_full > 0.0) {
-            const double pred = (step / (last_full * last_full)) * step * step;
+          // (s / s_prev^2) s^2 for this full step s and the one before it,
+          // or, after a first full step, (s / r) r_new: the step scaled by
+          // the reduction of the residual it was taken from. When that is
+          // far below tol and the residual is already below tol, the
+          // verifying Newton step is skipped.
+          if (taken == step) {
+            const double pred = last_full > 0.0 ? (step / (last_full * last_full)) * step * step
+                                                : step * (res2 / res);
             if (pred < 0.01 * A.tol && res2 < A.tol) return it;
           }
           last_full = taken == step ? step : 0.0;
