@@ -38,6 +38,8 @@ METRIC = "packet line-interactions/s + NLTE cell-solves/s vs plain FP64 at 1e-8 
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 ITERATIONS = 5
+EXTRAS = ("clumpy50_step", "deterministic_rays", "photoionisation", "spherical_grid", "spectrum",
+          "batched_nlte")
 
 
 def parse():
@@ -56,6 +58,9 @@ def parse():
                     help="population accuracy of the NLTE solves (the metric's 1e-8)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the 50^3 step, spectrum and batched measurements")
+    ap.add_argument("--extras", default=",".join(EXTRAS),
+                    help="comma-separated extra measurements to run (default: all of "
+                         + ", ".join(EXTRAS) + ")")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device-to-device copy before the step loop, whose "
                          "FETCH_SIZE/WRITE_SIZE counters calibrate the HBM traffic figures")
@@ -103,8 +108,13 @@ def main():
     params, norm, hist = warmstart.train_on_workload(ctx, w50, epochs=args.epochs)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t_setup
+    chosen = set() if args.no_extras else {e for e in args.extras.split(",") if e}
+    unknown = chosen - set(EXTRAS)
+    if unknown:
+        print(f"bench.py: unknown extras {sorted(unknown)}", file=sys.stderr)
+        sys.exit(2)
     extras = {}
-    if not args.no_extras:
+    if "clumpy50_step" in chosen:
         extras["clumpy50_step"] = bench_clumpy50(ex, ctx, w50, params, norm, args)
         torch.cuda.empty_cache()
     w = synth.large()
@@ -227,16 +237,15 @@ def main():
     del loop
     torch.cuda.empty_cache()
     out.update(extras)
-    if not args.no_extras:
-        out["deterministic_rays"] = bench_rays(ex, ctx, w50)
-        torch.cuda.empty_cache()
-        out["photoionisation"] = bench_photoion(ex, ctx, w50)
-        torch.cuda.empty_cache()
-        out["spherical_grid"] = bench_spherical(ex, ctx)
-        torch.cuda.empty_cache()
-        out["spectrum"] = bench_spectrum(ex, ctx, w50)
-        torch.cuda.empty_cache()
-        out["batched_nlte"] = bench_batched(ex, ctx)
+    legs = {"deterministic_rays": lambda: bench_rays(ex, ctx, w50),
+            "photoionisation": lambda: bench_photoion(ex, ctx, w50),
+            "spherical_grid": lambda: bench_spherical(ex, ctx),
+            "spectrum": lambda: bench_spectrum(ex, ctx, w50),
+            "batched_nlte": lambda: bench_batched(ex, ctx)}
+    for name, leg in legs.items():
+        if name in chosen:
+            out[name] = leg()
+            torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         say("cpu_baseline: oracle on a sample")
         out["cpu_baseline"] = cpu_baseline(w, n_inter, sample, gpe_s, ref, args)
