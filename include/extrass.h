@@ -373,9 +373,10 @@ int extrass_rates(extrass_handle h, extrass_atom_handle atom, const extrass_grid
  * sum of cell_packets; explicit packets are not supported) through the cube,
  * one octant at a time: an octant's visit emits its own cells' packets (first
  * visit), resumes the packets queued for it, accumulates into est_octant and
- * queues every packet that crosses into another octant. Visits repeat in
- * octant order until no packet is queued (at most 4 rounds: a straight ray
- * crosses each coordinate plane once). Packets keep their ids, Philox streams
+ * queues every packet that crosses into another octant. Rounds of visits,
+ * forwards and backwards in octant order in turn, repeat until no packet is
+ * queued (at most 4 rounds: a straight ray crosses each coordinate plane
+ * once). Packets keep their ids, Philox streams
  * and arithmetic, so the events equal those of extrass_transport.
  *
  * After each visit, if atom is not NULL, the visit's estimators are turned
@@ -388,16 +389,19 @@ int extrass_rates(extrass_handle h, extrass_atom_handle atom, const extrass_grid
  * n: even. est_octant: device [(n/2)^3 * L] (local cell i + (n/2)(j + (n/2) k)
  * within the octant, octant o = (i >= n/2) + 2 (j >= n/2) + 4 (k >= n/2)).
  * A spherical grid is split instead into its n_domains equal phi ranges (the
- * paper's phi decomposition), visited in order for at most n_domains rounds
- * (each range is convex); est_octant is then [C / n_domains * L], the
- * subdomain's cells in their global order, and V is each cell's own volume.
+ * paper's phi decomposition), visited in rounds as the octants, for at most
+ * n_domains + 1 rounds (each range is convex); est_octant is then
+ * [C / n_domains * L], the subdomain's cells in their global order, and V is
+ * each cell's own volume.
  * est_octant may be NULL when only the rates are wanted (atom given,
  * est_global NULL, the grid's tau_ct/line_trans set and line_trans the
  * inverse of the atom's transition -> line map, else EXTRASS_EINVAL): each
  * interaction on an atom line then adds dN / f_corr straight into
  * gamma_pe[c,t], which is divided by n_l V at the end. No octant table is
  * kept and no flush runs; lines of no atom transition are not recorded. The
- * rates equal the table path's up to the order of the additions.
+ * rates equal the table path's up to the order of the additions and the
+ * division, taken as a product with 1 / (n_l V) (atoms of more than 8192
+ * levels: EXTRASS_EUNSUPPORTED).
  * queue_capacity: packets each subdomain's queue holds; the workspace holds one
  * queue of 120-byte records per subdomain. A full queue loses packets: stats[QUEUE_FULL]
  * is set and the call returns EXTRASS_ENOSPACE. The host waits for the stream

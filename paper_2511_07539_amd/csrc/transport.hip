@@ -334,16 +334,24 @@ __global__ __launch_bounds__(256) void k_octant_flush(double* __restrict__ eo, u
 }
 
 // Rates from the direct sums: gamma_pe[c,t] = sum(dN / f_corr) / (n_l V).
-__global__ void k_rates_direct(int64_t C, int N, int T, const int32_t* __restrict__ lo,
-                               const double* __restrict__ pops, CellVolume V,
-                               double* __restrict__ gamma) {
-  const int64_t total = C * T;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t c = e / T;
-    const int t = (int)(e - c * T);
-    const double Nl = pops[c * N + lo[t]] * V(c);
-    gamma[e] = Nl > 0.0 ? gamma[e] / Nl : 0.0;
+// One work-group per cell row: the reciprocals 1 / (n_l V) of the cell's
+// levels go to LDS once, then the row is scaled in place (coalesced). Empty
+// levels give zero rates.
+__global__ __launch_bounds__(256) void k_rates_direct(int64_t C, int N, int T,
+                                                     const int32_t* __restrict__ lo,
+                                                     const double* __restrict__ pops,
+                                                     CellVolume V, double* __restrict__ gamma) {
+  extern __shared__ double inv[];  // [N]
+  for (int64_t c = blockIdx.x; c < C; c += gridDim.x) {
+    const double vc = V(c);
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+      const double Nl = pops[c * N + i] * vc;
+      inv[i] = Nl > 0.0 ? 1.0 / Nl : 0.0;
+    }
+    __syncthreads();
+    double* g = gamma + c * T;
+    for (int t = threadIdx.x; t < T; t += blockDim.x) g[t] = g[t] * inv[lo[t]];
+    __syncthreads();
   }
 }
 
@@ -1487,6 +1495,8 @@ extern "C" int extrass_transport_streamed(extrass_handle h, const extrass_grid* 
     return fail(h, EXTRASS_EINVAL, "extrass_transport_streamed: whole sampling plan only");
   if (atom && (!pops || !gamma_pe || !(t_exp > 0.0)))
     return fail(h, EXTRASS_EINVAL, "extrass_transport_streamed: rates need pops, gamma_pe, t_exp");
+  if (direct && atom->N > 8192)  // a cell's level reciprocals are staged in 64 KB of LDS
+    return fail(h, EXTRASS_EUNSUPPORTED, "extrass_transport_streamed: more than 8192 levels");
   if (atom && atom->maxLine >= g->n_lines)
     return fail(h, EXTRASS_EINVAL,
                 "extrass_transport_streamed: a transition's line index is beyond the grid's lines");
@@ -1659,9 +1669,10 @@ extern "C" int extrass_transport_streamed(extrass_handle h, const extrass_grid* 
     if ((int64_t)tail[o] != head[o])
       return fail(h, EXTRASS_EHIP, "extrass_transport_streamed: packets left in a queue");
   if (direct) {
-    const int64_t blocks = std::min<int64_t>((C * atom->T + 255) / 256, 16384);
-    hipLaunchKernelGGL(k_rates_direct, dim3((unsigned)blocks), dim3(256), 0, st, C, atom->N, atom->T,
-                       atom->d.o_lo, pops, cell_volume, gamma_pe);
+    const int64_t blocks = std::min<int64_t>(C, 16384);
+    hipLaunchKernelGGL(k_rates_direct, dim3((unsigned)blocks), dim3(256),
+                       (size_t)atom->N * sizeof(double), st, C, atom->N, atom->T, atom->d.o_lo, pops,
+                       cell_volume, gamma_pe);
     EXTRASS_HIP_TRY(h, hipGetLastError());
   }
   return EXTRASS_OK;
