@@ -38,8 +38,8 @@ METRIC = "packet line-interactions/s + NLTE cell-solves/s vs plain FP64 at 1e-8 
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 ITERATIONS = 5
-EXTRAS = ("clumpy50_step", "deterministic_rays", "photoionisation", "spherical_grid", "spectrum",
-          "batched_nlte")
+EXTRAS = ("clumpy50_step", "clumpy100_octant_table", "deterministic_rays", "photoionisation",
+          "spherical_grid", "spectrum", "batched_nlte")
 
 
 def parse():
@@ -234,6 +234,8 @@ def main():
     say("accuracy sample")
     sample, gpe_s = accuracy_sample(w, args.cpu_cells)
     out["nlte_accuracy"], ref = nlte_accuracy(ex, ctx, loop, w, sample, gpe_s, params, norm, args)
+    if "clumpy100_octant_table" in chosen:
+        out["clumpy100_octant_table"] = bench_octant_table(ex, ctx, loop, w)
     del loop
     torch.cuda.empty_cache()
     out.update(extras)
@@ -250,6 +252,48 @@ def main():
         say("cpu_baseline: oracle on a sample")
         out["cpu_baseline"] = cpu_baseline(w, n_inter, sample, gpe_s, ref, args)
     print(json.dumps(out), flush=True)
+
+
+def bench_octant_table(ex, ctx, loop, w):
+    """The 100^3 streamed transport with each octant's [C/8 x L] FP64
+    estimator table resident (30 GB at 30 000 lines), flushed into the rates
+    after every visit, against the step's table-free mode (rates summed per
+    interaction), on the same opacities and populations (the loop's last);
+    HIP events, one warm-up call each. Both take the same events, so their
+    rates agree up to the order of the additions."""
+    import numpy as np
+    import torch
+    dev = "cuda:0"
+    s = torch.cuda.current_stream()
+    ex.line_tau(ctx, loop.atom, loop.pops, w.t_exp, tau=loop.grid.tau_ct, fcorr=loop.grid.fcorr_ct)
+    half = w.n // 2
+    table = torch.empty((half ** 3, w.n_lines), dtype=torch.float64, device=dev)
+    g_tab = torch.empty_like(loop.gamma)
+    g_dir = torch.empty_like(loop.gamma)
+    stats = torch.empty(ex.STATS, dtype=torch.float64, device=dev)
+    res = {"workload": w.name, "octant_table_gb": table.numel() * 8 / 1e9}
+    for name, est, gam in (("octant_table", table, g_tab), ("direct", None, g_dir)):
+        times = []
+        for _ in range(2):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            ex.transport_streamed(ctx, loop.grid, w.seed, w.lambda_lo, w.lambda_hi, w.n_packets,
+                                  atom=loop.atom, pops=loop.pops, t_exp=w.t_exp, iteration=0,
+                                  geometry_fp32=True, est_octant=est, gamma=gam, stats=stats,
+                                  octant_table=est is not None)
+            e1.record(s)
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+        sd = ex.stats_dict(stats)
+        res[name] = {"ms": times[-1], "interactions": sd["n_inter"],
+                     "line_interactions_per_s": sd["n_inter"] / (times[-1] * 1e-3)}
+    on = (g_dir > 0) & (g_tab > 0)
+    rel = ((g_tab - g_dir).abs() / g_dir.clamp_min(1e-300))[on]
+    res["rates_max_rel_diff"] = float(rel.max()) if rel.numel() else 0.0
+    res["rates_zero_pattern_equal"] = bool(torch.equal(g_dir > 0, g_tab > 0))
+    del table, g_tab, g_dir
+    torch.cuda.empty_cache()
+    return res
 
 
 def accuracy_sample(w, n):

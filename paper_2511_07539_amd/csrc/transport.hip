@@ -95,10 +95,10 @@ struct TArgs {
   int64_t sub_c0;            // spherical grid: first cell of the current subdomain
   int64_t n_emit;            // packets emitted in this visit (first visit only)
   const int64_t* ostart;     // [Coct+1] prefix of cell_packets over the octant's cells
-  const struct QPk* inbox;   // packets entering this octant
-  int64_t n_in;
-  struct QPk* qbase;         // 8 queues of qcap records
-  unsigned long long* qtail; // [8]
+  const int64_t* visit;      // [2] set on the device before the visit: packets in
+                             // the visit (emitted + resumed), first queued record
+  struct QPk* qbase;         // one queue of qcap records per subdomain
+  unsigned long long* qtail; // [subdomains] queue tails
   int64_t qcap;
   uint8_t* touched;          // [Coct] rows that received an estimator this visit
   double* gdirect;           // octant mode without a table: [C*T] sums of dN / f_corr per
@@ -379,7 +379,22 @@ __global__ void k_sph_trig(const double* th, int nt, int np, double* cth, double
 }
 
 __global__ void k_reset_u64(unsigned long long* p, int n) {
-  if ((int)threadIdx.x < n) p[threadIdx.x] = 0ull;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0ull;
+}
+
+// Before a streamed visit of subdomain o: the visit's packets (ne emitted,
+// plus those queued for o since its last visit, up to the queue's capacity)
+// and the first of the queued records; the packet pool restarts.
+__global__ void k_visit_begin(int o, int64_t ne, int64_t qcap, unsigned long long* counters,
+                              int64_t* visit) {
+  if (threadIdx.x != 0) return;
+  const int64_t t = (int64_t)counters[1 + o];
+  const int64_t avail = t < qcap ? t : qcap;
+  int64_t* head = visit + 2;
+  visit[0] = ne + (avail - head[o]);
+  visit[1] = head[o];
+  head[o] = avail;
+  counters[0] = 0ull;
 }
 
 __global__ void k_zero(double* __restrict__ p, int64_t n) {
@@ -838,6 +853,14 @@ __device__ __forceinline__ void transport_body(const TArgs& A) {
   Tally t;
   const int64_t C = A.C;
   (void)C;
+  // a streamed visit learns its size from the device (no host round trip)
+  int64_t count = A.count;
+  const QPk* inbox = nullptr;
+  if constexpr (OCT) {
+    count = A.visit[0];
+    inbox = A.qbase + (int64_t)A.oct * A.qcap + A.visit[1];
+    if (count == 0) return;
+  }
 
   for (;;) {
     // ---- hand idle lanes new packet ids (ballot + popcount over the wave).
@@ -855,8 +878,8 @@ __device__ __forceinline__ void transport_body(const TArgs& A) {
         if (lane == 0) base = atomicAdd(A.queue, (unsigned long long)kPool);
         base = __shfl(base, 0);
         pool_base = base;
-        pool_left = base >= (uint64_t)A.count ? 0 : ((uint64_t)A.count - base < (uint64_t)kPool
-                                                       ? (uint64_t)A.count - base : (uint64_t)kPool);
+        pool_left = base >= (uint64_t)count ? 0 : ((uint64_t)count - base < (uint64_t)kPool
+                                                     ? (uint64_t)count - base : (uint64_t)kPool);
         if (pool_left == 0) exhausted = true;
       }
       const int rank = __popcll(m & ((1ull << lane) - 1ull));
@@ -866,7 +889,7 @@ __device__ __forceinline__ void transport_body(const TArgs& A) {
         if ((uint64_t)rank < take) {
           const int64_t idx = (int64_t)(pool_base + rank);
           if (OCT && idx >= A.n_emit) {
-            pid = resume<G>(A.inbox[idx - A.n_emit], q);
+            pid = resume<G>(inbox[idx - A.n_emit], q);
             nxt = line_rec(A, q.k);
             if constexpr (PI) {  // absorbed up to the wall it came through
               q.Dp = (double)q.D;
@@ -1413,6 +1436,8 @@ struct StreamWs {
   int64_t* start;
   LineRec* lines;
   unsigned long long* counters;  // [0] packet pool, [1..n] queue tails, [n + 1] map flag
+  int64_t* visit;                // [0] packets of the current visit, [1] its first queued
+                                 // record, [2..n + 1] records of each queue already resumed
   int64_t* ostart;               // octants: 8 x (Co + 1)
   QPk* queues;                   // n x qcap
   uint8_t* touched;              // [Co]
@@ -1433,6 +1458,7 @@ StreamWs stream_layout(const extrass_grid* g, int64_t qcap, void* ws) {
   w.start = cv.take<int64_t>(C + 1);
   w.lines = cv.take<LineRec>(g->n_lines > 0 ? g->n_lines : 1);
   w.counters = cv.take<unsigned long long>(dm.n + 8);
+  w.visit = cv.take<int64_t>(dm.n + 2);
   if (!dm.slices) w.ostart = cv.take<int64_t>(8 * (Co + 1));
   w.queues = cv.take<QPk>((size_t)(dm.n * (qcap > 0 ? qcap : 1)));
   w.touched = cv.take<uint8_t>(Co);
@@ -1533,7 +1559,9 @@ extern "C" int extrass_transport_streamed(extrass_handle h, const extrass_grid* 
     A.sph_cth = w.sph_cth;
     A.sph_cs = w.sph_cs;
   }
-  hipLaunchKernelGGL(k_reset_u64, dim3(1), dim3(64), 0, st, w.counters, ND + 8);
+  hipLaunchKernelGGL(k_reset_u64, dim3(1), dim3(256), 0, st, w.counters, ND + 8);
+  hipLaunchKernelGGL(k_reset_u64, dim3(1), dim3(256), 0, st,
+                     reinterpret_cast<unsigned long long*>(w.visit), ND + 2);
   if (atom) zero_doubles(gamma_pe, C * (int64_t)atom->T, st);
   if (est_global) zero_doubles(est_global, C * (int64_t)L, st);
   if (direct) {
@@ -1611,25 +1639,30 @@ extern "C" int extrass_transport_streamed(extrass_handle h, const extrass_grid* 
 
   std::vector<int64_t> head(ND, 0);
   std::vector<unsigned long long> tail(ND, 0);
-  // a ray enters each convex subdomain at most once: the cube's octants take
+  // A ray enters each convex subdomain at most once: the cube's octants take
   // at most 4 rounds, a spherical grid's phi ranges at most n_domains. Rounds
   // alternate their direction: phi along a straight ray is monotonic, so a
   // packet moving towards lower phi ranges is handed on within a backward
   // round instead of waiting one round per range (a visit costs about 1 ms
-  // however few packets it resumes)
+  // however few packets it resumes). Each visit learns its size on the
+  // device (k_visit_begin), so the host waits once per round, to see whether
+  // any packet is still queued, not before every visit.
+  // launch size of a later round's visit: the packets queued for it when the
+  // round began, or an equal share of all those queued, whichever is more
+  // (packets handed over during the round add to it; the kernel takes every
+  // packet whatever its size)
+  std::vector<int64_t> queued_at(ND, 0);
+  int64_t queued_all = 0;
   for (int round = 0; round < dm.rounds; ++round) {
-    bool any = false;
     for (int v = 0; v < ND; ++v) {
       const int o = (round & 1) ? ND - 1 - v : v;
-      EXTRASS_HIP_TRY(h, hipMemcpyAsync(tail.data(), w.counters + 1, ND * sizeof(unsigned long long),
-                                        hipMemcpyDeviceToHost, st));
-      EXTRASS_HIP_TRY(h, hipStreamSynchronize(st));
-      const int64_t avail = std::min<int64_t>((int64_t)tail[o], queue_capacity);
-      const int64_t n_in = avail - head[o];
       const int64_t ne = round == 0 ? n_emit[o] : 0;
-      if (n_in + ne == 0) continue;
-      any = true;
-      hipLaunchKernelGGL(k_reset_u64, dim3(1), dim3(64), 0, st, w.counters, 1);
+      const int64_t expect = round == 0 ? ne + queued_all
+                                        : std::max<int64_t>(queued_at[o], queued_all / ND);
+      const int64_t blocks = std::max<int64_t>(
+          1, std::min<int64_t>((int64_t)h->num_cus * 8, (expect + kBlock - 1) / kBlock));
+      hipLaunchKernelGGL(k_visit_begin, dim3(1), dim3(64), 0, st, o, ne, (int64_t)queue_capacity,
+                         w.counters, w.visit);
       A.oct = o;
       A.lo[0] = (o & 1) ? half : 0;
       A.lo[1] = (o & 2) ? half : 0;
@@ -1637,12 +1670,7 @@ extern "C" int extrass_transport_streamed(extrass_handle h, const extrass_grid* 
       A.ostart = dm.slices ? nullptr : w.ostart + o * (Co + 1);
       A.sub_c0 = dm.slices ? (int64_t)o * Co : 0;
       A.n_emit = ne;
-      A.inbox = w.queues + (int64_t)o * queue_capacity + head[o];
-      A.n_in = n_in;
-      A.count = ne + n_in;
-      int64_t blocks = (int64_t)h->num_cus * 8;
-      const int64_t max_blocks = (A.count + kBlock - 1) / kBlock;
-      if (blocks > max_blocks) blocks = max_blocks;
+      A.visit = w.visit;
       launch_transport(s->geometry_fp32 != 0, false, A.pi_M > 0, g->spherical != nullptr,
                        (unsigned)blocks, st, A);
       EXTRASS_HIP_TRY(h, hipGetLastError());
@@ -1653,12 +1681,23 @@ extern "C" int extrass_transport_streamed(extrass_handle h, const extrass_grid* 
                            atom ? atom->d.o_lo : nullptr, atom ? atom->d.o_line : nullptr, pops,
                            cell_volume, atom ? gamma_pe : nullptr, est_global);
       EXTRASS_HIP_TRY(h, hipGetLastError());
-      head[o] = avail;
     }
-    if (!any && round > 0) break;
+    EXTRASS_HIP_TRY(h, hipMemcpyAsync(tail.data(), w.counters + 1, ND * sizeof(unsigned long long),
+                                      hipMemcpyDeviceToHost, st));
+    EXTRASS_HIP_TRY(h, hipMemcpyAsync(head.data(), w.visit + 2, ND * sizeof(int64_t),
+                                      hipMemcpyDeviceToHost, st));
+    EXTRASS_HIP_TRY(h, hipStreamSynchronize(st));
+    queued_all = 0;
+    for (int o = 0; o < ND; ++o) {
+      queued_at[o] = std::min<int64_t>((int64_t)tail[o], queue_capacity) - head[o];
+      queued_all += queued_at[o];
+    }
+    if (queued_all == 0) break;
   }
   double full = 0.0;
   EXTRASS_HIP_TRY(h, hipMemcpyAsync(tail.data(), w.counters + 1, ND * sizeof(unsigned long long),
+                                    hipMemcpyDeviceToHost, st));
+  EXTRASS_HIP_TRY(h, hipMemcpyAsync(head.data(), w.visit + 2, ND * sizeof(int64_t),
                                     hipMemcpyDeviceToHost, st));
   EXTRASS_HIP_TRY(h, hipMemcpyAsync(&full, stats + EXTRASS_STAT_QUEUE_FULL, sizeof(double),
                                     hipMemcpyDeviceToHost, st));

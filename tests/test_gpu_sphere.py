@@ -240,6 +240,28 @@ def test_streamed_phi_domains_equal_unsplit(ex, ctx, sph, n_domains):
     assert rel <= 1e-12
 
 
+def test_many_phi_domains_equal_unsplit(ex, ctx):
+    """64 phi domains of two slices each: more subdomains than a wavefront
+    has lanes, so the queue tails and visit records are cleared and read
+    beyond the first 64 entries."""
+    w = synth.spherical(6, 4, 128, 300, 50_000, number=10)
+    say("case: spherical grid 6 x 4 x 128 streamed over 64 phi domains")
+    grid = ex.spherical_grid(w.r_edge, w.theta_edge, w.n_phi, w.tau_scale, w.cell_photons,
+                             w.cell_packets, w.line_lambda, w.line_tau0, n_domains=64)
+    est, st_u, _ = ex.transport(ctx, grid, w.seed, w.lambda_lo, w.lambda_hi, w.n_packets)
+    # a thin range sees many of the packets pass: room for all of them
+    _, st_s, eg = ex.transport_streamed(ctx, grid, w.seed, w.lambda_lo, w.lambda_hi, w.n_packets,
+                                        est_global=True, queue_capacity=w.n_packets)
+    torch.cuda.synchronize()
+    su, ss = ex.stats_dict(st_u), ex.stats_dict(st_s)
+    for k in ("n_inter", "n_checks", "n_cross", "n_escaped", "n_killed"):
+        assert su[k] == ss[k], k
+    a, b = eg.cpu().numpy(), est.cpu().numpy()
+    nz = b != 0
+    assert np.array_equal(a != 0, nz)
+    assert np.max(np.abs(a[nz] - b[nz]) / b[nz]) <= 1e-12
+
+
 def test_rates_use_each_spherical_cells_volume(ex, ctx, sph):
     w = sph
     aw = synth.clumpy(n=16, n_lines=1000, n_packets=1000, number=12)
