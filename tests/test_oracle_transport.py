@@ -14,6 +14,7 @@ import math
 
 import numpy as np
 import pytest
+from scipy import integrate
 
 import oracle
 import synth
@@ -359,3 +360,42 @@ def test_rates_hand_computed_two_cells():
     # cell 0: t0 lower 0 line 2: 7 / (2 * 0.5) = 7; t1 lower 1 line 0: 3 / (4 * 0.5) = 1.5
     # cell 1: t0 lower level empty -> 0;            t1: 11 / (8 * 0.5) = 2.75
     np.testing.assert_array_equal(got, [[7.0, 1.5], [0.0, 2.75]])
+
+
+def test_line_tau_equals_line_opacity_integrated_along_a_ray():
+    """Eq. A2 against its derivation rather than its formula: the textbook
+    absorption cross section of a line, sigma(nu) = (g_u/g_l) A lambda^2 / (8
+    pi) phi(nu), corrected for stimulated emission by (1 - g_l n_u / (g_u
+    n_l)), integrated by quadrature along a ray through homologous flow, where
+    the comoving frequency falls as nu_L (1 - s / (c t)), with a narrow
+    Gaussian profile phi. The ray starts a fraction D of the way before the
+    resonance, so the integral is the Sobolev depth times (1 - D) exactly."""
+    c = 2.99792458e10
+    lam0 = 5000e-8
+    nu0 = c / lam0
+    t = 1e6
+    A_ul, g_l, g_u = 1e7, 2.0, 4.0
+    at = synth.Atom(species_offset=np.array([0, 2], np.int32), level_ion=np.array([0, 0], np.int32),
+                    level_energy=np.zeros(2), level_g=np.array([g_l, g_u]),
+                    trans_lower=np.array([0], np.int32), trans_upper=np.array([1], np.int32),
+                    trans_A=np.array([A_ul]), trans_lambda=np.array([lam0]),
+                    trans_upsilon=np.array([1.0]), trans_line=np.array([0], np.int32),
+                    ion_alpha0=np.zeros(3), species_mass=np.array([1.0]))
+    D = 1e-6
+    width = 1e-9 * nu0  # Gaussian sigma in frequency
+    nu_L = nu0 / (1.0 - D)
+    for n_l, n_u in ((1e3, 10.0), (5.0, 9.0), (2e-3, 0.0)):
+        tau_a2, _ = oracle.line_tau(np.array([[n_l, n_u]]), at, t)
+        stim = 1.0 - g_l * n_u / (g_u * n_l)
+
+        def alpha(u):
+            # u = s - s_res: the comoving frequency nu_L (1 - s / (c t)) is
+            # nu0 - nu_L u / (c t) there (nu_L (1 - s_res / (c t)) = nu0)
+            x = -nu_L * u / (c * t) / width
+            phi = np.exp(-0.5 * x * x) / (width * np.sqrt(2 * np.pi))
+            return n_l * (g_u / g_l) * A_ul * (c / nu0) ** 2 / (8 * np.pi) * stim * phi
+
+        ds = width / nu_L * c * t  # the profile's width along the ray
+        tau, _ = integrate.quad(alpha, -40 * ds, 40 * ds, points=[0.0], epsabs=0, epsrel=1e-12,
+                                limit=400)
+        assert tau / (1.0 - D) == pytest.approx(tau_a2[0], rel=1e-10), (n_l, n_u)
