@@ -531,25 +531,27 @@ def bench_spherical(ex, ctx):
     """Transport on the paper's spherical (r, theta, phi) grid: 48 x 32 x 64 =
     98 304 cells (shells growing outwards), 5000 background lines, 1e7
     sampled packets, FP64 geometry; the estimator table [C x L] written as in
-    the cube's step; unsplit, and streamed over 8 phi domains (the paper's
-    decomposition). HIP events, median of 5."""
+    the cube's step; unsplit, and streamed over 2, 4 and 8 phi domains (the
+    paper's decomposition; 8 is the bench's figure). HIP events, median of 5."""
     import numpy as np
     import torch
     import synth
     dev = "cuda:0"
     w = synth.spherical(48, 32, 64, 5000, 10_000_000, number=8)
-    grid = ex.spherical_grid(w.r_edge, w.theta_edge, w.n_phi, w.tau_scale, w.cell_photons,
-                             w.cell_packets, w.line_lambda, w.line_tau0, device=dev, n_domains=8)
     est = torch.empty((w.n_cells, w.n_lines), dtype=torch.float64, device=dev)
     stats = torch.empty(ex.STATS, dtype=torch.float64, device=dev)
     s = torch.cuda.current_stream()
     out = {"workload": w.name, "cells": w.n_cells, "lines": w.n_lines, "packets": w.n_packets}
-    for name in ("unsplit", "streamed_8_phi_domains"):
+    for nd in (0, 2, 4, 8):
+        grid = ex.spherical_grid(w.r_edge, w.theta_edge, w.n_phi, w.tau_scale, w.cell_photons,
+                                 w.cell_packets, w.line_lambda, w.line_tau0, device=dev,
+                                 n_domains=nd)
+        name = "unsplit" if nd == 0 else f"streamed_{nd}_phi_domains"
         times = []
         for _ in range(6):
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(s)
-            if name == "unsplit":
+            if nd == 0:
                 ex.transport(ctx, grid, w.seed, w.lambda_lo, w.lambda_hi, w.n_packets, est=est,
                              stats=stats)
             else:
@@ -564,6 +566,8 @@ def bench_spherical(ex, ctx):
                      "line_interactions_per_s": sd["n_inter"] / (ms * 1e-3),
                      "crossings_per_packet": sd["n_cross"] / w.n_packets,
                      "escaped_fraction": sd["w_esc"] / sd["w_emit"]}
+        del grid
+        torch.cuda.empty_cache()
     return out
 
 
