@@ -279,7 +279,12 @@ extern "C" int extrass_atom_destroy(extrass_atom_handle a) {
 // One workgroup per cell at a time: the cell's populations are staged in LDS,
 // then every transition's tau and stimulated-emission factor is written, in
 // the caller's transition order (coalesced stores).
-__global__ __launch_bounds__(256) void k_line_tau(int64_t n_cells, int N, int T,
+// A tile of cpt cells per pass: their populations go to LDS, then the
+// tile's (cell, transition) entries are formed in order, so the threads'
+// writes of both outputs are contiguous across the tile. (One cell per pass
+// left the last of its four passes over 800 transitions a quarter busy and
+// synchronised the work-group per cell.)
+__global__ __launch_bounds__(256) void k_line_tau(int64_t n_cells, int N, int T, int cpt,
                                                  const double* __restrict__ pops,
                                                  const int32_t* __restrict__ lo,
                                                  const int32_t* __restrict__ up,
@@ -287,19 +292,23 @@ __global__ __launch_bounds__(256) void k_line_tau(int64_t n_cells, int N, int T,
                                                  const double* __restrict__ r, double t_exp,
                                                  double* __restrict__ tau,
                                                  double* __restrict__ fcorr) {
-  extern __shared__ double pc[];  // [N]
-  for (int64_t c = blockIdx.x; c < n_cells; c += gridDim.x) {
-    for (int i = threadIdx.x; i < N; i += blockDim.x) pc[i] = pops[c * N + i];
+  extern __shared__ double pc[];  // [cpt * N]
+  for (int64_t c0 = (int64_t)blockIdx.x * cpt; c0 < n_cells; c0 += (int64_t)gridDim.x * cpt) {
+    const int nc = (int)(n_cells - c0 < cpt ? n_cells - c0 : cpt);
+    for (int i = threadIdx.x; i < nc * N; i += blockDim.x) pc[i] = pops[c0 * N + i];
     __syncthreads();
-    for (int t = threadIdx.x; t < T; t += blockDim.x) {
-      const double nl = pc[lo[t]], nu = pc[up[t]];
+    double* tau_t = tau + c0 * T;
+    double* fc_t = fcorr + c0 * T;
+    for (int e = threadIdx.x; e < nc * T; e += blockDim.x) {
+      const int k = e / T, t = e - k * T;
+      const double nl = pc[k * N + lo[t]], nu = pc[k * N + up[t]];
       double tv = 0.0, fc = 1.0;
       if (nl > 0.0) {
         fc = 1.0 - r[t] * nu / nl;
         tv = K[t] * nl * fc * t_exp;
       }
-      tau[c * T + t] = tv;
-      fcorr[c * T + t] = fc;
+      tau_t[e] = tv;
+      fc_t[e] = fc;
     }
     __syncthreads();
   }
@@ -314,9 +323,12 @@ extern "C" int extrass_line_tau(extrass_handle h, extrass_atom_handle a, int64_t
   EXTRASS_HIP_TRY(h, hipSetDevice(h->device));
   if (a->N > 8192)  // a cell's populations are staged in 64 KB of LDS
     return fail(h, EXTRASS_EUNSUPPORTED, "extrass_line_tau: more than 8192 levels");
-  const int64_t blocks = std::min<int64_t>(n_cells, (int64_t)h->num_cus * 32);
-  hipLaunchKernelGGL(k_line_tau, dim3((unsigned)blocks), dim3(256), sizeof(double) * a->N,
-                     static_cast<hipStream_t>(stream), n_cells, a->N, a->T, pops, a->d.o_lo,
+  // cells per tile: up to 4, within 64 KB of LDS
+  const int cpt = std::max(1, std::min(4, 8192 / a->N));
+  const int64_t tiles = (n_cells + cpt - 1) / cpt;
+  const int64_t blocks = std::min<int64_t>(tiles, (int64_t)h->num_cus * 32);
+  hipLaunchKernelGGL(k_line_tau, dim3((unsigned)blocks), dim3(256), sizeof(double) * a->N * cpt,
+                     static_cast<hipStream_t>(stream), n_cells, a->N, a->T, cpt, pops, a->d.o_lo,
                      a->d.o_up, a->d.o_K, a->d.o_r, t_exp, tau_ct, fcorr_ct);
   EXTRASS_HIP_TRY(h, hipGetLastError());
   return EXTRASS_OK;
