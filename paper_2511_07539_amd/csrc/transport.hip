@@ -1,4 +1,5 @@
-// Monte Carlo packet transport with Sobolev line absorption (Sec. 2.3, 2.3.2).
+// Monte Carlo packet transport with Sobolev line absorption (Sec. 2.3; the
+// photoexcitation estimators of Sec. 2.3.2, the continuum of Sec. 2.3.1).
 //
 // One persistent kernel: every lane follows one packet at a time, one event
 // per loop trip (either the next line resonance inside the current cell or
@@ -13,14 +14,18 @@
 // path. Weights, estimators and the line wavelength arithmetic stay FP64.
 //
 // Octant mode (velocity-space subdomains streamed through HBM): the kernel
-// follows only packets inside one octant of the cube and accumulates into
-// that octant's estimator table. A packet that crosses into another octant
-// is stored, whole, in that octant's queue and continues when the octant is
-// visited. A straight ray crosses each coordinate plane at most once, so it
-// never returns to an octant it has left and visits at most four. Emitted
-// packets keep their global ids and Philox streams, and a stored packet
-// resumes with the same arithmetic, so the split run takes the same events
-// as the unsplit one.
+// follows only packets inside one subdomain, an octant of the cube or a
+// range of phi slices of the spherical grid, and accumulates into that
+// subdomain's estimator table (or straight into the rates). A packet that
+// crosses into another subdomain is stored, whole, in that subdomain's queue
+// and continues when it is visited. Subdomains are convex, so a straight ray
+// never returns to one it has left (a cube's ray visits at most four
+// octants). Emitted packets keep their global ids and Philox streams, and a
+// stored packet resumes with the same arithmetic, so the split run takes
+// the same events as the unsplit one.
+//
+// The spherical grid (Sec. 2) replaces the wall search by the first exit
+// root among the cell's spheres, cones and half-planes (sph_exit).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -119,7 +124,7 @@ struct TArgs {
   double sph_dphi;
 };
 
-// A packet in flight between octants: the whole state after a wall crossing.
+// A packet in flight between subdomains: the whole state after a wall crossing.
 struct QPk {
   double x[3], d[3], D, lamL, lam_e, w, w0, wabs;
   int32_t ci[3], k;
@@ -994,7 +999,7 @@ __device__ __forceinline__ void transport_body(const TArgs& A) {
           const int dst = A.sub_slices ? q.ci[2] / A.sub_slices
                                        : (q.ci[0] >= A.half) | ((q.ci[1] >= A.half) << 1) |
                                              ((q.ci[2] >= A.half) << 2);
-          if (dst != A.oct) {  // hand the packet to its next octant
+          if (dst != A.oct) {  // hand the packet to its next subdomain
             // one atomic per destination and wave: the lanes handing over to
             // the first lane's destination take consecutive slots, then the
             // rest repeat (a per-lane atomic on a handful of shared tails
