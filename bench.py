@@ -183,6 +183,18 @@ def main():
     cold_ms = e0.elapsed_time(e1)
     cold_iters = float(it_c.float().mean())
     cold_ok = int((st_c == 0).sum())
+    # the warm-started pass on the same rates: BF16 network guess (fused
+    # inference included in the time), then the FP64 solve from it
+    say("MLP-warm-started pass on the same rates")
+    e0.record(s)
+    ex.nlte_warm_start(ctx, loop.atom, loop.cells, loop.deposition, params, norm, pops=pops_c)
+    ex.nlte_solve(ctx, loop.atom, loop.cells, tol=args.nlte_tol, guess=pops_c,
+                  warm_budget=args.warm_budget, pops=pops_c, status=st_c, iters=it_c)
+    e1.record(s)
+    torch.cuda.synchronize()
+    warm_same_ms = e0.elapsed_time(e1)
+    warm_same = {"ms": warm_same_ms, "iters_mean": float(it_c.float().mean()),
+                 "converged": int((st_c <= 1).sum()), "cold_fallbacks": int((st_c == 1).sum())}
     del pops_c, st_c, it_c
 
     # roofline of the dominant kernel
@@ -224,6 +236,7 @@ def main():
             "warm_later_iterations_ms": float(per_it[1:, 2].mean()),
             "plain_fp64_cold_ms": cold_ms, "plain_fp64_cold_iters_mean": cold_iters,
             "plain_fp64_cold_converged": cold_ok,
+            "mlp_warm_same_rates": warm_same,
             "cell_solves_per_s_warm_later": w.n_cells / (per_it[1:, 2].mean() * 1e-3),
             "cell_solves_per_s_plain_fp64": w.n_cells / (cold_ms * 1e-3)},
         "warm_start_training": {"workload": w50.name, "epochs": args.epochs,
