@@ -17,8 +17,8 @@ the 50^3 workload's cells (its own transport, rates and NLTE solves).
 
 Prints one JSON line. `value` is packet line-interactions per second of the
 whole step; NLTE cell-solves per second are reported beside it, with the
-plain FP64 cold-start NLTE pass on the last iteration's rates, timed after
-the step loop. The accuracy of both NLTE passes is measured against the
+plain FP64 cold-start NLTE pass and the network-started pass on the last
+iteration's rates, timed after the step loop. The accuracy of both NLTE passes is measured against the
 oracle (tol 1e-12) on a sample of cells with seeded rates, solved by both.
 The roofline object covers the kernel that dominates the step, timed with HIP
 events on the stream the library launches on. Extra keys: the one-iteration
