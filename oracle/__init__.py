@@ -100,11 +100,11 @@ def lib():
                                          C.c_void_p, C.c_void_p]
         L.oracle_gth.argtypes = [C.c_int32, C.c_void_p, C.c_void_p]
         L.oracle_emission_bins.argtypes = [C.POINTER(_Atom), C.c_int64, C.c_void_p, C.c_double,
-                                           C.c_double, C.c_double, C.c_double, C.c_int32,
-                                           C.c_void_p, C.c_void_p, C.c_void_p]
+                                           C.c_double, C.c_void_p, C.c_double, C.c_double,
+                                           C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]
         L.oracle_ray_packets.restype = C.c_int64
-        L.oracle_ray_packets.argtypes = [C.c_int32, C.c_double, C.c_int64, C.c_int64, C.c_int32,
-                                         C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
+        L.oracle_ray_packets.argtypes = [C.c_int32, C.c_double, C.c_void_p, C.c_int64, C.c_int64,
+                                         C.c_int32, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
                                          C.POINTER(C.POINTER(C.c_double))]
         L.oracle_sphere_cell.restype = C.c_int64
         L.oracle_sphere_cell.argtypes = [C.POINTER(_Sphere), C.c_void_p]
@@ -229,6 +229,16 @@ class Sphere:
         out = np.zeros(cap)
         m = lib().oracle_sphere_crossings(C.byref(self.s), _p(a), _p(b), _p(out), cap)
         return out[:m].copy()
+
+    def middles(self):
+        """The middle of every cell [C, 3] in cell order: mid-radius, mid-angle
+        of the polar bin and mid-slice (where the deterministic rays start)."""
+        rm = 0.5 * (self.r_edge[:-1] + self.r_edge[1:])
+        tm = 0.5 * (self.theta_edge[:-1] + self.theta_edge[1:])
+        pm = (np.arange(self.n_phi) + 0.5) * 2 * np.pi / self.n_phi
+        R, T, P = np.meshgrid(rm, tm, pm, indexing="ij")  # [n_r, n_theta, n_phi]
+        x = np.stack([R * np.sin(T) * np.cos(P), R * np.sin(T) * np.sin(P), R * np.cos(T)], -1)
+        return np.ascontiguousarray(x.transpose(2, 1, 0, 3).reshape(-1, 3))
 
     def volumes(self, scale=1.0):
         """Cell volumes [C] in (scale x)^3 units: (r_b^3 - r_a^3)/3 (cos th_a -
@@ -479,29 +489,42 @@ def gth(R):
 def emission_bins(inp: "NLTEInputs", pops, t_exp, cell_volume, lambda_min, lambda_max, n_lambda):
     """Line emission per cell and logarithmic wavelength bin (Sec. 2.3, Eq. A3):
     returns (energy [C, n_lambda] erg s^-1, reddest line wavelength per bin
-    [n_lambda] (0 where empty), energy outside the range [C])."""
+    [n_lambda] (0 where empty), energy outside the range [C]). cell_volume is
+    one volume for every cell (cm^3) or an array of each cell's volume."""
     pops = np.ascontiguousarray(pops, dtype=np.float64)
     C_ = pops.size // inp.n_levels
     E = np.zeros((C_, n_lambda))
     lam = np.zeros(n_lambda)
     out = np.zeros(C_)
-    lib().oracle_emission_bins(C.byref(inp.atom), C_, _p(pops), t_exp, cell_volume, lambda_min,
-                               lambda_max, n_lambda, _p(E), _p(lam), _p(out))
+    vols = None
+    if np.ndim(cell_volume):
+        vols = np.ascontiguousarray(cell_volume, dtype=np.float64)
+        assert vols.size == C_
+    lib().oracle_emission_bins(C.byref(inp.atom), C_, _p(pops), t_exp,
+                               0.0 if vols is not None else float(cell_volume),
+                               _p(vols) if vols is not None else None, lambda_min, lambda_max,
+                               n_lambda, _p(E), _p(lam), _p(out))
     return E, lam, out
 
 
-def ray_packets(n, beta_max, bin_energy, bin_lambda, n_theta, n_phi, first=0, count=None):
+def ray_packets(n, beta_max, bin_energy, bin_lambda, n_theta, n_phi, first=0, count=None,
+                sphere=None):
     """The deterministic rays of cells [first, first+count) as explicit packets
     [R, 8] (x, y, z, n_x, n_y, n_z, lambda_e, w0), cell by cell, bin by bin,
-    viewer by viewer (theta-major)."""
+    viewer by viewer (theta-major), from the middle of each cell: the cube's
+    cell centre, or with sphere (a Sphere) the middle of the spherical cell."""
     E = np.ascontiguousarray(bin_energy, dtype=np.float64)
     lam = np.ascontiguousarray(bin_lambda, dtype=np.float64)
     n_lambda = lam.size
     if count is None:
         count = E.size // n_lambda - first
+    origins = None
+    if sphere is not None:
+        origins = np.ascontiguousarray(sphere.middles()[first:first + count])
     ptr = C.POINTER(C.c_double)()
-    nr = lib().oracle_ray_packets(n, beta_max, first, count, n_lambda, _p(E), _p(lam), n_theta,
-                                  n_phi, C.byref(ptr))
+    nr = lib().oracle_ray_packets(n, beta_max, _p(origins) if origins is not None else None,
+                                  first, count, n_lambda, _p(E), _p(lam), n_theta, n_phi,
+                                  C.byref(ptr))
     if nr > 0:
         buf = (C.c_double * (8 * nr)).from_address(C.addressof(ptr.contents))
         out = np.frombuffer(buf, dtype=np.float64).reshape(nr, 8).copy()

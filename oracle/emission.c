@@ -27,9 +27,9 @@
 static double beta_sobolev(double tau) { return tau <= 0.0 ? 1.0 : -expm1(-tau) / tau; }
 
 void oracle_emission_bins(const or_atom* a, int64_t n_cells, const double* pops, double t_exp,
-                          double cell_volume, double lambda_min, double lambda_max,
-                          int32_t n_lambda, double* bin_energy, double* bin_lambda,
-                          double* outside) {
+                          double cell_volume, const double* volumes, double lambda_min,
+                          double lambda_max, int32_t n_lambda, double* bin_energy,
+                          double* bin_lambda, double* outside) {
   double dlog = log(lambda_max / lambda_min);
   memset(bin_lambda, 0, sizeof(double) * (size_t)n_lambda);
   for (int32_t t = 0; t < a->n_trans; ++t) {
@@ -42,6 +42,7 @@ void oracle_emission_bins(const or_atom* a, int64_t n_cells, const double* pops,
   }
   for (int64_t c = 0; c < n_cells; ++c) {
     const double* n = pops + c * a->n_levels;
+    const double V = volumes ? volumes[c] : cell_volume;
     double* E = bin_energy + c * n_lambda;
     memset(E, 0, sizeof(double) * (size_t)n_lambda);
     outside[c] = 0.0;
@@ -50,7 +51,7 @@ void oracle_emission_bins(const or_atom* a, int64_t n_cells, const double* pops,
       double gl = a->level_g[lo], gu = a->level_g[up], lam = a->trans_lambda[t];
       double tau = a->trans_A[t] / (8.0 * M_PI) * (gu / gl) * lam * lam * lam * t_exp *
                    (n[lo] - (gl / gu) * n[up]);
-      double e = a->trans_A[t] * beta_sobolev(tau) * n[up] * cell_volume * (H_PLANCK * C_LIGHT / lam);
+      double e = a->trans_A[t] * beta_sobolev(tau) * n[up] * V * (H_PLANCK * C_LIGHT / lam);
       if (lam >= lambda_min && lam < lambda_max) {
         int32_t b = (int32_t)floor(n_lambda * log(lam / lambda_min) / dlog);
         if (b < 0) b = 0;
@@ -63,16 +64,21 @@ void oracle_emission_bins(const or_atom* a, int64_t n_cells, const double* pops,
   }
 }
 
-int64_t oracle_ray_packets(int32_t n, double beta_max, int64_t first, int64_t count,
-                           int32_t n_lambda, const double* bin_energy, const double* bin_lambda,
-                           int32_t n_theta, int32_t n_phi, double** packets) {
+int64_t oracle_ray_packets(int32_t n, double beta_max, const double* origins, int64_t first,
+                           int64_t count, int32_t n_lambda, const double* bin_energy,
+                           const double* bin_lambda, int32_t n_theta, int32_t n_phi,
+                           double** packets) {
   double h = 2.0 * beta_max / n;
   int64_t cap = 1024, nr = 0;
   double* out = (double*)malloc(sizeof(double) * 8 * (size_t)cap);
   for (int64_t c = first; c < first + count; ++c) {
-    int32_t ci[3] = {(int32_t)(c % n), (int32_t)((c / n) % n), (int32_t)(c / ((int64_t)n * n))};
     double x[3];
-    for (int a = 0; a < 3; ++a) x[a] = -beta_max + (ci[a] + 0.5) * h;
+    if (origins) {  /* the middle of the cell, given */
+      for (int a = 0; a < 3; ++a) x[a] = origins[3 * (c - first) + a];
+    } else {        /* the centre of the cube's cell */
+      int32_t ci[3] = {(int32_t)(c % n), (int32_t)((c / n) % n), (int32_t)(c / ((int64_t)n * n))};
+      for (int a = 0; a < 3; ++a) x[a] = -beta_max + (ci[a] + 0.5) * h;
+    }
     for (int32_t b = 0; b < n_lambda; ++b) {
       double E = bin_energy[c * n_lambda + b];
       if (!(E > 0.0)) continue;

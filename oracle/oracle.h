@@ -182,24 +182,28 @@ void oracle_gth(int32_t N, const double* R, double* pi);
  * Delta E = h c / lambda_t) into bin floor(n_lambda ln(lambda_t / lambda_min) /
  * ln(lambda_max / lambda_min)). Outputs: bin_energy [C * n_lambda] erg s^-1;
  * bin_lambda [n_lambda], the reddest transition wavelength in each bin (0 if
- * none); outside [C], erg s^-1 of transitions outside the range. pops [C*N]. */
+ * none); outside [C], erg s^-1 of transitions outside the range. pops [C*N].
+ * V is volumes[c] (cm^3, per cell) when volumes is not NULL, else cell_volume. */
 void oracle_emission_bins(const or_atom* a, int64_t n_cells, const double* pops, double t_exp,
-                          double cell_volume, double lambda_min, double lambda_max,
-                          int32_t n_lambda, double* bin_energy, double* bin_lambda,
-                          double* outside);
+                          double cell_volume, const double* volumes, double lambda_min,
+                          double lambda_max, int32_t n_lambda, double* bin_energy,
+                          double* bin_lambda, double* outside);
 
 /* Rays of the deterministic emission as explicit packets (x, y, z, n_x, n_y,
  * n_z, lambda_e, w0): for each cell c in [first, first + count), each bin b
  * with energy, each viewer k (theta-major: k = i_theta n_phi + i_phi) one ray
- * from the cell centre towards the viewer at theta = (i_theta + 1/2) pi /
+ * from the middle of the cell (origins[3 (c - first) ..] when origins is not
+ * NULL, else the centre of the cube's cell) towards the viewer at theta =
+ * (i_theta + 1/2) pi /
  * n_theta, phi = (i_phi + 1/2) 2 pi / n_phi, starting at the bin's reddest
  * wavelength with N = E_bin (Delta Omega_k / 4 pi) / (h c / lambda_b) photons
  * s^-1 (reading of the ray weight E_bin / Delta Omega_k / E_phot), Delta
  * Omega_k = (2 pi / n_phi)(cos theta_lo - cos theta_hi). Returns the number of
  * rays written to *packets (malloc'ed; free with oracle_free). */
-int64_t oracle_ray_packets(int32_t n, double beta_max, int64_t first, int64_t count,
-                           int32_t n_lambda, const double* bin_energy, const double* bin_lambda,
-                           int32_t n_theta, int32_t n_phi, double** packets);
+int64_t oracle_ray_packets(int32_t n, double beta_max, const double* origins, int64_t first,
+                           int64_t count, int32_t n_lambda, const double* bin_energy,
+                           const double* bin_lambda, int32_t n_theta, int32_t n_phi,
+                           double** packets);
 
 /* ---- Batched NLTE problem (one element, three ion stages per cell) -------
  * Sec. 2.2 rate model with frozen rates: every bound-bound pair of a stage has

@@ -127,3 +127,22 @@ def test_thin_rays_escape_isotropically():
     dom = (2 * np.pi / nph) * (np.cos((np.arange(nt * nph) // nph) * np.pi / nt) -
                                np.cos((np.arange(nt * nph) // nph + 1) * np.pi / nt))
     np.testing.assert_allclose(per_view / dom, per_view.sum() / (4 * np.pi), rtol=1e-12)
+
+
+def test_emission_with_each_cells_volume():
+    """Per-cell volumes (the spherical grid's): the same two-level emission by
+    hand with a different volume in each of two cells."""
+    lam_in = 6300e-8
+    atom = _atom([lam_in], [2.0e6])
+    inp = _inputs(atom, C=2)
+    nl, nu = 3.0e6, 2.0e5
+    pops = np.array([[nl, nu], [nl, nu]])
+    V = np.array([2.5e45, 7.0e43])
+    t = 1.728e7
+    lmin, lmax, nb = 3000e-8, 10000e-8, 1204
+    E, _, _ = oracle.emission_bins(inp, pops, t, V, lmin, lmax, nb)
+    tau = 2.0e6 / (8 * math.pi) * (4.0 / 2.0) * lam_in ** 3 * t * (nl - (2.0 / 4.0) * nu)
+    beta = (1.0 - math.exp(-tau)) / tau
+    b = int(math.floor(nb * math.log(lam_in / lmin) / math.log(lmax / lmin)))
+    for c in range(2):
+        assert E[c, b] == pytest.approx(2.0e6 * beta * nu * V[c] * HC / lam_in, rel=1e-13)

@@ -184,3 +184,41 @@ def test_thin_limit_and_conservation_on_spherical_grid():
             np.testing.assert_allclose(pk[:, 0] * 4000, (rho * 1e40).sum(), rtol=0.6)
         else:
             assert st["n_inter"] > 1000 and st["n_cross"] > 4000
+
+
+def test_cell_middles_lie_in_their_cells():
+    """The rays' starting points on the spherical grid (mid-radius, mid-angle,
+    mid-slice) classified by numpy fall in their own cells."""
+    S = _grid(n_r=7, n_theta=5, n_phi=9, seed=8)
+    m = S.middles()
+    assert m.shape == (S.n_cells, 3)
+    for c in range(S.n_cells):
+        assert _np_cell(S, m[c]) == c
+
+
+def test_rays_from_spherical_cells_carry_their_photons_once():
+    """Deterministic rays from the middles of spherical cells, through lines of
+    zero opacity: every ray escapes unshifted in direction, and the escaped
+    photons of each cell equal its bins' photons (the viewers' solid angles
+    sum to 4 pi)."""
+    S = _grid(n_r=4, n_theta=3, n_phi=4, seed=9)
+    C = S.n_cells
+    g = np.random.default_rng(10)
+    nb = 3
+    lam = np.array([4500.0, 5200.0, 6100.0]) * A
+    E = g.uniform(0.5, 2.0, (C, nb)) * 1e30
+    E[::5, 1] = 0.0  # some empty bins
+    rays = oracle.ray_packets(1, 1.0, E, lam, 4, 6, sphere=S)
+    photons = E / (6.62607015e-27 * 2.99792458e10 / lam)
+    assert rays[:, 7].sum() == pytest.approx(photons.sum(), rel=1e-13)
+    inp = oracle.TransportInputs(1, 1.0, np.ones(C, np.float32), np.ones(C), np.zeros(C, np.int32),
+                                 np.array([5000 * A]), np.array([0.0], np.float32), 0, 0, 1,
+                                 explicit_packets=rays, sphere=S)
+    r = oracle.transport(inp, per_packet=True)
+    assert r["stats"]["n_escaped"] == len(rays) and len(r["records"]) == 0
+    assert r["stats"]["w_esc"] == pytest.approx(photons.sum(), rel=1e-13)
+    # each ray starts in the cell whose bins it carries, in cell order
+    per_cell = (E > 0).sum(1) * 24
+    cells = np.repeat(np.arange(C), per_cell)
+    for i in range(0, len(rays), 11):
+        assert S.cell(rays[i, :3]) == cells[i]
