@@ -109,9 +109,10 @@ typedef struct {
  * uniform in the slice (u2) for the position; the direction, wavelength and
  * weight are drawn as in the cube. Explicit packets start in the cell their
  * position falls in; one beyond the outer sphere is dropped and flagged
- * (EXTRASS_STAT_BAD_PACKETS). Spherical grids run with FP64 positions and
- * distances (geometry_fp32 is ignored) and sampled or explicit packets (no
- * rays). extrass_transport_streamed splits them into n_domains equal ranges of
+ * (EXTRASS_STAT_BAD_PACKETS). Deterministic rays start at the middle of the
+ * cell: mid-radius, mid-angle of the polar bin, mid-slice. Spherical grids run
+ * with FP64 positions and distances (geometry_fp32 is ignored).
+ * extrass_transport_streamed splits them into n_domains equal ranges of
  * phi (Sec. 2.4.1's phi decomposition; each a contiguous range of cells). */
 typedef struct extrass_spherical {
   int32_t n_r, n_theta, n_phi;  /* each >= 1; C at most 2^31 - 1 */
@@ -293,7 +294,9 @@ int extrass_emission_plan_destroy(extrass_emission_plan p);
  * extrass_rays.bin_lambda (owned by the plan). */
 int extrass_emission_plan_info(extrass_emission_plan p, int32_t* n_bins, int32_t* bin_number,
                                double* bin_lambda, const double** device_lambda);
-/* For the grid's cells (C = n^3, V = (2 beta_max / n c t_exp)^3) at
+/* For the grid's cells (the cube: C = n^3, V = (2 beta_max / n c t_exp)^3;
+ * a spherical grid: each cell's own volume (c t_exp)^3 (r_b^3 - r_a^3) / 3
+ * (cos theta_a - cos theta_b) 2 pi / n_phi) at
  * populations pops [C*N]: bin_photons [C*B] (device, overwritten) photons
  * s^-1 per occupied bin, E_bin / (h c / lambda_bin); outside [C] (device, may
  * be NULL) erg s^-1 emitted in lines outside [lambda_min, lambda_max). */

@@ -60,7 +60,7 @@ __global__ void k_emission(int64_t C, int N, int B, extrass_atom_ctx::Dev d,
                            const int32_t* __restrict__ slot_start,
                            const int32_t* __restrict__ slot_trans,
                            const double* __restrict__ bin_lambda, const double* __restrict__ pops,
-                           double t_exp, double V, double* __restrict__ bin_photons) {
+                           double t_exp, CellVolume V, double* __restrict__ bin_photons) {
   const int64_t total = C * B;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
@@ -72,13 +72,13 @@ __global__ void k_emission(int64_t C, int N, int B, extrass_atom_ctx::Dev d,
       const int t = slot_trans[i];
       acc += escaping_decays(d, t, pc, t_exp) * (bin_lambda[j] / d.o_lam[t]);
     }
-    bin_photons[e] = acc * V;
+    bin_photons[e] = acc * V(c);
   }
 }
 
 __global__ void k_emission_outside(int64_t C, int N, int n_out, extrass_atom_ctx::Dev d,
                                    const int32_t* __restrict__ out_trans,
-                                   const double* __restrict__ pops, double t_exp, double V,
+                                   const double* __restrict__ pops, double t_exp, CellVolume V,
                                    double* __restrict__ outside) {
   for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < C;
        c += (int64_t)gridDim.x * blockDim.x) {
@@ -88,7 +88,7 @@ __global__ void k_emission_outside(int64_t C, int N, int n_out, extrass_atom_ctx
       const int t = out_trans[i];
       acc += escaping_decays(d, t, pc, t_exp) * (kHC / d.o_lam[t]);
     }
-    outside[c] = acc * V;
+    outside[c] = acc * V(c);
   }
 }
 
@@ -174,13 +174,13 @@ extern "C" int extrass_emission_plan_info(extrass_emission_plan p, int32_t* n_bi
 extern "C" int extrass_emission(extrass_handle h, extrass_emission_plan p, extrass_atom_handle a,
                                 const extrass_grid* g, double t_exp, const double* pops,
                                 double* bin_photons, double* outside, void* stream) {
-  if (!h || !p || !a || !g || !pops || !bin_photons || g->spherical || g->n <= 0 || g->n > 1024 ||
-      !(g->beta_max > 0.0) || !(t_exp > 0.0) || p->T != a->T || p->device != h->device)
+  if (!h || !p || !a || !g || !pops || !bin_photons || !grid_shape_ok(g) || !(t_exp > 0.0) ||
+      p->T != a->T || p->device != h->device)
     return fail(h, EXTRASS_EINVAL, "extrass_emission: bad argument");
-  const int64_t C = (int64_t)g->n * g->n * g->n;
+  const int64_t C = grid_cell_count(g);
   EXTRASS_HIP_TRY(h, hipSetDevice(h->device));
   hipStream_t st = static_cast<hipStream_t>(stream);
-  const double V = cell_volume(g->n, g->beta_max, t_exp);
+  const CellVolume V = grid_volumes(g, t_exp);
   if (p->B > 0) {
     const int64_t blocks = std::min<int64_t>((C * p->B + 255) / 256, 65536);
     hipLaunchKernelGGL(k_emission, dim3((unsigned)blocks), dim3(256), 0, st, C, a->N, p->B, a->d,

@@ -621,10 +621,26 @@ __device__ void emit(const TArgs& A, int64_t p, Packet<G>& q) {
     const int k = static_cast<int>(p - cb * V);
     const int64_t c = cb / A.ray_B;
     const int j = static_cast<int>(cb - c * A.ray_B);
-    ci[0] = static_cast<int>(c % A.n);
-    ci[1] = static_cast<int>((c / A.n) % A.n);
-    ci[2] = static_cast<int>(c / ((int64_t)A.n * A.n));
-    for (int a = 0; a < 3; ++a) x[a] = -A.beta + (static_cast<double>(ci[a]) + 0.5) * A.h;
+    if constexpr (SPH) {
+      // the middle of the spherical cell: mid-radius, mid-angle, mid-slice
+      ci[0] = static_cast<int>(c % A.sph_nr);
+      ci[1] = static_cast<int>((c / A.sph_nr) % A.sph_nt);
+      ci[2] = static_cast<int>(c / ((int64_t)A.sph_nr * A.sph_nt));
+      const double rm = 0.5 * (A.sph_r[ci[0]] + A.sph_r[ci[0] + 1]);
+      const double tm = 0.5 * (A.sph_th[ci[1]] + A.sph_th[ci[1] + 1]);
+      const double pm = (ci[2] + 0.5) * A.sph_dphi;
+      double stm, ctm, spm, cpm;
+      sincos(tm, &stm, &ctm);
+      sincos(pm, &spm, &cpm);
+      x[0] = rm * stm * cpm;
+      x[1] = rm * stm * spm;
+      x[2] = rm * ctm;
+    } else {
+      ci[0] = static_cast<int>(c % A.n);
+      ci[1] = static_cast<int>((c / A.n) % A.n);
+      ci[2] = static_cast<int>(c / ((int64_t)A.n * A.n));
+      for (int a = 0; a < 3; ++a) x[a] = -A.beta + (static_cast<double>(ci[a]) + 0.5) * A.h;
+    }
     const int it = k / A.ray_np, ip = k - it * A.ray_np;
     const double th = (it + 0.5) * M_PI / A.ray_nt;
     const double ph = (ip + 0.5) * 2.0 * M_PI / A.ray_np;
@@ -1125,9 +1141,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
 // The spherical grid's exit search (three surfaces of each kind, square
 // roots, the cone quadratics) needs more registers than three wavefronts per
 // SIMD leave: two per SIMD.
-template <bool PI, bool OCT>
+template <bool RAYS, bool PI, bool OCT>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void k_transport_sph(TArgs A) {
-  transport_body<double, false, PI, true, OCT>(A);
+  transport_body<double, RAYS, PI, true, OCT>(A);
 }
 
 }  // namespace
@@ -1241,8 +1257,8 @@ static void launch_transport(bool fp32, bool rays, bool pi, bool sph, unsigned b
   const bool oct = A.oct >= 0;
   if (oct) {  // streamed visits: sampled packets only
     if (sph) {
-      if (pi) hipLaunchKernelGGL((k_transport_sph<true, true>), g, b, 0, st, A);
-      else hipLaunchKernelGGL((k_transport_sph<false, true>), g, b, 0, st, A);
+      if (pi) hipLaunchKernelGGL((k_transport_sph<false, true, true>), g, b, 0, st, A);
+      else hipLaunchKernelGGL((k_transport_sph<false, false, true>), g, b, 0, st, A);
     } else if (pi) {
       if (fp32) hipLaunchKernelGGL((k_transport<float, false, true, false, true>), g, b, 0, st, A);
       else hipLaunchKernelGGL((k_transport<double, false, true, false, true>), g, b, 0, st, A);
@@ -1250,9 +1266,11 @@ static void launch_transport(bool fp32, bool rays, bool pi, bool sph, unsigned b
       if (fp32) hipLaunchKernelGGL((k_transport<float, false, false, false, true>), g, b, 0, st, A);
       else hipLaunchKernelGGL((k_transport<double, false, false, false, true>), g, b, 0, st, A);
     }
-  } else if (sph) {
-    if (pi) hipLaunchKernelGGL((k_transport_sph<true, false>), g, b, 0, st, A);
-    else hipLaunchKernelGGL((k_transport_sph<false, false>), g, b, 0, st, A);
+  } else if (sph) {  // FP64 geometry on the spherical grid
+    if (rays && pi) hipLaunchKernelGGL((k_transport_sph<true, true, false>), g, b, 0, st, A);
+    else if (rays) hipLaunchKernelGGL((k_transport_sph<true, false, false>), g, b, 0, st, A);
+    else if (pi) hipLaunchKernelGGL((k_transport_sph<false, true, false>), g, b, 0, st, A);
+    else hipLaunchKernelGGL((k_transport_sph<false, false, false>), g, b, 0, st, A);
   } else if (pi) {
     if (rays && fp32) hipLaunchKernelGGL((k_transport<float, true, true, false, false>), g, b, 0, st, A);
     else if (rays) hipLaunchKernelGGL((k_transport<double, true, true, false, false>), g, b, 0, st, A);
@@ -1296,8 +1314,6 @@ extern "C" int extrass_transport(extrass_handle h, const extrass_grid* g, const 
   TArgs A{};
   if (!set_photoion(g, A)) return fail(h, EXTRASS_EINVAL, "extrass_transport: bad photoion");
   if (!set_spherical(g, A)) return fail(h, EXTRASS_EINVAL, "extrass_transport: bad spherical grid");
-  if (g->spherical && rays)
-    return fail(h, EXTRASS_EINVAL, "extrass_transport: deterministic rays need the cube");
   TransportWs tw;
   const size_t need = ws_layout(g, s, &tw, ws);
   if (ws_bytes < need) return fail(h, EXTRASS_ENOSPACE, "extrass_transport: workspace too small");

@@ -286,3 +286,59 @@ def test_streamed_phi_domains_arguments(ex, ctx, sph):
                                  w.cell_packets, w.line_lambda, w.line_tau0, n_domains=nd)
         with pytest.raises(ex.ExtrassError, match="invalid argument"):
             ex.transport_streamed(ctx, grid, w.seed, w.lambda_lo, w.lambda_hi, w.n_packets)
+
+
+def _sphere_emission(w):
+    """The 10-level atom of the small plain workload with log-uniform
+    populations in every spherical cell; emission binned in 0.1 % steps over
+    2900-10500 A (the atom's lines lie in 3000-10000 A)."""
+    aw = synth.sphere_small()
+    g = np.random.default_rng(21)
+    pops = 10 ** g.uniform(0.0, 4.0, (w.n_cells, aw.atom.n_levels))
+    lmin, lmax = 2900e-8, 10500e-8
+    nb = int(np.ceil(np.log(lmax / lmin) / np.log(1.001)))
+    S = oracle.Sphere(w.r_edge, w.theta_edge, w.n_phi)
+    inp = oracle.nlte_inputs_from_workload(aw)
+    E, lam, out = oracle.emission_bins(inp, pops, w.t_exp, S.volumes(C_LIGHT * w.t_exp), lmin,
+                                       lmax, nb)
+    return aw, pops, (lmin, lmax, nb), E, lam, out, S
+
+
+def test_emission_and_rays_on_spherical_grid(ex, ctx, sph):
+    """The paper's rays on its own grid: emission per (cell, bin) with each
+    spherical cell's volume, then one ray per (cell, occupied bin, viewer)
+    from the middle of the cell through the grid's lines, against the oracle's
+    rays transported on the same grid (per estimator entry, near ties at
+    surfaces counted). 5 x 7 viewers: no ray runs exactly through the
+    origin."""
+    w = sph
+    aw, pops, (lmin, lmax, nb), E, lam, out, S = _sphere_emission(w)
+    atom = ex.Atom(ctx, aw.atom)
+    plan = ex.EmissionPlan(ctx, atom, lmin, lmax, nb)
+    occ = np.flatnonzero(lam > 0)
+    grid = _gpu_grid(ex, w)
+    say(f"case: emission on the spherical grid, {w.n_cells} cells, {plan.n_bins} bins")
+    ph, outside = ex.emission(ctx, plan, atom, grid, w.t_exp, torch.as_tensor(pops, device="cuda:0"))
+    torch.cuda.synchronize()
+    HC = 6.62607015e-27 * C_LIGHT
+    np.testing.assert_allclose(ph.cpu().numpy(), E[:, occ] / (HC / lam[occ]), rtol=1e-13, atol=0)
+    np.testing.assert_allclose(outside.cpu().numpy(), out, rtol=1e-13, atol=0)
+    nt, nph = 5, 7
+    rays = oracle.ray_packets(1, 1.0, E, lam, nt, nph, sphere=S)
+    inp, _ = _oracle_inputs(w, explicit=rays)
+    say(f"case: oracle, {len(rays)} rays on the spherical grid (host)")
+    r = oracle.transport(inp)
+    ref = oracle.dense_estimator(r["records"], w.n_cells, w.n_lines)
+    say(f"case: GPU rays on the spherical grid, {len(rays)} rays")
+    est, st, _ = ex.transport_rays(ctx, grid, plan, ph, nt, nph)
+    torch.cuda.synchronize()
+    sd = ex.stats_dict(st)
+    m = _near_tie_metric(est.cpu().numpy(), ref, r["records"], w)
+    say(m, {k: (sd[k], r["stats"][k]) for k in ("n_inter", "n_cross", "n_escaped")})
+    assert sd["error_flag"] == 0 and sd["bad_packets"] == 0
+    assert m["clean_max_rel"] <= 1e-9 and m["moved"] == 0
+    assert m["tainted"] <= 1e-3 * m["clean"]
+    for k in ("n_inter", "n_cross", "n_escaped"):
+        assert abs(sd[k] - r["stats"][k]) <= max(m["near_ties"], 0), k
+    assert sd["w_emit"] == pytest.approx(r["stats"]["w_emit"], rel=1e-12)
+    assert sd["w_emit"] == pytest.approx(float(ph.sum()), rel=1e-12)
