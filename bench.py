@@ -581,6 +581,32 @@ def bench_spherical(ex, ctx):
                      "escaped_fraction": sd["w_esc"] / sd["w_emit"]}
         del grid
         torch.cuda.empty_cache()
+    # the paper's rays on its grid: line emission of the small plain
+    # workload's 10-level atom at log-uniform populations in every cell, one
+    # ray per (cell, occupied 0.1 % bin, 20 x 20 viewer) from the cell's middle
+    aw = synth.sphere_small()
+    g = np.random.default_rng(21)
+    pops = torch.as_tensor(10 ** g.uniform(0.0, 4.0, (w.n_cells, aw.atom.n_levels)), device=dev)
+    atom = ex.Atom(ctx, aw.atom)
+    lo, hi = 2900e-8, 10500e-8
+    plan = ex.EmissionPlan(ctx, atom, lo, hi, int(np.ceil(np.log(hi / lo) / np.log(1.001))))
+    grid = ex.spherical_grid(w.r_edge, w.theta_edge, w.n_phi, w.tau_scale, w.cell_photons,
+                             w.cell_packets, w.line_lambda, w.line_tau0, device=dev)
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    e[0].record(s)
+    ph, _ = ex.emission(ctx, plan, atom, grid, w.t_exp, pops)
+    e[1].record(s)
+    _, st, _ = ex.transport_rays(ctx, grid, plan, ph, 20, 20, est=est, stats=stats)
+    e[2].record(s)
+    torch.cuda.synchronize()
+    sd = ex.stats_dict(st)
+    n_rays = w.n_cells * plan.n_bins * 400
+    out["deterministic_rays"] = {"occupied_bins": plan.n_bins, "viewers": [20, 20],
+                                 "rays": n_rays, "ms_emission": e[0].elapsed_time(e[1]),
+                                 "ms_rays": e[1].elapsed_time(e[2]),
+                                 "rays_per_s": n_rays / (e[1].elapsed_time(e[2]) * 1e-3),
+                                 "interactions": sd["n_inter"],
+                                 "escaped_fraction": sd["w_esc"] / sd["w_emit"]}
     return out
 
 
