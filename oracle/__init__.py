@@ -90,7 +90,7 @@ def lib():
         L.oracle_line_tau.argtypes = [C.c_int64, C.c_int32, C.c_int32] + [C.c_void_p] * 6 + \
             [C.c_double, C.c_void_p, C.c_void_p]
         L.oracle_rates.argtypes = [C.c_int64, C.c_int32, C.c_int32, C.c_int32] + [C.c_void_p] * 4 + \
-            [C.c_double, C.c_void_p]
+            [C.c_double, C.c_void_p, C.c_void_p]
         L.oracle_nlte.restype = C.c_int
         L.oracle_nlte.argtypes = [C.POINTER(_Atom), C.POINTER(_Cells), C.c_int64, C.c_int64,
                                   C.c_int, C.c_int, C.c_double, C.c_int, C.c_void_p, C.c_void_p,
@@ -388,14 +388,18 @@ def line_tau(pops, atom, t_exp):
 
 
 def rates(est, pops, atom, cell_volume):
+    """Photoexcitation rate per atom in the lower level [C*T]: est / (n_l V),
+    cell_volume one volume for every cell or an array of each cell's."""
     est = np.ascontiguousarray(est, dtype=np.float64)
     pops = np.ascontiguousarray(pops, dtype=np.float64)
     C_ = pops.size // atom.n_levels
     L = est.size // C_
     out = np.zeros(C_ * atom.n_trans)
     lo, tl = _keep(atom.trans_lower, atom.trans_line)
+    vols = np.ascontiguousarray(cell_volume, dtype=np.float64) if np.ndim(cell_volume) else None
     lib().oracle_rates(C_, L, atom.n_levels, atom.n_trans, _p(est), _p(pops), _p(lo), _p(tl),
-                       cell_volume, _p(out))
+                       0.0 if vols is not None else float(cell_volume),
+                       _p(vols) if vols is not None else None, _p(out))
     return out
 
 

@@ -117,9 +117,12 @@ void oracle_line_tau(int64_t n_cells, int32_t n_levels, int32_t n_trans, const d
                      double* tau_ct, double* fcorr_ct);
 
 /* ---- Photoexcitation rates -------------------------------------------------- */
+/* V is volumes[c] (cm^3, per cell, a spherical grid's) when volumes is not
+ * NULL, else cell_volume. */
 void oracle_rates(int64_t n_cells, int32_t n_lines, int32_t n_levels, int32_t n_trans,
                   const double* est, const double* pops, const int32_t* lower,
-                  const int32_t* trans_line, double cell_volume, double* gamma_pe);
+                  const int32_t* trans_line, double cell_volume, const double* volumes,
+                  double* gamma_pe);
 
 /* ---- NLTE statistical equilibrium ------------------------------------------ */
 typedef struct {

@@ -655,10 +655,12 @@ void oracle_line_tau(int64_t n_cells, int32_t n_levels, int32_t n_trans, const d
  * give the photoexcitation rate per lower atom. */
 void oracle_rates(int64_t n_cells, int32_t n_lines, int32_t n_levels, int32_t n_trans,
                   const double* est, const double* pops, const int32_t* lower,
-                  const int32_t* trans_line, double cell_volume, double* gamma_pe) {
+                  const int32_t* trans_line, double cell_volume, const double* volumes,
+                  double* gamma_pe) {
   for (int64_t c = 0; c < n_cells; ++c) {
+    const double V = volumes ? volumes[c] : cell_volume;
     for (int32_t t = 0; t < n_trans; ++t) {
-      double Nl = pops[c * n_levels + lower[t]] * cell_volume;
+      double Nl = pops[c * n_levels + lower[t]] * V;
       double e = est[c * n_lines + trans_line[t]];
       gamma_pe[c * n_trans + t] = Nl > 0.0 ? e / Nl : 0.0;
     }

@@ -360,6 +360,9 @@ def test_rates_hand_computed_two_cells():
     # cell 0: t0 lower 0 line 2: 7 / (2 * 0.5) = 7; t1 lower 1 line 0: 3 / (4 * 0.5) = 1.5
     # cell 1: t0 lower level empty -> 0;            t1: 11 / (8 * 0.5) = 2.75
     np.testing.assert_array_equal(got, [[7.0, 1.5], [0.0, 2.75]])
+    # each cell's own volume (a spherical grid's): 0.5 and 0.25
+    got = oracle.rates(est, pops, atom, np.array([0.5, 0.25])).reshape(2, 2)
+    np.testing.assert_array_equal(got, [[7.0, 1.5], [0.0, 5.5]])
 
 
 def test_line_tau_equals_line_opacity_integrated_along_a_ray():
