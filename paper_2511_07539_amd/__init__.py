@@ -296,12 +296,18 @@ def spherical_grid(r_edge, theta_edge, n_phi, tau_scale, cell_photons, cell_pack
     return g
 
 
-def grid_from_workload(w, device="cuda:0", tau_ct=None, fcorr_ct=None):
+def grid_from_workload(w, device="cuda:0", tau_ct=None, fcorr_ct=None, n_domains=0):
+    """The workload's grid: its cube, or for a workload on a spherical grid
+    (w.r_edge) that grid with n_domains phi subdomains."""
     line_trans = None
     if tau_ct is not None:
         lt = np.full(w.n_lines, -1, dtype=np.int32)
         lt[w.atom.trans_line] = np.arange(w.atom.n_trans, dtype=np.int32)
         line_trans = lt
+    if getattr(w, "r_edge", None) is not None:
+        return spherical_grid(w.r_edge, w.theta_edge, w.n_phi, w.tau_scale, w.cell_photons,
+                              w.cell_packets, w.line_lambda, w.line_tau0, device, line_trans,
+                              tau_ct, fcorr_ct, n_domains)
     return Grid(w.n, w.beta_max, w.tau_scale, w.cell_photons, w.cell_packets, w.line_lambda,
                 w.line_tau0, device, line_trans, tau_ct, fcorr_ct)
 

@@ -38,11 +38,13 @@ class GlobalLoop:
     unless octant_table is set. With ion_energy [S*3] (erg) the transport also
     photoionises (Sec. 2.3.1): each iteration builds the continuum opacity from
     the current populations, and the NLTE solve takes the photoionisation
-    rates the transport measured."""
+    rates the transport measured. A workload on a spherical grid streams over
+    n_domains equal phi ranges (the paper's decomposition, Sec. 2.4.1); the
+    cube over its 8 velocity octants."""
 
     def __init__(self, ctx: Context, w, device="cuda:0", geometry_fp32=True, queue_capacity=None,
                  max_iter=200, tol=1e-10, warm_budget=30, octant_table=False, ion_energy=None,
-                 pi_levels_per_stage=25):
+                 pi_levels_per_stage=25, n_domains=8):
         self.ctx, self.w, self.device = ctx, w, device
         self.geometry_fp32, self.queue_capacity = geometry_fp32, queue_capacity
         self.max_iter, self.tol, self.warm_budget = max_iter, tol, warm_budget
@@ -61,7 +63,8 @@ class GlobalLoop:
                            gamma_pi=self.gamma_pi)
         self.deposition = torch.as_tensor(w.deposition, device=device)
         tau = torch.empty((C, T), dtype=torch.float64, device=device)
-        self.grid = grid_from_workload(w, device=device, tau_ct=tau, fcorr_ct=torch.empty_like(tau))
+        self.grid = grid_from_workload(w, device=device, tau_ct=tau, fcorr_ct=torch.empty_like(tau),
+                                       n_domains=n_domains)
         del tau
         if self.pi_plan is not None:
             M = self.pi_plan.M
@@ -73,8 +76,8 @@ class GlobalLoop:
         self.status = torch.empty(C, dtype=torch.int32, device=device)
         self.iters = torch.empty(C, dtype=torch.int32, device=device)
         self.stats = torch.empty(16, dtype=torch.float64, device=device)
-        half = w.n // 2
-        self.est_oct = (torch.empty((half ** 3, w.n_lines), dtype=torch.float64, device=device)
+        sub = C // n_domains if self.grid.spherical is not None else (w.n // 2) ** 3
+        self.est_oct = (torch.empty((sub, w.n_lines), dtype=torch.float64, device=device)
                         if octant_table else None)
         lv_species = torch.as_tensor(
             np.repeat(np.arange(w.atom.n_species), np.diff(w.atom.species_offset)), device=device)
@@ -257,12 +260,13 @@ class RayLoop:
 
 def run(ctx: Context, w, iterations=5, params=None, norm=None, warm_budget=30, geometry_fp32=True,
         queue_capacity=None, max_iter=200, tol=1e-10, device="cuda:0", log=None,
-        octant_table=False, ion_energy=None):
+        octant_table=False, ion_energy=None, n_domains=8):
     """Returns (pops [C, N], status [C], history) of `iterations` global
     iterations over workload w (see GlobalLoop)."""
     loop = GlobalLoop(ctx, w, device=device, geometry_fp32=geometry_fp32,
                       queue_capacity=queue_capacity, max_iter=max_iter, tol=tol,
-                      warm_budget=warm_budget, octant_table=octant_table, ion_energy=ion_energy)
+                      warm_budget=warm_budget, octant_table=octant_table, ion_energy=ion_energy,
+                      n_domains=n_domains)
     pops, status, hist = loop.run(iterations, params, norm, log=log)
     return pops.clone(), status.clone(), hist
 

@@ -237,6 +237,47 @@ def ion_energies(workload: int, atom: Atom, chi_lo_ev: float = 0.5,
     return out
 
 
+def _cell_states(wl, number, rho, active, atom, T_range, mass_fractions):
+    """The atom's per-cell state on workload wl (cube or spherical grid):
+    T_e, species and electron densities, non-thermal ionisation rates and
+    gamma-ray deposition, drawn from the cell-state stream."""
+    S = atom.n_species
+    gc = rng(number, STREAM_CELLS)
+    C = len(rho)
+    lo, hi = T_range
+    T_e = np.where(active, 10.0 ** gc.uniform(np.log10(lo), np.log10(hi), size=C), lo)
+    # mass fractions vary per cell around the given means (first species
+    # uniform within +-0.2 of its mean, the rest in proportion)
+    X = np.tile(np.asarray(mass_fractions, float), (C, 1))
+    if S > 1:
+        x0 = np.clip(X[:, 0] + gc.uniform(-0.2, 0.2, C), 0.05, 0.95)
+        rest = X[:, 1:] / X[:, 1:].sum(axis=1, keepdims=True)
+        X = np.column_stack([x0, (1.0 - x0)[:, None] * rest])
+    n_sp = np.zeros((C, S))
+    for s in range(S):
+        n_sp[:, s] = X[:, s] * rho / (atom.species_mass[s] * M_U)
+    n_e = 0.5 * n_sp.sum(axis=1)
+    # gamma-ray deposition ~ rho times lognormal scatter (sigma_ln ~ 1); non-thermal
+    # ionisation per atom ~ deposition per atom, with one constant per
+    # (species, stage) drawn log-uniformly, scaled so that the rates span
+    # about 1e-7..1e-3 s^-1 over the cells
+    dep = np.where(active, rho * _lognormal_unit_mean(gc, 1.3, C), 0.0)
+    per_atom = np.where(active, dep / np.maximum(n_sp.sum(axis=1), 1e-300), 0.0)
+    ref = np.median(per_atom[active]) if active.any() else 1.0
+    gam = np.zeros((C, S, 3))
+    nz = int(atom.level_ion.max()) + 1
+    if nz > 1:
+        kz = _log_uniform(gc, 1e-6, 1e-4, (S, nz - 1))
+        gam[:, :, : nz - 1] = kz[None, :, :] * (per_atom / ref)[:, None, None]
+    dep_scale = 1e-7 / max(np.median(dep[active]) if active.any() else 1.0, 1e-300)
+    wl.deposition = dep * dep_scale
+    wl.atom = atom
+    wl.T_e = T_e
+    wl.n_e = n_e
+    wl.n_species = n_sp.ravel()
+    wl.gamma_ion = gam.ravel()
+
+
 def _finish(name, number, n, beta_max, t_exp, rho, lines_lo_A, lines_hi_A, n_lines,
             tau_lo, tau_hi, n_packets, photons_total, atom_spec, T_range,
             couple_lines, mass_fractions):
@@ -256,41 +297,7 @@ def _finish(name, number, n, beta_max, t_exp, rho, lines_lo_A, lines_hi_A, n_lin
                   seed=packet_seed(number), couple_lines=couple_lines)
     if atom_spec is not None:
         atom = make_atom(number, line_lambda=lam, lines_available=n_lines, **atom_spec)
-        S = atom.n_species
-        gc = rng(number, STREAM_CELLS)
-        C = n ** 3
-        lo, hi = T_range
-        T_e = np.where(active, 10.0 ** gc.uniform(np.log10(lo), np.log10(hi), size=C), lo)
-        # mass fractions vary per cell around the given means (first species
-        # uniform within +-0.2 of its mean, the rest in proportion)
-        X = np.tile(np.asarray(mass_fractions, float), (C, 1))
-        if S > 1:
-            x0 = np.clip(X[:, 0] + gc.uniform(-0.2, 0.2, C), 0.05, 0.95)
-            rest = X[:, 1:] / X[:, 1:].sum(axis=1, keepdims=True)
-            X = np.column_stack([x0, (1.0 - x0)[:, None] * rest])
-        n_sp = np.zeros((C, S))
-        for s in range(S):
-            n_sp[:, s] = X[:, s] * rho / (atom.species_mass[s] * M_U)
-        n_e = 0.5 * n_sp.sum(axis=1)
-        # gamma-ray deposition ~ rho times lognormal scatter (sigma_ln ~ 1); non-thermal
-        # ionisation per atom ~ deposition per atom, with one constant per
-        # (species, stage) drawn log-uniformly, scaled so that the rates span
-        # about 1e-7..1e-3 s^-1 over the cells
-        dep = np.where(active, rho * _lognormal_unit_mean(gc, 1.3, C), 0.0)
-        per_atom = np.where(active, dep / np.maximum(n_sp.sum(axis=1), 1e-300), 0.0)
-        ref = np.median(per_atom[active]) if active.any() else 1.0
-        gam = np.zeros((C, S, 3))
-        nz = int(atom.level_ion.max()) + 1
-        if nz > 1:
-            kz = _log_uniform(gc, 1e-6, 1e-4, (S, nz - 1))
-            gam[:, :, : nz - 1] = kz[None, :, :] * (per_atom / ref)[:, None, None]
-        dep_scale = 1e-7 / max(np.median(dep[active]) if active.any() else 1.0, 1e-300)
-        wl.deposition = dep * dep_scale
-        wl.atom = atom
-        wl.T_e = T_e
-        wl.n_e = n_e
-        wl.n_species = n_sp.ravel()
-        wl.gamma_ion = gam.ravel()
+        _cell_states(wl, number, rho, active, atom, T_range, mass_fractions)
     return wl
 
 
@@ -432,7 +439,9 @@ class SphericalWorkload:
     """Inputs on a spherical (r, theta, phi) grid (Sec. 2): shell edges r_edge
     (x = v/c, from 0), polar edges theta_edge, n_phi equal azimuthal slices;
     cell c = i_r + n_r (i_theta + n_theta i_phi). Per-cell arrays have
-    n_r n_theta n_phi entries; no atom (background lines only)."""
+    n_r n_theta n_phi entries. Without an atom every line is a background
+    line; with one (spherical(atom=True)) its transitions take lines of the
+    list and the cells carry the atom's state, as on the cube."""
     name: str
     number: int
     r_edge: np.ndarray
@@ -449,6 +458,12 @@ class SphericalWorkload:
     lambda_hi: float
     n_packets: int
     seed: int
+    atom: Optional[Atom] = None
+    T_e: Optional[np.ndarray] = None
+    n_e: Optional[np.ndarray] = None
+    n_species: Optional[np.ndarray] = None
+    gamma_ion: Optional[np.ndarray] = None
+    deposition: Optional[np.ndarray] = None
 
     @property
     def n_r(self) -> int:
@@ -475,7 +490,8 @@ class SphericalWorkload:
 
 
 def spherical(n_r: int = 40, n_theta: int = 30, n_phi: int = 60, n_lines: int = 5000,
-              n_packets: int = 10_000_000, number: int = 8, power: float = 1.5) -> SphericalWorkload:
+              n_packets: int = 10_000_000, number: int = 8, power: float = 1.5,
+              atom: bool = False) -> SphericalWorkload:
     """Clumped homologous ejecta on a spherical grid, v_max 5000 km/s, t = 200 d.
 
     Shell edges r_i = R (i / n_r)^power (cells grow outwards, as the paper's
@@ -484,7 +500,10 @@ def spherical(n_r: int = 40, n_theta: int = 30, n_phi: int = 60, n_lines: int = 
     (multiplier lognormal, median 10, sigma_ln 0.5) renormalised per shell to
     conserve its mass, times 10 % noise; 1 M_sun in all. Lines in
     2000-25000 A with tau0 log-uniform in 1e-4..1e4 scaled by rho/rho_bar;
-    emission proportional to mass; packets by largest remainder."""
+    emission proportional to mass; packets by largest remainder. With atom,
+    the cube workloads' atom (two species of mass 16 and 56, three stages of
+    20+15+15 levels) on these lines, and its cell state drawn as on the cube
+    (T_e log-uniform in 2000-10000 K, mass fractions 0.7/0.3 +- 0.2)."""
     R = 5000.0 / C_KMS
     t_exp = 200.0 * DAY
     r_edge = R * (np.arange(n_r + 1) / n_r) ** power
@@ -518,6 +537,11 @@ def spherical(n_r: int = 40, n_theta: int = 30, n_phi: int = 60, n_lines: int = 
     sw.cell_packets = largest_remainder(mass / mass.sum(), n_packets)
     sw.line_lambda = lam
     sw.line_tau0 = tau0
+    if atom:
+        a = make_atom(number, line_lambda=lam, lines_available=n_lines, ion_levels=[20, 15, 15],
+                      masses=[16.0, 56.0], e_max_ev=10.0)
+        _cell_states(sw, number, rho, np.ones(C, bool), a, (2000.0, 10000.0), [0.7, 0.3])
+        sw.name += "_atom"
     return sw
 
 
