@@ -607,6 +607,21 @@ def bench_spherical(ex, ctx):
                                  "rays_per_s": n_rays / (e[1].elapsed_time(e[2]) * 1e-3),
                                  "interactions": sd["n_inter"],
                                  "escaped_fraction": sd["w_esc"] / sd["w_emit"]}
+    del grid, est, plan, atom, pops, ph
+    torch.cuda.empty_cache()
+    # the global loop on the spherical grid (the cube workloads' 100-level
+    # atom in every cell), streamed over 8 phi domains with the rates summed
+    # per interaction, from the cold start: two iterations
+    from paper_2511_07539_amd import globalloop
+    wa = synth.spherical(48, 32, 64, 5000, 10_000_000, number=8, atom=True)
+    loop = globalloop.GlobalLoop(ctx, wa, tol=1e-8, n_domains=8)
+    _, st_l, hist = loop.run(2)
+    out["global_loop_8_phi_domains"] = {
+        "workload": wa.name, "iterations": [
+            {k: h[k] for k in ("ms_line_tau", "ms_transport", "ms_nlte", "interactions",
+                               "cells_converged", "nlte_iters_mean")} for h in hist]}
+    del loop
+    torch.cuda.empty_cache()
     return out
 
 
