@@ -470,7 +470,11 @@ typedef struct {
                           a system still in its fixed-point phase or with a
                           fixed-point residual above 1e-6 restarts from the cold
                           start with the iterations left (status 1); so does one
-                          whose line search stalls before. 0: never */
+                          whose line search stalls before. 0: never, and the guess
+                          is taken as near the root (a previous solution): the
+                          fixed-point steps continue until they change no
+                          population by more than 0.1 in log n (1.0 with a
+                          budget) before Newton starts */
 } extrass_nlte_opts;
 
 /* Statistical equilibrium per cell and species (Sec. 2.2, Eqs. A1-A2):

@@ -684,7 +684,11 @@ __device__ __forceinline__ int solve_system(const NArgs& A, const Sys& y, double
       const double tot = wave_sum(v);
       n = live ? v * (y.ntot / tot) : 0.0;
       ++it;
-      if (change < (warm ? 1.0 : 0.7) || it >= 60) phase = RESID;
+      // the fixed-point phase ends at a change below 0.7 from the cold start,
+      // 1.0 from a guess checked against a warm budget (a learned guess),
+      // 0.1 from a guess trusted without one (the previous global
+      // iteration's populations: more fixed-point steps, fewer Newton steps)
+      if (change < (warm ? (check_at == 0 ? 0.1 : 1.0) : 0.7) || it >= 60) phase = RESID;
       used = it;
       if (it >= max_iter || (check_at > 0 && it == check_at)) return -1;
       best_it = it;
