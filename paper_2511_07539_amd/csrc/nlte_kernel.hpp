@@ -27,8 +27,9 @@
 //     coupled ion stages. A trust radius on max |d ln n| and a decrease test
 //     on sum (P(n)/n - 1)^2 globalise the iteration.
 // Convergence: max |d ln n| < tol with max |P(n)/n - 1| < tol; or, after a
-// full Newton step s following a full step s', a predicted next step
-// (s / s'^2) s^2 below tol / 100 with the residual below tol; or, with the
+// full Newton step s, a predicted next step below tol / 10 with the residual
+// below tol (the step after s is predicted as (s / s'^2) s^2 when a full step
+// s' preceded s, else as s scaled by the residual's reduction); or, with the
 // residual below tol, a step below 1e-11 that has stopped shrinking (for tol
 // under that floor). Every exit counted as converged has met the residual
 // test.
@@ -715,12 +716,12 @@ __device__ __forceinline__ int solve_system(const NArgs& A, const Sys& y, double
           // (s / s_prev^2) s^2 for this full step s and the one before it,
           // or, after a first full step, (s / r) r_new: the step scaled by
           // the reduction of the residual it was taken from. When that is
-          // far below tol and the residual is already below tol, the
+          // below tol/10 and the residual is already below tol, the
           // verifying Newton step is skipped.
           if (taken == step) {
             const double pred = last_full > 0.0 ? (step / (last_full * last_full)) * step * step
                                                 : step * (res2 / res);
-            if (pred < 0.01 * A.tol && res2 < A.tol) return it;
+            if (pred < 0.1 * A.tol && res2 < A.tol) return it;
           }
           last_full = taken == step ? step : 0.0;
           phase = NEWTON;
