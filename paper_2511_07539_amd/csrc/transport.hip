@@ -75,7 +75,8 @@ struct TArgs {
   const double* fcorr_ct;
   uint64_t seed;
   uint32_t iteration;
-  int64_t first, count;
+  int64_t first, count;  // packet ids [first, first + count) (a streamed visit reads its
+                          // count from `visit`)
   double lam_lo, lam_hi;
   const double* explicit_pk;
   // deterministic rays (ray_ph not NULL): B occupied bins, viewers nt x np
@@ -93,7 +94,7 @@ struct TArgs {
   double* stats;
   double* pk_out;
   unsigned long long* queue;
-  // octant mode (oct >= 0)
+  // streamed visits (oct >= 0: the subdomain visited)
   int oct, half;
   int lo[3];                 // first cell index of the octant per axis
   int sub_slices;            // spherical grid: phi slices per subdomain (0: octants of the cube)
