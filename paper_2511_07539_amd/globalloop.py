@@ -161,7 +161,8 @@ class RayLoop:
     """Global iterations with the paper's own radiative transfer (Sec. 2.3):
     the cells' line emission (Eq. A3) from the current populations, sent as
     deterministic rays, one per (cell, occupied 0.1 % wavelength bin, viewer),
-    from each cell's middle -> estimators -> rates -> NLTE. Each iteration
+    from each cell's middle (of the cube or the spherical grid) -> estimators
+    -> rates -> NLTE. Each iteration
     reports the global convergence figure L_bol / L_dep: the luminosity of the
     escaping rays, plus the emission outside the binned range, plus the
     deposition of cells whose NLTE solve failed, over the total deposition
@@ -198,8 +199,10 @@ class RayLoop:
         self.new = torch.empty_like(self.pops)
         self.status = torch.empty(C, dtype=torch.int32, device=device)
         self.iters = torch.empty(C, dtype=torch.int32, device=device)
-        V = (2.0 * w.beta_max / w.n * 2.99792458e10 * w.t_exp) ** 3
-        self.dep_cell = torch.as_tensor(w.deposition, device=device) * V   # erg s^-1 per cell
+        # cell volumes: the cube's, or each spherical cell's (the workload's inputs)
+        V = (w.cell_volumes() if getattr(w, "r_edge", None) is not None
+             else (2.0 * w.beta_max / w.n * 2.99792458e10 * w.t_exp) ** 3)
+        self.dep_cell = torch.as_tensor(w.deposition * V, device=device)   # erg s^-1 per cell
         self.L_dep = float(self.dep_cell.sum())
 
     @property

@@ -22,6 +22,7 @@ pytestmark = pytest.mark.gpu
 
 A = synth.ANGSTROM
 C_LIGHT = 2.99792458e10
+HC = 6.62607015e-27 * C_LIGHT
 
 
 def say(*a):
@@ -320,7 +321,6 @@ def test_emission_and_rays_on_spherical_grid(ex, ctx, sph):
     say(f"case: emission on the spherical grid, {w.n_cells} cells, {plan.n_bins} bins")
     ph, outside = ex.emission(ctx, plan, atom, grid, w.t_exp, torch.as_tensor(pops, device="cuda:0"))
     torch.cuda.synchronize()
-    HC = 6.62607015e-27 * C_LIGHT
     np.testing.assert_allclose(ph.cpu().numpy(), E[:, occ] / (HC / lam[occ]), rtol=1e-13, atol=0)
     np.testing.assert_allclose(outside.cpu().numpy(), out, rtol=1e-13, atol=0)
     nt, nph = 5, 7
@@ -342,3 +342,46 @@ def test_emission_and_rays_on_spherical_grid(ex, ctx, sph):
         assert abs(sd[k] - r["stats"][k]) <= max(m["near_ties"], 0), k
     assert sd["w_emit"] == pytest.approx(r["stats"]["w_emit"], rel=1e-12)
     assert sd["w_emit"] == pytest.approx(float(ph.sum()), rel=1e-12)
+
+
+def test_ray_loop_on_spherical_grid(ex, ctx):
+    """One iteration of the ray-driven global loop on a spherical grid whose
+    cells carry the 100-level atom: the escaping luminosity and the emission
+    outside the binned range equal the oracle's (its cold start, emission with
+    each cell's volume, rays from the cell middles, transport on the same
+    grid), and L_dep is the deposition times each cell's volume."""
+    from paper_2511_07539_amd import globalloop
+    w = synth.spherical(6, 4, 8, 1500, 10_000, number=11, atom=True)
+    nt, nph = 3, 5
+    lam_t = w.atom.trans_lambda
+    lmin, lmax = 0.97 * float(lam_t.min()), 1.03 * float(lam_t.max())
+    nb = int(np.ceil(np.log(lmax / lmin) / np.log(1.001)))
+    loop = globalloop.RayLoop(ctx, w, n_theta=nt, n_phi=nph, lambda_min=lmin, lambda_max=lmax)
+    say(f"case: ray-driven loop on a 6 x 4 x 8 spherical grid, {loop.plan.n_bins} bins, "
+        f"{nt} x {nph} viewers")
+    _, status, hist, _ = loop.run(iterations=1)
+    rec = hist[0]
+    say(rec)
+    S = oracle.Sphere(w.r_edge, w.theta_edge, w.n_phi)
+    V = w.cell_volumes()
+    inp0 = oracle.nlte_inputs_from_workload(w)
+    pops = np.stack([oracle.nlte_cold(inp0, c) for c in range(w.n_cells)])
+    E, lam, out = oracle.emission_bins(inp0, pops, w.t_exp, V, lmin, lmax, nb)
+    tau, fc = oracle.line_tau(pops, w.atom, w.t_exp)
+    rays = oracle.ray_packets(1, 1.0, E, lam, nt, nph, sphere=S)
+    lt = np.full(w.n_lines, -1, np.int32)
+    lt[w.atom.trans_line] = np.arange(w.atom.n_trans, dtype=np.int32)
+    inp = oracle.TransportInputs(1, 1.0, w.tau_scale, w.cell_photons, w.cell_packets,
+                                 w.line_lambda, w.line_tau0, 0, 0, 1, 0, lt, tau, fc,
+                                 explicit_packets=rays, sphere=S)
+    r = oracle.transport(inp, per_packet=True)
+    near = int((r["records"]["margin"] < 1e-10).sum())
+    say(f"oracle: {len(rays)} rays, {r['stats']['n_inter']:.0f} interactions, {near} near ties")
+    pk = r["packets"]
+    esc = pk[:, 0] > 0
+    L_esc = HC * np.sum(pk[esc, 0] / pk[esc, 1])
+    assert rec["photons_emitted"] == pytest.approx(rays[:, 7].sum(), rel=1e-12)
+    assert rec["L_outside_range"] == pytest.approx(out.sum(), rel=1e-12, abs=1e-300)
+    assert rec["L_dep"] == pytest.approx(float(np.sum(w.deposition * V)), rel=1e-12)
+    assert abs(rec["interactions"] - r["stats"]["n_inter"]) <= near
+    assert rec["L_escaping"] == pytest.approx(L_esc, rel=1e-10 if near == 0 else 1e-6)
