@@ -197,6 +197,23 @@ def main():
                  "converged": int((st_c <= 1).sum()), "cold_fallbacks": int((st_c == 1).sum())}
     del pops_c, st_c, it_c
 
+    # the same step with the mixed-precision NLTE pass (fixed-point steps
+    # reduced in FP32, residuals and Newton systems in FP64)
+    say("step with the mixed-precision NLTE pass")
+    loop.nlte_fp32 = True
+    ev_m = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(ITERATIONS)]
+    step(ev_m)
+    torch.cuda.synchronize()
+    loop.nlte_fp32 = False
+    nlte_m = [ev_m[k][2].elapsed_time(ev_m[k][3]) for k in range(ITERATIONS)]
+    it_m = iters_sum.cpu().numpy()
+    mixed = {"nlte_ms_per_iteration": nlte_m,
+             "warm_later_iterations_ms": float(np.mean(nlte_m[1:])),
+             "nlte_iters_mean": (it_m[:, 0] / w.n_cells).tolist(),
+             "cells_converged_per_iteration": it_m[:, 1].astype(int).tolist(),
+             "plain_fp64_cold_ms": cold_ms,
+             "fp64_warm_later_iterations_ms": float(per_it[1:, 2].mean())}
+
     # roofline of the dominant kernel
     fl = nlte_flops_per_iteration(w.atom)
     flops = float(it_np[:, 0].sum() * sum(fl))   # iteration count is the larger of the species'
@@ -238,7 +255,8 @@ def main():
             "plain_fp64_cold_converged": cold_ok,
             "mlp_warm_same_rates": warm_same,
             "cell_solves_per_s_warm_later": w.n_cells / (per_it[1:, 2].mean() * 1e-3),
-            "cell_solves_per_s_plain_fp64": w.n_cells / (cold_ms * 1e-3)},
+            "cell_solves_per_s_plain_fp64": w.n_cells / (cold_ms * 1e-3),
+            "mixed_precision_pass": mixed},
         "warm_start_training": {"workload": w50.name, "epochs": args.epochs,
                                 "loss_first": hist[0], "loss_last": hist[-1],
                                 "setup_s": t_train},
@@ -323,8 +341,9 @@ def accuracy_sample(w, n):
 
 def nlte_accuracy(ex, ctx, loop, w, cells, gpe, params, norm, args):
     """Componentwise max |n - n_oracle| / n_oracle of the GPU's NLTE solves on
-    the sample: the plain FP64 cold start and the MLP warm start, both at the
-    bench's tol, against the oracle at 1e-12 on the same seeded inputs."""
+    the sample: the plain FP64 cold start and the MLP warm start, each also
+    with the fixed-point steps reduced in FP32, all at the bench's tol, against
+    the oracle at 1e-12 on the same seeded inputs."""
     import numpy as np
     import torch
 
@@ -336,6 +355,9 @@ def nlte_accuracy(ex, ctx, loop, w, cells, gpe, params, norm, args):
     guess = ex.nlte_warm_start(ctx, loop.atom, cl, w.deposition[cells], params, norm)
     pw, sw, _ = ex.nlte_solve(ctx, loop.atom, cl, tol=args.nlte_tol, guess=guess,
                               warm_budget=args.warm_budget)
+    pcm, scm, _ = ex.nlte_solve(ctx, loop.atom, cl, tol=args.nlte_tol, factor_fp32=True)
+    pwm, swm, _ = ex.nlte_solve(ctx, loop.atom, cl, tol=args.nlte_tol, guess=guess,
+                                warm_budget=args.warm_budget, factor_fp32=True)
     torch.cuda.synchronize()
     inp = oracle.NLTEInputs(w.atom, w.t_exp, w.T_e[cells], w.n_e[cells],
                             w.n_species.reshape(-1, S)[cells].ravel(),
@@ -352,7 +374,8 @@ def nlte_accuracy(ex, ctx, loop, w, cells, gpe, params, norm, args):
                 "compared": int(ok.sum())}
     acc = {"tol": args.nlte_tol, "reference": "oracle, tol 1e-12", "cells": int(len(cells)),
            "oracle_converged": int((so == 0).sum()),
-           "plain_fp64_cold": rel(pc, sc), "mlp_warm": rel(pw, sw)}
+           "plain_fp64_cold": rel(pc, sc), "mlp_warm": rel(pw, sw),
+           "mixed_cold": rel(pcm, scm), "mixed_mlp_warm": rel(pwm, swm)}
     return acc, {"oracle_s": t_or, "status": so}
 
 

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libextrass.so")
 OBJ = os.path.join(HERE, "_build")
-SOURCES = ["atom.hip", "transport.hip", "spectrum.hip", "nlte.hip", "nlte_blocks.hip", "nlte_whole.hip", "mlp.hip",
+SOURCES = ["atom.hip", "transport.hip", "spectrum.hip", "nlte.hip", "nlte_blocks.hip", "nlte_blocks_mixed.hip", "nlte_whole.hip", "mlp.hip",
            "batched.hip", "emission.hip", "photoion.hip"]
 
 HIPCC_FLAGS = [

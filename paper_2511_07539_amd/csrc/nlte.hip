@@ -38,9 +38,6 @@ extern "C" int extrass_nlte_solve(extrass_handle h, extrass_atom_handle a, const
   if (cl->n_cells < 0 || !cl->T_e || !cl->n_e || !cl->n_species || !cl->gamma_ion ||
       o->max_iter < 0 || !(o->tol > 0.0))
     return fail(h, EXTRASS_EINVAL, "extrass_nlte_solve: bad cells or options");
-  if (o->factor_fp32)
-    return fail(h, EXTRASS_EUNSUPPORTED,
-                "extrass_nlte_solve: FP32 factors are not supported (FP64 only)");
   if (ws_bytes < extrass_nlte_workspace(a, cl->n_cells))
     return fail(h, EXTRASS_ENOSPACE, "extrass_nlte_solve: workspace too small");
   if (cl->n_cells == 0) return EXTRASS_OK;
@@ -87,6 +84,10 @@ extern "C" int extrass_nlte_solve(extrass_handle h, extrass_atom_handle a, const
   A.gsz = a->maxNs * A.NP;
   A.block_rows = (a->blockLanes + 1) & ~1;
   const bool blocks_fit = a->maxBlock <= 32 && a->blockLanes <= 64;
+  if (o->factor_fp32 && !blocks_fit)
+    return fail(h, EXTRASS_EUNSUPPORTED,
+                "extrass_nlte_solve: the mixed-precision pass needs stage blocks of at most 32 states "
+                "in 64 lanes");
   // stage blocks: kernels for blocks of at most 12, 16, 21, 22, 24 or 32
   // states (the reduction runs NTB - 1 unrolled steps on NTB-entry register
   // rows, so a bound one above the largest block costs a step and an entry:
@@ -112,11 +113,14 @@ extern "C" int extrass_nlte_solve(extrass_handle h, extrass_atom_handle a, const
   int64_t blocks = std::min<int64_t>((int64_t)h->num_cus * per_cu, items);
   if (blocks < 1) blocks = 1;
   // The stage-block reduction serves atoms whose blocks fit (at most 32
-  // states each, side by side in 64 lanes) in FP64; otherwise the
-  // whole-system register reduction, compiled for a few system sizes, the
-  // smallest that holds the largest species.
-  const bool launched = blocks_fit ? launch_nlte_blocks(ntb, (unsigned)blocks, lds, st, A)
-                                   : launch_nlte_whole(nt, (unsigned)blocks, lds, st, A);
+  // states each, side by side in 64 lanes), in FP64 or with the fixed-point
+  // steps in FP32; otherwise the whole-system register reduction
+  // (FP64), compiled for a few system sizes, the smallest that holds the
+  // largest species.
+  const bool launched =
+      blocks_fit ? (o->factor_fp32 ? launch_nlte_blocks_mixed(ntb, (unsigned)blocks, lds, st, A)
+                                   : launch_nlte_blocks(ntb, (unsigned)blocks, lds, st, A))
+                 : launch_nlte_whole(nt, (unsigned)blocks, lds, st, A);
   if (!launched) return fail(h, EXTRASS_EINVAL, "extrass_nlte_solve: no kernel for this atom");
   EXTRASS_HIP_TRY(h, hipGetLastError());
   return EXTRASS_OK;

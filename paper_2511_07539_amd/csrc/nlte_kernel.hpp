@@ -38,6 +38,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "atom.hpp"
 #include "common.hpp"
@@ -79,9 +80,11 @@ struct NArgs {
 };
 
 // Kernel launchers, one translation unit each (compiled in parallel):
-// stage-block kernels for blocks of at most ntb states, whole-system kernels
-// for species of at most nt levels. Return false for an unsupported size.
+// stage-block kernels for blocks of at most ntb states (FP64, or with the
+// fixed-point steps reduced in FP32), whole-system kernels for species of at
+// most nt levels. Return false for an unsupported size.
 bool launch_nlte_blocks(int ntb, unsigned blocks, size_t lds, hipStream_t st, const NArgs& A);
+bool launch_nlte_blocks_mixed(int ntb, unsigned blocks, size_t lds, hipStream_t st, const NArgs& A);
 bool launch_nlte_whole(int nt, unsigned blocks, size_t lds, hipStream_t st, const NArgs& A);
 
 namespace {
@@ -366,6 +369,16 @@ __device__ __forceinline__ double rcp_pos(double S) {
   e = fma(-S, r, 1.0);
   return fma(r, e, r);
 }
+// The single-precision counterpart: one Newton step on the hardware estimate.
+__device__ __forceinline__ float rcp_pos(float S) {
+  const float r = __builtin_amdgcn_rcpf(S);
+  return fmaf(r, fmaf(-S, r, 1.0f), r);
+}
+
+// A pivot the reduction can divide by: positive, and in FP32 also normal
+// (the reciprocal of a subnormal overflows).
+__device__ __forceinline__ bool pivot_ok(double S) { return S > 0.0; }
+__device__ __forceinline__ bool pivot_ok(float S) { return S >= 1.17549435e-38f && S <= 3.4e38f; }
 
 // Solves x^T Q = b^T (rhs, with x of the ground `pin` fixed at 0) and the
 // stationary problem (pi of the ground `pin` = 1) for the generator whose
@@ -373,15 +386,29 @@ __device__ __forceinline__ double rcp_pos(double S) {
 // (x_l, pi_l) in out. LDS: scratch >= block_scratch(NTB, nrow) doubles
 // (16-byte aligned), xo/po >= 64 doubles each; nrow >= the lanes of the blocks.
 // Returns false when a pivot is not positive.
-template <int NTB>
+//
+// T = float reduces in single precision: rows, pivots, elimination and
+// back-substitution; the ground chain stays in FP64. Meant for the
+// stationary problem, whose reduction adds and multiplies positive numbers
+// only, so every component keeps FP32's relative accuracy. The matrix and
+// the right-hand side are first scaled by one power of two that takes the
+// largest entry of the system into [1, 2) (x and pi are unchanged by a
+// common scale), and pi of the reference ground is 2^100 instead of 1: rates
+// down to ~1e-38 of the largest and populations down to ~1e-68 of the
+// reference stay normal, and the products pi_j a_jr of the back-substitution
+// stay below ~2^107. A pivot or a pi outside the normal FP32 range returns
+// false.
+template <int NTB, class T = double>
 __device__ __forceinline__ bool reduce_blocks(const double* G, const int2* rt, int Ns, int nrow,
                                               const Blocks& k,
                                               bool rhs, double b_nat, int pin, double* scratch,
                                               double* xo, double* po, double* out) {
   static_assert(NTB <= 32, "row slots 32 and 33 carry the pivot and right-hand side");
+  constexpr bool kSingle = sizeof(T) == 4;
+  using T2 = typename std::conditional<kSingle, float2, double2>::type;
   const int lane = threadIdx.x;
   // [3][34]: pivot rows with the pivot and right-hand side in slots 32, 33
-  double* rows = scratch;
+  T* rows = reinterpret_cast<T*>(scratch);
   double* small = scratch + 102;  // reduced rates and right-hand sides of the ground pairs
   // The lane's block quantities are selected by its block z among values
   // every lane holds. Selecting among the descriptor's array elements
@@ -400,26 +427,38 @@ __device__ __forceinline__ bool reduce_blocks(const double* G, const int2* rt, i
   const int sn_z = z == 0 ? st1 : (z == 1 ? st2 : st3);
   const int my_lev = live ? (r < nex ? st_z + 1 + r : (r == nex ? st_z : sn_z)) : 0;
   const int2 my_rt = rt[my_lev];
-  double g[NTB];
+  double sc = 1.0;  // the common power-of-two scale (FP32 only)
+  if constexpr (kSingle) {
+    double m = 0.0;
+#pragma unroll
+    for (int b = 0; b < NTB; ++b) {
+      const int lev_b = b < nex ? st_z + 1 + b : (b == nex ? st_z : sn_z);
+      m = fmax(m, (live && b < B && b != r) ? fabs(G[my_rt.x + lev_b - my_rt.y]) : 0.0);
+    }
+    m = wave_max(m);
+    const int e = m > 0.0 ? -ilogb(m) : 0;
+    sc = uniform_d(ldexp(1.0, e < 1000 ? e : 1000));
+  }
+  T g[NTB];
 #pragma unroll
   for (int b = 0; b < NTB; ++b) {
     const int lev_b = b < nex ? st_z + 1 + b : (b == nex ? st_z : sn_z);
-    g[b] = (live && b < B && b != r) ? G[my_rt.x + lev_b - my_rt.y] : 0.0;
+    g[b] = (live && b < B && b != r) ? (T)(sc * G[my_rt.x + lev_b - my_rt.y]) : T(0);
   }
   // the scratch below overlays G: keep every row load ahead of its stores
   __asm__ volatile("" ::: "memory");
   // right-hand side: a ground's entry is counted in its own block only
-  double bb = __shfl(b_nat, my_lev, 64);
-  bb = (rhs && live && r <= nex) ? bb : 0.0;
-  double* myrow = rows + 34 * z;
+  double bbd = __shfl(b_nat, my_lev, 64);
+  T bb = (rhs && live && r <= nex) ? (T)(sc * bbd) : T(0);
+  T* myrow = rows + 34 * z;
   bool ok = true;
-  double my_inv = 0.0;  // 1 / pivot of this lane's state, kept for the back-substitution
+  T my_inv = T(0);  // 1 / pivot of this lane's state, kept for the back-substitution
   // a block has at most NTB - 1 excited levels (the top stage has no next ground)
 #pragma unroll
   for (int kk = 0; kk < NTB - 1; ++kk) {
     // row sum over the remaining states in 8 partial sums (the first term of
     // each seeds it: no additions of zero)
-    double acc[8];
+    T acc[8];
 #pragma unroll
     for (int b = kk + 1; b < NTB; ++b) {
       const int a = (b - kk - 1) & 7;
@@ -428,8 +467,8 @@ __device__ __forceinline__ bool reduce_blocks(const double* G, const int2* rt, i
     const int nrem = NTB - kk - 1;
 #pragma unroll
     for (int a = 0; a < 8; ++a)
-      if (a >= nrem) acc[a] = 0.0;
-    const double part = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+      if (a >= nrem) acc[a] = T(0);
+    const T part = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
     const bool act = live && kk < nex;
     // the pivot lane of each block publishes its row, its row sum (the pivot)
     // and its right-hand side
@@ -441,18 +480,18 @@ __device__ __forceinline__ bool reduce_blocks(const double* G, const int2* rt, i
     }
     __builtin_amdgcn_wave_barrier();
     if (act) {
-      const double S = myrow[32], bk = myrow[33];
-      if (!(S > 0.0)) ok = false;
-      const double inv = rcp_pos(S);
+      const T S = myrow[32], bk = myrow[33];
+      if (!pivot_ok(S)) ok = false;
+      const T inv = rcp_pos(S);
       if (r == kk) my_inv = inv;
-      const double f = g[kk] * inv;
+      const T f = g[kk] * inv;
 #pragma unroll
       // in chunks of 8: the chunk's pivot-row reads are issued together, then
       // its updates (left to itself, the scheduler kept the register
       // pressure down by waiting on each read before the next; 16 or 24 per
       // chunk spill more and are slower)
       for (int b0 = kk + 1; b0 < NTB; b0 += 8) {
-        double p[8];
+        T p[8];
 #pragma unroll
         for (int b = b0; b < b0 + 8 && b < NTB; ++b) p[b - b0] = myrow[b];
         __builtin_amdgcn_sched_group_barrier(0x100, 8, 0);   // LDS reads
@@ -462,22 +501,22 @@ __device__ __forceinline__ bool reduce_blocks(const double* G, const int2* rt, i
         __builtin_amdgcn_sched_barrier(0);
       }
       // every lane reads (no branch around the load); only r > kk keeps it
-      const double mr = myrow[r < NTB ? r : NTB - 1];
-      bb += (rhs && r > kk) ? bk * mr * inv : 0.0;
+      const T mr = myrow[r < NTB ? r : NTB - 1];
+      bb += (rhs && r > kk) ? bk * mr * inv : T(0);
     }
     __builtin_amdgcn_wave_barrier();
   }
   // reduced rates between the ground pair of each block: u_z (g_z -> g_z+1)
   // in the own-ground row, d_z (g_z+1 -> g_z) in the next-ground row
-  double cu = 0.0, cd = 0.0;
+  T cu = T(0), cd = T(0);
 #pragma unroll
   for (int b = 0; b < NTB; ++b) {
     cu = (b == nex + 1) ? g[b] : cu;
     cd = (b == nex) ? g[b] : cd;
   }
-  if (live && r == nex && B == nex + 2) { small[2 * z] = cu; small[6 + 2 * z] = bb; }
-  if (live && r == nex && B == nex + 1) small[6 + 2 * z] = bb;
-  if (live && r == nex + 1) { small[2 * z + 1] = cd; small[6 + 2 * z + 1] = bb; }
+  if (live && r == nex && B == nex + 2) { small[2 * z] = (double)cu; small[6 + 2 * z] = (double)bb; }
+  if (live && r == nex && B == nex + 1) small[6 + 2 * z] = (double)bb;
+  if (live && r == nex + 1) { small[2 * z + 1] = (double)cd; small[6 + 2 * z + 1] = (double)bb; }
   __builtin_amdgcn_wave_barrier();
   // ground-state chain
   const int K = k.nst;
@@ -493,7 +532,7 @@ __device__ __forceinline__ bool reduce_blocks(const double* G, const int2* rt, i
     pg[q] = 0.0;
     xg[q] = 0.0;
   }
-  pg[pin] = 1.0;
+  pg[pin] = kSingle ? 0x1p100 : 1.0;
 #pragma unroll
   for (int q = 1; q < 3; ++q)
     if (q > pin && q < K) pg[q] = pg[q - 1] * u[q - 1] / d[q - 1];
@@ -526,28 +565,28 @@ __device__ __forceinline__ bool reduce_blocks(const double* G, const int2* rt, i
   const double gz_p = z == 0 ? pg0 : (z == 1 ? pg1 : pg2);
   const double gn_x = z == 0 ? xg1 : (z == 1 ? xg2 : 0.0);
   const double gn_p = z == 0 ? pg1 : (z == 1 ? pg2 : 0.0);
-  double xm = 0.0, pm = 0.0;
-  if (live && r == nex) { xm = gz_x; pm = gz_p; }
-  if (live && r == nex + 1) { xm = gn_x; pm = gn_p; }
+  T xm = T(0), pm = T(0);
+  if (live && r == nex) { xm = (T)gz_x; pm = (T)gz_p; }
+  if (live && r == nex + 1) { xm = (T)gn_x; pm = (T)gn_p; }
   constexpr int LDW = NTB + 1;
-  double* Ld = scratch + kBlockScratch;   // [nrow][LDW] eliminated rows, by lane
-  double2* pv = reinterpret_cast<double2*>(Ld + nrow * LDW);  // [nrow] (x, pi) by lane
+  T* Ld = reinterpret_cast<T*>(scratch + kBlockScratch);  // [nrow][LDW] eliminated rows, by lane
+  T2* pv = reinterpret_cast<T2*>(Ld + nrow * LDW);          // [nrow] (x, pi) by lane
   if (live) {
 #pragma unroll
     for (int b = 0; b < NTB; ++b) Ld[lane * LDW + b] = g[b];
-    if (r == nex || r == nex + 1) pv[lane] = make_double2(xm, pm);
+    if (r == nex || r == nex + 1) pv[lane] = T2{xm, pm};
   }
   __builtin_amdgcn_wave_barrier();
-  double tx = 0.0, tp = 0.0;
+  T tx = T(0), tp = T(0);
   if (live && r < nex) {
     const int jg = base + nex;  // own ground, then the next ground
-    const double ag = Ld[jg * LDW + r];
-    const double2 vg = pv[jg];
+    const T ag = Ld[jg * LDW + r];
+    const T2 vg = pv[jg];
     tx += vg.x * ag;
     tp += vg.y * ag;
     if (B > nex + 1) {
-      const double an = Ld[(jg + 1) * LDW + r];
-      const double2 vn = pv[jg + 1];
+      const T an = Ld[(jg + 1) * LDW + r];
+      const T2 vn = pv[jg + 1];
       tx += vn.x * an;
       tp += vn.y * an;
     }
@@ -556,24 +595,26 @@ __device__ __forceinline__ bool reduce_blocks(const double* G, const int2* rt, i
 #pragma unroll
   for (int kk = NTB - 2; kk >= 0; --kk) {
     if (live && r == kk && kk < nex) {
-      xm = rhs ? (tx - bb) * my_inv : 0.0;
+      xm = rhs ? (tx - bb) * my_inv : T(0);
       pm = tp * my_inv;
-      pv[lane] = make_double2(xm, pm);
+      pv[lane] = T2{xm, pm};
     }
     __builtin_amdgcn_wave_barrier();
     if (live && r < kk && kk < nex) {
       const int j = base + kk;
-      const double a = Ld[j * LDW + r];
-      const double2 v = pv[j];
+      const T a = Ld[j * LDW + r];
+      const T2 v = pv[j];
       tx += v.x * a;
       tp += v.y * a;
     }
     __builtin_amdgcn_wave_barrier();
   }
+  if constexpr (kSingle)
+    if (live && r <= nex && !pivot_ok(pm)) ok = false;
   // back to level order
   if (live && r <= nex) {
-    xo[my_lev] = xm;
-    po[my_lev] = pm;
+    xo[my_lev] = (double)xm;
+    po[my_lev] = (double)pm;
   }
   __builtin_amdgcn_wave_barrier();
   out[0] = lane < Ns ? xo[lane] : 0.0;
@@ -589,7 +630,12 @@ __device__ __forceinline__ bool reduce_blocks(const double* G, const int2* rt, i
 //  RESID  - fixed-point residual h = P(n)/n - 1 at the current n;
 //  NEWTON - Newton step from the scaled Jacobian with right-hand side Q^T H;
 //  TRIAL  - fixed-point residual at a trial point inside the trust radius.
-template <int NT, int NTB>
+// MIX: the fixed-point steps reduce their stationary problem in FP32 (but
+// the first step from a guess, which may serve as the residual at the
+// guess); residuals and Newton systems stay FP64, so every exit test is that
+// of the FP64 solve. A step whose FP32 pivots or stationary components leave
+// the normal range is assembled again and reduced in FP64.
+template <int NT, int NTB, bool MIX = false>
 __device__ __forceinline__ int solve_system(const NArgs& A, const Sys& y, double* G, double* nb,
                                          double* hb,
                             double* rowbuf, double& n, int max_iter, int check_at, bool warm,
@@ -630,6 +676,7 @@ __device__ __forceinline__ int solve_system(const NArgs& A, const Sys& y, double
     if (live) const_cast<int2*>(y.rt)[lane] = make_int2(off, rlo);
   }
   double h = 0.0, x = 0.0, step = 0.0, taken = 0.0, trial = 0.0, phi = 0.0, res = 0.0;
+  bool force64 = false;  // MIX: redo this fixed-point step in FP64
   for (;;) {
     const bool newton = phase == NEWTON;
     const double at = phase == TRIAL ? trial : n;
@@ -651,7 +698,20 @@ __device__ __forceinline__ int solve_system(const NArgs& A, const Sys& y, double
           pin = q;
         }
       }
-      ok = reduce_blocks<NTB>(G, y.rt, y.Ns, A.block_rows, bl, newton, rhs, pin, rowbuf, nb, hb, xo);
+      if constexpr (MIX) {
+        if (phase == FIXED && !force64 && !(warm && it == 0)) {
+          ok = reduce_blocks<NTB, float>(G, y.rt, y.Ns, A.block_rows, bl, false, 0.0, pin, rowbuf, nb, hb, xo);
+          if (!ok) {
+            force64 = true;
+            continue;
+          }
+        } else {
+          ok = reduce_blocks<NTB, double>(G, y.rt, y.Ns, A.block_rows, bl, newton, rhs, pin, rowbuf, nb, hb, xo);
+        }
+        force64 = false;
+      } else {
+        ok = reduce_blocks<NTB>(G, y.rt, y.Ns, A.block_rows, bl, newton, rhs, pin, rowbuf, nb, hb, xo);
+      }
       done = true;
     } else if (newton) {
       // most populated level (first one on ties) goes last
@@ -787,7 +847,7 @@ __device__ double cold_start(const Sys& y, bool live) {
 
 // NTB > 0: stage-block reduction with blocks of at most NTB states (every
 // species fits); NTB = 0: whole-system reduction with NT >= the largest species.
-template <int NT, int NTB>
+template <int NT, int NTB, bool MIX = false>
 // Three wavefronts per SIMD (168 VGPRs): the solver is bound by the latency
 // of its wave-serial steps, and the third wavefront hides more of it than the
 // extra register spills cost.
@@ -865,7 +925,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 3))) void
         code = 1;
       }
       int used = 0;
-      its = solve_system<NT, NTB>(A, y, G, nb, hb, rowbuf, n, A.max_iter - spent,
+      its = solve_system<NT, NTB, MIX>(A, y, G, nb, hb, rowbuf, n, A.max_iter - spent,
                                   attempt == 0 && checked ? A.warm_budget : 0,
                                   attempt == 0 && A.use_guess, used);
       if (its >= 0) its += spent;

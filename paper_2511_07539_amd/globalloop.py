@@ -44,8 +44,11 @@ class GlobalLoop:
 
     def __init__(self, ctx: Context, w, device="cuda:0", geometry_fp32=True, queue_capacity=None,
                  max_iter=200, tol=1e-10, warm_budget=30, octant_table=False, ion_energy=None,
-                 pi_levels_per_stage=25, n_domains=8):
+                 pi_levels_per_stage=25, n_domains=8, nlte_fp32=False):
         self.ctx, self.w, self.device = ctx, w, device
+        # nlte_fp32: the NLTE solves reduce their fixed-point steps in FP32
+        # (residuals and Newton systems stay FP64)
+        self.nlte_fp32 = nlte_fp32
         self.geometry_fp32, self.queue_capacity = geometry_fp32, queue_capacity
         self.max_iter, self.tol, self.warm_budget = max_iter, tol, warm_budget
         self.octant_table = octant_table
@@ -116,7 +119,7 @@ class GlobalLoop:
         rec(2)
         nlte_solve(self.ctx, self.atom, self.cells, max_iter=self.max_iter, tol=self.tol,
                    guess=self.pops, warm_budget=warm_budget, pops=self.new, status=self.status,
-                   iters=self.iters)
+                   iters=self.iters, factor_fp32=self.nlte_fp32)
         rec(3)
         self.pops, self.new = self.new, self.pops
 

@@ -90,14 +90,16 @@ def _compare(pg, sg, po, so, inp=None, gpu_tol=1e-10, max_gpu_failures=0):
     return rel.max(), (b / b.max(axis=1, keepdims=True)).min()
 
 
-def test_sphere_small_all_cells(ex, ctx):
+@pytest.mark.parametrize("mixed", [False, True])
+def test_sphere_small_all_cells(ex, ctx, mixed):
+    """mixed: the fixed-point steps reduced in FP32, everything else FP64."""
     w = synth.sphere_small()
     gpe = _oracle_gamma(w)
     po, so, io = oracle.nlte(oracle.nlte_inputs_from_workload(w, gamma_pe=gpe), tol=1e-12)
     atom = ex.Atom(ctx, w.atom)
     cells = ex.cells_from_workload(w, gamma_pe=gpe)
-    say("case: sphere16 NLTE, 4096 cells, 10 levels")
-    pg, sg, ig = ex.nlte_solve(ctx, atom, cells, max_iter=200, tol=1e-10)
+    say(f"case: sphere16 NLTE, 4096 cells, 10 levels, FP32 fixed-point steps {mixed}")
+    pg, sg, ig = ex.nlte_solve(ctx, atom, cells, max_iter=200, tol=1e-10, factor_fp32=mixed)
     torch.cuda.synchronize()
     pg, sg, ig = pg.cpu().numpy(), sg.cpu().numpy(), ig.cpu().numpy()
     assert (so == 0).sum() == 2176 and (so == 3).sum() == 1920
@@ -107,8 +109,10 @@ def test_sphere_small_all_cells(ex, ctx):
     assert np.all(pg[so == 3] == 0)
 
 
-def test_three_stage_atom_sampled_cells(ex, ctx):
-    """2 species x (20+15+15) levels; 3000 cells sampled from the 50^3 workload."""
+@pytest.mark.parametrize("mixed", [False, True])
+def test_three_stage_atom_sampled_cells(ex, ctx, mixed):
+    """2 species x (20+15+15) levels; 3000 cells sampled from the 50^3
+    workload; mixed: the fixed-point steps reduced in FP32."""
     w = synth.paper_scale()
     g = np.random.default_rng(0)
     cells = np.sort(g.choice(w.n_cells, 3000, replace=False))
@@ -118,8 +122,8 @@ def test_three_stage_atom_sampled_cells(ex, ctx):
     po, so, io = oracle.nlte(inp, tol=1e-12)
     atom = ex.Atom(ctx, w.atom)
     cl = ex.cells_from_workload(w, gamma_pe=gpe, cells=cells)
-    say("case: clumpy50 NLTE, 3000 sampled cells, 2x50 levels")
-    pg, sg, ig = ex.nlte_solve(ctx, atom, cl, max_iter=200, tol=1e-10)
+    say(f"case: clumpy50 NLTE, 3000 sampled cells, 2x50 levels, FP32 fixed-point steps {mixed}")
+    pg, sg, ig = ex.nlte_solve(ctx, atom, cl, max_iter=200, tol=1e-10, factor_fp32=mixed)
     torch.cuda.synchronize()
     worst, span = _compare(pg.cpu().numpy(), sg.cpu().numpy(), po, so, inp=inp,
                            max_gpu_failures=len(cells) // 1000)
@@ -225,10 +229,56 @@ def test_tolerance_bounds_the_error(ex, ctx, paper_scale_all_cells, tol):
         assert rel.max() <= tol
 
 
-def test_fp32_factors_are_refused(ex, ctx):
-    w = synth.sphere_small()
+def test_mixed_precision_needs_stage_blocks(ex, ctx):
+    """A 40-level single-stage species (a block above 32 states) is solved by
+    the whole-system FP64 reduction only: the mixed-precision pass is refused."""
+    w = synth.clumpy(n=8, n_lines=3000, n_packets=1000, number=2, ion_levels=(40,))
     atom = ex.Atom(ctx, w.atom)
     cells = ex.cells_from_workload(w)
-    say("case: FP32 NLTE factors requested")
+    say("case: mixed-precision pass for a 40-level stage")
     with pytest.raises(ex.ExtrassError, match="unsupported"):
         ex.nlte_solve(ctx, atom, cells, factor_fp32=True)
+
+
+@pytest.mark.timeout(1200)
+def test_mixed_precision_pass_meets_tol(ex, ctx, paper_scale_all_cells):
+    """The mixed-precision pass (fixed-point steps reduced in FP32, residuals
+    and Newton systems in FP64) at tol 1e-8 on all 125 000 cells of the 50^3
+    workload: cold, from a perturbed guess with a warm budget, and from the
+    same guess trusted (no budget, the global loop's later iterations). Every
+    cell both sides converge is within tol of the oracle's root."""
+    tol = 1e-8
+    w, gpe, po, so, inp = paper_scale_all_cells
+    atom = ex.Atom(ctx, w.atom)
+    cl = ex.cells_from_workload(w, gamma_pe=gpe)
+    guess = torch.as_tensor(po * np.exp(np.random.default_rng(7).uniform(-0.4, 0.4, po.shape)),
+                            device="cuda:0")
+    say("case: clumpy50 NLTE, all cells, tol 1e-8, FP32 fixed-point steps: cold, warm, trusted")
+    runs = {
+        "cold": ex.nlte_solve(ctx, atom, cl, max_iter=200, tol=tol, factor_fp32=True),
+        "warm": ex.nlte_solve(ctx, atom, cl, max_iter=200, tol=tol, guess=guess, warm_budget=30,
+                              factor_fp32=True),
+        "trusted": ex.nlte_solve(ctx, atom, cl, max_iter=200, tol=tol, guess=guess, warm_budget=0,
+                                 factor_fp32=True),
+        "cold_fp64": ex.nlte_solve(ctx, atom, cl, max_iter=200, tol=tol),
+    }
+    torch.cuda.synchronize()
+    for name, (p, s_, it) in runs.items():
+        p, s_, it = p.cpu().numpy(), s_.cpu().numpy(), it.cpu().numpy()
+        claimed = np.where((s_ <= 1) & (so != 0))[0]
+        if len(claimed):
+            res = max(_fixed_point_residual(inp, c, p[c]) for c in claimed)
+            say(f"  {name}: {len(claimed)} GPU-only cells, fixed-point residual {res:.2e}")
+            assert res <= 10 * tol
+        ok = (so == 0) & (s_ <= 1)
+        rel = np.abs(p[ok] - po[ok]) / po[ok]
+        say(f"  {name}: converged {ok.sum()} of {len(so)}, max rel {rel.max():.3e}, "
+            f"mean iterations {it[s_ <= 1].mean():.3f}")
+        assert ok.sum() >= 0.999 * len(so)
+        assert rel.max() <= tol
+    # the FP32 steps ran (a fallback to FP64 on every step would reproduce
+    # the FP64 pass bit for bit)
+    pm, pd = runs["cold"][0].cpu().numpy(), runs["cold_fp64"][0].cpu().numpy()
+    differ = np.mean(np.any(pm != pd, axis=1))
+    say(f"  cells whose mixed and FP64 populations differ in some bit: {differ:.3f}")
+    assert differ > 0.5
