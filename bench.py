@@ -54,6 +54,10 @@ def parse():
                     help="cells the oracle solves for cpu_baseline and the accuracy check")
     ap.add_argument("--epochs", type=int, default=30)
     ap.add_argument("--warm-budget", type=int, default=30)
+    ap.add_argument("--nlte-precision", choices=("mixed", "fp64"), default="mixed",
+                    help="the step's NLTE pass: fixed-point steps in FP32 with FP64 residuals "
+                         "and Newton systems (mixed), or FP64 throughout; the other is timed "
+                         "beside it")
     ap.add_argument("--nlte-tol", type=float, default=1e-8,
                     help="population accuracy of the NLTE solves (the metric's 1e-8)")
     ap.add_argument("--no-extras", action="store_true",
@@ -119,7 +123,9 @@ def main():
         torch.cuda.empty_cache()
     w = synth.large()
     say(f"setup: {w.name} resident on the GPU")
-    loop = globalloop.GlobalLoop(ctx, w, tol=args.nlte_tol, warm_budget=args.warm_budget)
+    mixed_step = args.nlte_precision == "mixed"
+    loop = globalloop.GlobalLoop(ctx, w, tol=args.nlte_tol, warm_budget=args.warm_budget,
+                                 nlte_fp32=mixed_step)
     s = torch.cuda.current_stream()
     inter = torch.zeros(ITERATIONS, dtype=torch.float64, device=dev)
     iters_sum = torch.zeros((ITERATIONS, 2), dtype=torch.float64, device=dev)
@@ -189,7 +195,8 @@ def main():
     e0.record(s)
     ex.nlte_warm_start(ctx, loop.atom, loop.cells, loop.deposition, params, norm, pops=pops_c)
     ex.nlte_solve(ctx, loop.atom, loop.cells, tol=args.nlte_tol, guess=pops_c,
-                  warm_budget=args.warm_budget, pops=pops_c, status=st_c, iters=it_c)
+                  warm_budget=args.warm_budget, pops=pops_c, status=st_c, iters=it_c,
+                  factor_fp32=mixed_step)
     e1.record(s)
     torch.cuda.synchronize()
     warm_same_ms = e0.elapsed_time(e1)
@@ -197,22 +204,21 @@ def main():
                  "converged": int((st_c <= 1).sum()), "cold_fallbacks": int((st_c == 1).sum())}
     del pops_c, st_c, it_c
 
-    # the same step with the mixed-precision NLTE pass (fixed-point steps
+    # the same step with the other NLTE precision (mixed: fixed-point steps
     # reduced in FP32, residuals and Newton systems in FP64)
-    say("step with the mixed-precision NLTE pass")
-    loop.nlte_fp32 = True
+    other = "fp64" if mixed_step else "mixed"
+    say(f"step with the {other} NLTE pass")
+    loop.nlte_fp32 = not mixed_step
     ev_m = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(ITERATIONS)]
     step(ev_m)
     torch.cuda.synchronize()
-    loop.nlte_fp32 = False
+    loop.nlte_fp32 = mixed_step
     nlte_m = [ev_m[k][2].elapsed_time(ev_m[k][3]) for k in range(ITERATIONS)]
     it_m = iters_sum.cpu().numpy()
-    mixed = {"nlte_ms_per_iteration": nlte_m,
-             "warm_later_iterations_ms": float(np.mean(nlte_m[1:])),
-             "nlte_iters_mean": (it_m[:, 0] / w.n_cells).tolist(),
-             "cells_converged_per_iteration": it_m[:, 1].astype(int).tolist(),
-             "plain_fp64_cold_ms": cold_ms,
-             "fp64_warm_later_iterations_ms": float(per_it[1:, 2].mean())}
+    other_pass = {"nlte_precision": other, "nlte_ms_per_iteration": nlte_m,
+                  "warm_later_iterations_ms": float(np.mean(nlte_m[1:])),
+                  "nlte_iters_mean": (it_m[:, 0] / w.n_cells).tolist(),
+                  "cells_converged_per_iteration": it_m[:, 1].astype(int).tolist()}
 
     # roofline of the dominant kernel
     fl = nlte_flops_per_iteration(w.atom)
@@ -220,9 +226,11 @@ def main():
     dom = max(parts, key=parts.get)
     if dom == "nlte":
         ach = flops / (parts["nlte"] * 1e-3) / 1e12
-        roof = {"kernel": "extrass_nlte_solve (k_nlte)", "bound": "alu", "achieved": ach,
+        roof = {"kernel": "extrass_nlte_solve (k_nlte<0, 21, %s>)" % ("true" if mixed_step else "false"),
+                "bound": "alu", "achieved": ach,
                 "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": ach / FP64_PEAK_TFLOPS,
-                "traffic": recorded_traffic("extrass_nlte_clumpy100"),
+                "traffic": recorded_traffic("extrass_nlte_clumpy100_mixed" if mixed_step
+                                            else "extrass_nlte_clumpy100"),
                 "algorithmic_flops": flops,
                 "flops_per_system_iteration": fl}
     else:
@@ -239,7 +247,9 @@ def main():
         "config": {"workload": w.name, "cells": w.n_cells, "lines": w.n_lines,
                    "packets_per_iteration": w.n_packets, "global_iterations": ITERATIONS,
                    "subdomains": 8, "levels": w.atom.n_levels, "species": w.atom.n_species,
-                   "geometry": "fp32", "nlte_tol": args.nlte_tol},
+                   "geometry": "fp32", "nlte_tol": args.nlte_tol,
+                   "nlte_precision": ("mixed: fixed-point steps fp32, residuals and Newton fp64"
+                                      if mixed_step else "fp64")},
         "nlte_cell_solves_per_s": solves,
         "interactions_per_step": n_inter,
         "interactions_per_iteration": inter_np.tolist(),
@@ -256,7 +266,8 @@ def main():
             "mlp_warm_same_rates": warm_same,
             "cell_solves_per_s_warm_later": w.n_cells / (per_it[1:, 2].mean() * 1e-3),
             "cell_solves_per_s_plain_fp64": w.n_cells / (cold_ms * 1e-3),
-            "mixed_precision_pass": mixed},
+            "step_nlte_precision": args.nlte_precision,
+            "same_step_other_precision": other_pass},
         "warm_start_training": {"workload": w50.name, "epochs": args.epochs,
                                 "loss_first": hist[0], "loss_last": hist[-1],
                                 "setup_s": t_train},
@@ -432,8 +443,8 @@ def cpu_baseline(w, inter_step, sample, gpe, ref, args):
 def bench_clumpy50(ex, ctx, w, params, norm, args):
     """One global iteration on the 50^3 workload (125 000 cells, 5000 lines,
     1e7 packets) with the dense [C x L] FP64 estimator table: opacities ->
-    transport -> rates -> MLP warm start -> NLTE, from the cold-start
-    populations; HIP events per part; the transport's HBM roofline counts the
+    transport -> rates -> MLP warm start -> NLTE (the step's NLTE precision),
+    from the cold-start populations; HIP events per part; the transport's HBM roofline counts the
     table written once (8 C L bytes) plus the per-cell and per-line inputs."""
     import torch
     dev = "cuda:0"
@@ -468,7 +479,8 @@ def bench_clumpy50(ex, ctx, w, params, norm, args):
         ex.nlte_warm_start(ctx, atom, cells, dep, params, norm, pops=pops)
         mark(4)
         ex.nlte_solve(ctx, atom, cells, pops=pops, use_guess=True, warm_budget=args.warm_budget,
-                      tol=args.nlte_tol, status=status, iters=iters)
+                      tol=args.nlte_tol, status=status, iters=iters,
+                      factor_fp32=args.nlte_precision == "mixed")
         mark(5)
 
     step()
@@ -491,6 +503,7 @@ def bench_clumpy50(ex, ctx, w, params, norm, args):
             "nlte_cell_solves_per_s": w.n_cells / (ms * 1e-3), "ms_parts": parts,
             "cells_converged": int((status <= 1).sum()),
             "nlte_iters_mean": float(iters.float().mean()),
+            "nlte_precision": args.nlte_precision,
             "roofline_transport": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
                                    "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
                                    "algorithmic_bytes": bytes_alg,

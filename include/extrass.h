@@ -408,7 +408,8 @@ int extrass_rates(extrass_handle h, extrass_atom_handle atom, const extrass_grid
  * queue_capacity: packets each subdomain's queue holds; the workspace holds one
  * queue of 120-byte records per subdomain. A full queue loses packets: stats[QUEUE_FULL]
  * is set and the call returns EXTRASS_ENOSPACE. The host waits for the stream
- * between visits (queue lengths decide the next launch). */
+ * once per round of visits (the queue lengths decide whether another round
+ * runs). */
 size_t extrass_transport_streamed_workspace(const extrass_grid* grid, int64_t queue_capacity);
 int extrass_transport_streamed(extrass_handle h, const extrass_grid* grid, const extrass_source* src,
                                extrass_atom_handle atom, const double* pops, double t_exp,
