@@ -276,14 +276,15 @@ extern "C" int extrass_atom_destroy(extrass_atom_handle a) {
 }
 
 // ---------------------------------------------------------------- Eq. A2
-// One workgroup per cell at a time: the cell's populations are staged in LDS,
-// then every transition's tau and stimulated-emission factor is written, in
-// the caller's transition order (coalesced stores).
 // A tile of cpt cells per pass: their populations go to LDS, then the
 // tile's (cell, transition) entries are formed in order, so the threads'
 // writes of both outputs are contiguous across the tile. (One cell per pass
 // left the last of its four passes over 800 transitions a quarter busy and
-// synchronised the work-group per cell.)
+// synchronised the work-group per cell.) With STAGE, the transitions' levels
+// and constants are read into LDS once per work-group, which then walks its
+// tiles; each thread steps its (cell, transition) position by the block size
+// instead of dividing.
+template <bool STAGE>
 __global__ __launch_bounds__(256) void k_line_tau(int64_t n_cells, int N, int T, int cpt,
                                                  const double* __restrict__ pops,
                                                  const int32_t* __restrict__ lo,
@@ -292,23 +293,45 @@ __global__ __launch_bounds__(256) void k_line_tau(int64_t n_cells, int N, int T,
                                                  const double* __restrict__ r, double t_exp,
                                                  double* __restrict__ tau,
                                                  double* __restrict__ fcorr) {
-  extern __shared__ double pc[];  // [cpt * N]
+  extern __shared__ double smem[];
+  double* pc = smem;                                   // [cpt * N] populations of the tile
+  double* sK = smem + (size_t)cpt * N;                 // [T] (STAGE)
+  double* sR = sK + T;                                 // [T]
+  int2* sLU = reinterpret_cast<int2*>(sR + T);         // [T] lower, upper level
+  if constexpr (STAGE)
+    for (int t = threadIdx.x; t < T; t += blockDim.x) {
+      sK[t] = K[t];
+      sR[t] = r[t];
+      sLU[t] = make_int2(lo[t], up[t]);
+    }
   for (int64_t c0 = (int64_t)blockIdx.x * cpt; c0 < n_cells; c0 += (int64_t)gridDim.x * cpt) {
     const int nc = (int)(n_cells - c0 < cpt ? n_cells - c0 : cpt);
     for (int i = threadIdx.x; i < nc * N; i += blockDim.x) pc[i] = pops[c0 * N + i];
     __syncthreads();
     double* tau_t = tau + c0 * T;
     double* fc_t = fcorr + c0 * T;
+    int k = 0, t = threadIdx.x;
+    while (t >= T) {
+      t -= T;
+      ++k;
+    }
     for (int e = threadIdx.x; e < nc * T; e += blockDim.x) {
-      const int k = e / T, t = e - k * T;
-      const double nl = pc[k * N + lo[t]], nu = pc[k * N + up[t]];
+      const int2 lu = STAGE ? sLU[t] : make_int2(lo[t], up[t]);
+      const double rt = STAGE ? sR[t] : r[t];
+      const double Kt = STAGE ? sK[t] : K[t];
+      const double nl = pc[k * N + lu.x], nu = pc[k * N + lu.y];
       double tv = 0.0, fc = 1.0;
       if (nl > 0.0) {
-        fc = 1.0 - r[t] * nu / nl;
-        tv = K[t] * nl * fc * t_exp;
+        fc = 1.0 - rt * nu / nl;
+        tv = Kt * nl * fc * t_exp;
       }
       tau_t[e] = tv;
       fc_t[e] = fc;
+      t += blockDim.x;
+      while (t >= T) {
+        t -= T;
+        ++k;
+      }
     }
     __syncthreads();
   }
@@ -326,10 +349,25 @@ extern "C" int extrass_line_tau(extrass_handle h, extrass_atom_handle a, int64_t
   // cells per tile: up to 4, within 64 KB of LDS
   const int cpt = std::max(1, std::min(4, 8192 / a->N));
   const int64_t tiles = (n_cells + cpt - 1) / cpt;
-  const int64_t blocks = std::min<int64_t>(tiles, (int64_t)h->num_cus * 32);
-  hipLaunchKernelGGL(k_line_tau, dim3((unsigned)blocks), dim3(256), sizeof(double) * a->N * cpt,
-                     static_cast<hipStream_t>(stream), n_cells, a->N, a->T, cpt, pops, a->d.o_lo,
-                     a->d.o_up, a->d.o_K, a->d.o_r, t_exp, tau_ct, fcorr_ct);
+  const size_t pop_bytes = sizeof(double) * a->N * cpt;
+  // the transition table (24 B per transition) joins the tile in LDS when
+  // both fit in 48 KB; the grid is then what stays resident (each
+  // work-group walks many tiles with the table loaded once)
+  const size_t stage_bytes = pop_bytes + (size_t)24 * a->T;
+  const bool stage = stage_bytes <= 48 * 1024;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (stage) {
+    const int64_t per_cu = std::max<int64_t>(1, std::min<int64_t>(8, (160 * 1024) / stage_bytes));
+    const int64_t blocks = std::min<int64_t>(tiles, (int64_t)h->num_cus * per_cu);
+    hipLaunchKernelGGL(k_line_tau<true>, dim3((unsigned)blocks), dim3(256), stage_bytes, st,
+                       n_cells, a->N, a->T, cpt, pops, a->d.o_lo, a->d.o_up, a->d.o_K, a->d.o_r,
+                       t_exp, tau_ct, fcorr_ct);
+  } else {
+    const int64_t blocks = std::min<int64_t>(tiles, (int64_t)h->num_cus * 32);
+    hipLaunchKernelGGL(k_line_tau<false>, dim3((unsigned)blocks), dim3(256), pop_bytes, st,
+                       n_cells, a->N, a->T, cpt, pops, a->d.o_lo, a->d.o_up, a->d.o_K, a->d.o_r,
+                       t_exp, tau_ct, fcorr_ct);
+  }
   EXTRASS_HIP_TRY(h, hipGetLastError());
   return EXTRASS_OK;
 }
