@@ -182,3 +182,106 @@ def test_streamed_equals_unsplit_paper_scale(ex, ctx, fp32):
     say(f"support mismatches {mism}, max rel {worst:.2e}")
     assert mism == 0
     assert worst <= 1e-12
+
+
+@pytest.fixture(scope="module")
+def large_sparse():
+    """The 100^3 workload (1e6 cells, 30 000 lines, the 100-level atom) with
+    seeded level populations (per species, weights log-uniform over six
+    decades, summing to the species density) and a sparse sampling plan of
+    1e5 packets laid out as the full plan's 1e8 (largest remainder over the
+    same weights), so that the oracle can transport every packet."""
+    import dataclasses
+    w = synth.large()
+    g = np.random.default_rng(100)
+    N, S = w.atom.n_levels, w.atom.n_species
+    off = w.atom.species_offset
+    wt = 10.0 ** g.uniform(-6.0, 0.0, (w.n_cells, N))
+    pops = np.empty_like(wt)
+    ns = w.n_species.reshape(-1, S)
+    for s_ in range(S):
+        blk = wt[:, off[s_]:off[s_ + 1]]
+        pops[:, off[s_]:off[s_ + 1]] = blk / blk.sum(1, keepdims=True) * ns[:, s_:s_ + 1]
+    plan = synth.largest_remainder(w.cell_packets / w.cell_packets.sum(), 100_000)
+    ws = dataclasses.replace(w, cell_packets=plan.astype(np.int32), n_packets=int(plan.sum()))
+    return ws, pops
+
+
+@pytest.mark.timeout(900)
+def test_full_size_streamed_rates_match_oracle(ex, ctx, large_sparse):
+    """The bench's transport configuration at full size: 100^3 cells, 30 000
+    lines, 8 octants streamed with the rates summed per interaction. Each
+    side computes its own Eq. A2 opacities from the same populations (GPU
+    against oracle on 20 000 sampled cells, to 1e-13 of the terms of the
+    stimulated-emission factor), then transports the same
+    1e5 packets: FP64 geometry takes the same events (identical
+    interaction counts) and every rate the oracle's records touch agrees to
+    1e-10, with the same zero pattern; FP32 geometry (the bench's) keeps the
+    interaction count and the summed atom-line rates within 1e-3."""
+    import dataclasses
+    w, pops = large_sparse
+    C, T, L = w.n_cells, w.atom.n_trans, w.n_lines
+    V = (2 * w.beta_max / w.n * synth.C_CGS * w.t_exp) ** 3
+    atom = ex.Atom(ctx, w.atom)
+    pg = torch.as_tensor(pops, device="cuda:0")
+    say("case: 100^3 x 30000 opacities from seeded populations (GPU and oracle)")
+    tau_g, fc_g = ex.line_tau(ctx, atom, pg, w.t_exp)
+    tau_o, fc_o = oracle.line_tau(pops, w.atom, w.t_exp)
+    sample = np.sort(np.random.default_rng(5).choice(C, 20_000, replace=False))
+    sg = torch.as_tensor(sample, device="cuda:0")
+    tg = tau_g.reshape(C, T)[sg].cpu().numpy()
+    fg = fc_g.reshape(C, T)[sg].cpu().numpy()
+    to, fo = tau_o.reshape(C, T)[sample], fc_o.reshape(C, T)[sample]
+    # f = 1 - r n_u / n_l cancels where the populations are near inversion:
+    # both are held to the size of the terms of that difference, 1 + |1 - f|
+    # (tau = K n_l t f carries the same factor)
+    terms = 1.0 + np.abs(1.0 - fo)
+    assert np.max(np.abs(fg - fo) / terms) <= 1e-13
+    nzf = fo != 0
+    pre = np.abs(to[nzf] / fo[nzf])                      # K n_l t_exp
+    assert np.max(np.abs(tg[nzf] - to[nzf]) / (pre * terms[nzf])) <= 1e-13
+    assert np.all(tg[~nzf] == 0) and np.all(to[~nzf] == 0)
+
+    grid = ex.grid_from_workload(w, tau_ct=tau_g, fcorr_ct=fc_g)
+    say("case: oracle transport of the 1e5 packets on the full grid")
+    r = oracle.transport(oracle.transport_inputs_from_workload(w, tau_ct=tau_o, fcorr_ct=fc_o))
+    rec = r["records"]
+    line_trans = np.full(L, -1, dtype=np.int64)
+    line_trans[w.atom.trans_line] = np.arange(T)
+    lt = line_trans[rec["line"]]
+    on = lt >= 0
+    cells_hit, inv = np.unique(rec["cell"][on], return_inverse=True)
+    est = np.zeros(len(cells_hit) * T)
+    np.add.at(est, inv * T + lt[on], rec["value"][on])    # packet order, as dense_estimator
+    atom_t = dataclasses.replace(w.atom, trans_line=np.arange(T, dtype=w.atom.trans_line.dtype))
+    ref = oracle.rates(est, pops[cells_hit], atom_t, V).reshape(-1, T)
+    say(f"  oracle: {r['stats']['n_inter']:.0f} interactions, {on.sum()} on atom lines, "
+        f"{len(cells_hit)} cells touched")
+    for fp32 in (False, True):
+        say(f"case: GPU streamed over 8 octants, rates per interaction, FP32 geometry {fp32}")
+        gam, st, _ = ex.transport_streamed(ctx, grid, w.seed, w.lambda_lo, w.lambda_hi, w.n_packets,
+                                           atom=atom, pops=pg, t_exp=w.t_exp, geometry_fp32=fp32,
+                                           octant_table=False)
+        torch.cuda.synchronize()
+        sd = ex.stats_dict(st)
+        hit = torch.as_tensor(cells_hit, device="cuda:0")
+        got = gam[hit].cpu().numpy()
+        untouched = torch.ones(C, dtype=torch.bool, device="cuda:0")
+        untouched[hit] = False
+        rest = int((gam[untouched] != 0).sum())
+        if not fp32:
+            assert sd["n_inter"] == r["stats"]["n_inter"]
+            nz = ref > 0
+            assert np.array_equal(got > 0, nz)
+            rel = np.max(np.abs(got[nz] - ref[nz]) / ref[nz])
+            say(f"  rates on {nz.sum()} touched entries: max rel {rel:.2e}; nonzero elsewhere {rest}")
+            assert rel <= 1e-10 and rest == 0
+        else:
+            d_inter = abs(sd["n_inter"] - r["stats"]["n_inter"]) / r["stats"]["n_inter"]
+            n_l = pops[cells_hit][:, w.atom.trans_lower]
+            tot_ref = float((ref * n_l).sum())
+            tot = float((gam * pg[:, torch.as_tensor(w.atom.trans_lower.astype(np.int64),
+                                                      device="cuda:0")]).sum())
+            say(f"  interactions {sd['n_inter']:.0f} (rel diff {d_inter:.1e}); summed atom-line "
+                f"rates rel diff {abs(tot - tot_ref) / tot_ref:.1e}")
+            assert d_inter <= 1e-3 and abs(tot - tot_ref) <= 1e-3 * tot_ref
