@@ -556,7 +556,8 @@ int extrass_nlte_warm_start(extrass_handle h, extrass_atom_handle atom, const ex
  *   level i of stage z in cell c, counter (c, z, i, 2^63):
  *     g = 1 + floor(9 u0); E = 0 (ground, i = 0) or 69 k T_e u1
  *   pair l < u of stage z, counter (c, z, l, u): radiative iff u0 < 0.2, with
- *     A = 10^(-3 + 11 u1), Gamma_PE = 10^(-11 + 6 u3); q = 10^(-10 + 3 u2)
+ *     A = 10^(-3 + 11 u1), Gamma_PE = gamma_pe_table[min(n - 1, floor(u3 n))]
+ *     (n = n_gamma_pe); q = 10^(-10 + 3 u2)
  *   upper (higher E; higher index on a tie) -> lower: A + n_e q + (g_l/g_u) Gamma_PE
  *   lower -> upper: n_e q (g_u/g_l) exp(-(E_u - E_l)/kT) + Gamma_PE
  *   every level of stage z -> ground of z+1: gamma_ion[c*2 + z]
@@ -583,6 +584,10 @@ typedef struct {
   const double* n_e;             /* device [C] cm^-3 */
   const double* gamma_ion;       /* device [C*2] s^-1 */
   double alpha0[2];              /* cm^3 s^-1 at 1e4 K, recombination into stage z */
+  const double* gamma_pe_table;  /* device [n_gamma_pe] s^-1, ascending: the photoexcitation
+                                    rates a radiative pair takes its rate from (rates
+                                    measured from the estimators of a transport run) */
+  int64_t n_gamma_pe;            /* >= 1, else EXTRASS_EINVAL */
 } extrass_batched;
 
 typedef struct {

@@ -70,7 +70,7 @@ class _Cells(C.Structure):
 class _Batched(C.Structure):
     _fields_ = [("n_cells", C.c_int64), ("seed", C.c_uint64), ("level_count", C.c_void_p),
                 ("T_e", C.c_void_p), ("n_e", C.c_void_p), ("gamma_ion", C.c_void_p),
-                ("alpha0", C.c_double * 2)]
+                ("alpha0", C.c_double * 2), ("gpe_table", C.c_void_p), ("n_gpe", C.c_int64)]
 
 
 def lib():
@@ -545,10 +545,12 @@ class BatchedInputs:
         self.k = dict(level_count=np.ascontiguousarray(b.level_count, dtype=np.int32),
                       T_e=np.ascontiguousarray(b.T_e, dtype=np.float64),
                       n_e=np.ascontiguousarray(b.n_e, dtype=np.float64),
-                      gamma_ion=np.ascontiguousarray(b.gamma_ion, dtype=np.float64))
+                      gamma_ion=np.ascontiguousarray(b.gamma_ion, dtype=np.float64),
+                      gpe_table=np.ascontiguousarray(b.gamma_pe_table, dtype=np.float64))
         self.s = _Batched(int(b.n_cells), int(b.seed), _p(self.k["level_count"]),
                           _p(self.k["T_e"]), _p(self.k["n_e"]), _p(self.k["gamma_ion"]),
-                          (C.c_double * 2)(*[float(a) for a in b.alpha0]))
+                          (C.c_double * 2)(*[float(a) for a in b.alpha0]),
+                          _p(self.k["gpe_table"]), len(self.k["gpe_table"]))
         self.pop_offset = np.ascontiguousarray(b.pop_offset, dtype=np.int64)
         self.n_cells = int(b.n_cells)
 

@@ -15,7 +15,9 @@
  *     Boltzmann factors reach e^-69 ~ 1e-30 at the cell's temperature.
  *   pair l < u of stage z in cell c: counter (c, z, l, u);
  *     radiative iff u0 < 0.2: A = 10^(-3 + 11 u1) s^-1 and
- *     Gamma_PE = 10^(-11 + 6 u3) s^-1 (a stand-in for estimator rates);
+ *     Gamma_PE = gpe_table[min(n - 1, floor(u3 n))] s^-1, n = n_gpe: one of
+ *     the photoexcitation rates measured from the estimators of a transport
+ *     run (the stored table of the 16^3 sphere workload's rates);
  *     downward collision coefficient q = 10^(-10 + 3 u2) cm^3 s^-1.
  *   uniforms u_k = (x_k >> 11) 2^-53 of the four output words.
  * The upper level of a pair is the one with the higher energy (the higher
@@ -67,7 +69,9 @@ void oracle_batched_matrix(const or_batched* p, int64_t c, double* R) {
         const int up = E[b] >= E[a] ? b : a, lo = up == b ? a : b;
         const int rad = u[0] < 0.2;
         const double A = rad ? pow(10.0, -3.0 + 11.0 * u[1]) : 0.0;
-        const double gam = rad ? pow(10.0, -11.0 + 6.0 * u[3]) : 0.0;
+        int64_t it = (int64_t)(u[3] * (double)p->n_gpe);
+        if (it > p->n_gpe - 1) it = p->n_gpe - 1;
+        const double gam = rad ? p->gpe_table[it] : 0.0;
         const double q = pow(10.0, -10.0 + 3.0 * u[2]);
         R[up * N + lo] = A + ne * q + (g[lo] / g[up]) * gam;
         R[lo * N + up] = ne * q * (g[up] / g[lo]) * exp(-(E[up] - E[lo]) / kT) + gam;

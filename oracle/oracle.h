@@ -225,6 +225,8 @@ typedef struct {
   const double* n_e;              /* [C] */
   const double* gamma_ion;        /* [C*2] */
   double alpha0[2];
+  const double* gpe_table;        /* [n_gpe] photoexcitation rates a radiative pair draws from */
+  int64_t n_gpe;
 } or_batched;
 
 /* Dense rate matrix R[i*N+j] (i -> j, s^-1) of cell c, N = levels of the cell. */

@@ -89,7 +89,8 @@ class _Opts(C.Structure):
 class _Batched(C.Structure):
     _fields_ = [("n_cells", C.c_int64), ("seed", C.c_uint64), ("level_count", C.c_void_p),
                 ("level_count_d", C.c_void_p), ("T_e", C.c_void_p), ("n_e", C.c_void_p),
-                ("gamma_ion", C.c_void_p), ("alpha0", C.c_double * 2)]
+                ("gamma_ion", C.c_void_p), ("alpha0", C.c_double * 2),
+                ("gamma_pe_table", C.c_void_p), ("n_gamma_pe", C.c_int64)]
 
 
 class _BOpts(C.Structure):
@@ -755,13 +756,15 @@ class Batched:
         self.n_e = _dev(b.n_e, torch.float64, device)
         self.gamma_ion = _dev(b.gamma_ion, torch.float64, device)
         self.alpha0 = [float(a) for a in b.alpha0]
+        self.gamma_pe_table = _dev(b.gamma_pe_table, torch.float64, device)
         self.n_pops = int(self.level_count.astype(np.int64).sum())
         self.device = device
 
     def struct(self):
         return _Batched(self.n_cells, self.seed, self.level_count.ctypes.data,
                         _ptr(self.level_count_d), _ptr(self.T_e), _ptr(self.n_e),
-                        _ptr(self.gamma_ion), (C.c_double * 2)(*self.alpha0))
+                        _ptr(self.gamma_ion), (C.c_double * 2)(*self.alpha0),
+                        _ptr(self.gamma_pe_table), self.gamma_pe_table.numel())
 
 
 def _bopts(factor_fp32, refine, tol, panel, per_cu):

@@ -75,6 +75,8 @@ struct Args {
   const double* T_e;
   const double* n_e;
   const double* gion;
+  const double* gpe_tab;  // [n_gpe] photoexcitation rates, ascending
+  int64_t n_gpe;
   double alpha0_0, alpha0_1;
   double* A64;
   float* A32;
@@ -126,7 +128,9 @@ __device__ __forceinline__ void pair_rates(const Args& A, int64_t c, int z, int 
     const int up = Es[u] >= Es[l] ? u : l, lo = up == u ? l : u;
     const bool rad = unit53(r.v[0]) < 0.2;
     const double Ad = rad ? exp10(-3.0 + 11.0 * unit53(r.v[1])) : 0.0;
-    const double gam = rad ? exp10(-11.0 + 6.0 * unit53(r.v[3])) : 0.0;
+    int64_t it = (int64_t)(unit53(r.v[3]) * (double)A.n_gpe);
+    it = it < A.n_gpe - 1 ? it : A.n_gpe - 1;
+    const double gam = rad ? A.gpe_tab[it] : 0.0;
     const double q10 = exp10(-10.0 + 3.0 * unit53(r.v[2]));
     const double down = Ad + ne * q10 + (gs[lo] / gs[up]) * gam;
     const double upw = ne * q10 * (gs[up] / gs[lo]) * exp(-(Es[up] - Es[lo]) / kT) + gam;
@@ -179,14 +183,15 @@ __global__ __launch_bounds__(kThreads) void k_assemble(Args A, int fp32) {
   double* M64 = A.A64 + bk.a;
   float* M32 = fp32 ? A.A32 + bk.a : nullptr;
   // FP32 copy: scaled by a power of two that brings the largest possible rate
-  // of the cell (A <= 1e8, q <= 1e-7, Gamma_PE <= 1e-5, g ratio <= 9, ionisation
+  // of the cell (A <= 1e8, q <= 1e-7, Gamma_PE <= the table's last, g ratio <= 9, ionisation
   // and recombination of either stage) to ~2^100, so that rates ~70 decades
   // below it stay normal. GTH quotients are scale-free; the factor is the same
   // for the blocks of a cell, whose reduced rates meet in the ground-state chain.
   double sc = 1.0;
   if (fp32) {
     const double rec_max = ne * fmax(A.alpha0_0, A.alpha0_1) * pow(T / 1e4, -0.8);
-    const double bound = 1e8 + 9.0 * ne * 1e-7 + 9.0 * 1e-5 + fmax(A.gion[2 * c], A.gion[2 * c + 1]) +
+    const double bound = 1e8 + 9.0 * ne * 1e-7 + 9.0 * A.gpe_tab[A.n_gpe - 1] +
+                         fmax(A.gion[2 * c], A.gion[2 * c + 1]) +
                          rec_max;
     sc = ldexp(1.0, 100 - ilogb(bound));
     if (tid == 0) A.scale[blockIdx.x] = sc;
@@ -696,8 +701,11 @@ size_t arena_bytes(const Layout& y, int64_t a_elems, int64_t v_elems, int64_t nb
 int validate(extrass_handle h, const extrass_batched* p) {
   if (!p || p->n_cells < 0) return fail(h, EXTRASS_EINVAL, "extrass_batched: bad problem");
   if (p->n_cells == 0) return EXTRASS_OK;
-  if (!p->level_count || !p->level_count_d || !p->T_e || !p->n_e || !p->gamma_ion)
+  if (!p->level_count || !p->level_count_d || !p->T_e || !p->n_e || !p->gamma_ion ||
+      !p->gamma_pe_table)
     return fail(h, EXTRASS_EINVAL, "extrass_batched: null array");
+  if (p->n_gamma_pe < 1)
+    return fail(h, EXTRASS_EINVAL, "extrass_batched: empty photoexcitation table");
   for (int64_t c = 0; c < p->n_cells; ++c) {
     const int32_t* Lc = p->level_count + 3 * c;
     for (int z = 0; z < 3; ++z)
@@ -864,6 +872,8 @@ Args chunk_args(const extrass_batched* p, const Layout& y, const Plan& P, const 
   a.T_e = p->T_e;
   a.n_e = p->n_e;
   a.gion = p->gamma_ion;
+  a.gpe_tab = p->gamma_pe_table;
+  a.n_gpe = p->n_gamma_pe;
   a.alpha0_0 = p->alpha0[0];
   a.alpha0_1 = p->alpha0[1];
   Carver cw(cv.arena_base, cv.arena_cap);

@@ -19,6 +19,7 @@ cm^-3, times in s. The velocity coordinate is x = v/c: the cube spans
 from __future__ import annotations
 
 import dataclasses
+import os
 from typing import Optional
 
 import numpy as np
@@ -379,9 +380,12 @@ class Batched:
         g = 1 + floor(9 u0); E = 0 for i = 0, else 69 k T_e(c) u1
       pair l < u of stage z in cell c: counter (c, z, l, u), uniforms u0..u3
         radiative iff u0 < 0.2 with A = 10^(-3 + 11 u1) s^-1 and
-        Gamma_PE = 10^(-11 + 6 u3) s^-1; q_down = 10^(-10 + 3 u2) cm^3 s^-1
+        Gamma_PE = gamma_pe_table[min(n - 1, floor(u3 n))] s^-1 (n entries);
+        q_down = 10^(-10 + 3 u2) cm^3 s^-1
     where uniforms are (x >> 11) * 2^-53 of the four 64-bit output words.
-    This module holds only the stored inputs below.
+    The table holds the photoexcitation rates the oracle measures on the 16^3
+    sphere workload (synth/make_photoexcitation_table.py writes it). This
+    module holds only the stored inputs below.
     """
     name: str
     n_cells: int
@@ -391,11 +395,19 @@ class Batched:
     n_e: np.ndarray           # f64 [C] cm^-3
     gamma_ion: np.ndarray     # f64 [C*2] s^-1, any level of stage z -> ground of z+1
     alpha0: np.ndarray        # f64 [2] cm^3 s^-1 at 1e4 K, recombination into stage z
+    gamma_pe_table: np.ndarray  # f64 [n] s^-1, photoexcitation rates drawn from (sorted)
 
     @property
     def pop_offset(self) -> np.ndarray:
         n = self.level_count.reshape(-1, 3).sum(1).astype(np.int64)
         return np.concatenate([[0], np.cumsum(n)])
+
+
+def photoexcitation_table() -> np.ndarray:
+    """The stored photoexcitation rates of the 16^3 sphere workload (sorted,
+    positive; written by make_photoexcitation_table.py with the oracle)."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "photoexcitation_sphere16.npy")
+    return np.load(path, allow_pickle=False)
 
 
 def batched(n: int = 50, lo: int = 20, hi: int = 300, number: int = 3,
@@ -411,7 +423,7 @@ def batched(n: int = 50, lo: int = 20, hi: int = 300, number: int = 3,
     return Batched(name=f"batched{n}_L{lo}-{hi}", n_cells=C, seed=SEED_BASE + number,
                    level_count=counts.ravel().copy(), T_e=w.T_e[:C].copy(),
                    n_e=w.n_e[:C].copy(), gamma_ion=gion.ravel().copy(),
-                   alpha0=np.array([2.0e-12, 4.0e-12]))
+                   alpha0=np.array([2.0e-12, 4.0e-12]), gamma_pe_table=photoexcitation_table())
 
 
 def batched_custom(level_count, T_e, n_e, gamma_ion, alpha0=(2.0e-12, 4.0e-12),
@@ -426,7 +438,7 @@ def batched_custom(level_count, T_e, n_e, gamma_ion, alpha0=(2.0e-12, 4.0e-12),
                    gamma_ion=np.broadcast_to(np.asarray(gamma_ion, float).reshape(-1, 2)
                                              if np.ndim(gamma_ion) else
                                              np.full((1, 2), float(gamma_ion)), (C, 2)).ravel().copy(),
-                   alpha0=np.asarray(alpha0, float))
+                   alpha0=np.asarray(alpha0, float), gamma_pe_table=photoexcitation_table())
 
 
 def large() -> Workload:
