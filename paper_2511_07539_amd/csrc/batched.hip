@@ -23,7 +23,14 @@
 //                     rows) brought to their elimination time by unit-triangular
 //                     recurrences, one column or row per thread;
 //                 (d) trailing update A_TT += C diag(1/S) R on matrix cores
-//                     (MFMA 16x16x4 in T), one 32 x 32 tile per wavefront step.
+//                     (MFMA 16x16x4 in T), one 32 x 32 tile per wavefront step;
+//                     panels go in groups of 32 states: each panel's rows and
+//                     columns take the update of the group's earlier panels
+//                     before its steps (a)-(c), and the rest of the trailing
+//                     matrix takes one update of the whole group (rank up to
+//                     32), read and written once per group (groups of 48 and
+//                     64 states measured the same: the wider update re-reads
+//                     its operands per 32 x 32 tile).
 //                 Every term is a product of non-negative rates: there is no
 //                 subtraction, so populations down to 1e-30 keep their accuracy.
 //  k_chain        per cell: the ground-state chain
@@ -53,6 +60,11 @@ constexpr double kBoltz = 1.380649e-16;  // erg/K
 constexpr int kThreads = 256;
 constexpr int kMaxLevels = 1023;
 constexpr int kMaxB = kMaxLevels + 1;
+// states eliminated per group of panels (column factors kept for one update);
+// a panel wider than the group is a group of its own
+constexpr int kGroup = 32;
+// rows of column factors per resident work-group: the widest group
+constexpr int kCtRows = kGroup > 64 ? kGroup : 64;
 constexpr uint64_t kPhiloxStream = 6;
 
 struct Blk {
@@ -89,7 +101,7 @@ struct Args {
   const int32_t* cell_blk;  // [ncell*3] block of each stage, -1 if absent
   double* gval;          // [ncell*3] ground-state values (populations or corrections)
   unsigned long long* maxrel;  // [ncell] bits of max |correction / population|
-  void* ct;              // panel-column scratch per resident work-group
+  void* ct;              // column factors of one group of panels per resident work-group
   int maxB;              // largest block of the problem (LDS of the assembly)
   int ldct;
   unsigned int* queue;
@@ -267,20 +279,28 @@ template <> struct Acc<float> {
   }
 };
 
-// A[t0+r][t0+s] += sum_k ct[k][r] * A[p0+k][t0+s] for r, s < nt, k < np.
-// Operand layout of the 16x16x4 instructions (lane l): A-operand row l%16,
-// k l/16; B-operand column l%16, k l/16; accumulator column l%16, row
-// Acc<T>::row(l/16, q) for register q. Rows [np, roundup4(np)) of ct are zero.
+// M[t][u] += sum_{k < K} Ct(k, t) M[p0 + k][u] for t in [r0, r0 + nr),
+// u in [s0, s0 + ns): the rank-K update of a window of the trailing matrix by
+// the panel rows p0 .. p0 + K - 1 (at their elimination time) and their
+// column factors, Ct(k, t) = ct[k][t - cb.b[k / nb]] (the column factors of
+// each panel of nb rows start at that panel's first trailing row). Operand layout
+// of the 16x16x4 instructions (lane l): A-operand row l%16, k l/16; B-operand
+// column l%16, k l/16; accumulator column l%16, row Acc<T>::row(l/16, q) for
+// register q. Rows [K, roundup4(K)) of ct are zero.
+struct Bases {
+  int b[4];
+};
+
 template <class T>
-__device__ void trailing_update(T* M, int B, int p0, int np, int t0, int nt, const T* ct,
-                                int ldct) {
+__device__ void trailing_update(T* M, int B, int p0, int K, int r0, int nr, int s0, int ns,
+                                const T* ct, int ldct, int nb, const Bases& cb) {
   typedef typename Acc<T>::type V;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int nside = (nt + 31) >> 5;
-  const int ksteps = (np + 3) >> 2;
+  const int nsr = (nr + 31) >> 5, nss = (ns + 31) >> 5;
+  const int ksteps = (K + 3) >> 2;
   const int lr = lane & 15, lk = lane >> 4;
-  for (int tile = wave; tile < nside * nside; tile += kThreads / 64) {
-    const int r0 = (tile / nside) << 5, s0 = (tile % nside) << 5;
+  for (int tile = wave; tile < nsr * nss; tile += kThreads / 64) {
+    const int tr = (tile / nss) << 5, ts0 = (tile % nss) << 5;
     V acc[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -288,21 +308,22 @@ __device__ void trailing_update(T* M, int B, int p0, int np, int t0, int nt, con
       for (int b = 0; b < 2; ++b)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const int r = r0 + 16 * a + Acc<T>::row(lk, q), s = s0 + 16 * b + lr;
-          acc[a][b][q] = (r < nt && s < nt) ? M[(int64_t)(t0 + r) * B + t0 + s] : T(0);
+          const int r = tr + 16 * a + Acc<T>::row(lk, q), c = ts0 + 16 * b + lr;
+          acc[a][b][q] = (r < nr && c < ns) ? M[(int64_t)(r0 + r) * B + s0 + c] : T(0);
         }
     for (int ks = 0; ks < ksteps; ++ks) {
       const int k = 4 * ks + lk;
+      const int cbk = cb.b[k / nb];
       T av[2], bv[2];
 #pragma unroll
       for (int a = 0; a < 2; ++a) {
-        const int r = r0 + 16 * a + lr;
-        av[a] = r < nt ? ct[(int64_t)k * ldct + r] : T(0);
+        const int r = tr + 16 * a + lr;
+        av[a] = r < nr ? ct[(int64_t)k * ldct + (r0 + r - cbk)] : T(0);
       }
 #pragma unroll
       for (int b = 0; b < 2; ++b) {
-        const int s = s0 + 16 * b + lr;
-        bv[b] = (s < nt && k < np) ? M[(int64_t)(p0 + k) * B + t0 + s] : T(0);
+        const int c = ts0 + 16 * b + lr;
+        bv[b] = (c < ns && k < K) ? M[(int64_t)(p0 + k) * B + s0 + c] : T(0);
       }
 #pragma unroll
       for (int a = 0; a < 2; ++a)
@@ -315,8 +336,8 @@ __device__ void trailing_update(T* M, int B, int p0, int np, int t0, int nt, con
       for (int b = 0; b < 2; ++b)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const int r = r0 + 16 * a + Acc<T>::row(lk, q), s = s0 + 16 * b + lr;
-          if (r < nt && s < nt) M[(int64_t)(t0 + r) * B + t0 + s] = acc[a][b][q];
+          const int r = tr + 16 * a + Acc<T>::row(lk, q), c = ts0 + 16 * b + lr;
+          if (r < nr && c < ns) M[(int64_t)(r0 + r) * B + s0 + c] = acc[a][b][q];
         }
   }
 }
@@ -333,7 +354,9 @@ __global__ __launch_bounds__(kThreads) void k_factor(Args A) {
   __shared__ double inv_s[NB];
   __shared__ int item;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  T* ct = reinterpret_cast<T*>(A.ct) + (int64_t)blockIdx.x * NB * A.ldct;
+  // column factors of a group of kGroup / NB panels for the combined update
+  constexpr int P = kGroup / NB > 1 ? kGroup / NB : 1;
+  T* ct = reinterpret_cast<T*>(A.ct) + (int64_t)blockIdx.x * kCtRows * A.ldct;
   T* arena = sizeof(T) == 8 ? reinterpret_cast<T*>(A.A64) : reinterpret_cast<T*>(A.A32);
   for (;;) {
     if (tid == 0) item = (int)atomicAdd(A.queue, 1u);
@@ -345,8 +368,10 @@ __global__ __launch_bounds__(kThreads) void k_factor(Args A) {
     const int B = bk.B, ne = bk.L - 1;
     T* M = arena + bk.a;
     double* S = A.S + bk.v;
-    for (int p0 = 0; p0 < ne; p0 += NB) {
-      const int np = min(NB, ne - p0), t0 = p0 + np, nt = B - t0;
+    // One panel of np states from p0: (a)-(c) below; its column factors go
+    // to ctp, row t - t0 of each.
+    auto panel = [&](int p0, int np, T* ctp) {
+      const int t0 = p0 + np;
       // (a) trailing row sums of the panel rows; the diagonal block into LDS
       for (int k = wave; k < np; k += kThreads / 64) {
         double s = 0.0;
@@ -432,15 +457,36 @@ __global__ __launch_bounds__(kThreads) void k_factor(Args A) {
           if (i < np) {
             const T v = (T)(cv[i] * inv_s[i]);
             M[(int64_t)t * B + p0 + i] = v;
-            ct[(int64_t)i * A.ldct + (t - t0)] = v;
+            ctp[(int64_t)i * A.ldct + (t - t0)] = v;
           } else if (i < np4) {
-            ct[(int64_t)i * A.ldct + (t - t0)] = T(0);
+            ctp[(int64_t)i * A.ldct + (t - t0)] = T(0);
           }
         }
       }
       __syncthreads();
-      // (d) trailing update
-      trailing_update<T>(M, B, p0, np, t0, nt, ct, A.ldct);
+    };
+    // Panels in groups of kGroup states. Before its steps (a)-(c), a panel's
+    // rows and columns (all that those steps read) take the update of the
+    // group's earlier panels; after the group, (d) one update of rank up to
+    // kGroup brings the rest of the trailing matrix forward by all of them,
+    // read and written once per group instead of once per panel.
+    for (int g0 = 0; g0 < ne; g0 += P * NB) {
+      Bases cb{};
+      int K = 0, pj = g0;
+#pragma unroll 1
+      for (int j = 0; j < P && pj < ne; ++j) {
+        const int np = min(NB, ne - pj);
+        if (j > 0) {
+          trailing_update<T>(M, B, g0, K, pj, np, pj, B - pj, ct, A.ldct, NB, cb);
+          trailing_update<T>(M, B, g0, K, pj + np, B - pj - np, pj, np, ct, A.ldct, NB, cb);
+          __syncthreads();
+        }
+        panel(pj, np, ct + (int64_t)j * NB * A.ldct);
+        pj += np;
+        cb.b[j] = pj;
+        K += np;
+      }
+      trailing_update<T>(M, B, g0, K, pj, B - pj, pj, B - pj, ct, A.ldct, NB, cb);
       __syncthreads();
     }
     if (tid == 0 && B == bk.L + 1) {
@@ -730,7 +776,7 @@ Layout make_layout(extrass_handle h, const extrass_batched* p, const extrass_bat
   y.G = (int64_t)h->num_cus * y.per_cu;
   const size_t el = y.fp32 ? sizeof(float) : sizeof(double);
   y.fixed = carve_bytes<Blk>(3 * p->n_cells) + carve_bytes<int32_t>(3 * p->n_cells) +
-            carve_bytes<int64_t>(p->n_cells + 1) + (size_t)y.G * y.panel * y.ldct * el + 256 +
+            carve_bytes<int64_t>(p->n_cells + 1) + (size_t)y.G * kCtRows * y.ldct * el + 256 +
             carve_bytes<unsigned int>(1);
   return y;
 }
@@ -842,7 +888,8 @@ int upload_tables(extrass_handle h, const Plan& P, const Layout& y, void* ws, si
   cv.blk = cw.take<Blk>(3 * C);
   cv.cell_blk = cw.take<int32_t>(3 * C);
   cv.pop = cw.take<int64_t>(C + 1);
-  cv.ct = cw.take<char>((size_t)y.G * y.panel * y.ldct * (y.fp32 ? sizeof(float) : sizeof(double)));
+  // column factors of one group of panels per resident work-group
+  cv.ct = cw.take<char>((size_t)y.G * kCtRows * y.ldct * (y.fp32 ? sizeof(float) : sizeof(double)));
   cv.queue = cw.take<unsigned int>(1);
   if (!cw.ok()) return fail(h, EXTRASS_ENOSPACE, "extrass_batched: workspace too small");
   const size_t used = (cw.used + 255) & ~size_t(255);
