@@ -466,17 +466,18 @@ typedef struct {
                           populations are then within about tol relative of the root */
   int32_t use_guess;   /* 1: start from pops on entry (a non-positive entry means
                           the cold start for that system); 0: cold start */
-  int32_t factor_fp32; /* 0: every reduction in FP64. 1: the mixed-precision pass: the
-                          fixed-point steps reduce their stationary problem in FP32
-                          (a reduction of positive numbers only, so each population
-                          keeps FP32's relative accuracy; matrix scaled by one power
-                          of two to a largest entry in [1, 2), the reference ground's
-                          population to 2^100), except the first step from a guess; residuals and
-                          Newton systems stay FP64, so the exit test, and the
-                          accuracy tol, are those of 0. A step with an FP32 pivot or
-                          population outside the normal range is assembled again
-                          and reduced in FP64. Stage-block atoms only (blocks of at
-                          most 32 states in 64 lanes), else EXTRASS_EUNSUPPORTED */
+  int32_t factor_fp32; /* 0: every reduction in FP64. 1: the mixed-precision pass:
+                          the fixed-point steps, except the first from a guess,
+                          reduce their stationary problem in FP32 (positive numbers
+                          only, so each population keeps FP32's relative accuracy;
+                          the matrix is scaled by one power of two to a largest
+                          entry in [1, 2), the reference ground's population is
+                          2^100). Residuals and Newton systems stay FP64, so the
+                          exit test, and the accuracy tol, are those of 0. A step
+                          with an FP32 pivot or population outside the normal
+                          range is assembled again and reduced in FP64. Stage-block
+                          atoms only (blocks of at most 32 states in 64 lanes),
+                          else EXTRASS_EUNSUPPORTED */
   int32_t warm_budget; /* with use_guess: after this many iterations from the guess,
                           a system still in its fixed-point phase or with a
                           fixed-point residual above 1e-6 restarts from the cold
