@@ -133,11 +133,14 @@ def test_three_stage_atom_sampled_cells(ex, ctx, mixed):
     assert span < 1e-20
 
 
-@pytest.mark.parametrize("ion_levels", [(10, 10, 24), (40,)])
-def test_other_atom_shapes(ex, ctx, ion_levels):
+@pytest.mark.parametrize("ion_levels,mixed", [((10, 10, 24), False), ((10, 10, 24), True),
+                                              ((40,), False)])
+def test_other_atom_shapes(ex, ctx, ion_levels, mixed):
     """Stage blocks that fill a 24-row block exactly (top stage of 24 levels:
-    23 excited levels, no next ground), and a 40-level single-stage species
-    whose block exceeds 32 rows (whole-system reduction)."""
+    23 excited levels, no next ground), also with the fixed-point steps in
+    FP32 (the 24-state instance of the mixed kernel), and a 40-level
+    single-stage species whose block exceeds 32 rows (whole-system
+    reduction)."""
     w = synth.clumpy(n=16, n_lines=3000, n_packets=1000, number=2, ion_levels=ion_levels)
     g = np.random.default_rng(1)
     cells = np.sort(g.choice(w.n_cells, 600, replace=False))
@@ -147,8 +150,8 @@ def test_other_atom_shapes(ex, ctx, ion_levels):
     po, so, _ = oracle.nlte(inp, tol=1e-12)
     atom = ex.Atom(ctx, w.atom)
     cl = ex.cells_from_workload(w, gamma_pe=gpe, cells=cells)
-    say(f"case: NLTE with stages {ion_levels}, 600 sampled cells")
-    pg, sg, _ = ex.nlte_solve(ctx, atom, cl, max_iter=200, tol=1e-10)
+    say(f"case: NLTE with stages {ion_levels}, 600 sampled cells, FP32 fixed-point steps {mixed}")
+    pg, sg, _ = ex.nlte_solve(ctx, atom, cl, max_iter=200, tol=1e-10, factor_fp32=mixed)
     torch.cuda.synchronize()
     sgn = sg.cpu().numpy()
     worst, span = _compare(pg.cpu().numpy(), sgn, po, so, inp=inp,
