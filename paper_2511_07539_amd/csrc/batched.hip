@@ -291,19 +291,20 @@ struct Bases {
   int b[4];
 };
 
-template <class T>
+template <class T, int RA = 2>
 __device__ void trailing_update(T* M, int B, int p0, int K, int r0, int nr, int s0, int ns,
                                 const T* ct, int ldct, int nb, const Bases& cb) {
   typedef typename Acc<T>::type V;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int nsr = (nr + 31) >> 5, nss = (ns + 31) >> 5;
+  // tiles of 16 RA rows x 32 columns per wavefront
+  const int nsr = (nr + 16 * RA - 1) / (16 * RA), nss = (ns + 31) >> 5;
   const int ksteps = (K + 3) >> 2;
   const int lr = lane & 15, lk = lane >> 4;
   for (int tile = wave; tile < nsr * nss; tile += kThreads / 64) {
-    const int tr = (tile / nss) << 5, ts0 = (tile % nss) << 5;
-    V acc[2][2];
+    const int tr = (tile / nss) * (16 * RA), ts0 = (tile % nss) << 5;
+    V acc[RA][2];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < RA; ++a)
 #pragma unroll
       for (int b = 0; b < 2; ++b)
 #pragma unroll
@@ -314,9 +315,9 @@ __device__ void trailing_update(T* M, int B, int p0, int K, int r0, int nr, int 
     for (int ks = 0; ks < ksteps; ++ks) {
       const int k = 4 * ks + lk;
       const int cbk = cb.b[k / nb];
-      T av[2], bv[2];
+      T av[RA], bv[2];
 #pragma unroll
-      for (int a = 0; a < 2; ++a) {
+      for (int a = 0; a < RA; ++a) {
         const int r = tr + 16 * a + lr;
         av[a] = r < nr ? ct[(int64_t)k * ldct + (r0 + r - cbk)] : T(0);
       }
@@ -326,12 +327,12 @@ __device__ void trailing_update(T* M, int B, int p0, int K, int r0, int nr, int 
         bv[b] = (c < ns && k < K) ? M[(int64_t)(p0 + k) * B + s0 + c] : T(0);
       }
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+      for (int a = 0; a < RA; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = Acc<T>::mma(av[a], bv[b], acc[a][b]);
     }
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < RA; ++a)
 #pragma unroll
       for (int b = 0; b < 2; ++b)
 #pragma unroll
@@ -486,7 +487,10 @@ __global__ __launch_bounds__(kThreads) void k_factor(Args A) {
         cb.b[j] = pj;
         K += np;
       }
-      trailing_update<T>(M, B, g0, K, pj, B - pj, pj, B - pj, ct, A.ldct, NB, cb);
+      // 64 x 32 tiles per wavefront in FP64 (fewer operand loads per entry);
+      // in FP32 they cost the kernel its third wavefront per SIMD
+      trailing_update<T, sizeof(T) == 8 ? 4 : 2>(M, B, g0, K, pj, B - pj, pj, B - pj, ct, A.ldct,
+                                                 NB, cb);
       __syncthreads();
     }
     if (tid == 0 && B == bk.L + 1) {
