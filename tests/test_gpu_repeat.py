@@ -85,17 +85,18 @@ def test_streamed_rates_repeat(ex, ctx, coupled):
     _reordered_sum(out[0][0], out[1][0], "rates")
 
 
-def test_nlte_repeats_bitwise(ex, ctx, coupled):
+@pytest.mark.parametrize("mixed", [False, True])
+def test_nlte_repeats_bitwise(ex, ctx, coupled, mixed):
     w, atom, cold, grid = coupled
-    say("case: NLTE solve twice on the rates of one transport")
+    say(f"case: NLTE solve twice on the rates of one transport, FP32 fixed-point steps {mixed}")
     est, _, _ = ex.transport(ctx, grid, w.seed, w.lambda_lo, w.lambda_hi, w.n_packets,
                              geometry_fp32=True)
     gam = ex.rates(ctx, atom, grid, w.t_exp, est, cold)
     cells = ex.cells_from_workload(w, gamma_pe=gam)
-    a = ex.nlte_solve(ctx, atom, cells, tol=1e-8)
-    b = ex.nlte_solve(ctx, atom, cells, tol=1e-8)
-    c = ex.nlte_solve(ctx, atom, cells, tol=1e-8, guess=a[0])
-    d = ex.nlte_solve(ctx, atom, cells, tol=1e-8, guess=a[0])
+    a = ex.nlte_solve(ctx, atom, cells, tol=1e-8, factor_fp32=mixed)
+    b = ex.nlte_solve(ctx, atom, cells, tol=1e-8, factor_fp32=mixed)
+    c = ex.nlte_solve(ctx, atom, cells, tol=1e-8, guess=a[0], factor_fp32=mixed)
+    d = ex.nlte_solve(ctx, atom, cells, tol=1e-8, guess=a[0], factor_fp32=mixed)
     torch.cuda.synchronize()
     for x, y in ((a, b), (c, d)):
         assert torch.equal(x[0], y[0]) and torch.equal(x[1], y[1]) and torch.equal(x[2], y[2])
